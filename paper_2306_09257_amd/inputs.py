@@ -1,0 +1,204 @@
+"""Seeded synthetic problem generators shared by the library tests, the bench
+and the oracle checks.
+
+This module describes *problems* (grid, layer rows, channel sets, permittivity
+maps, objective weights).  It contains none of the method's arithmetic: no
+operator entries, no propagation constants, no solves.  Both the HIP path and
+the CPU oracle consume what it returns.
+
+Layer layout (top to bottom, rows of the y axis):
+    PML_top (medium eps_top) | eps_top layer | design slab | eps_bot layer | PML_bot (eps_bot)
+The source row sits one row below the top PML, the projection row two rows
+above the bottom PML.  Channels are the Fourier orders a with |a| < nx*dx/lambda
+(the continuum propagating set in air), the same orders on both sides; the
+paper's metasurface benchmark counts channels the same way (Supplement Sec. 1,
+2W/lambda channels; Sec. 3 for the beam splitter's angular window).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    nx: int
+    ny: int
+    dx_over_lambda: float
+    npml_top: int
+    npml_bot: int
+    design_row0: int
+    design_row1: int
+    in_orders: np.ndarray
+    out_orders: np.ndarray
+    eps_top: float = 1.0
+    eps_bot: float = 2.25
+    pml_R0: float = 1e-8
+    pml_power: int = 3
+    src_row: int = -1
+    prj_row: int = -1
+
+    def __post_init__(self):
+        self.in_orders = np.asarray(self.in_orders, dtype=np.int32)
+        self.out_orders = np.asarray(self.out_orders, dtype=np.int32)
+        if self.src_row < 0:
+            self.src_row = self.npml_top + 1
+        if self.prj_row < 0:
+            self.prj_row = self.ny - self.npml_bot - 2
+
+    @property
+    def n_in(self) -> int:
+        return int(self.in_orders.size)
+
+    @property
+    def n_out(self) -> int:
+        return int(self.out_orders.size)
+
+    @property
+    def n_unknowns(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def n_design_rows(self) -> int:
+        return self.design_row1 - self.design_row0
+
+    @property
+    def h(self) -> float:
+        """k0*dx, the dimensionless frequency of the dx^2-scaled operator."""
+        return 2.0 * math.pi * self.dx_over_lambda
+
+    def background_eps(self) -> np.ndarray:
+        """[ny][nx] permittivity with the design rows left at eps_top."""
+        eps = np.empty((self.ny, self.nx), dtype=np.float64)
+        eps[: self.design_row1, :] = self.eps_top
+        eps[self.design_row1:, :] = self.eps_bot
+        return eps
+
+
+def channel_orders(nx: int, dx_over_lambda: float, sin_max: float = 1.0,
+                   n_medium: float = 1.0) -> np.ndarray:
+    """Orders a with |a| < n_medium * sin_max * nx*dx/lambda (strict)."""
+    lim = n_medium * sin_max * nx * dx_over_lambda
+    amax = int(math.ceil(lim)) - 1
+    while amax + 1 < lim:
+        amax += 1
+    a = np.arange(-amax, amax + 1, dtype=np.int32)
+    return a[np.abs(a) < lim]
+
+
+def layout_rows(ny: int):
+    """(npml, top layer, design, bottom layer, npml) for the row counts used
+    by the workloads: 60, 92, 140, 160 (and the pattern for others)."""
+    table = {60: (16, 4, 20, 4, 16), 92: (16, 20, 20, 20, 16),
+             140: (20, 30, 40, 30, 20), 160: (20, 40, 40, 40, 20)}
+    if ny in table:
+        return table[ny]
+    raise ValueError(f"no layer layout for ny={ny}")
+
+
+def make_problem(nx: int, ny: int, dx_over_lambda: float = 0.05,
+                 layout: Optional[Sequence[int]] = None,
+                 in_orders=None, out_orders=None, **kw) -> Problem:
+    lay = tuple(layout) if layout is not None else layout_rows(ny)
+    if sum(lay) != ny:
+        raise ValueError("layout rows must sum to ny")
+    npml_t, top, des, bot, npml_b = lay
+    d0 = npml_t + top
+    if in_orders is None:
+        in_orders = channel_orders(nx, dx_over_lambda)
+    if out_orders is None:
+        out_orders = in_orders
+    return Problem(nx=nx, ny=ny, dx_over_lambda=dx_over_lambda,
+                   npml_top=npml_t, npml_bot=npml_b, design_row0=d0,
+                   design_row1=d0 + des, in_orders=in_orders,
+                   out_orders=out_orders, **kw)
+
+
+# ----------------------------------------------------------------------------
+# permittivity maps and objective weights (numpy default_rng, draw order: eps
+# first, then w)
+# ----------------------------------------------------------------------------
+
+def eps_uniform(prob: Problem, rng: np.random.Generator, lo=1.0, hi=4.0) -> np.ndarray:
+    eps = prob.background_eps()
+    eps[prob.design_row0:prob.design_row1, :] = rng.uniform(
+        lo, hi, size=(prob.n_design_rows, prob.nx))
+    return eps
+
+
+def _gauss_kernel_fwhm(fwhm: float) -> np.ndarray:
+    sigma = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    r = int(math.ceil(3.0 * sigma))
+    x = np.arange(-r, r + 1, dtype=np.float64)
+    k = np.exp(-0.5 * (x / sigma) ** 2)
+    return k / k.sum()
+
+
+def eps_binary_smoothed(prob: Problem, rng: np.random.Generator,
+                        lo=1.0, hi=4.0, fwhm=3.0) -> np.ndarray:
+    """Bernoulli(1/2) pixels over {lo, hi}, then a normalised separable Gaussian
+    of the given FWHM: periodic wrap in x, mirror reflection at the slab's y
+    edges.  The result stays within [lo, hi]."""
+    eps = prob.background_eps()
+    nd = prob.n_design_rows
+    m = np.where(rng.random((nd, prob.nx)) < 0.5, lo, hi)
+    k = _gauss_kernel_fwhm(fwhm)
+    r = (k.size - 1) // 2
+    # x: periodic
+    sm = np.zeros_like(m)
+    for t in range(-r, r + 1):
+        sm += k[t + r] * np.roll(m, -t, axis=1)
+    # y: reflect at the slab edges
+    padded = np.pad(sm, ((r, r), (0, 0)), mode="symmetric")
+    out = np.zeros_like(sm)
+    for t in range(-r, r + 1):
+        out += k[t + r] * padded[r + t: r + t + nd, :]
+    eps[prob.design_row0:prob.design_row1, :] = np.clip(out, lo, hi)
+    return eps
+
+
+def weights_uniform(prob: Problem, rng: np.random.Generator) -> np.ndarray:
+    return rng.uniform(0.0, 1.0, size=(prob.n_out, prob.n_in))
+
+
+# ----------------------------------------------------------------------------
+# the named workloads
+# ----------------------------------------------------------------------------
+
+def metasurface_small(seed: int = 0):
+    """240 x 92 grid (22,080 unknowns), 23 x 23 channels, 4,800 design pixels,
+    i.i.d. U[1,4] design permittivity, w ~ U[0,1]."""
+    prob = make_problem(240, 92)
+    rng = np.random.default_rng(seed)
+    eps = eps_uniform(prob, rng)
+    w = weights_uniform(prob, rng)
+    return prob, eps, w
+
+
+def metasurface_wide(seed: int = 1, nx: int = 24000):
+    """24,000 x 160 grid (3.84M unknowns), 2,399 x 2,399 channels, 960,000
+    design pixels: binary {1,4} pixels smoothed by a 3-px-FWHM Gaussian."""
+    prob = make_problem(nx, 160)
+    rng = np.random.default_rng(seed)
+    eps = eps_binary_smoothed(prob, rng)
+    w = weights_uniform(prob, rng)
+    return prob, eps, w
+
+
+def tiny_problem(nx=24, ny=60, seed=0, layout=None, n_orders=None, **kw):
+    """Small grids for oracle pins and parity tests."""
+    lay = layout
+    if lay is None:
+        lay = layout_rows(ny) if ny in (60, 92, 140, 160) else None
+    prob = make_problem(nx, ny, layout=lay, **kw)
+    if n_orders is not None:
+        a = np.arange(-(n_orders // 2), n_orders - n_orders // 2, dtype=np.int32)
+        prob.in_orders = a
+        prob.out_orders = a
+    rng = np.random.default_rng(seed)
+    eps = eps_uniform(prob, rng)
+    w = weights_uniform(prob, rng)
+    return prob, eps, w
