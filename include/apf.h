@@ -1,0 +1,164 @@
+/*
+ * apf.h -- C ABI of the MI355X augmented-partial-factorization library.
+ *
+ * One sparse direct factorization of the augmented matrix K = [A, B; C, D]
+ * of a 2D TM (Ez) finite-difference frequency-domain problem yields the
+ * generalised scattering matrix S = C A^-1 B - D (Sec. 2 of Li, Lin and Hsu,
+ * "Fast multi-channel inverse design through augmented partial
+ * factorization", arXiv 2306.09257) and the gradient of an objective f(S)
+ * with respect to every design-pixel permittivity (Sec. 2, Eqs. (1)-(3)).
+ *
+ * Discretisation (the paper leaves it to its solver package; this library
+ * fixes it and documents it here):
+ *   - Ez on nodes (i, j), i = 0..nx-1 along x (periodic), j = 0..ny-1 rows
+ *     from the top; node index n = j*nx + i; spacing dx in both directions.
+ *   - Time convention exp(-i w t).  Uniaxial PML stretching y in the top
+ *     npml_top and bottom npml_bot rows: s(d) = 1 + i alpha (d/L)^m, d the
+ *     distance in pixels past the PML's inner face (the half-row between the
+ *     PML and the first physical row), m = pml_power,
+ *     alpha = (m+1) ln(1/R0) / (2 h sqrt(eps_pml) L), h = 2 pi dx/lambda.
+ *   - A (dx^2-scaled, complex symmetric):
+ *       (A E)_ij = s_j (2E_ij - E_i+1,j - E_i-1,j)
+ *                + (1/s_j+1/2 + 1/s_j-1/2) E_ij - E_i,j+1/s_j+1/2 - E_i,j-1/s_j-1/2
+ *                - h^2 eps_ji s_j E_ij,      E = 0 beyond rows 0 and ny-1.
+ *   - Channel a: phi_a(i) = exp(2 pi i a i/nx)/sqrt(nx), q_a in (0, pi) with
+ *     sin^2(q_a/2) = h^2 eps_medium/4 - sin^2(pi a/nx).
+ *     B[(i, src_row), a] = -2i sqrt(sin q_a) phi_a(i)   (unit-flux line source)
+ *     C[b, (i, prj_row)] = sqrt(sin q_b) conj(phi_b(i)), D = 0.
+ *
+ * Conventions of every entry point:
+ *   - Complex arrays are interleaved (re, im) float64 pairs, row-major.
+ *   - Pointers named *_dev are device pointers owned by the caller; they must
+ *     stay valid until the work queued on `stream` has finished.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on it, except where stated.
+ *   - No exceptions cross the ABI; every call returns an apf_status and, on
+ *     failure, leaves a thread-local message for apf_last_error().
+ *   - Calls on one handle must not overlap in time (the handle owns the
+ *     factors and workspaces they share); distinct handles are independent.
+ */
+#ifndef APF_H
+#define APF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  APF_OK = 0,
+  APF_EINVAL = -1,     /* bad argument or descriptor                       */
+  APF_ENOMEM = -2,     /* device or host allocation failed                 */
+  APF_EHIP = -3,       /* a HIP runtime call failed                        */
+  APF_ESINGULAR = -4,  /* a zero pivot appeared in a pivot block           */
+  APF_ENOTCONV = -5,   /* iterative refinement did not reach its tolerance */
+  APF_ESTATE = -6      /* call out of order (see apf_grad / apf_factor_schur) */
+} apf_status;
+
+typedef enum {
+  APF_FP64 = 0,        /* every front operation in complex FP64            */
+  APF_MIXED = 1        /* reserved: complex FP32 fronts + FP64 refinement   */
+} apf_precision;
+
+typedef struct apf_handle apf_handle;
+
+/* Problem descriptor (host memory; copied by apf_create).
+ * Rows: [0, npml_top) top PML | top medium eps_top | design rows
+ * [design_row0, design_row1) | bottom medium eps_bot | bottom PML.
+ * src_row must lie in the top medium and prj_row in the bottom medium, both
+ * outside the PML and outside the design rows; the design rows must not
+ * overlap the PML.  Every channel order must propagate in the medium of its
+ * row.  nx >= 3. */
+typedef struct {
+  int32_t nx, ny;
+  double dx_over_lambda;
+  int32_t npml_top, npml_bot;
+  double pml_R0;
+  int32_t pml_power;
+  double eps_top, eps_bot;
+  int32_t src_row, prj_row;
+  int32_t design_row0, design_row1;
+  int32_t n_in, n_out;
+  const int32_t *in_orders;   /* n_in channel orders a (source row)       */
+  const int32_t *out_orders;  /* n_out channel orders b (projection row)  */
+  int32_t leaf_size;          /* max nodes of a nested-dissection leaf; 0 = default (64) */
+} apf_problem_desc;
+
+/* Validate the descriptor and create a handle (host only, no GPU work). */
+apf_status apf_create(const apf_problem_desc *desc, apf_handle **out);
+
+/* Symbolic analysis (host only; idempotent; cached on the handle): geometric
+ * nested dissection of the periodic grid, elimination tree, frontal index
+ * sets, extend-add maps, level schedule and exact work counts.  The sparsity
+ * of K does not depend on eps, so one analysis serves every later call
+ * (Sec. 2: one partial factorization per evaluation of S). */
+apf_status apf_analyze(apf_handle *h);
+
+/* Assemble A (the 5-point operator above with the given permittivity), B
+ * and C on the GPU, straight into the frontal workspaces.
+ *   eps_dev: float64 [ny][nx] relative permittivity (real; must be nonzero
+ *   and finite -- checked on the host-visible copy is not possible, so the
+ *   factorization reports APF_ESINGULAR if it produces a zero pivot).
+ * The first call allocates the device plan (workspaces, factor storage, task
+ * lists) and synchronises `stream` once; later calls only enqueue work.
+ * Requires apf_analyze. */
+apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *stream);
+
+/* Numeric multifrontal partial factorization of K = [A, B; C, 0] (Sec. 2):
+ * eliminates every grid unknown and writes the Schur-complement block as
+ *   S_dev: complex128 [n_out][n_in],  S = C A^-1 B.
+ * The factors are kept on the handle for apf_grad.  Synchronises `stream` at
+ * the end to read the pivot status word (returns APF_ESINGULAR on a zero
+ * pivot).  Requires apf_assemble since the last factorization. */
+apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev,
+                            void *stream);
+
+/* Objective helper for f = sum_nm w_nm |S_nm|^2 (Sec. 2, Eq. (1) needs the
+ * Wirtinger derivative dF/dS):
+ *   S_dev, dfdS_dev: complex128 [n_out][n_in]; w_dev: float64 [n_out][n_in];
+ *   f_dev: one float64.  Writes f and dF/dS = w * conj(S). */
+apf_status apf_weighted_power(apf_handle *h, const double *S_dev,
+                              const double *w_dev, double *f_dev,
+                              double *dfdS_dev, void *stream);
+
+/* Gradient of a real objective f(S) with respect to the permittivity of every
+ * design pixel (Sec. 2, Eq. (1) with dS/deps_k of Eq. (3), U_k = e_k and
+ * Sigma_k = dA_kk/deps_k = -h^2):
+ *   df/deps_k = sum_nm 2 Re(dF/dS_nm dS_nm/deps_k)
+ *             = 2 h^2 Re sum_m Lam_km Y_km,
+ *   Y = A^-1 B, Lam = A^-1 (C^T dF/dS)  (the M_in weighted adjoint problems).
+ *   dfdS_dev: complex128 [n_out][n_in], the Wirtinger derivative dF/dS.
+ *   grad_dev: float64 [design_row1 - design_row0][nx] (overwritten).
+ * Uses the factors of the last apf_factor_schur (else APF_ESTATE). */
+apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev,
+                    void *stream);
+
+/* Free the handle, its symbolic data, factors and device buffers.  Waits for
+ * nothing: the caller must have synchronised the streams it used. */
+apf_status apf_destroy(apf_handle *h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *apf_last_error(void);
+
+/* Read a named statistic of an analysed handle (host only):
+ *   "n_fronts", "n_levels", "max_front" (largest p+b), "factor_cmacs" and
+ *   "grad_cmacs" (complex multiply-adds the factorization and the gradient
+ *   perform, counted as executed GEMM work), "algo_factor_cmacs" (the
+ *   algorithmic count sum over fronts of the rank-p updates), "ws_bytes",
+ *   "factor_bytes", "rhs_chunk", "n_sweep_fronts". */
+apf_status apf_query(apf_handle *h, const char *key, double *value);
+
+/* Structure export for host-side validation (host only, after apf_analyze).
+ *   info[8]: parent (-1 for the root), height, p (pivots), b (boundary
+ *   size), has_B, has_C, in_sweep, first elimination index.
+ *   pivots (p entries) and boundary (b entries) receive node indices
+ *   j*nx+i; either may be NULL. */
+apf_status apf_front(apf_handle *h, int32_t f, int32_t info[8],
+                     int32_t *pivots, int32_t *boundary);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APF_H */

@@ -1,0 +1,213 @@
+"""ctypes binding of the APF C ABI (include/apf.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors passed in are torch device tensors; the HIP stream is
+torch's current stream.  If the library is not built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libapf.so")
+
+APF_OK = 0
+APF_EINVAL = -1
+APF_ENOMEM = -2
+APF_EHIP = -3
+APF_ESINGULAR = -4
+APF_ENOTCONV = -5
+APF_ESTATE = -6
+APF_FP64 = 0
+APF_MIXED = 1
+
+ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_weighted_power",
+                "apf_grad", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
+
+
+class APFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"APF status {status}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx_over_lambda", ctypes.c_double),
+                ("npml_top", ctypes.c_int32), ("npml_bot", ctypes.c_int32),
+                ("pml_R0", ctypes.c_double), ("pml_power", ctypes.c_int32),
+                ("eps_top", ctypes.c_double), ("eps_bot", ctypes.c_double),
+                ("src_row", ctypes.c_int32), ("prj_row", ctypes.c_int32),
+                ("design_row0", ctypes.c_int32), ("design_row1", ctypes.c_int32),
+                ("n_in", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("in_orders", ctypes.POINTER(ctypes.c_int32)),
+                ("out_orders", ctypes.POINTER(ctypes.c_int32)),
+                ("leaf_size", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libapf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2306_09257_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.apf_create.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(vp)]
+    lib.apf_analyze.argtypes = [vp]
+    lib.apf_assemble.argtypes = [vp, vp, vp]
+    lib.apf_factor_schur.argtypes = [vp, i32, vp, vp]
+    lib.apf_weighted_power.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.apf_grad.argtypes = [vp, vp, vp, vp]
+    lib.apf_destroy.argtypes = [vp]
+    lib.apf_last_error.argtypes = []
+    lib.apf_last_error.restype = ctypes.c_char_p
+    lib.apf_query.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl)]
+    lib.apf_front.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    for name in ENTRY_POINTS:
+        if name != "apf_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != APF_OK:
+        raise APFError(status, _lib.apf_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class APF:
+    """One APF problem: the handle of include/apf.h.
+
+    `prob` is a problem description with the fields of apf_problem_desc
+    (paper_2306_09257_amd.inputs.Problem)."""
+
+    def __init__(self, prob, leaf_size: int = 0):
+        lib = load_library()
+        self.prob = prob
+        self._in = np.ascontiguousarray(prob.in_orders, dtype=np.int32)
+        self._out = np.ascontiguousarray(prob.out_orders, dtype=np.int32)
+        d = _Desc(prob.nx, prob.ny, prob.dx_over_lambda, prob.npml_top, prob.npml_bot,
+                  prob.pml_R0, prob.pml_power, prob.eps_top, prob.eps_bot,
+                  prob.src_row, prob.prj_row, prob.design_row0, prob.design_row1,
+                  self._in.size, self._out.size,
+                  self._in.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                  self._out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                  leaf_size)
+        h = ctypes.c_void_p()
+        _check(lib.apf_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    # -- host-side -----------------------------------------------------------
+    def analyze(self):
+        _check(self._lib.apf_analyze(self._h))
+        return self
+
+    def query(self, key: str) -> float:
+        v = ctypes.c_double()
+        _check(self._lib.apf_query(self._h, key.encode(), ctypes.byref(v)))
+        return v.value
+
+    def front(self, f: int):
+        info = (ctypes.c_int32 * 8)()
+        _check(self._lib.apf_front(self._h, f, info, None, None))
+        p, b = info[2], info[3]
+        piv = (ctypes.c_int32 * max(p, 1))()
+        bnd = (ctypes.c_int32 * max(b, 1))()
+        _check(self._lib.apf_front(self._h, f, info, piv, bnd))
+        return list(info), np.array(piv[:p], dtype=np.int64), np.array(bnd[:b], dtype=np.int64)
+
+    # -- device-side ---------------------------------------------------------
+    def assemble(self, eps):
+        """eps: float64 [ny][nx] device tensor."""
+        assert eps.dtype.is_floating_point and eps.is_contiguous() and eps.is_cuda
+        assert tuple(eps.shape) == (self.prob.ny, self.prob.nx)
+        self._eps = eps
+        _check(self._lib.apf_assemble(self._h, _ptr(eps), _stream()))
+
+    def factor_schur(self, S=None, precision: int = APF_FP64):
+        import torch
+        if S is None:
+            S = torch.empty((self.prob.n_out, self.prob.n_in), dtype=torch.complex128, device="cuda")
+        assert S.dtype == torch.complex128 and S.is_contiguous()
+        _check(self._lib.apf_factor_schur(self._h, precision, _ptr(S), _stream()))
+        return S
+
+    def weighted_power(self, S, w):
+        import torch
+        f = torch.empty((), dtype=torch.float64, device=S.device)
+        G = torch.empty_like(S)
+        assert w.dtype == torch.float64 and w.is_contiguous() and S.is_contiguous()
+        _check(self._lib.apf_weighted_power(self._h, _ptr(S), _ptr(w), _ptr(f), _ptr(G), _stream()))
+        return f, G
+
+    def grad(self, dfdS, out=None):
+        import torch
+        assert dfdS.dtype == torch.complex128 and dfdS.is_contiguous()
+        if out is None:
+            out = torch.empty((self.prob.n_design_rows, self.prob.nx), dtype=torch.float64, device=dfdS.device)
+        _check(self._lib.apf_grad(self._h, _ptr(dfdS), _ptr(out), _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.apf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(apf: APF, eps, precision: int = APF_FP64):
+    """S = C A^-1 B for the permittivity map eps ([ny][nx] float64, device)."""
+    apf.assemble(eps)
+    return apf.factor_schur(precision=precision)
+
+
+def make_autograd_function():
+    """torch.autograd.Function around the library: forward S(eps), backward
+    grad_eps from the weighted adjoint of apf_grad.  torch hands backward
+    grad_S = 2 conj(dF/dS) for a real loss (its convention for complex
+    inputs), so the Wirtinger derivative passed to the library is
+    conj(grad_S)/2."""
+    import torch
+
+    class APFFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, eps_design, apf: APF, eps_background, precision=APF_FP64):
+            prob = apf.prob
+            eps = eps_background.clone()
+            eps[prob.design_row0:prob.design_row1] = eps_design
+            apf.assemble(eps.contiguous())
+            S = apf.factor_schur(precision=precision)
+            ctx.apf = apf
+            return S
+
+        @staticmethod
+        def backward(ctx, grad_S):
+            dfdS = (grad_S.conj() * 0.5).contiguous()
+            g = ctx.apf.grad(dfdS)
+            return g, None, None, None
+
+    return APFFunction

@@ -1,0 +1,200 @@
+// Host symbolic analysis: geometric nested dissection of the x-periodic
+// nx-by-ny grid, elimination tree, frontal index sets and extend-add maps.
+//
+// The augmented matrix K = [A, B; C, 0] (Sec. 2) keeps the sparsity of A for
+// its grid unknowns; the channel columns of B live on the source row and the
+// channel rows of C on the projection row.  A front therefore carries the
+// M_in channel columns when its subtree holds source-row nodes and the M_out
+// channel rows when it holds projection-row nodes; the channel-by-channel
+// block is never pivoted and is summed straight into S.
+#include <algorithm>
+#include <stdexcept>
+#include <unordered_map>
+
+#include "apf_internal.h"
+
+namespace apf {
+
+namespace {
+
+struct Builder {
+  const Desc &d;
+  Symbolic &s;
+  int leaf;
+  Builder(const Desc &d_, Symbolic &s_) : d(d_), s(s_), leaf(d_.leaf_size > 0 ? d_.leaf_size : 64) {}
+
+  int node(int x, int y) const { return y * d.nx + x; }
+
+  // Nested dissection of the rectangle [x0,x1) x [y0,y1): cut the longer side
+  // with one grid line of nodes; the two halves become children.  Children
+  // are emitted before their parent, so `fronts` is a postorder.
+  int region(int x0, int x1, int y0, int y1) {
+    int w = x1 - x0, hh = y1 - y0;
+    if (w <= 0 || hh <= 0) return -1;
+    Front f;
+    f.x0 = x0; f.x1 = x1; f.y0 = y0; f.y1 = y1;
+    int c[2] = {-1, -1};
+    if ((int64_t)w * hh <= leaf) {
+      for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) f.piv.push_back(node(x, y));
+    } else if (w >= hh) {
+      int xs = x0 + w / 2;
+      c[0] = region(x0, xs, y0, y1);
+      c[1] = region(xs + 1, x1, y0, y1);
+      for (int y = y0; y < y1; ++y) f.piv.push_back(node(xs, y));
+    } else {
+      int ys = y0 + hh / 2;
+      c[0] = region(x0, x1, y0, ys);
+      c[1] = region(x0, x1, ys + 1, y1);
+      for (int x = x0; x < x1; ++x) f.piv.push_back(node(x, ys));
+    }
+    int id = (int)s.fronts.size();
+    for (int k = 0; k < 2; ++k)
+      if (c[k] >= 0) { f.child[f.nchild++] = c[k]; }
+    s.fronts.push_back(std::move(f));
+    for (int k = 0; k < s.fronts[id].nchild; ++k) s.fronts[s.fronts[id].child[k]].parent = id;
+    return id;
+  }
+};
+
+}  // namespace
+
+void analyze(const Desc &d, Symbolic &s) {
+  if (d.nx < 3 || d.ny < 1) throw std::runtime_error("grid must have nx >= 3 and ny >= 1");
+  s = Symbolic();
+  s.nx = d.nx;
+  s.ny = d.ny;
+  const int nx = d.nx, ny = d.ny;
+  const int64_t N = (int64_t)nx * ny;
+  Builder bld(d, s);
+
+  // The periodic ring is opened by the root separator: grid column x = 0.
+  int child = bld.region(1, nx, 0, ny);
+  {
+    Front root;
+    root.x0 = 0; root.x1 = nx; root.y0 = 0; root.y1 = ny;
+    for (int y = 0; y < ny; ++y) root.piv.push_back(bld.node(0, y));
+    if (child >= 0) root.child[root.nchild++] = child;
+    int id = (int)s.fronts.size();
+    s.fronts.push_back(std::move(root));
+    if (child >= 0) s.fronts[child].parent = id;
+  }
+  const int nf = (int)s.fronts.size();
+
+  // Elimination order, node -> (front, local) maps.
+  s.node_front.assign(N, -1);
+  s.node_local.assign(N, -1);
+  s.node_elim.assign(N, -1);
+  int64_t e = 0;
+  for (int f = 0; f < nf; ++f) {
+    Front &F = s.fronts[f];
+    F.elim0 = e;
+    for (int k = 0; k < F.p(); ++k) {
+      int n = F.piv[k];
+      if (s.node_front[n] != -1) throw std::runtime_error("node pivoted twice");
+      s.node_front[n] = f;
+      s.node_local[n] = k;
+      s.node_elim[n] = e++;
+    }
+  }
+  if (e != N) throw std::runtime_error("nested dissection does not cover the grid");
+
+  // Boundary sets: grid neighbours of the subtree's region that lie outside it.
+  // Each is a pivot of an ancestor separator (the separators split regions
+  // along full grid lines, and the periodic wrap meets the root column).
+  for (int f = 0; f < nf; ++f) {
+    Front &F = s.fronts[f];
+    if (F.parent < 0) continue;
+    std::vector<int> b;
+    int xl = (F.x0 - 1 + nx) % nx, xr = F.x1 % nx;
+    for (int y = F.y0; y < F.y1; ++y) {
+      b.push_back(bld.node(xl, y));
+      b.push_back(bld.node(xr, y));
+    }
+    if (F.y0 > 0)
+      for (int x = F.x0; x < F.x1; ++x) b.push_back(bld.node(x, F.y0 - 1));
+    if (F.y1 < ny)
+      for (int x = F.x0; x < F.x1; ++x) b.push_back(bld.node(x, F.y1));
+    std::vector<int> keep;
+    keep.reserve(b.size());
+    for (int n : b) {
+      int x = n % nx, y = n / nx;
+      bool inside = x >= F.x0 && x < F.x1 && y >= F.y0 && y < F.y1;
+      if (!inside) keep.push_back(n);
+    }
+    std::sort(keep.begin(), keep.end(), [&](int a, int c) { return s.node_elim[a] < s.node_elim[c]; });
+    keep.erase(std::unique(keep.begin(), keep.end()), keep.end());
+    for (int n : keep)
+      if (s.node_elim[n] < F.elim0 + F.p()) throw std::runtime_error("boundary node eliminated before its front");
+    F.bnd = std::move(keep);
+  }
+
+  // Extend-add maps: child boundary node -> parent-local index.
+  std::vector<int> stamp(N, -1);
+  for (int f = 0; f < nf; ++f) {
+    Front &P = s.fronts[f];
+    for (int k = 0; k < P.p(); ++k) stamp[P.piv[k]] = k;
+    for (int k = 0; k < P.b(); ++k) stamp[P.bnd[k]] = P.p() + k;
+    for (int c = 0; c < P.nchild; ++c) {
+      Front &Ch = s.fronts[P.child[c]];
+      Ch.rmap.resize(Ch.b());
+      for (int k = 0; k < Ch.b(); ++k) {
+        int loc = stamp[Ch.bnd[k]];
+        if (loc < 0) throw std::runtime_error("child boundary not in parent front");
+        Ch.rmap[k] = loc;
+      }
+    }
+    for (int k = 0; k < P.p(); ++k) stamp[P.piv[k]] = -1;
+    for (int k = 0; k < P.b(); ++k) stamp[P.bnd[k]] = -1;
+  }
+
+  // Heights, channel blocks, sweep set, levels.
+  int H = 0;
+  for (int f = 0; f < nf; ++f) {
+    Front &F = s.fronts[f];
+    int h = 0;
+    for (int c = 0; c < F.nchild; ++c) h = std::max(h, s.fronts[F.child[c]].height + 1);
+    F.height = h;
+    H = std::max(H, h);
+    F.hasB = F.y0 <= d.src_row && d.src_row < F.y1;
+    F.hasC = F.y0 <= d.prj_row && d.prj_row < F.y1;
+    F.sweep = F.y0 < d.design_row1 && d.design_row0 < F.y1;
+    F.sfront = F.hasB && F.hasC;
+  }
+  s.levels.assign(H + 1, {});
+  for (int f = 0; f < nf; ++f) s.levels[s.fronts[f].height].push_back(f);
+
+  s.node_sweep_row.assign(N, -1);
+  int64_t r = 0;
+  for (int f = 0; f < nf; ++f) {
+    Front &F = s.fronts[f];
+    if (!F.sweep) continue;
+    for (int k = 0; k < F.p(); ++k) s.node_sweep_row[F.piv[k]] = r++;
+  }
+  s.n_sweep_rows = r;
+
+  // Work counts (complex multiply-adds).
+  const double Mi = d.n_in, Mo = d.n_out;
+  s.k_total = 0;
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = s.fronts[f];
+    double p = F.p(), b = F.b(), mB = F.hasB ? Mi : 0, mC = F.hasC ? Mo : 0;
+    s.max_front = std::max(s.max_front, F.p() + F.b());
+    if (F.sfront) s.k_total += F.p();
+    // rank-p elimination of the (p+b+mC) x (p+b+mB) front, channel block included
+    double a = p + b + mC - 1, c = p + b + mB - 1;
+    s.algo_factor_cmacs += p * a * c - (a + c) * p * (p - 1) / 2 + p * (p - 1) * (2 * p - 1) / 6;
+    double w = p * p * p;                       // pivot-block inverse
+    w += p * p * b + p * p * mB;                // X12, X1B
+    w += b * p * b + b * p * mB + b * p * mC;   // Schur updates of the contribution block
+    if (F.sweep) w += b * p * p + (F.hasC ? p * p * mC : 0);   // Y21, XC1T
+    w += mC * p * mB;                           // channel block into S
+    s.factor_cmacs += w;
+    if (F.sweep) {
+      s.grad_cmacs += 2 * p * b * Mi;           // two sweeps
+      if (F.hasC) s.grad_cmacs += p * mC * Mi;  // weighted adjoint source
+    }
+  }
+}
+
+}  // namespace apf

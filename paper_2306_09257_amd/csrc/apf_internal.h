@@ -1,0 +1,116 @@
+// Internal structures shared by the host analysis, the device plan and the
+// kernels of the APF library.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/apf.h"
+
+namespace apf {
+
+// complex128 as two doubles (the device code uses double2 with the same layout)
+struct cplx { double re, im; };
+
+// ---------------------------------------------------------------------------
+// Symbolic data (host)
+// ---------------------------------------------------------------------------
+struct Front {
+  int parent = -1;
+  int height = 0;
+  int child[2] = {-1, -1};
+  int nchild = 0;
+  int x0 = 0, x1 = 0, y0 = 0, y1 = 0;   // region of the subtree (x periodic)
+  std::vector<int> piv;                 // pivot nodes, elimination order
+  std::vector<int> bnd;                 // boundary nodes, sorted by elimination index
+  std::vector<int> rmap;                // boundary -> parent-local index (0..p+b of the parent)
+  bool hasB = false, hasC = false, sweep = false, sfront = false;
+  int64_t elim0 = 0;                    // elimination index of piv[0]
+  int p() const { return (int)piv.size(); }
+  int b() const { return (int)bnd.size(); }
+};
+
+struct Symbolic {
+  int nx = 0, ny = 0;
+  std::vector<Front> fronts;            // postorder: children before parents; root last
+  std::vector<int> node_front;          // node -> front owning it as a pivot
+  std::vector<int> node_local;          // node -> index among that front's pivots
+  std::vector<int64_t> node_elim;       // node -> elimination index
+  std::vector<std::vector<int>> levels; // fronts by height
+  int64_t n_sweep_rows = 0;
+  std::vector<int64_t> node_sweep_row;  // -1 if the node's front is not in the sweep set
+  int64_t k_total = 0;                  // sum of p over S-fronts (has_B and has_C)
+  double algo_factor_cmacs = 0, factor_cmacs = 0, grad_cmacs = 0;
+  int max_front = 0;
+};
+
+struct Desc {
+  int nx, ny;
+  double dx_over_lambda;
+  int npml_top, npml_bot;
+  double pml_R0;
+  int pml_power;
+  double eps_top, eps_bot;
+  int src_row, prj_row, design_row0, design_row1;
+  int n_in, n_out;
+  std::vector<int> in_orders, out_orders;
+  int leaf_size;
+};
+
+// Builds the nested-dissection tree and every index set of the symbolic
+// factorization.  Throws std::runtime_error on an invalid grid.
+void analyze(const Desc &d, Symbolic &sym);
+
+// ---------------------------------------------------------------------------
+// Device plan structures (POD, copied to the GPU)
+// ---------------------------------------------------------------------------
+struct FrontDev {
+  int32_t p, b, mB, mC;
+  int32_t sweep_row0;      // row of the first pivot in the X/V sweep arrays, -1 if none
+  int32_t pad;
+  cplx *core;              // (p+b) x (p+b) row-major frontal core
+  cplx *bp_piv, *bp_bnd;   // B-panel rows: p x mB and b x mB (ld mB)
+  cplx *cpt_piv, *cpt_bnd; // C-panel transposed rows: p x mC and b x mC (ld mC)
+  const int32_t *rmap;     // b entries: boundary -> parent-local index
+  int32_t parent;
+  int32_t pad2;
+};
+
+struct AsmEntry {          // one stencil entry of A: Aval[src] is added at dest
+  int64_t src;             // node*5 + direction (0 centre, 1 x-1, 2 x+1, 3 y-1, 4 y+1)
+  cplx *dest;
+};
+
+struct PanelEntry {        // one source (B) or projection (C) node: a whole row of the panel
+  int32_t node, pad;
+  cplx *dest;
+};
+
+enum GemmFlags : int32_t {
+  G_TRANS_A = 1,           // A(i,k) = A[k*lda + i]
+  G_NEG = 2,               // C = Cin - A*B  (else Cin + A*B)
+  G_CIN = 4,               // Cin present (else treated as zero)
+  G_B_COFF = 8,            // add the launch's column offset to B
+  G_CIN_COFF = 16,         // add the launch's column offset to Cin
+  G_B_EXT = 32,            // B is the launch's external pointer (caller buffer)
+  G_C_EXT = 64,            // C is the launch's external pointer (caller buffer)
+};
+
+struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
+  const cplx *A;
+  const cplx *B;
+  const cplx *Cin;
+  cplx *C;
+  const int32_t *browmap;  // if set, row k of B is B + browmap[k]*ldb
+  int32_t M, N, K;
+  int32_t lda, ldb, ldcin, ldc;
+  int32_t flags;
+  int32_t tm, tn;
+};
+
+struct ZeroRange { cplx *ptr; int64_t n; };
+
+constexpr int GEMM_TILE = 64;
+
+}  // namespace apf

@@ -1,0 +1,649 @@
+// C ABI of the APF library: descriptor validation, symbolic analysis, the
+// device plan (buffers and per-level task arrays) and the per-call drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "apf_internal.h"
+#include "kernels.h"
+
+using namespace apf;
+
+namespace {
+
+thread_local std::string g_err;
+
+apf_status fail(apf_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) throw HipError(std::string(#x) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+constexpr int64_t ALIGN = 32;  // complex elements (512 bytes)
+int64_t up(int64_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
+
+// First-fit allocator over one arena, for workspaces whose lifetimes are
+// level intervals of the elimination tree.
+struct Arena {
+  std::map<int64_t, int64_t> free_;  // offset -> size
+  int64_t top = 0;
+  int64_t alloc(int64_t n) {
+    n = up(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        int64_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > n) free_[off + n] = sz - n;
+        return off;
+      }
+    }
+    int64_t off = top;
+    top += n;
+    return off;
+  }
+  void release(int64_t off, int64_t n) {
+    n = up(n);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+// Host staging of a device blob of task arrays.
+struct Blob {
+  std::vector<char> h;
+  int64_t add(const void *p, size_t bytes) {
+    size_t off = (h.size() + 255) / 256 * 256;
+    h.resize(off + bytes);
+    if (bytes) std::memcpy(h.data() + off, p, bytes);
+    return (int64_t)off;
+  }
+  template <class T>
+  int64_t add(const std::vector<T> &v) { return add(v.data(), v.size() * sizeof(T)); }
+};
+
+struct LevelTasks {
+  int64_t zero = -1, scat = -1, pB = -1, pC = -1, ext[2] = {-1, -1}, inv = -1, g1 = -1, g2 = -1, sw = -1;
+  int nzero = 0, nscat = 0, npB = 0, npC = 0, next[2] = {0, 0}, maxb[2] = {0, 0}, ninv = 0, ng1 = 0, ng2 = 0,
+      nsw = 0;
+};
+
+struct Plan {
+  int device = -1;
+  cplx *ws = nullptr, *fs = nullptr, *sb = nullptr, *sc = nullptr, *X = nullptr, *V = nullptr, *aval = nullptr;
+  char *blob = nullptr;
+  int *status = nullptr;
+  double *part = nullptr;
+  int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
+  int rhs_chunk = 0;
+  std::vector<LevelTasks> lv;
+  int64_t gS = -1, vinit = -1, drows = -1, in_orders = -1, out_orders = -1, fronts = -1;
+  int ngS = 0, nvinit = 0, ndesign = 0;
+  template <class T>
+  T *at(int64_t off) const { return off < 0 ? nullptr : reinterpret_cast<T *>(blob + off); }
+};
+
+void add_tiles(std::vector<GemmTask> &v, const GemmTask &t) {
+  if (t.M <= 0 || t.N <= 0) return;
+  for (int tm = 0; tm < t.M; tm += GEMM_TILE)
+    for (int tn = 0; tn < t.N; tn += GEMM_TILE) {
+      GemmTask u = t;
+      u.tm = tm;
+      u.tn = tn;
+      v.push_back(u);
+    }
+}
+
+GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, int M, int N, int K, int flags,
+              const cplx *Cin = nullptr, int ldcin = 0, const int32_t *browmap = nullptr) {
+  GemmTask t{};
+  t.A = A; t.B = B; t.C = C; t.Cin = Cin; t.browmap = browmap;
+  t.M = M; t.N = N; t.K = K;
+  t.lda = lda; t.ldb = ldb; t.ldc = ldc; t.ldcin = ldcin;
+  t.flags = flags;
+  return t;
+}
+
+}  // namespace
+
+struct apf_handle {
+  Desc d;
+  bool analyzed = false;
+  Symbolic sym;
+  Phys phys{};
+  bool planned = false;
+  Plan plan;
+  int state = 0;  // 0 analysed, 1 assembled, 2 factored
+};
+
+// ---------------------------------------------------------------------------
+// validation and creation
+// ---------------------------------------------------------------------------
+static double pml_alpha(double h, double eps, int L, int m, double R0) {
+  return (m + 1) * std::log(1.0 / R0) / (2.0 * h * std::sqrt(eps) * L);
+}
+
+static bool propagates(int a, int nx, double h, double eps) {
+  double s = std::sin(M_PI * a / nx);
+  double rhs = h * h * eps / 4.0 - s * s;
+  return rhs > 0.0 && rhs < 1.0;
+}
+
+extern "C" apf_status apf_create(const apf_problem_desc *in, apf_handle **out) {
+  if (!in || !out) return fail(APF_EINVAL, "null argument");
+  *out = nullptr;
+  const apf_problem_desc &q = *in;
+  if (q.nx < 3 || q.ny < 3) return fail(APF_EINVAL, "need nx >= 3 and ny >= 3");
+  if ((int64_t)q.nx * q.ny > INT_MAX / 8) return fail(APF_EINVAL, "grid too large");
+  if (!(q.dx_over_lambda > 0.0) || !std::isfinite(q.dx_over_lambda)) return fail(APF_EINVAL, "bad dx_over_lambda");
+  if (q.npml_top < 0 || q.npml_bot < 0 || q.npml_top + q.npml_bot >= q.ny) return fail(APF_EINVAL, "bad PML rows");
+  if ((q.npml_top > 0 || q.npml_bot > 0) && !(q.pml_R0 > 0.0 && q.pml_R0 < 1.0)) return fail(APF_EINVAL, "bad pml_R0");
+  if (q.pml_power < 0 || q.pml_power > 8) return fail(APF_EINVAL, "bad pml_power");
+  if (!(q.eps_top > 0.0) || !(q.eps_bot > 0.0)) return fail(APF_EINVAL, "bad background permittivity");
+  const int lo = q.npml_top, hi = q.ny - q.npml_bot;  // physical rows [lo, hi)
+  if (!(q.design_row0 >= lo && q.design_row0 < q.design_row1 && q.design_row1 <= hi))
+    return fail(APF_EINVAL, "design rows must be non-empty and outside the PML");
+  if (!(q.src_row >= lo && q.src_row < q.design_row0)) return fail(APF_EINVAL, "src_row must be in the top medium");
+  if (!(q.prj_row >= q.design_row1 && q.prj_row < hi)) return fail(APF_EINVAL, "prj_row must be in the bottom medium");
+  if (q.n_in < 1 || q.n_out < 1 || !q.in_orders || !q.out_orders) return fail(APF_EINVAL, "need channels");
+  if (q.leaf_size < 0 || q.leaf_size > 1024) return fail(APF_EINVAL, "leaf_size must be in [0, 1024]");
+  if (q.ny > 1024) return fail(APF_EINVAL, "ny > 1024 is not supported (separator length)");
+  const double h = 2.0 * M_PI * q.dx_over_lambda;
+  for (int k = 0; k < q.n_in; ++k)
+    if (!propagates(q.in_orders[k], q.nx, h, q.eps_top)) return fail(APF_EINVAL, "input order does not propagate");
+  for (int k = 0; k < q.n_out; ++k)
+    if (!propagates(q.out_orders[k], q.nx, h, q.eps_bot)) return fail(APF_EINVAL, "output order does not propagate");
+  apf_handle *H = new (std::nothrow) apf_handle();
+  if (!H) return fail(APF_ENOMEM, "host allocation failed");
+  Desc &d = H->d;
+  d.nx = q.nx; d.ny = q.ny; d.dx_over_lambda = q.dx_over_lambda;
+  d.npml_top = q.npml_top; d.npml_bot = q.npml_bot; d.pml_R0 = q.pml_R0; d.pml_power = q.pml_power;
+  d.eps_top = q.eps_top; d.eps_bot = q.eps_bot;
+  d.src_row = q.src_row; d.prj_row = q.prj_row; d.design_row0 = q.design_row0; d.design_row1 = q.design_row1;
+  d.n_in = q.n_in; d.n_out = q.n_out;
+  d.in_orders.assign(q.in_orders, q.in_orders + q.n_in);
+  d.out_orders.assign(q.out_orders, q.out_orders + q.n_out);
+  d.leaf_size = q.leaf_size;
+  Phys &P = H->phys;
+  P.nx = d.nx; P.ny = d.ny; P.h2 = h * h;
+  P.npml_top = d.npml_top; P.npml_bot = d.npml_bot; P.pml_power = d.pml_power;
+  P.alpha_top = d.npml_top > 0 ? pml_alpha(h, d.eps_top, d.npml_top, d.pml_power, d.pml_R0) : 0.0;
+  P.alpha_bot = d.npml_bot > 0 ? pml_alpha(h, d.eps_bot, d.npml_bot, d.pml_power, d.pml_R0) : 0.0;
+  P.eps_src = d.eps_top; P.eps_prj = d.eps_bot;
+  *out = H;
+  g_err.clear();
+  return APF_OK;
+}
+
+extern "C" apf_status apf_analyze(apf_handle *h) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  if (h->analyzed) return APF_OK;
+  try {
+    analyze(h->d, h->sym);
+  } catch (const std::bad_alloc &) {
+    return fail(APF_ENOMEM, "host allocation failed in analysis");
+  } catch (const std::exception &e) {
+    return fail(APF_EINVAL, e.what());
+  }
+  h->analyzed = true;
+  return APF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device plan
+// ---------------------------------------------------------------------------
+static void build_plan(apf_handle *H) {
+  Symbolic &S = H->sym;
+  const Desc &d = H->d;
+  Plan &P = H->plan;
+  const int nf = (int)S.fronts.size();
+  const int H_ = (int)S.levels.size() - 1;
+  const int Mi = d.n_in, Mo = d.n_out;
+  HIPCHK(hipGetDevice(&P.device));
+
+  // ---- sizes and offsets ----------------------------------------------------
+  struct Off { int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, x12 = -1, x1b = -1, y21 = -1, xc1t = -1, sk = -1; int64_t wsz = 0; };
+  std::vector<Off> o(nf);
+  Arena ar;
+  std::vector<std::vector<int>> release_at(H_ + 2);
+  int64_t fs = 0, ktot = 0;
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    int64_t p = F.p(), b = F.b(), n = p + b, mB = F.hasB ? Mi : 0, mC = F.hasC ? Mo : 0;
+    Off &q = o[f];
+    int64_t w = 0;
+    q.core = w; w += up(n * n);
+    if (mB) { q.bp = w; w += up(n * mB); }
+    if (mC && !F.sfront) { q.cpiv = w; w += up(p * mC); }
+    if (mC) { q.cbnd = w; w += up(b * mC); }
+    if (!F.sweep) { q.x12 = w; w += up(p * b); }
+    if (mB && !F.sweep && !F.sfront) { q.x1b = w; w += up(p * mB); }
+    q.wsz = w;
+    if (F.sweep) {
+      q.x12 = -2 - fs; fs += up(p * b);   // negative: persistent store (decoded below)
+      q.y21 = fs; fs += up(b * p);
+      if (mB && !F.sfront) { q.x1b = -2 - fs; fs += up(p * mB); }
+      if (mC) { q.xc1t = fs; fs += up(p * mC); }
+    }
+    if (F.sfront) { q.sk = ktot; ktot += p; }
+  }
+  // lifetime allocation, level by level
+  for (int lvl = 0; lvl <= H_; ++lvl) {
+    for (int f : release_at[lvl]) ar.release(o[f].ws, o[f].wsz);
+    for (int f : S.levels[lvl]) {
+      o[f].ws = ar.alloc(o[f].wsz);
+      const Front &F = S.fronts[f];
+      int end = F.parent >= 0 ? S.fronts[F.parent].height : H_;
+      release_at[end + 1].push_back(f);
+    }
+  }
+  P.ws_elems = std::max<int64_t>(ar.top, 1);
+  P.fs_elems = std::max<int64_t>(fs, 1);
+  S.k_total = ktot;
+
+  HIPCHK(hipMalloc(&P.ws, P.ws_elems * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.fs, P.fs_elems * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.sb, std::max<int64_t>(ktot * Mi, 1) * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.sc, std::max<int64_t>(ktot * Mo, 1) * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.aval, (int64_t)d.nx * d.ny * 5 * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.status, sizeof(int)));
+  HIPCHK(hipMalloc(&P.part, 1024 * sizeof(double)));
+  HIPCHK(hipMemset(P.status, 0, sizeof(int)));
+
+  // sweep arrays: pick the right-hand-side chunk from the free memory
+  {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    int64_t rows = std::max<int64_t>(S.n_sweep_rows, 1);
+    double budget = 0.5 * (double)fr;
+    int64_t chunk = (int64_t)(budget / (2.0 * rows * sizeof(cplx)));
+    chunk = std::min<int64_t>(chunk, Mi);
+    if (chunk < Mi) chunk = std::max<int64_t>(64, chunk / 64 * 64);
+    P.rhs_chunk = (int)std::max<int64_t>(chunk, 1);
+    P.x_elems = rows * P.rhs_chunk;
+    HIPCHK(hipMalloc(&P.X, P.x_elems * sizeof(cplx)));
+    HIPCHK(hipMalloc(&P.V, P.x_elems * sizeof(cplx)));
+  }
+
+  auto WS = [&](int64_t off) -> cplx * { return P.ws + off; };
+  auto FSx = [&](int64_t off) -> cplx * { return P.fs + off; };
+
+  // ---- integer arrays (first blob pass) --------------------------------------
+  Blob ib;
+  {
+    // offset 0 is reserved so that a rebased offset is never mistaken for null
+    const char pad[16] = {0};
+    ib.add(pad, sizeof pad);
+  }
+  std::vector<int64_t> rmap_off(nf, -1), bndrow_off(nf, -1);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    if (F.b()) rmap_off[f] = ib.add(F.rmap);
+    if (F.sweep && F.b()) {
+      std::vector<int32_t> br(F.b());
+      for (int k = 0; k < F.b(); ++k) br[k] = (int32_t)S.node_sweep_row[F.bnd[k]];
+      bndrow_off[f] = ib.add(br);
+    }
+  }
+  {
+    std::vector<int32_t> dr;
+    for (int y = d.design_row0; y < d.design_row1; ++y)
+      for (int x = 0; x < d.nx; ++x) dr.push_back((int32_t)S.node_sweep_row[(int64_t)y * d.nx + x]);
+    P.ndesign = (int)dr.size();
+    P.drows = ib.add(dr);
+  }
+  P.in_orders = ib.add(d.in_orders);
+  P.out_orders = ib.add(d.out_orders);
+  P.lv.assign(H_ + 1, LevelTasks());
+  std::vector<int64_t> kid_off[2], inv_off;
+  for (int lvl = 0; lvl <= H_; ++lvl) {
+    std::vector<int32_t> k0, k1, inv;
+    int mb0 = 0, mb1 = 0;
+    for (int f : S.levels[lvl]) {
+      const Front &F = S.fronts[f];
+      if (F.nchild > 0) { k0.push_back(F.child[0]); mb0 = std::max(mb0, S.fronts[F.child[0]].b()); }
+      if (F.nchild > 1) { k1.push_back(F.child[1]); mb1 = std::max(mb1, S.fronts[F.child[1]].b()); }
+      if (F.p() > 0) inv.push_back(f);
+    }
+    LevelTasks &L = P.lv[lvl];
+    L.ext[0] = ib.add(k0); L.next[0] = (int)k0.size(); L.maxb[0] = mb0;
+    L.ext[1] = ib.add(k1); L.next[1] = (int)k1.size(); L.maxb[1] = mb1;
+    L.inv = ib.add(inv); L.ninv = (int)inv.size();
+  }
+  const int64_t ib_size = (int64_t)ib.h.size();
+
+  // The task structures reference the integer arrays; both go into one blob
+  // whose device base is known once it is allocated.  Reserve generously,
+  // build, then upload.
+  // ---- device front descriptors and tasks (second pass) ---------------------
+  // the blob base is needed for pointers into it: allocate after sizing.
+  std::vector<FrontDev> fd(nf);
+  // temporary: compute pointers relative to a null base, fixed up below
+  char *base = nullptr;
+  // Sizing pass is avoided by allocating the blob at the end and rebasing the
+  // int-array pointers: they are stored as offsets here and converted once
+  // the base is known.
+  auto ipt = [&](int64_t off) -> const int32_t * {
+    return off < 0 ? nullptr : reinterpret_cast<const int32_t *>(base + off);
+  };
+  (void)ipt;
+
+  // Build everything with base = nullptr, remember which fields need rebasing.
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    const Off &q = o[f];
+    FrontDev &D = fd[f];
+    int64_t p = F.p(), b = F.b(), n = p + b;
+    D.p = (int)p; D.b = (int)b;
+    D.mB = F.hasB ? Mi : 0;
+    D.mC = F.hasC ? Mo : 0;
+    D.sweep_row0 = F.sweep ? (int32_t)S.node_sweep_row[F.piv[0]] : -1;
+    D.core = WS(q.ws + q.core);
+    D.bp_piv = D.mB ? WS(q.ws + q.bp) : nullptr;
+    D.bp_bnd = D.mB ? WS(q.ws + q.bp) + p * D.mB : nullptr;
+    if (D.mC) {
+      D.cpt_piv = F.sfront ? P.sc + q.sk * Mo : WS(q.ws + q.cpiv);
+      D.cpt_bnd = WS(q.ws + q.cbnd);
+    } else {
+      D.cpt_piv = D.cpt_bnd = nullptr;
+    }
+    D.rmap = reinterpret_cast<const int32_t *>((intptr_t)rmap_off[f]);  // offset; rebased below
+    D.parent = F.parent;
+    (void)n;
+  }
+  auto X12 = [&](int f) -> cplx * {
+    const Off &q = o[f];
+    return q.x12 <= -2 ? FSx(-2 - q.x12) : WS(q.ws + q.x12);
+  };
+  auto X1B = [&](int f) -> cplx * {
+    const Front &F = S.fronts[f];
+    const Off &q = o[f];
+    if (F.sfront) return P.sb + q.sk * Mi;
+    return q.x1b <= -2 ? FSx(-2 - q.x1b) : WS(q.ws + q.x1b);
+  };
+
+  std::vector<std::vector<ZeroRange>> zr(H_ + 1);
+  std::vector<std::vector<AsmEntry>> ae(H_ + 1);
+  std::vector<std::vector<PanelEntry>> pb(H_ + 1), pc(H_ + 1);
+  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), sw(H_ + 1);
+  std::vector<GemmTask> gS, vinit;
+  std::vector<int> loc((int64_t)d.nx * d.ny, -1);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    const FrontDev &D = fd[f];
+    const int lvl = F.height;
+    const int p = F.p(), b = F.b(), n = p + b, mB = D.mB, mC = D.mC;
+    zr[lvl].push_back({D.core, (int64_t)n * n});
+    if (mB) zr[lvl].push_back({D.bp_piv, (int64_t)n * mB});
+    if (mC) {
+      zr[lvl].push_back({D.cpt_piv, (int64_t)p * mC});
+      if (b) zr[lvl].push_back({D.cpt_bnd, (int64_t)b * mC});
+    }
+    // stencil entries owned by this front (the earlier-eliminated end of each edge)
+    for (int k = 0; k < p; ++k) loc[F.piv[k]] = k;
+    for (int k = 0; k < b; ++k) loc[F.bnd[k]] = p + k;
+    for (int k = 0; k < p; ++k) {
+      const int u = F.piv[k];
+      const int x = u % d.nx, y = u / d.nx;
+      const int64_t eu = S.node_elim[u];
+      int nb[5] = {u, y * d.nx + (x - 1 + d.nx) % d.nx, y * d.nx + (x + 1) % d.nx, y > 0 ? u - d.nx : -1,
+                   y < d.ny - 1 ? u + d.nx : -1};
+      for (int dir = 0; dir < 5; ++dir) {
+        const int v = nb[dir];
+        if (v < 0) continue;
+        if (dir > 0 && S.node_elim[v] < eu) continue;   // owned by the front of v
+        const int lu = loc[u], lv = loc[v];
+        if (lv < 0) throw std::runtime_error("stencil neighbour outside the front");
+        ae[lvl].push_back({(int64_t)u * 5 + dir, D.core + (int64_t)lu * n + lv});
+        if (dir > 0) ae[lvl].push_back({(int64_t)u * 5 + dir, D.core + (int64_t)lv * n + lu});   // A = A^T
+      }
+      if (mB && y == d.src_row) pb[lvl].push_back({u, 0, D.bp_piv + (int64_t)k * mB});
+      if (mC && y == d.prj_row) pc[lvl].push_back({u, 0, D.cpt_piv + (int64_t)k * mC});
+    }
+    for (int k = 0; k < p; ++k) loc[F.piv[k]] = -1;
+    for (int k = 0; k < b; ++k) loc[F.bnd[k]] = -1;
+
+    // factorization GEMMs; the pivot block holds G = F11^-1 after k_inverse
+    cplx *core = D.core;
+    cplx *F12 = core + p, *F21 = core + (int64_t)p * n, *F22 = core + (int64_t)p * n + p;
+    if (b) add_tiles(g1[lvl], gemm(core, n, F12, n, X12(f), b, p, b, p, 0));                 // X12 = G F12
+    if (F.sweep && b) add_tiles(g1[lvl], gemm(F21, n, core, n, FSx(o[f].y21), p, b, p, p, 0));  // Y21 = F21 G
+    if (mB) add_tiles(g1[lvl], gemm(core, n, D.bp_piv, mB, X1B(f), mB, p, mB, p, 0));       // X1B = G F1B
+    if (mC && F.sweep) add_tiles(g1[lvl], gemm(core, n, D.cpt_piv, mC, FSx(o[f].xc1t), mC, p, mC, p, G_TRANS_A));  // XC1T = G^T FC1^T
+    if (b) add_tiles(g2[lvl], gemm(F21, n, X12(f), b, F22, n, b, b, p, G_NEG | G_CIN, F22, n));          // F22 -= F21 X12
+    if (b && mB) add_tiles(g2[lvl], gemm(F21, n, X1B(f), mB, D.bp_bnd, mB, b, mB, p, G_NEG | G_CIN, D.bp_bnd, mB));  // F2B -= F21 X1B
+    if (b && mC) add_tiles(g2[lvl], gemm(X12(f), b, D.cpt_piv, mC, D.cpt_bnd, mC, b, mC, p, G_TRANS_A | G_NEG | G_CIN, D.cpt_bnd, mC));  // FC2^T -= X12^T FC1^T
+
+    // gradient sweeps (root to leaves): Y_f = X1B_f - X12 Y_bnd ; Lam_f = XC1T_f G - Y21^T Lam_bnd
+    if (F.sweep) {
+      const int ch = P.rhs_chunk;
+      cplx *Xf = P.X + (int64_t)D.sweep_row0 * ch, *Vf = P.V + (int64_t)D.sweep_row0 * ch;
+      const int32_t *bm = reinterpret_cast<const int32_t *>((intptr_t)bndrow_off[f]);  // rebased below
+      GemmTask ty = gemm(X12(f), b, P.X, ch, Xf, ch, p, ch, b, G_NEG | (mB ? G_CIN | G_CIN_COFF : 0),
+                         mB ? X1B(f) : nullptr, mB, b ? bm : nullptr);
+      GemmTask tv = gemm(FSx(o[f].y21), p, P.V, ch, Vf, ch, p, ch, b, G_TRANS_A | G_NEG | (mC ? G_CIN : 0),
+                         mC ? Vf : nullptr, ch, b ? bm : nullptr);
+      add_tiles(sw[lvl], ty);
+      add_tiles(sw[lvl], tv);
+      if (mC) add_tiles(vinit, gemm(FSx(o[f].xc1t), mC, nullptr, Mi, Vf, ch, p, ch, mC, G_B_EXT | G_B_COFF));
+    }
+  }
+  // S = sum over fronts holding both channel blocks of FC1 X1B = SC^T SB
+  add_tiles(gS, gemm(P.sc, Mo, P.sb, Mi, nullptr, Mi, Mo, Mi, (int)ktot, G_TRANS_A | G_C_EXT));
+
+  // ---- assemble the blob ------------------------------------------------------
+  Blob &bl = ib;  // continue after the integer arrays
+  for (int lvl = 0; lvl <= H_; ++lvl) {
+    LevelTasks &L = P.lv[lvl];
+    L.zero = bl.add(zr[lvl]); L.nzero = (int)zr[lvl].size();
+    L.scat = bl.add(ae[lvl]); L.nscat = (int)ae[lvl].size();
+    L.pB = bl.add(pb[lvl]); L.npB = (int)pb[lvl].size();
+    L.pC = bl.add(pc[lvl]); L.npC = (int)pc[lvl].size();
+    L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
+    L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
+    L.sw = bl.add(sw[lvl]); L.nsw = (int)sw[lvl].size();
+  }
+  P.gS = bl.add(gS); P.ngS = (int)gS.size();
+  P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
+  P.fronts = bl.add(fd);
+  HIPCHK(hipMalloc(&P.blob, bl.h.size()));
+  base = P.blob;
+  // rebase the pointers into the integer section
+  auto rebase = [&](const int32_t *&ptr) {
+    if (ptr) ptr = reinterpret_cast<const int32_t *>(base + (intptr_t)ptr);
+  };
+  {
+    FrontDev *fdv = reinterpret_cast<FrontDev *>(bl.h.data() + P.fronts);
+    for (int f = 0; f < nf; ++f) {
+      if (rmap_off[f] >= 0) rebase(fdv[f].rmap);
+      else fdv[f].rmap = nullptr;
+    }
+    for (int lvl = 0; lvl <= H_; ++lvl) {
+      GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + P.lv[lvl].sw);
+      for (int k = 0; k < P.lv[lvl].nsw; ++k) rebase(t[k].browmap);
+    }
+  }
+  (void)ib_size;
+  HIPCHK(hipMemcpy(P.blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
+  H->planned = true;
+}
+
+static void free_plan(Plan &P) {
+  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  P = Plan();
+}
+
+template <class F>
+static apf_status guarded(F &&fn) {
+  try {
+    return fn();
+  } catch (const HipError &e) {
+    return fail(APF_EHIP, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(APF_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(APF_EINVAL, e.what());
+  }
+}
+
+extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *stream) {
+  if (!h || !eps_dev) return fail(APF_EINVAL, "null argument");
+  if (!h->analyzed) return fail(APF_ESTATE, "apf_analyze has not run");
+  return guarded([&]() -> apf_status {
+    hipStream_t s = (hipStream_t)stream;
+    if (!h->planned) {
+      try {
+        build_plan(h);
+      } catch (...) {
+        free_plan(h->plan);
+        throw;
+      }
+    }
+    HIPCHK(launch_stencil(h->phys, eps_dev, h->plan.aval, s));
+    h->state = 1;
+    return APF_OK;
+  });
+}
+
+extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev, void *stream) {
+  if (!h || !S_dev) return fail(APF_EINVAL, "null argument");
+  if (prec != APF_FP64) return fail(APF_EINVAL, "only APF_FP64 is implemented");
+  if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
+  return guarded([&]() -> apf_status {
+    hipStream_t s = (hipStream_t)stream;
+    Plan &P = h->plan;
+    const FrontDev *fr = P.at<FrontDev>(P.fronts);
+    HIPCHK(hipMemsetAsync(P.status, 0, sizeof(int), s));
+    for (size_t lvl = 0; lvl < P.lv.size(); ++lvl) {
+      const LevelTasks &L = P.lv[lvl];
+      HIPCHK(launch_zero(P.at<ZeroRange>(L.zero), L.nzero, s));
+      HIPCHK(launch_scatter_A(P.at<AsmEntry>(L.scat), L.nscat, P.aval, s));
+      HIPCHK(launch_assemble_panel(P.at<PanelEntry>(L.pB), L.npB, h->phys, P.at<int32_t>(P.in_orders), h->d.n_in, 1, s));
+      HIPCHK(launch_assemble_panel(P.at<PanelEntry>(L.pC), L.npC, h->phys, P.at<int32_t>(P.out_orders), h->d.n_out, 0, s));
+      HIPCHK(launch_extend_add(fr, P.at<int32_t>(L.ext[0]), L.next[0], L.maxb[0], s));
+      HIPCHK(launch_extend_add(fr, P.at<int32_t>(L.ext[1]), L.next[1], L.maxb[1], s));
+      HIPCHK(launch_inverse(fr, P.at<int32_t>(L.inv), L.ninv, P.status, s));
+      HIPCHK(launch_gemm(P.at<GemmTask>(L.g1), L.ng1, 0, INT_MAX, nullptr, s));
+      HIPCHK(launch_gemm(P.at<GemmTask>(L.g2), L.ng2, 0, INT_MAX, nullptr, s));
+    }
+    HIPCHK(launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s));
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, P.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) {
+      h->state = 0;
+      return fail(APF_ESINGULAR, "zero pivot in a pivot block");
+    }
+    h->state = 2;
+    return APF_OK;
+  });
+}
+
+extern "C" apf_status apf_weighted_power(apf_handle *h, const double *S_dev, const double *w_dev, double *f_dev,
+                                         double *dfdS_dev, void *stream) {
+  if (!h || !S_dev || !w_dev || !f_dev || !dfdS_dev) return fail(APF_EINVAL, "null argument");
+  if (!h->planned) return fail(APF_ESTATE, "apf_assemble has not run");
+  return guarded([&]() -> apf_status {
+    int64_t n = (int64_t)h->d.n_in * h->d.n_out;
+    int npart = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    HIPCHK(launch_weighted_power(reinterpret_cast<const cplx *>(S_dev), w_dev, f_dev,
+                                 reinterpret_cast<cplx *>(dfdS_dev), n, h->plan.part, npart, (hipStream_t)stream));
+    return APF_OK;
+  });
+}
+
+extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev, void *stream) {
+  if (!h || !dfdS_dev || !grad_dev) return fail(APF_EINVAL, "null argument");
+  if (h->state != 2) return fail(APF_ESTATE, "apf_factor_schur has not run since the last assembly");
+  return guarded([&]() -> apf_status {
+    hipStream_t s = (hipStream_t)stream;
+    Plan &P = h->plan;
+    const int Mi = h->d.n_in, ch = P.rhs_chunk;
+    const cplx *G = reinterpret_cast<const cplx *>(dfdS_dev);
+    const double two_h2 = 2.0 * h->phys.h2;
+    for (int m0 = 0, c = 0; m0 < Mi; m0 += ch, ++c) {
+      const int w = std::min(ch, Mi - m0);
+      HIPCHK(launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s));
+      for (int lvl = (int)P.lv.size() - 1; lvl >= 0; --lvl) {
+        const LevelTasks &L = P.lv[lvl];
+        HIPCHK(launch_gemm(P.at<GemmTask>(L.sw), L.nsw, m0, w, nullptr, s));
+      }
+      HIPCHK(launch_contract(P.at<int32_t>(P.drows), P.ndesign, P.X, P.V, ch, w, two_h2, grad_dev, c > 0, s));
+    }
+    return APF_OK;
+  });
+}
+
+extern "C" apf_status apf_destroy(apf_handle *h) {
+  if (!h) return APF_OK;
+  free_plan(h->plan);
+  delete h;
+  return APF_OK;
+}
+
+extern "C" const char *apf_last_error(void) { return g_err.c_str(); }
+
+extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
+  if (!h || !key || !value) return fail(APF_EINVAL, "null argument");
+  if (!h->analyzed) return fail(APF_ESTATE, "apf_analyze has not run");
+  const Symbolic &S = h->sym;
+  std::string k(key);
+  if (k == "n_fronts") *value = (double)S.fronts.size();
+  else if (k == "n_levels") *value = (double)S.levels.size();
+  else if (k == "max_front") *value = S.max_front;
+  else if (k == "factor_cmacs") *value = S.factor_cmacs;
+  else if (k == "grad_cmacs") *value = S.grad_cmacs;
+  else if (k == "algo_factor_cmacs") *value = S.algo_factor_cmacs;
+  else if (k == "n_sweep_rows") *value = (double)S.n_sweep_rows;
+  else if (k == "n_sweep_fronts") {
+    double c = 0;
+    for (const Front &F : S.fronts) c += F.sweep;
+    *value = c;
+  } else if (k == "k_total") *value = (double)S.k_total;
+  else if (k == "ws_bytes") *value = h->planned ? (double)h->plan.ws_elems * sizeof(cplx) : -1.0;
+  else if (k == "factor_bytes") *value = h->planned ? (double)h->plan.fs_elems * sizeof(cplx) : -1.0;
+  else if (k == "rhs_chunk") *value = h->planned ? (double)h->plan.rhs_chunk : -1.0;
+  else return fail(APF_EINVAL, "unknown key " + k);
+  return APF_OK;
+}
+
+extern "C" apf_status apf_front(apf_handle *h, int32_t f, int32_t info[8], int32_t *pivots, int32_t *boundary) {
+  if (!h || !info) return fail(APF_EINVAL, "null argument");
+  if (!h->analyzed) return fail(APF_ESTATE, "apf_analyze has not run");
+  const Symbolic &S = h->sym;
+  if (f < 0 || f >= (int32_t)S.fronts.size()) return fail(APF_EINVAL, "front index out of range");
+  const Front &F = S.fronts[f];
+  info[0] = F.parent; info[1] = F.height; info[2] = F.p(); info[3] = F.b();
+  info[4] = F.hasB; info[5] = F.hasC; info[6] = F.sweep; info[7] = (int32_t)F.elim0;
+  if (pivots) std::copy(F.piv.begin(), F.piv.end(), pivots);
+  if (boundary) std::copy(F.bnd.begin(), F.bnd.end(), boundary);
+  return APF_OK;
+}

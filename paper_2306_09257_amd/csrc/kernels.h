@@ -1,0 +1,32 @@
+// Launchers of the APF HIP kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "apf_internal.h"
+
+namespace apf {
+
+// Physical parameters the assembly kernels evaluate the operator from.
+struct Phys {
+  int nx, ny;
+  double h2;                    // (k0 dx)^2
+  int npml_top, npml_bot, pml_power;
+  double alpha_top, alpha_bot;  // PML stretch amplitudes
+  double eps_src, eps_prj;      // media of the source and projection rows
+};
+
+hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s);
+hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStream_t s);
+hipError_t launch_scatter_A(const AsmEntry *e, int n, const cplx *Aval, hipStream_t s);
+hipError_t launch_assemble_panel(const PanelEntry *e, int n, const Phys &P, const int32_t *orders, int m,
+                                 int is_source, hipStream_t s);
+hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, int maxb, hipStream_t s);
+hipError_t launch_inverse(const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
+hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s);
+hipError_t launch_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
+                           double two_h2, double *grad, int accumulate, hipStream_t s);
+hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx *G, int64_t n, double *part,
+                                 int npart, hipStream_t s);
+
+}  // namespace apf

@@ -1,0 +1,468 @@
+// HIP kernels of the APF library for gfx950 (MI355X).
+//
+// Every front of one elimination-tree level is processed by one launch of
+// each kernel below; the host plan holds the per-level task arrays.
+#include <hip/hip_runtime.h>
+
+#include "apf_internal.h"
+#include "kernels.h"
+
+namespace apf {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cinv(double2 a) {
+  // 1/a with scaling against overflow of |a|^2
+  double s = fmax(fabs(a.x), fabs(a.y));
+  if (s == 0.0) return make_double2(0.0, 0.0);
+  double ar = a.x / s, ai = a.y / s;
+  double d = ar * ar + ai * ai;
+  return make_double2(ar / (d * s), -ai / (d * s));
+}
+__device__ __forceinline__ double2 ld2(const cplx *p) { return *reinterpret_cast<const double2 *>(p); }
+__device__ __forceinline__ void st2(cplx *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
+
+// ---------------------------------------------------------------------------
+// Zero the frontal workspaces of one level.
+// ---------------------------------------------------------------------------
+__global__ void k_zero(const ZeroRange *r, int n) {
+  for (int k = blockIdx.y; k < n; k += gridDim.y) {
+    const ZeroRange z = r[k];
+    double2 *p = reinterpret_cast<double2 *>(z.ptr);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < z.n; i += (int64_t)gridDim.x * blockDim.x)
+      p[i] = make_double2(0.0, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Assembly of A (the 5-point UPML operator) into frontal cores, and of the
+// source / projection rows into the channel panels.
+// ---------------------------------------------------------------------------
+__device__ double2 stretch(const Phys &P, double y) {
+  // s(d) = 1 + i alpha (d/L)^m past the PML's inner face (half-row)
+  double yt = P.npml_top - 0.5, yb = P.ny - P.npml_bot - 0.5;
+  if (P.npml_top > 0 && y < yt) {
+    double t = (yt - y) / P.npml_top;
+    return make_double2(1.0, P.alpha_top * pow(t, (double)P.pml_power));
+  }
+  if (P.npml_bot > 0 && y > yb) {
+    double t = (y - yb) / P.npml_bot;
+    return make_double2(1.0, P.alpha_bot * pow(t, (double)P.pml_power));
+  }
+  return make_double2(1.0, 0.0);
+}
+
+// Stencil values of A for every node (a1): Aval[node][dir], dir 0 centre,
+// 1 x-1, 2 x+1, 3 y-1, 4 y+1 (x periodic; entries beyond the first and last
+// rows are never scattered).
+__global__ void k_stencil(Phys P, const double *eps, cplx *Aval) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n >= (int64_t)P.nx * P.ny) return;
+  const int j = (int)(n / P.nx);
+  const double2 sj = stretch(P, (double)j);
+  const double2 up = cinv(stretch(P, j - 0.5)), dn = cinv(stretch(P, j + 0.5));
+  const double ep = eps[n];
+  double2 c = cadd(make_double2(2.0 * sj.x, 2.0 * sj.y), cadd(up, dn));
+  c = csub(c, make_double2(P.h2 * ep * sj.x, P.h2 * ep * sj.y));
+  cplx *o = Aval + n * 5;
+  st2(o + 0, c);
+  st2(o + 1, make_double2(-sj.x, -sj.y));
+  st2(o + 2, make_double2(-sj.x, -sj.y));
+  st2(o + 3, make_double2(-up.x, -up.y));
+  st2(o + 4, make_double2(-dn.x, -dn.y));
+}
+
+// Scatter of the stencil values of one level's fronts into their cores.
+__global__ void k_scatter_A(const AsmEntry *e, int n, const cplx *Aval) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const AsmEntry E = e[t];
+  st2(E.dest, cadd(ld2(E.dest), ld2(Aval + E.src)));
+}
+
+// Channel value at column i of order a in a medium: sqrt(sin q) phi_a(i), with
+// q from sin^2(q/2) = h^2 eps/4 - sin^2(pi a/nx) and phi_a(i) = e^{2 pi i a i/nx}/sqrt(nx).
+__device__ double2 channel_value(const Phys &P, int a, int i, double eps_medium, bool conj_phase) {
+  double sa = sin(M_PI * (double)a / P.nx);
+  double rhs = P.h2 * eps_medium * 0.25 - sa * sa;
+  double q = 2.0 * asin(sqrt(rhs));
+  double amp = sqrt(sin(q) / P.nx);
+  int64_t ph = ((int64_t)a * i) % P.nx;
+  if (ph < 0) ph += P.nx;
+  double ang = 2.0 * M_PI * (double)ph / P.nx;
+  double s, c;
+  sincos(ang, &s, &c);
+  return make_double2(amp * c, conj_phase ? -amp * s : amp * s);
+}
+
+// B rows: -2i sqrt(sin q_a) phi_a(i); C^T rows: sqrt(sin q_b) conj(phi_b(i)).
+__global__ void k_assemble_panel(const PanelEntry *e, int n, Phys P, const int32_t *orders, int m,
+                                 int is_source) {
+  const PanelEntry E = e[blockIdx.x];
+  const int i = E.node % P.nx;
+  double eps_m = is_source ? P.eps_src : P.eps_prj;
+  for (int a = threadIdx.x; a < m; a += blockDim.x) {
+    double2 v = channel_value(P, orders[a], i, eps_m, !is_source);
+    if (is_source) v = make_double2(2.0 * v.y, -2.0 * v.x);   // times -2i
+    st2(E.dest + a, cadd(ld2(E.dest + a), v));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Extend-add: scatter-add one child's contribution block (core, B rows,
+// C^T rows) into its parent.  grid = (children, boundary rows of the child).
+// ---------------------------------------------------------------------------
+__global__ void k_extend_add(const FrontDev *fr, const int32_t *kids, int nkids) {
+  const int c = kids[blockIdx.x];
+  const FrontDev C = fr[c];
+  const int r = blockIdx.y;
+  if (r >= C.b) return;
+  const FrontDev P = fr[C.parent];
+  const int nc = C.p + C.b, np = P.p + P.b;
+  const int pr = C.rmap[r];
+  const cplx *src = C.core + (int64_t)(C.p + r) * nc + C.p;
+  cplx *dst = P.core + (int64_t)pr * np;
+  for (int s = threadIdx.x; s < C.b; s += blockDim.x) {
+    cplx *d = dst + C.rmap[s];
+    st2(d, cadd(ld2(d), ld2(src + s)));
+  }
+  if (C.mB) {
+    const cplx *sb = C.bp_bnd + (int64_t)r * C.mB;
+    cplx *db = pr < P.p ? P.bp_piv + (int64_t)pr * P.mB : P.bp_bnd + (int64_t)(pr - P.p) * P.mB;
+    for (int s = threadIdx.x; s < C.mB; s += blockDim.x) st2(db + s, cadd(ld2(db + s), ld2(sb + s)));
+  }
+  if (C.mC) {
+    const cplx *sc = C.cpt_bnd + (int64_t)r * C.mC;
+    cplx *dc = pr < P.p ? P.cpt_piv + (int64_t)pr * P.mC : P.cpt_bnd + (int64_t)(pr - P.p) * P.mC;
+    for (int s = threadIdx.x; s < C.mC; s += blockDim.x) st2(dc + s, cadd(ld2(dc + s), ld2(sc + s)));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pivot-block inverse G = F11^-1, in place, by Gauss-Jordan elimination with
+// partial (row) pivoting.  One workgroup per front.  Small blocks are staged
+// in LDS; larger ones are updated in global memory (L2 resident).
+// ---------------------------------------------------------------------------
+constexpr int INV_THREADS = 256;
+constexpr int INV_LDS_MAXP = 64;
+constexpr int INV_MAXP = 1024;
+
+__device__ void gauss_jordan(cplx *a, int lda, int p, double2 *rowbuf, double2 *colbuf, int *perm,
+                             double *redv, int *redi, int *status) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < p; ++k) {
+    double bv = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < p; i += INV_THREADS) {
+      double2 v = ld2(a + (int64_t)i * lda + k);
+      double m = v.x * v.x + v.y * v.y;
+      if (m > bv) { bv = m; bi = i; }
+    }
+    redv[tid] = bv;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int s = INV_THREADS / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        double ov = redv[tid + s];
+        int oi = redi[tid + s];
+        if (ov > redv[tid] || (ov == redv[tid] && oi < redi[tid])) { redv[tid] = ov; redi[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int r = redi[0];
+    const bool zero = !(redv[0] > 0.0);
+    if (tid == 0) {
+      perm[k] = r;
+      if (zero) atomicOr(status, 1);
+    }
+    __syncthreads();
+    if (r != k) {
+      for (int j = tid; j < p; j += INV_THREADS) {
+        double2 x = ld2(a + (int64_t)k * lda + j), y = ld2(a + (int64_t)r * lda + j);
+        st2(a + (int64_t)k * lda + j, y);
+        st2(a + (int64_t)r * lda + j, x);
+      }
+    }
+    __syncthreads();
+    const double2 inv = cinv(ld2(a + (int64_t)k * lda + k));
+    for (int j = tid; j < p; j += INV_THREADS) {
+      double2 v = (j == k) ? inv : cmul(ld2(a + (int64_t)k * lda + j), inv);
+      rowbuf[j] = v;
+    }
+    for (int i = tid; i < p; i += INV_THREADS)
+      colbuf[i] = (i == k) ? make_double2(0.0, 0.0) : ld2(a + (int64_t)i * lda + k);
+    __syncthreads();
+    for (int j = tid; j < p; j += INV_THREADS) st2(a + (int64_t)k * lda + j, rowbuf[j]);
+    for (int e = tid; e < p * p; e += INV_THREADS) {
+      int i = e / p, j = e - i * p;
+      if (i == k) continue;
+      double2 old = (j == k) ? make_double2(0.0, 0.0) : ld2(a + (int64_t)i * lda + j);
+      st2(a + (int64_t)i * lda + j, csub(old, cmul(colbuf[i], rowbuf[j])));
+    }
+    __syncthreads();
+  }
+  // (P F)^-1 = F^-1 P^-1: undo the row interchanges as column interchanges
+  for (int k = p - 1; k >= 0; --k) {
+    int r = perm[k];
+    if (r != k) {
+      for (int i = tid; i < p; i += INV_THREADS) {
+        double2 x = ld2(a + (int64_t)i * lda + k), y = ld2(a + (int64_t)i * lda + r);
+        st2(a + (int64_t)i * lda + k, y);
+        st2(a + (int64_t)i * lda + r, x);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(INV_THREADS) void k_inverse(const FrontDev *fr, const int32_t *ids, int *status) {
+  const FrontDev F = fr[ids[blockIdx.x]];
+  const int p = F.p, n = F.p + F.b;
+  __shared__ double2 rowbuf[INV_MAXP], colbuf[INV_MAXP];
+  __shared__ int perm[INV_MAXP];
+  __shared__ double redv[INV_THREADS];
+  __shared__ int redi[INV_THREADS];
+  __shared__ double2 tile[INV_LDS_MAXP * INV_LDS_MAXP];
+  if (p <= INV_LDS_MAXP) {
+    for (int e = threadIdx.x; e < p * p; e += INV_THREADS) {
+      int i = e / p, j = e - i * p;
+      tile[e] = ld2(F.core + (int64_t)i * n + j);
+    }
+    __syncthreads();
+    gauss_jordan(reinterpret_cast<cplx *>(tile), p, p, rowbuf, colbuf, perm, redv, redi, status);
+    __syncthreads();
+    for (int e = threadIdx.x; e < p * p; e += INV_THREADS) {
+      int i = e / p, j = e - i * p;
+      st2(F.core + (int64_t)i * n + j, tile[e]);
+    }
+  } else {
+    gauss_jordan(F.core, n, p, rowbuf, colbuf, perm, redv, redi, status);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched complex FP64 GEMM on MFMA: one 64x64 output tile per workgroup of
+// four waves; each wave owns a 32x32 quadrant as 2x2 blocks of 16x16, with
+// the real and imaginary parts in separate accumulators (four real
+// v_mfma_f64_16x16x4 per complex block and k-step of 4).
+// ---------------------------------------------------------------------------
+constexpr int KT = 16;
+
+__global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext) {
+  const GemmTask T = tasks[blockIdx.x];
+  const int M = T.M, K = T.K;
+  const int N = T.N < nlim ? T.N : nlim;
+  if (T.tn >= N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool transA = T.flags & G_TRANS_A;
+  const cplx *Bp = (T.flags & G_B_EXT) ? ext : T.B;
+  if (T.flags & G_B_COFF) Bp += coff;
+  cplx *Cp = (T.flags & G_C_EXT) ? const_cast<cplx *>(ext) : T.C;
+
+  __shared__ double2 As[KT][64];
+  __shared__ double2 Bs[KT][64];
+
+  d4 cre[2][2], cim[2][2];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      cre[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+      cim[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+
+  for (int k0 = 0; k0 < K; k0 += KT) {
+    double2 ra[4], rb[4];
+    if (!transA) {
+      const int i = tid >> 2, kq = (tid & 3) * 4;
+      const int gi = T.tm + i;
+      for (int q = 0; q < 4; ++q) {
+        const int gk = k0 + kq + q;
+        ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gi * T.lda + gk) : make_double2(0.0, 0.0);
+      }
+    } else {
+      const int k = tid >> 4, iq = (tid & 15) * 4;
+      const int gk = k0 + k;
+      for (int q = 0; q < 4; ++q) {
+        const int gi = T.tm + iq + q;
+        ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gk * T.lda + gi) : make_double2(0.0, 0.0);
+      }
+    }
+    {
+      const int k = tid >> 4, jq = (tid & 15) * 4;
+      const int gk = k0 + k;
+      const cplx *row = nullptr;
+      if (gk < K) row = Bp + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb;
+      for (int q = 0; q < 4; ++q) {
+        const int gj = T.tn + jq + q;
+        rb[q] = (row && gj < N) ? ld2(row + gj) : make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    if (!transA) {
+      const int i = tid >> 2, kq = (tid & 3) * 4;
+      for (int q = 0; q < 4; ++q) As[kq + q][i] = ra[q];
+    } else {
+      const int k = tid >> 4, iq = (tid & 15) * 4;
+      for (int q = 0; q < 4; ++q) As[k][iq + q] = ra[q];
+    }
+    {
+      const int k = tid >> 4, jq = (tid & 15) * 4;
+      for (int q = 0; q < 4; ++q) Bs[k][jq + q] = rb[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+      const int kx = kk + (lane >> 4);
+      double2 a[2], b[2];
+      a[0] = As[kx][wr + (lane & 15)];
+      a[1] = As[kx][wr + 16 + (lane & 15)];
+      b[0] = Bs[kx][wc + (lane & 15)];
+      b[1] = Bs[kx][wc + 16 + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].x, cre[r][c], 0, 0, 0);
+          cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[r].y, b[c].y, cre[r][c], 0, 0, 0);
+          cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].y, cim[r][c], 0, 0, 0);
+          cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].y, b[c].x, cim[r][c], 0, 0, 0);
+        }
+    }
+  }
+
+  // D layout of v_mfma_f64_16x16x4: lane l, element q -> row (l/16) + 4q, column l%16.
+  const bool neg = T.flags & G_NEG;
+  const cplx *Cin = (T.flags & G_CIN) ? T.Cin : nullptr;
+  if (Cin && (T.flags & G_CIN_COFF)) Cin += coff;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gi = T.tm + wr + 16 * r + (lane >> 4) + 4 * q;
+        const int gj = T.tn + wc + 16 * c + (lane & 15);
+        if (gi < M && gj < N) {
+          double2 v = make_double2(cre[r][c][q], cim[r][c][q]);
+          if (neg) v = make_double2(-v.x, -v.y);
+          if (Cin) v = cadd(v, ld2(Cin + (int64_t)gi * T.ldcin + gj));
+          st2(Cp + (int64_t)gi * T.ldc + gj, v);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient contraction: grad_k += -2 Re(sigma_k sum_m Lam_km Y_km),
+// sigma_k = -h^2 outside the PML.  One wave per design pixel.
+// ---------------------------------------------------------------------------
+__global__ void k_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
+                           double two_h2, double *grad, int accumulate) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= n) return;
+  const int64_t r = rows[wave];
+  double acc = 0.0;
+  for (int m = lane; m < ncols; m += 64) {
+    double2 x = ld2(X + r * ld + m), v = ld2(V + r * ld + m);
+    acc += x.x * v.x - x.y * v.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) grad[wave] = (accumulate ? grad[wave] : 0.0) + two_h2 * acc;
+}
+
+// ---------------------------------------------------------------------------
+// f = sum w |S|^2, dF/dS = w conj(S): block partial sums, then one block.
+// ---------------------------------------------------------------------------
+__global__ void k_wpow_partial(const double2 *S, const double *w, double2 *G, int64_t n, double *part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double2 s = S[t];
+    double ww = w[t];
+    acc += ww * (s.x * s.x + s.y * s.y);
+    G[t] = make_double2(ww * s.x, -ww * s.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_wpow_final(const double *part, int n, double *f) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) acc += part[t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *f = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(16, n < 32768 ? n : 32768), dim3(256), 0, s, r, n);
+  return hipGetLastError();
+}
+hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStream_t s) {
+  int64_t N = (int64_t)P.nx * P.ny;
+  hipLaunchKernelGGL(k_stencil, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, eps, Aval);
+  return hipGetLastError();
+}
+hipError_t launch_scatter_A(const AsmEntry *e, int n, const cplx *Aval, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_A, dim3((n + 255) / 256), dim3(256), 0, s, e, n, Aval);
+  return hipGetLastError();
+}
+hipError_t launch_assemble_panel(const PanelEntry *e, int n, const Phys &P, const int32_t *orders, int m,
+                                 int is_source, hipStream_t s) {
+  if (n == 0 || m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n, P, orders, m, is_source);
+  return hipGetLastError();
+}
+hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, int maxb, hipStream_t s) {
+  if (nkids == 0 || maxb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extend_add, dim3(nkids, maxb), dim3(256), 0, s, fr, kids, nkids);
+  return hipGetLastError();
+}
+hipError_t launch_inverse(const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inverse, dim3(n), dim3(INV_THREADS), 0, s, fr, ids, status);
+  return hipGetLastError();
+}
+hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm, dim3(n), dim3(256), 0, s, t, coff, nlim, ext);
+  return hipGetLastError();
+}
+hipError_t launch_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
+                           double two_h2, double *grad, int accumulate, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_contract, dim3((n + 3) / 4), dim3(256), 0, s, rows, n, X, V, ld, ncols, two_h2, grad,
+                     accumulate);
+  return hipGetLastError();
+}
+hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx *G, int64_t n, double *part,
+                                 int npart, hipStream_t s) {
+  hipLaunchKernelGGL(k_wpow_partial, dim3(npart), dim3(256), 0, s, reinterpret_cast<const double2 *>(S), w,
+                     reinterpret_cast<double2 *>(G), n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wpow_final, dim3(1), dim3(256), 0, s, part, npart, f);
+  return hipGetLastError();
+}
+
+}  // namespace apf

@@ -1,0 +1,112 @@
+"""GPU parity of the HIP APF path against the CPU FP64 oracle, through the C
+ABI (the binding only marshals arguments).
+
+Tolerances (FP64 path): normwise relative error <= 1e-10 for S (Frobenius)
+and for the gradient (2-norm), the bar stated for the plain FP64 path.
+"""
+import numpy as np
+import pytest
+
+from paper_2306_09257_amd import inputs
+import oracle.apf as oapf
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _run_gpu(prob, eps, w, leaf=0):
+    from paper_2306_09257_amd import binding
+    print(f"[gpu] nx={prob.nx} ny={prob.ny} n_in={prob.n_in} n_out={prob.n_out} leaf={leaf}", flush=True)
+    apf = binding.APF(prob, leaf_size=leaf).analyze()
+    eps_d = _dev(eps, torch.float64)
+    w_d = _dev(w, torch.float64)
+    apf.assemble(eps_d)
+    S = apf.factor_schur()
+    f, G = apf.weighted_power(S, w_d)
+    g = apf.grad(G)
+    torch.cuda.synchronize()
+    return apf, S.cpu().numpy(), float(f.cpu()), G.cpu().numpy(), g.cpu().numpy()
+
+
+CASES = [
+    dict(nx=24, ny=60, leaf=0, seed=0),
+    dict(nx=37, ny=60, leaf=16, seed=1),       # odd width, small leaves: ragged tiles
+    dict(nx=3, ny=60, leaf=0, seed=2),         # narrowest periodic grid
+    dict(nx=64, ny=92, leaf=64, seed=3),
+    dict(nx=130, ny=60, leaf=128, seed=4),     # channel panels wider than one 64-wide tile
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c['nx']}x{c['ny']}-leaf{c['leaf']}")
+def test_S_and_grad_match_oracle_small(case):
+    prob, eps, w = inputs.tiny_problem(nx=case["nx"], ny=case["ny"], seed=case["seed"])
+    _, S, f, G, g = _run_gpu(prob, eps, w, case["leaf"])
+    S_o, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
+    assert _rel(S, S_o) < TOL
+    assert abs(f - f_o) < TOL * abs(f_o)
+    assert _rel(G, w * np.conj(S_o)) < TOL
+    assert _rel(g, g_o) < TOL
+
+
+def test_metasurface_240x92_matches_oracle():
+    """240 x 92 grid (22,080 unknowns), 23 x 23 channels, 4,800 design pixels."""
+    prob, eps, w = inputs.metasurface_small(seed=0)
+    apf, S, f, G, g = _run_gpu(prob, eps, w)
+    S_o, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
+    print(f"[gpu] 240x92 rel err S {_rel(S, S_o):.2e} grad {_rel(g, g_o):.2e}", flush=True)
+    assert _rel(S, S_o) < TOL
+    assert _rel(g, g_o) < TOL
+
+
+def test_repeat_is_bitwise_deterministic_and_reassembles():
+    prob, eps, w = inputs.tiny_problem(nx=40, ny=60, seed=5)
+    from paper_2306_09257_amd import binding
+    apf = binding.APF(prob).analyze()
+    outs = []
+    for e in (eps, eps + 0.0, eps):
+        apf.assemble(_dev(e, torch.float64))
+        outs.append(apf.factor_schur().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    # a different permittivity gives the oracle's S for that permittivity
+    eps2 = eps.copy()
+    eps2[prob.design_row0:prob.design_row1] = 4.0 - eps2[prob.design_row0:prob.design_row1] + 1.0
+    apf.assemble(_dev(eps2, torch.float64))
+    S2 = apf.factor_schur().cpu().numpy()
+    assert _rel(S2, oapf.scattering_matrix(prob, eps2)) < TOL
+
+
+def test_grad_before_factor_is_a_state_error():
+    from paper_2306_09257_amd import binding
+    prob, eps, w = inputs.tiny_problem(nx=24, ny=60, seed=6)
+    apf = binding.APF(prob).analyze()
+    apf.assemble(_dev(eps, torch.float64))
+    G = torch.zeros((prob.n_out, prob.n_in), dtype=torch.complex128, device="cuda")
+    with pytest.raises(binding.APFError) as ei:
+        apf.grad(G)
+    assert ei.value.status == binding.APF_ESTATE
+
+
+def test_autograd_function_matches_oracle_gradient():
+    from paper_2306_09257_amd import binding
+    prob, eps, w = inputs.tiny_problem(nx=32, ny=60, seed=7)
+    apf = binding.APF(prob).analyze()
+    Fn = binding.make_autograd_function()
+    r0, r1 = prob.design_row0, prob.design_row1
+    eps_bg = _dev(eps, torch.float64)
+    x = _dev(eps[r0:r1], torch.float64).requires_grad_(True)
+    S = Fn.apply(x, apf, eps_bg)
+    loss = (_dev(w, torch.float64) * S.abs() ** 2).sum()
+    loss.backward()
+    _, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
+    assert abs(float(loss) - f_o) < TOL * abs(f_o)
+    assert _rel(x.grad.cpu().numpy(), g_o) < TOL

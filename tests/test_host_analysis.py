@@ -1,0 +1,160 @@
+"""Host-side checks of the C library (no GPU): it loads, exports every entry
+point of include/apf.h, validates descriptors, and its nested-dissection
+analysis is a valid multifrontal structure for the 5-point periodic grid."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2306_09257_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "apf.h")
+
+binding = pytest.importorskip("paper_2306_09257_amd.binding")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libapf.so is not built (run paper_2306_09257_amd/build.py)")
+    return binding.load_library()
+
+
+def test_exports_every_declared_entry_point(lib):
+    decl = re.findall(r"^\s*(?:const\s+char\s*\*\s*|apf_status\s+)(apf_\w+)\s*\(", open(HEADER).read(), re.M)
+    assert set(decl) == set(binding.ENTRY_POINTS)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def _problem(nx, ny, **kw):
+    prob, eps, w = inputs.tiny_problem(nx=nx, ny=ny, **kw)
+    return prob
+
+
+@pytest.mark.parametrize("mut,msg", [
+    (lambda p: setattr(p, "design_row0", 2), "PML"),
+    (lambda p: setattr(p, "src_row", p.design_row0), "src_row"),
+    (lambda p: setattr(p, "prj_row", p.design_row1 - 1), "prj_row"),
+    (lambda p: setattr(p, "in_orders", np.array([40], dtype=np.int32)), "propagate"),
+    (lambda p: setattr(p, "nx", 2), "nx"),
+])
+def test_descriptor_validation(lib, mut, msg):
+    prob = _problem(24, 60)
+    mut(prob)
+    with pytest.raises(binding.APFError) as ei:
+        binding.APF(prob)
+    assert ei.value.status == binding.APF_EINVAL
+    assert msg in str(ei.value)
+
+
+def _structure(apf):
+    nf = int(apf.query("n_fronts"))
+    fronts = [apf.front(f) for f in range(nf)]
+    return fronts
+
+
+@pytest.mark.parametrize("nx,ny,leaf", [(24, 60, 0), (37, 60, 16), (9, 92, 0), (240, 92, 64), (50, 60, 4)])
+def test_nested_dissection_is_a_valid_multifrontal_structure(lib, nx, ny, leaf):
+    prob = _problem(nx, ny)
+    apf = binding.APF(prob, leaf_size=leaf).analyze()
+    fronts = _structure(apf)
+    nf = len(fronts)
+    N = nx * ny
+    owner = -np.ones(N, dtype=np.int64)
+    elim = -np.ones(N, dtype=np.int64)
+    for f, (info, piv, bnd) in enumerate(fronts):
+        assert (owner[piv] == -1).all(), "node pivoted twice"
+        owner[piv] = f
+        elim[piv] = info[7] + np.arange(piv.size)
+    assert (owner >= 0).all(), "some node never pivoted"
+    assert sorted(elim.tolist()) == list(range(N))
+    # postorder and single root
+    roots = [f for f, (info, _, _) in enumerate(fronts) if info[0] < 0]
+    assert roots == [nf - 1]
+    for f, (info, _, _) in enumerate(fronts):
+        if info[0] >= 0:
+            assert info[0] > f
+            assert fronts[info[0]][0][1] > info[1], "parent height must exceed child height"
+    # ancestors
+    anc = []
+    for f in range(nf):
+        s, g = set(), fronts[f][0][0]
+        while g >= 0:
+            s.add(g)
+            g = fronts[g][0][0]
+        anc.append(s)
+    varset = [set(piv.tolist()) | set(bnd.tolist()) for (_, piv, bnd) in fronts]
+    for f, (info, piv, bnd) in enumerate(fronts):
+        # boundary nodes are pivots of ancestors, sorted by elimination order
+        assert all(owner[v] in anc[f] for v in bnd)
+        assert (np.diff(elim[bnd]) > 0).all()
+        # child contribution block fits in the parent front
+        if info[0] >= 0:
+            assert set(bnd.tolist()) <= varset[info[0]]
+    # every grid edge (u, v): the later node is in the front of the earlier one
+    for u in range(N):
+        x, y = u % nx, u // nx
+        nbs = [y * nx + (x - 1) % nx, y * nx + (x + 1) % nx]
+        if y > 0:
+            nbs.append(u - nx)
+        if y < ny - 1:
+            nbs.append(u + nx)
+        for v in nbs:
+            a, b = (u, v) if elim[u] < elim[v] else (v, u)
+            assert b in varset[owner[a]], (u, v)
+    # channel blocks and sweep set follow the subtree's rows
+    rows_sub = [set() for _ in range(nf)]
+    for f in range(nf):
+        for v in fronts[f][1]:
+            g = f
+            while g >= 0:
+                rows_sub[g].add(int(v) // nx)
+                g = fronts[g][0][0]
+    for f, (info, _, _) in enumerate(fronts):
+        assert info[4] == (prob.src_row in rows_sub[f])
+        assert info[5] == (prob.prj_row in rows_sub[f])
+        assert info[6] == bool(rows_sub[f] & set(range(prob.design_row0, prob.design_row1)))
+
+
+def test_work_counts_match_a_brute_force_symbolic_elimination(lib):
+    """The algorithmic count (rank-p updates of each rectangular front) must
+    equal a dense symbolic elimination of K in the same order on a tiny grid:
+    sum over eliminated k of (#later rows in col k) * (#later cols in row k)."""
+    prob = _problem(10, 60)
+    apf = binding.APF(prob, leaf_size=16).analyze()
+    fronts = _structure(apf)
+    nx, ny = prob.nx, prob.ny
+    N = nx * ny
+    order = np.concatenate([piv for (_, piv, _) in fronts])
+    pos = np.empty(N, dtype=np.int64)
+    pos[order] = np.arange(N)
+    Mi, Mo = prob.n_in, prob.n_out
+    # pattern of K in elimination order: grid part plus channel rows/columns
+    pat = np.zeros((N + Mo, N + Mi), dtype=bool)
+    for u in range(N):
+        x, y = u % nx, u // nx
+        pat[pos[u], pos[u]] = True
+        for v in (y * nx + (x - 1) % nx, y * nx + (x + 1) % nx):
+            pat[pos[u], pos[v]] = True
+        if y > 0:
+            pat[pos[u], pos[u - nx]] = True
+        if y < ny - 1:
+            pat[pos[u], pos[u + nx]] = True
+        if y == prob.src_row:
+            pat[pos[u], N:] = True
+        if y == prob.prj_row:
+            pat[N:, pos[u]] = True
+    count = 0.0
+    for k in range(N):
+        rows = np.nonzero(pat[k + 1:, k])[0] + k + 1
+        cols = np.nonzero(pat[k, k + 1:])[0] + k + 1
+        count += rows.size * cols.size
+        pat[np.ix_(rows, cols)] = True
+    # the multifrontal fronts are dense: their count bounds the exact fill count
+    algo = apf.query("algo_factor_cmacs")
+    assert algo >= count
+    # and the channel-free part is tight for leaves and separators of a strip
+    assert algo <= 1.6 * count
