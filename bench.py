@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""APF solves per second (S and the full permittivity gradient) on one MI355X.
+
+One step = assemble A from eps + multifrontal partial factorization of
+K = [A, B; C, 0] giving S + objective f = sum w|S|^2 and its Wirtinger
+derivative + the gradient over every design pixel (weighted-adjoint sweeps
+and contraction).  The symbolic analysis depends only on the grid and is done
+once, outside the timed region.  Inputs (eps, w) are resident in HBM.
+
+Workload (default): 1,200-wavelength metasurface, 24,000 x 160 grid
+(3.84M unknowns, dx = lambda/20), 2,399 input x 2,399 output channels,
+960,000 design pixels of binary {1, 4} permittivity smoothed by a 3-px-FWHM
+Gaussian, f = sum w |S|^2 with w ~ U[0, 1].  Synthetic, seeded.
+
+Prints one JSON line.  The roofline block is for the batched complex FP64
+MFMA GEMM kernel (k_gemm): its algorithmic flops (8 per complex MAC of the
+M x N x K products the tasks specify) over its HIP-event time in the timed
+region.  The cpu_baseline block times the CPU FP64 oracle on a bounded
+narrow-strip sample of the same workload and scales it by the oracle's cost
+model to the full workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "metasurface_24000x160": dict(kind="wide", nx=24000, seed=1),
+    "metasurface_240x92": dict(kind="small", seed=0),
+}
+
+
+def make_workload(name):
+    from paper_2306_09257_amd import inputs
+    spec = WORKLOADS[name]
+    if spec["kind"] == "wide":
+        return inputs.metasurface_wide(seed=spec["seed"], nx=spec["nx"])
+    return inputs.metasurface_small(seed=spec["seed"])
+
+
+def oracle_cost_model(nx, ny, m):
+    """Complex MACs of the oracle's cyclic column-block solve for S and the
+    gradient: two solves (forward, weighted adjoint), each eliminating nx
+    column blocks of size ny against 2 ny + m right-hand sides, with a dense
+    border update per column."""
+    return 2.0 * nx * ny * ny * (4.3 * ny + 4.0 * m)
+
+
+def cpu_baseline(prob_full):
+    """Oracle on a 960-column strip of the same layout and eps recipe."""
+    import numpy as np  # noqa: F401
+    from paper_2306_09257_amd import inputs
+    import oracle.apf as oapf
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(i["num_threads"] for i in threadpool_info()) if threadpool_info() else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    nx_s = 960
+    prob, eps, w = inputs.metasurface_wide(seed=1, nx=nx_s)
+    t0 = time.perf_counter()
+    oapf.solve_S_and_grad(prob, eps, w=w, solver=oapf.make_solver(prob, eps, "column"))
+    dt = time.perf_counter() - t0
+    scale = oracle_cost_model(prob_full.nx, prob_full.ny, prob_full.n_in) / \
+        oracle_cost_model(prob.nx, prob.ny, prob.n_in)
+    return {
+        "value": 1.0 / (dt * scale), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+        "sample": f"oracle S+grad on a {nx_s}x{prob.ny} strip ({prob.n_in} channels) of the same "
+                  f"layout and eps recipe: {dt:.2f} s; scaled by the oracle's cost model "
+                  f"2*nx*ny^2*(4.3*ny+4*M) (x{scale:.0f}) to the full workload",
+        "sample_seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="metasurface_24000x160", choices=sorted(WORKLOADS))
+    ap.add_argument("--leaf", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the APF path here is a "
+              f"single-GPU build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2306_09257_amd import binding
+
+    prob, eps, w = make_workload(args.workload)
+    print(f"[bench] workload {args.workload}: {prob.nx}x{prob.ny}, {prob.n_in}x{prob.n_out} channels",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    apf = binding.APF(prob, leaf_size=args.leaf).analyze()
+    t_an = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    eps_d = torch.as_tensor(eps, dtype=torch.float64, device=dev).contiguous()
+    w_d = torch.as_tensor(w, dtype=torch.float64, device=dev).contiguous()
+    S = torch.empty((prob.n_out, prob.n_in), dtype=torch.complex128, device=dev)
+    grad = torch.empty((prob.n_design_rows, prob.nx), dtype=torch.float64, device=dev)
+
+    def step():
+        apf.assemble(eps_d)
+        apf.factor_schur(S)
+        f, G = apf.weighted_power(S, w_d)
+        apf.grad(G, out=grad)
+        return f
+
+    t0 = time.perf_counter()
+    step()                      # first call builds the device plan
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    print(f"[bench] analysis {t_an:.2f} s, first step (plan + run) {t_plan:.2f} s", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    apf.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = apf.profile()
+    apf.set_profiling(False)
+    ms_step = 1e3 * dt / args.steps
+    value = args.steps / dt
+
+    cm = {k: apf.query("gemm_cmacs_" + k) for k in ("factor", "schur", "sweep")}
+    gemm_ms = (prof["gemm_factor"][0] + prof["gemm_schur"][0] + prof["gemm_sweep"][0]) / args.steps
+    gemm_launches = (prof["gemm_factor"][1] + prof["gemm_schur"][1] + prof["gemm_sweep"][1]) / args.steps
+    gemm_flop = 8.0 * (cm["factor"] + cm["schur"] + cm["sweep"])
+    achieved = gemm_flop / (gemm_ms * 1e-3) / 1e12
+    roofline = {
+        "kernel": "k_gemm (batched complex FP64 MFMA GEMM, all launches of a step)",
+        "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+        "flop_per_step": gemm_flop, "launches_per_step": gemm_launches,
+        "avg_launch_ms": gemm_ms / max(gemm_launches, 1),
+    }
+    phases = {c: round(prof[c][0] / args.steps, 3) for c in prof}
+
+    out = {
+        "metric": "APF solves/sec (S+grad f) at N unknowns, M channels",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128 (f64)", "data": "synthetic",
+        "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "unknowns": prob.nx * prob.ny,
+                   "n_in": prob.n_in, "n_out": prob.n_out, "design_pixels": prob.n_design_rows * prob.nx,
+                   "precision": "fp64", "leaf_size": args.leaf or 64},
+        "roofline": roofline,
+        "phase_ms_per_step": phases,
+        "analysis_s": t_an,
+        "factor_cmacs_algorithmic": apf.query("algo_factor_cmacs"),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,6 +134,11 @@ apf_status apf_weighted_power(apf_handle *h, const double *S_dev,
 apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev,
                     void *stream);
 
+/* Enable (on != 0) or disable per-class HIP-event timing of every launch
+ * the handle makes (counters reset).  When on, each call waits for its own
+ * events at its end, so calls become synchronous. */
+apf_status apf_set_profiling(apf_handle *h, int32_t on);
+
 /* Free the handle, its symbolic data, factors and device buffers.  Waits for
  * nothing: the caller must have synchronised the streams it used. */
 apf_status apf_destroy(apf_handle *h);
@@ -144,9 +149,17 @@ const char *apf_last_error(void);
 /* Read a named statistic of an analysed handle (host only):
  *   "n_fronts", "n_levels", "max_front" (largest p+b), "factor_cmacs" and
  *   "grad_cmacs" (complex multiply-adds the factorization and the gradient
- *   perform, counted as executed GEMM work), "algo_factor_cmacs" (the
- *   algorithmic count sum over fronts of the rank-p updates), "ws_bytes",
- *   "factor_bytes", "rhs_chunk", "n_sweep_fronts". */
+ *   perform), "algo_factor_cmacs" (sum over fronts of the rank-p updates of
+ *   the rectangular front, channel block included), "ws_bytes" (workspace
+ *   peak), "factor_bytes", "schur_store_bytes", "n_sweep_rows",
+ *   "n_sweep_fronts", "k_total";
+ *   after the first apf_assemble: "rhs_chunk", "gemm_cmacs_factor",
+ *   "gemm_cmacs_schur", "gemm_cmacs_sweep" (complex multiply-adds issued to
+ *   the GEMM kernel per call);
+ *   with profiling on: "ms_<class>" and "launches_<class>", the summed
+ *   HIP-event time and launch count since profiling was enabled, for the
+ *   classes stencil, zero, assemble, extend_add, inverse, gemm_factor,
+ *   gemm_schur, gemm_sweep, contract, wpow. */
 apf_status apf_query(apf_handle *h, const char *key, double *value);
 
 /* Structure export for host-side validation (host only, after apf_analyze).

@@ -26,7 +26,9 @@ APF_FP64 = 0
 APF_MIXED = 1
 
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_weighted_power",
-                "apf_grad", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
+                "apf_grad", "apf_set_profiling", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
+PROFILE_CLASSES = ("stencil", "zero", "assemble", "extend_add", "inverse", "gemm_factor", "gemm_schur",
+                   "gemm_sweep", "contract", "wpow")
 
 
 class APFError(RuntimeError):
@@ -67,6 +69,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_factor_schur.argtypes = [vp, i32, vp, vp]
     lib.apf_weighted_power.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.apf_grad.argtypes = [vp, vp, vp, vp]
+    lib.apf_set_profiling.argtypes = [vp, i32]
     lib.apf_destroy.argtypes = [vp]
     lib.apf_last_error.argtypes = []
     lib.apf_last_error.restype = ctypes.c_char_p
@@ -125,6 +128,13 @@ class APF:
         v = ctypes.c_double()
         _check(self._lib.apf_query(self._h, key.encode(), ctypes.byref(v)))
         return v.value
+
+    def set_profiling(self, on: bool):
+        _check(self._lib.apf_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        """{class: (ms, launches)} summed since profiling was enabled."""
+        return {c: (self.query("ms_" + c), int(self.query("launches_" + c))) for c in PROFILE_CLASSES}
 
     def front(self, f: int):
         info = (ctypes.c_int32 * 8)()

@@ -11,7 +11,7 @@ ARCH = "gfx950"
 # packed FP32 instructions are disabled on purpose (see the design notes)
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC"]
+HOST_FLAGS = ["-x", "c++", "-O2", "-std=c++17", "-fPIC", "-I/opt/rocm/include"]
 SOURCES = [("kernels.hip", True), ("api.cpp", False), ("analyze.cpp", False)]
 
 

@@ -94,8 +94,64 @@ struct LevelTasks {
       nsw = 0;
 };
 
+// Per-class HIP-event timing of the launches (off unless enabled).
+enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_EXTADD, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
+                 P_CONTRACT, P_WPOW, P_NCLASS };
+const char *const kProfNames[P_NCLASS] = {"stencil", "zero", "assemble", "extend_add", "inverse",
+                                          "gemm_factor", "gemm_schur", "gemm_sweep", "contract", "wpow"};
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> marks;  // (class, index of the start event)
+  double ms[P_NCLASS] = {0};
+  int64_t count[P_NCLASS] = {0};
+  size_t used = 0;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  template <class Fn>
+  void run(int cls, hipStream_t s, Fn &&fn) {
+    if (!on) {
+      HIPCHK(fn());
+      return;
+    }
+    size_t i0 = used;
+    hipEvent_t a = next(), b = next();
+    HIPCHK(hipEventRecord(a, s));
+    HIPCHK(fn());
+    HIPCHK(hipEventRecord(b, s));
+    marks.push_back({cls, (int)i0});
+  }
+  void collect() {
+    for (auto &m : marks) {
+      float t = 0.f;
+      HIPCHK(hipEventSynchronize(pool[m.second + 1]));
+      HIPCHK(hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]));
+      ms[m.first] += t;
+      count[m.first] += 1;
+    }
+    marks.clear();
+    used = 0;
+  }
+  void reset() {
+    for (int k = 0; k < P_NCLASS; ++k) { ms[k] = 0; count[k] = 0; }
+    marks.clear();
+    used = 0;
+  }
+  ~Profiler() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct Plan {
   int device = -1;
+  double gemm_cmacs_factor = 0, gemm_cmacs_schur = 0, gemm_cmacs_sweep = 0;
   cplx *ws = nullptr, *fs = nullptr, *sb = nullptr, *sc = nullptr, *X = nullptr, *V = nullptr, *aval = nullptr;
   char *blob = nullptr;
   int *status = nullptr;
@@ -109,8 +165,11 @@ struct Plan {
   T *at(int64_t off) const { return off < 0 ? nullptr : reinterpret_cast<T *>(blob + off); }
 };
 
+double g_cmacs_acc = 0;   // executed complex MACs of the tasks added (plan building only)
+
 void add_tiles(std::vector<GemmTask> &v, const GemmTask &t) {
   if (t.M <= 0 || t.N <= 0) return;
+  g_cmacs_acc += (double)t.M * t.N * t.K;
   for (int tm = 0; tm < t.M; tm += GEMM_TILE)
     for (int tn = 0; tn < t.N; tn += GEMM_TILE) {
       GemmTask u = t;
@@ -130,6 +189,14 @@ GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, 
   return t;
 }
 
+// Offsets of one front's blocks: workspace (transient) sub-blocks relative
+// to its workspace block `ws`; factor-store offsets encoded as -2 - offset
+// for blocks that live in the persistent store.
+struct Off {
+  int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, x12 = -1, x1b = -1, y21 = -1, xc1t = -1, sk = -1;
+  int64_t wsz = 0;
+};
+
 }  // namespace
 
 struct apf_handle {
@@ -139,6 +206,8 @@ struct apf_handle {
   Phys phys{};
   bool planned = false;
   Plan plan;
+  std::vector<Off> off;
+  Profiler prof;
   int state = 0;  // 0 analysed, 1 assembled, 2 factored
 };
 
@@ -201,11 +270,14 @@ extern "C" apf_status apf_create(const apf_problem_desc *in, apf_handle **out) {
   return APF_OK;
 }
 
+static void size_plan(apf_handle *H);
+
 extern "C" apf_status apf_analyze(apf_handle *h) {
   if (!h) return fail(APF_EINVAL, "null handle");
   if (h->analyzed) return APF_OK;
   try {
     analyze(h->d, h->sym);
+    size_plan(h);
   } catch (const std::bad_alloc &) {
     return fail(APF_ENOMEM, "host allocation failed in analysis");
   } catch (const std::exception &e) {
@@ -218,18 +290,17 @@ extern "C" apf_status apf_analyze(apf_handle *h) {
 // ---------------------------------------------------------------------------
 // device plan
 // ---------------------------------------------------------------------------
-static void build_plan(apf_handle *H) {
+// Memory plan (host only): workspace offsets from a lifetime-interval
+// allocation over the levels, persistent factor offsets, store sizes.
+static void size_plan(apf_handle *H) {
   Symbolic &S = H->sym;
   const Desc &d = H->d;
   Plan &P = H->plan;
   const int nf = (int)S.fronts.size();
   const int H_ = (int)S.levels.size() - 1;
   const int Mi = d.n_in, Mo = d.n_out;
-  HIPCHK(hipGetDevice(&P.device));
-
-  // ---- sizes and offsets ----------------------------------------------------
-  struct Off { int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, x12 = -1, x1b = -1, y21 = -1, xc1t = -1, sk = -1; int64_t wsz = 0; };
-  std::vector<Off> o(nf);
+  std::vector<Off> &o = H->off;
+  o.assign(nf, Off());
   Arena ar;
   std::vector<std::vector<int>> release_at(H_ + 2);
   int64_t fs = 0, ktot = 0;
@@ -266,7 +337,20 @@ static void build_plan(apf_handle *H) {
   P.ws_elems = std::max<int64_t>(ar.top, 1);
   P.fs_elems = std::max<int64_t>(fs, 1);
   S.k_total = ktot;
+}
 
+static void build_plan(apf_handle *H) {
+  Symbolic &S = H->sym;
+  const Desc &d = H->d;
+  Plan &P = H->plan;
+  const int nf = (int)S.fronts.size();
+  const int H_ = (int)S.levels.size() - 1;
+  const int Mi = d.n_in, Mo = d.n_out;
+  HIPCHK(hipGetDevice(&P.device));
+  size_plan(H);
+
+  const std::vector<Off> &o = H->off;
+  const int64_t ktot = S.k_total;
   HIPCHK(hipMalloc(&P.ws, P.ws_elems * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.fs, P.fs_elems * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.sb, std::max<int64_t>(ktot * Mi, 1) * sizeof(cplx)));
@@ -394,6 +478,7 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), sw(H_ + 1);
   std::vector<GemmTask> gS, vinit;
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
+  double cm_factor = 0, cm_sweep = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
     const FrontDev &D = fd[f];
@@ -432,6 +517,7 @@ static void build_plan(apf_handle *H) {
     // factorization GEMMs; the pivot block holds G = F11^-1 after k_inverse
     cplx *core = D.core;
     cplx *F12 = core + p, *F21 = core + (int64_t)p * n, *F22 = core + (int64_t)p * n + p;
+    g_cmacs_acc = 0;
     if (b) add_tiles(g1[lvl], gemm(core, n, F12, n, X12(f), b, p, b, p, 0));                 // X12 = G F12
     if (F.sweep && b) add_tiles(g1[lvl], gemm(F21, n, core, n, FSx(o[f].y21), p, b, p, p, 0));  // Y21 = F21 G
     if (mB) add_tiles(g1[lvl], gemm(core, n, D.bp_piv, mB, X1B(f), mB, p, mB, p, 0));       // X1B = G F1B
@@ -440,6 +526,8 @@ static void build_plan(apf_handle *H) {
     if (b && mB) add_tiles(g2[lvl], gemm(F21, n, X1B(f), mB, D.bp_bnd, mB, b, mB, p, G_NEG | G_CIN, D.bp_bnd, mB));  // F2B -= F21 X1B
     if (b && mC) add_tiles(g2[lvl], gemm(X12(f), b, D.cpt_piv, mC, D.cpt_bnd, mC, b, mC, p, G_TRANS_A | G_NEG | G_CIN, D.cpt_bnd, mC));  // FC2^T -= X12^T FC1^T
 
+    cm_factor += g_cmacs_acc;
+    g_cmacs_acc = 0;
     // gradient sweeps (root to leaves): Y_f = X1B_f - X12 Y_bnd ; Lam_f = XC1T_f G - Y21^T Lam_bnd
     if (F.sweep) {
       const int ch = P.rhs_chunk;
@@ -453,9 +541,14 @@ static void build_plan(apf_handle *H) {
       add_tiles(sw[lvl], tv);
       if (mC) add_tiles(vinit, gemm(FSx(o[f].xc1t), mC, nullptr, Mi, Vf, ch, p, ch, mC, G_B_EXT | G_B_COFF));
     }
+    cm_sweep += g_cmacs_acc * ((double)Mi / P.rhs_chunk);
   }
+  P.gemm_cmacs_factor = cm_factor;
+  P.gemm_cmacs_sweep = cm_sweep;
   // S = sum over fronts holding both channel blocks of FC1 X1B = SC^T SB
+  g_cmacs_acc = 0;
   add_tiles(gS, gemm(P.sc, Mo, P.sb, Mi, nullptr, Mi, Mo, Mi, (int)ktot, G_TRANS_A | G_C_EXT));
+  P.gemm_cmacs_schur = g_cmacs_acc;
 
   // ---- assemble the blob ------------------------------------------------------
   Blob &bl = ib;  // continue after the integer arrays
@@ -527,7 +620,9 @@ extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *s
         throw;
       }
     }
-    HIPCHK(launch_stencil(h->phys, eps_dev, h->plan.aval, s));
+    Profiler &pr = h->prof;
+    pr.run(P_STENCIL, s, [&] { return launch_stencil(h->phys, eps_dev, h->plan.aval, s); });
+    if (pr.on) pr.collect();
     h->state = 1;
     return APF_OK;
   });
@@ -542,22 +637,34 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
     Plan &P = h->plan;
     const FrontDev *fr = P.at<FrontDev>(P.fronts);
     HIPCHK(hipMemsetAsync(P.status, 0, sizeof(int), s));
+    Profiler &pr = h->prof;
     for (size_t lvl = 0; lvl < P.lv.size(); ++lvl) {
       const LevelTasks &L = P.lv[lvl];
-      HIPCHK(launch_zero(P.at<ZeroRange>(L.zero), L.nzero, s));
-      HIPCHK(launch_scatter_A(P.at<AsmEntry>(L.scat), L.nscat, P.aval, s));
-      HIPCHK(launch_assemble_panel(P.at<PanelEntry>(L.pB), L.npB, h->phys, P.at<int32_t>(P.in_orders), h->d.n_in, 1, s));
-      HIPCHK(launch_assemble_panel(P.at<PanelEntry>(L.pC), L.npC, h->phys, P.at<int32_t>(P.out_orders), h->d.n_out, 0, s));
-      HIPCHK(launch_extend_add(fr, P.at<int32_t>(L.ext[0]), L.next[0], L.maxb[0], s));
-      HIPCHK(launch_extend_add(fr, P.at<int32_t>(L.ext[1]), L.next[1], L.maxb[1], s));
-      HIPCHK(launch_inverse(fr, P.at<int32_t>(L.inv), L.ninv, P.status, s));
-      HIPCHK(launch_gemm(P.at<GemmTask>(L.g1), L.ng1, 0, INT_MAX, nullptr, s));
-      HIPCHK(launch_gemm(P.at<GemmTask>(L.g2), L.ng2, 0, INT_MAX, nullptr, s));
+      pr.run(P_ZERO, s, [&] { return launch_zero(P.at<ZeroRange>(L.zero), L.nzero, s); });
+      pr.run(P_ASSEMBLE, s, [&] {
+        hipError_t e = launch_scatter_A(P.at<AsmEntry>(L.scat), L.nscat, P.aval, s);
+        if (e == hipSuccess)
+          e = launch_assemble_panel(P.at<PanelEntry>(L.pB), L.npB, h->phys, P.at<int32_t>(P.in_orders), h->d.n_in, 1, s);
+        if (e == hipSuccess)
+          e = launch_assemble_panel(P.at<PanelEntry>(L.pC), L.npC, h->phys, P.at<int32_t>(P.out_orders), h->d.n_out, 0, s);
+        return e;
+      });
+      pr.run(P_EXTADD, s, [&] {
+        hipError_t e = launch_extend_add(fr, P.at<int32_t>(L.ext[0]), L.next[0], L.maxb[0], s);
+        if (e == hipSuccess) e = launch_extend_add(fr, P.at<int32_t>(L.ext[1]), L.next[1], L.maxb[1], s);
+        return e;
+      });
+      pr.run(P_INVERSE, s, [&] { return launch_inverse(fr, P.at<int32_t>(L.inv), L.ninv, P.status, s); });
+      pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm(P.at<GemmTask>(L.g1), L.ng1, 0, INT_MAX, nullptr, s); });
+      pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm(P.at<GemmTask>(L.g2), L.ng2, 0, INT_MAX, nullptr, s); });
     }
-    HIPCHK(launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s));
+    pr.run(P_GEMM_SCHUR, s, [&] {
+      return launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s);
+    });
     int st = 0;
     HIPCHK(hipMemcpyAsync(&st, P.status, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (pr.on) pr.collect();
     if (st) {
       h->state = 0;
       return fail(APF_ESINGULAR, "zero pivot in a pivot block");
@@ -574,8 +681,13 @@ extern "C" apf_status apf_weighted_power(apf_handle *h, const double *S_dev, con
   return guarded([&]() -> apf_status {
     int64_t n = (int64_t)h->d.n_in * h->d.n_out;
     int npart = (int)std::min<int64_t>(1024, (n + 255) / 256);
-    HIPCHK(launch_weighted_power(reinterpret_cast<const cplx *>(S_dev), w_dev, f_dev,
-                                 reinterpret_cast<cplx *>(dfdS_dev), n, h->plan.part, npart, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    Profiler &pr = h->prof;
+    pr.run(P_WPOW, s, [&] {
+      return launch_weighted_power(reinterpret_cast<const cplx *>(S_dev), w_dev, f_dev,
+                                   reinterpret_cast<cplx *>(dfdS_dev), n, h->plan.part, npart, s);
+    });
+    if (pr.on) pr.collect();
     return APF_OK;
   });
 }
@@ -591,13 +703,26 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     const double two_h2 = 2.0 * h->phys.h2;
     for (int m0 = 0, c = 0; m0 < Mi; m0 += ch, ++c) {
       const int w = std::min(ch, Mi - m0);
-      HIPCHK(launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s));
+      Profiler &pr = h->prof;
+      pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s); });
       for (int lvl = (int)P.lv.size() - 1; lvl >= 0; --lvl) {
         const LevelTasks &L = P.lv[lvl];
-        HIPCHK(launch_gemm(P.at<GemmTask>(L.sw), L.nsw, m0, w, nullptr, s));
+        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(L.sw), L.nsw, m0, w, nullptr, s); });
       }
-      HIPCHK(launch_contract(P.at<int32_t>(P.drows), P.ndesign, P.X, P.V, ch, w, two_h2, grad_dev, c > 0, s));
+      pr.run(P_CONTRACT, s, [&] {
+        return launch_contract(P.at<int32_t>(P.drows), P.ndesign, P.X, P.V, ch, w, two_h2, grad_dev, c > 0, s);
+      });
     }
+    if (h->prof.on) h->prof.collect();
+    return APF_OK;
+  });
+}
+
+extern "C" apf_status apf_set_profiling(apf_handle *h, int32_t on) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  return guarded([&]() -> apf_status {
+    h->prof.reset();
+    h->prof.on = on != 0;
     return APF_OK;
   });
 }
@@ -628,10 +753,22 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
     for (const Front &F : S.fronts) c += F.sweep;
     *value = c;
   } else if (k == "k_total") *value = (double)S.k_total;
-  else if (k == "ws_bytes") *value = h->planned ? (double)h->plan.ws_elems * sizeof(cplx) : -1.0;
-  else if (k == "factor_bytes") *value = h->planned ? (double)h->plan.fs_elems * sizeof(cplx) : -1.0;
+  else if (k == "ws_bytes") *value = (double)h->plan.ws_elems * sizeof(cplx);
+  else if (k == "factor_bytes") *value = (double)h->plan.fs_elems * sizeof(cplx);
+  else if (k == "schur_store_bytes") *value = (double)S.k_total * (h->d.n_in + h->d.n_out) * sizeof(cplx);
   else if (k == "rhs_chunk") *value = h->planned ? (double)h->plan.rhs_chunk : -1.0;
-  else return fail(APF_EINVAL, "unknown key " + k);
+  else if (k == "gemm_cmacs_factor") *value = h->planned ? h->plan.gemm_cmacs_factor : -1.0;
+  else if (k == "gemm_cmacs_schur") *value = h->planned ? h->plan.gemm_cmacs_schur : -1.0;
+  else if (k == "gemm_cmacs_sweep") *value = h->planned ? h->plan.gemm_cmacs_sweep : -1.0;
+  else if (k.rfind("ms_", 0) == 0 || k.rfind("launches_", 0) == 0) {
+    bool ms = k[0] == 'm';
+    std::string cls = k.substr(ms ? 3 : 9);
+    int c = -1;
+    for (int i = 0; i < P_NCLASS; ++i)
+      if (cls == kProfNames[i]) c = i;
+    if (c < 0) return fail(APF_EINVAL, "unknown profile class " + cls);
+    *value = ms ? h->prof.ms[c] : (double)h->prof.count[c];
+  } else return fail(APF_EINVAL, "unknown key " + k);
   return APF_OK;
 }
 
