@@ -89,10 +89,16 @@ struct Blob {
 };
 
 struct LevelTasks {
-  int64_t zero = -1, scat = -1, pB = -1, pC = -1, ext[2] = {-1, -1}, inv = -1, g1 = -1, g2 = -1, sw = -1;
-  int nzero = 0, nscat = 0, npB = 0, npC = 0, next[2] = {0, 0}, maxb[2] = {0, 0}, ninv = 0, ng1 = 0, ng2 = 0,
-      nsw = 0;
+  int64_t zero = -1, scat = -1, pB = -1, pC = -1, ext[2] = {-1, -1}, extrow[2] = {-1, -1}, g1 = -1, g2 = -1, sw = -1;
+  int nzero = 0, nscat = 0, npB = 0, npC = 0, next[2] = {0, 0}, nextrow[2] = {0, 0}, ng1 = 0, ng2 = 0, nsw = 0;
+  int64_t inv[N_INV_VARIANTS];
+  int ninv[N_INV_VARIANTS];
+  LevelTasks() {
+    for (int v = 0; v < N_INV_VARIANTS; ++v) { inv[v] = -1; ninv[v] = 0; }
+  }
 };
+
+constexpr int64_t ZERO_CHUNK = 8192;   // complex elements per zeroing block
 
 // Per-class HIP-event timing of the launches (off unless enabled).
 enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_EXTADD, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
@@ -405,20 +411,26 @@ static void build_plan(apf_handle *H) {
   P.in_orders = ib.add(d.in_orders);
   P.out_orders = ib.add(d.out_orders);
   P.lv.assign(H_ + 1, LevelTasks());
-  std::vector<int64_t> kid_off[2], inv_off;
   for (int lvl = 0; lvl <= H_; ++lvl) {
-    std::vector<int32_t> k0, k1, inv;
-    int mb0 = 0, mb1 = 0;
+    std::vector<int32_t> kids[2], inv[N_INV_VARIANTS];
+    std::vector<int2> rows[2];
     for (int f : S.levels[lvl]) {
       const Front &F = S.fronts[f];
-      if (F.nchild > 0) { k0.push_back(F.child[0]); mb0 = std::max(mb0, S.fronts[F.child[0]].b()); }
-      if (F.nchild > 1) { k1.push_back(F.child[1]); mb1 = std::max(mb1, S.fronts[F.child[1]].b()); }
-      if (F.p() > 0) inv.push_back(f);
+      for (int c = 0; c < F.nchild; ++c) {
+        const Front &Ch = S.fronts[F.child[c]];
+        if (Ch.b() == 0) continue;
+        kids[c].push_back(F.child[c]);
+        if (Ch.hasB || Ch.hasC)
+          for (int r = 0; r < Ch.b(); ++r) rows[c].push_back(make_int2(F.child[c], r));
+      }
+      if (F.p() > 0) inv[inverse_variant(F.p())].push_back(f);
     }
     LevelTasks &L = P.lv[lvl];
-    L.ext[0] = ib.add(k0); L.next[0] = (int)k0.size(); L.maxb[0] = mb0;
-    L.ext[1] = ib.add(k1); L.next[1] = (int)k1.size(); L.maxb[1] = mb1;
-    L.inv = ib.add(inv); L.ninv = (int)inv.size();
+    for (int c = 0; c < 2; ++c) {
+      L.ext[c] = ib.add(kids[c]); L.next[c] = (int)kids[c].size();
+      L.extrow[c] = ib.add(rows[c]); L.nextrow[c] = (int)rows[c].size();
+    }
+    for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = ib.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
   }
   const int64_t ib_size = (int64_t)ib.h.size();
 
@@ -484,11 +496,14 @@ static void build_plan(apf_handle *H) {
     const FrontDev &D = fd[f];
     const int lvl = F.height;
     const int p = F.p(), b = F.b(), n = p + b, mB = D.mB, mC = D.mC;
-    zr[lvl].push_back({D.core, (int64_t)n * n});
-    if (mB) zr[lvl].push_back({D.bp_piv, (int64_t)n * mB});
+    auto zero = [&](cplx *ptr, int64_t cnt) {
+      for (int64_t o0 = 0; o0 < cnt; o0 += ZERO_CHUNK) zr[lvl].push_back({ptr + o0, std::min(ZERO_CHUNK, cnt - o0)});
+    };
+    zero(D.core, (int64_t)n * n);
+    if (mB) zero(D.bp_piv, (int64_t)n * mB);
     if (mC) {
-      zr[lvl].push_back({D.cpt_piv, (int64_t)p * mC});
-      if (b) zr[lvl].push_back({D.cpt_bnd, (int64_t)b * mC});
+      zero(D.cpt_piv, (int64_t)p * mC);
+      if (b) zero(D.cpt_bnd, (int64_t)b * mC);
     }
     // stencil entries owned by this front (the earlier-eliminated end of each edge)
     for (int k = 0; k < p; ++k) loc[F.piv[k]] = k;
@@ -650,11 +665,17 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
         return e;
       });
       pr.run(P_EXTADD, s, [&] {
-        hipError_t e = launch_extend_add(fr, P.at<int32_t>(L.ext[0]), L.next[0], L.maxb[0], s);
-        if (e == hipSuccess) e = launch_extend_add(fr, P.at<int32_t>(L.ext[1]), L.next[1], L.maxb[1], s);
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < 2 && e == hipSuccess; ++c)
+          e = launch_extend_add(fr, P.at<int32_t>(L.ext[c]), L.next[c], P.at<int2>(L.extrow[c]), L.nextrow[c], s);
         return e;
       });
-      pr.run(P_INVERSE, s, [&] { return launch_inverse(fr, P.at<int32_t>(L.inv), L.ninv, P.status, s); });
+      pr.run(P_INVERSE, s, [&] {
+        hipError_t e = hipSuccess;
+        for (int v = 0; v < N_INV_VARIANTS && e == hipSuccess; ++v)
+          e = launch_inverse(v, fr, P.at<int32_t>(L.inv[v]), L.ninv[v], P.status, s);
+        return e;
+      });
       pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm(P.at<GemmTask>(L.g1), L.ng1, 0, INT_MAX, nullptr, s); });
       pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm(P.at<GemmTask>(L.g2), L.ng2, 0, INT_MAX, nullptr, s); });
     }

@@ -21,8 +21,11 @@ hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStrea
 hipError_t launch_scatter_A(const AsmEntry *e, int n, const cplx *Aval, hipStream_t s);
 hipError_t launch_assemble_panel(const PanelEntry *e, int n, const Phys &P, const int32_t *orders, int m,
                                  int is_source, hipStream_t s);
-hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, int maxb, hipStream_t s);
-hipError_t launch_inverse(const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
+hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, const int2 *rows, int nrows,
+                             hipStream_t s);
+constexpr int N_INV_VARIANTS = 8;
+int inverse_variant(int p);   // kernel variant of a pivot block of size p
+hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s);
 hipError_t launch_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
                            double two_h2, double *grad, int accumulate, hipStream_t s);

@@ -24,19 +24,23 @@ __device__ __forceinline__ double2 cinv(double2 a) {
   double d = ar * ar + ai * ai;
   return make_double2(ar / (d * s), -ai / (d * s));
 }
+// by-value select: a conditional over lvalues would take the operands'
+// addresses and push register arrays into scratch
+__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b) {
+  return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
 __device__ __forceinline__ double2 ld2(const cplx *p) { return *reinterpret_cast<const double2 *>(p); }
 __device__ __forceinline__ void st2(cplx *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
 
 // ---------------------------------------------------------------------------
 // Zero the frontal workspaces of one level.
 // ---------------------------------------------------------------------------
+// One block per range; the host splits ranges into chunks of at most
+// ZERO_CHUNK elements so that blocks are evenly loaded.
 __global__ void k_zero(const ZeroRange *r, int n) {
-  for (int k = blockIdx.y; k < n; k += gridDim.y) {
-    const ZeroRange z = r[k];
-    double2 *p = reinterpret_cast<double2 *>(z.ptr);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < z.n; i += (int64_t)gridDim.x * blockDim.x)
-      p[i] = make_double2(0.0, 0.0);
-  }
+  const ZeroRange z = r[blockIdx.x];
+  double2 *p = reinterpret_cast<double2 *>(z.ptr);
+  for (int64_t i = threadIdx.x; i < z.n; i += blockDim.x) p[i] = make_double2(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -114,23 +118,31 @@ __global__ void k_assemble_panel(const PanelEntry *e, int n, Phys P, const int32
 }
 
 // ---------------------------------------------------------------------------
-// Extend-add: scatter-add one child's contribution block (core, B rows,
-// C^T rows) into its parent.  grid = (children, boundary rows of the child).
+// Extend-add: scatter-add one child's contribution block into its parent.
+// k_extadd_core: one block per child, the b x b core block.
+// k_extadd_panel: one block per (child, boundary row) of a child that carries
+// channel panels: its B row and C^T row.
+// Children of one parent are processed in separate launches (slots), so no
+// two blocks of a launch write the same parent entry.
 // ---------------------------------------------------------------------------
-__global__ void k_extend_add(const FrontDev *fr, const int32_t *kids, int nkids) {
-  const int c = kids[blockIdx.x];
-  const FrontDev C = fr[c];
-  const int r = blockIdx.y;
-  if (r >= C.b) return;
+__global__ void k_extadd_core(const FrontDev *fr, const int32_t *kids) {
+  const FrontDev C = fr[kids[blockIdx.x]];
   const FrontDev P = fr[C.parent];
-  const int nc = C.p + C.b, np = P.p + P.b;
-  const int pr = C.rmap[r];
-  const cplx *src = C.core + (int64_t)(C.p + r) * nc + C.p;
-  cplx *dst = P.core + (int64_t)pr * np;
-  for (int s = threadIdx.x; s < C.b; s += blockDim.x) {
-    cplx *d = dst + C.rmap[s];
-    st2(d, cadd(ld2(d), ld2(src + s)));
+  const int nc = C.p + C.b, np = P.p + P.b, b = C.b;
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    const int r = e / b, c = e - r * b;
+    const cplx *src = C.core + (int64_t)(C.p + r) * nc + C.p + c;
+    cplx *d = P.core + (int64_t)C.rmap[r] * np + C.rmap[c];
+    st2(d, cadd(ld2(d), ld2(src)));
   }
+}
+
+__global__ void k_extadd_panel(const FrontDev *fr, const int2 *tasks) {
+  const int2 t = tasks[blockIdx.x];
+  const FrontDev C = fr[t.x];
+  const FrontDev P = fr[C.parent];
+  const int r = t.y;
+  const int pr = C.rmap[r];
   if (C.mB) {
     const cplx *sb = C.bp_bnd + (int64_t)r * C.mB;
     cplx *db = pr < P.p ? P.bp_piv + (int64_t)pr * P.mB : P.bp_bnd + (int64_t)(pr - P.p) * P.mB;
@@ -145,11 +157,9 @@ __global__ void k_extend_add(const FrontDev *fr, const int32_t *kids, int nkids)
 
 // ---------------------------------------------------------------------------
 // Pivot-block inverse G = F11^-1, in place, by Gauss-Jordan elimination with
-// partial (row) pivoting.  One workgroup per front.  Small blocks are staged
-// in LDS; larger ones are updated in global memory (L2 resident).
+// partial (row) pivoting.  One workgroup per front.
 // ---------------------------------------------------------------------------
 constexpr int INV_THREADS = 256;
-constexpr int INV_LDS_MAXP = 64;
 constexpr int INV_MAXP = 1024;
 
 __device__ void gauss_jordan(cplx *a, int lda, int p, double2 *rowbuf, double2 *colbuf, int *perm,
@@ -220,29 +230,144 @@ __device__ void gauss_jordan(cplx *a, int lda, int p, double2 *rowbuf, double2 *
   }
 }
 
-__global__ __launch_bounds__(INV_THREADS) void k_inverse(const FrontDev *fr, const int32_t *ids, int *status) {
+// Register-blocked Gauss-Jordan for p <= min(TR*RR, TC*RC): a TR x TC thread
+// grid; thread (ti, tj) keeps entries (ti + TR*ra, tj + TC*ca) in registers.
+// Pivoting is implicit: step k takes the largest not-yet-used row r of
+// column k as its pivot row and no rows move; with pi(k) = r the array ends
+// holding B^-1 for B = rows of F in pivot order, stored at row pi(k), so
+// F^-1[i][m] = array[pi(i)][pi^-1(m)].  Each step is one uniform complex
+// FMA per owned entry (after zeroing the pivot row and column in place) and
+// two barriers.
+template <int TR, int TC, int RR, int RC>
+__global__ __launch_bounds__(TR *TC) void k_inverse_reg(const FrontDev *fr, const int32_t *ids, int *status) {
+  constexpr int MAXP = TR * RR;
+  static_assert(TR * RR == TC * RC, "square coverage");
+  static_assert(TR <= 64 && (64 % TR) == 0, "a pivot-column group must sit inside one wave");
   const FrontDev F = fr[ids[blockIdx.x]];
   const int p = F.p, n = F.p + F.b;
+  const int tid = threadIdx.x, ti = tid % TR, tj = tid / TR;
+  __shared__ double2 rowbuf[MAXP], colbuf[MAXP];
+  __shared__ int used[MAXP], piv_row[MAXP], piv_step[MAXP];
+  __shared__ int s_r, s_bad;
+  for (int t = tid; t < MAXP; t += TR * TC) used[t] = 0;
+  if (tid == 0) s_bad = 0;
+  double2 a[RR][RC];
+#pragma unroll
+  for (int ra = 0; ra < RR; ++ra)
+#pragma unroll
+    for (int ca = 0; ca < RC; ++ca) {
+      const int i = ti + TR * ra, j = tj + TC * ca;
+      a[ra][ca] = (i < p && j < p) ? ld2(F.core + (int64_t)i * n + j) : make_double2(0.0, 0.0);
+    }
+  __syncthreads();
+  for (int k = 0; k < p; ++k) {
+    const int kc = k % TC, kq = k / TC;
+    // pivot search in column k among unused rows: the TR threads of column
+    // group kc are consecutive lanes of one wave
+    if (tj == kc) {
+      double bv = -1.0;
+      int bi = p;
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca) {
+        if (ca == kq) {
+#pragma unroll
+          for (int ra = 0; ra < RR; ++ra) {
+            const int i = ti + TR * ra;
+            const double2 v = a[ra][ca];
+            const double m = v.x * v.x + v.y * v.y;
+            if (i < p && !used[i] && (m > bv || (m == bv && i < bi))) { bv = m; bi = i; }
+          }
+        }
+      }
+#pragma unroll
+      for (int off = TR / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, TR);
+        const int oi = __shfl_xor(bi, off, TR);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (ti == 0) {
+        if (!(bv > 0.0)) s_bad = 1;
+        s_r = bi;
+        used[bi] = 1;
+        piv_row[k] = bi;
+        piv_step[bi] = k;
+      }
+    }
+    __syncthreads();
+    const int r = s_r, rr = r % TR, rq = r / TR;
+    // publish the pivot row and the pivot column, then clear them in place
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra) {
+      if (ra == rq && ti == rr) {
+#pragma unroll
+        for (int ca = 0; ca < RC; ++ca) {
+          const int j = tj + TC * ca;
+          if (j < p) rowbuf[j] = a[ra][ca];
+          a[ra][ca] = make_double2(0.0, 0.0);
+        }
+      }
+    }
+    if (tj == kc) {
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca) {
+        if (ca == kq) {
+#pragma unroll
+          for (int ra = 0; ra < RR; ++ra) {
+            const int i = ti + TR * ra;
+            if (i < p && i != r) colbuf[i] = a[ra][ca];
+            a[ra][ca] = make_double2(0.0, 0.0);
+          }
+        }
+      }
+    }
+    if (tid == 0) colbuf[r] = make_double2(-1.0, 0.0);
+    __syncthreads();
+    // a[i][j] -= m_i * srow_j with srow_j = row_r[j] / piv (j != k), 1/piv (j == k)
+    // and m_r = -1: row r becomes srow, column k becomes -m_i / piv
+    const double2 inv = cinv(rowbuf[k]);
+    double2 srow[RC], m[RR];
+#pragma unroll
+    for (int ca = 0; ca < RC; ++ca) {
+      const int j = tj + TC * ca;
+      srow[ca] = j < p ? cmul(rowbuf[j], inv) : make_double2(0.0, 0.0);
+      if (j == k) srow[ca] = inv;
+    }
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra) {
+      const int i = ti + TR * ra;
+      m[ra] = i < p ? colbuf[i] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra)
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca) {
+        double2 v = a[ra][ca];
+        v.x -= m[ra].x * srow[ca].x - m[ra].y * srow[ca].y;
+        v.y -= m[ra].x * srow[ca].y + m[ra].y * srow[ca].x;
+        a[ra][ca] = v;
+      }
+  }
+  __syncthreads();
+  if (tid == 0 && s_bad) atomicOr(status, 1);
+  // F^-1[piv_step[x]][piv_row[y]] = array[x][y]
+#pragma unroll
+  for (int ra = 0; ra < RR; ++ra)
+#pragma unroll
+    for (int ca = 0; ca < RC; ++ca) {
+      const int x = ti + TR * ra, y = tj + TC * ca;
+      if (x < p && y < p) st2(F.core + (int64_t)piv_step[x] * n + piv_row[y], a[ra][ca]);
+    }
+}
+
+// Fallback for pivot blocks larger than the register-blocked variants cover:
+// the same elimination on the block in global memory (L2 resident).
+__global__ __launch_bounds__(INV_THREADS) void k_inverse(const FrontDev *fr, const int32_t *ids, int *status) {
+  const FrontDev F = fr[ids[blockIdx.x]];
   __shared__ double2 rowbuf[INV_MAXP], colbuf[INV_MAXP];
   __shared__ int perm[INV_MAXP];
   __shared__ double redv[INV_THREADS];
   __shared__ int redi[INV_THREADS];
-  __shared__ double2 tile[INV_LDS_MAXP * INV_LDS_MAXP];
-  if (p <= INV_LDS_MAXP) {
-    for (int e = threadIdx.x; e < p * p; e += INV_THREADS) {
-      int i = e / p, j = e - i * p;
-      tile[e] = ld2(F.core + (int64_t)i * n + j);
-    }
-    __syncthreads();
-    gauss_jordan(reinterpret_cast<cplx *>(tile), p, p, rowbuf, colbuf, perm, redv, redi, status);
-    __syncthreads();
-    for (int e = threadIdx.x; e < p * p; e += INV_THREADS) {
-      int i = e / p, j = e - i * p;
-      st2(F.core + (int64_t)i * n + j, tile[e]);
-    }
-  } else {
-    gauss_jordan(F.core, n, p, rowbuf, colbuf, perm, redv, redi, status);
-  }
+  gauss_jordan(F.core, F.p + F.b, F.p, rowbuf, colbuf, perm, redv, redi, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,7 +539,7 @@ __global__ void k_wpow_final(const double *part, int n, double *f) {
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero, dim3(16, n < 32768 ? n : 32768), dim3(256), 0, s, r, n);
+  hipLaunchKernelGGL(k_zero, dim3(n), dim3(256), 0, s, r, n);
   return hipGetLastError();
 }
 hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStream_t s) {
@@ -433,14 +558,42 @@ hipError_t launch_assemble_panel(const PanelEntry *e, int n, const Phys &P, cons
   hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n, P, orders, m, is_source);
   return hipGetLastError();
 }
-hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, int maxb, hipStream_t s) {
-  if (nkids == 0 || maxb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_extend_add, dim3(nkids, maxb), dim3(256), 0, s, fr, kids, nkids);
-  return hipGetLastError();
+hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, const int2 *rows, int nrows,
+                             hipStream_t s) {
+  if (nkids > 0) {
+    hipLaunchKernelGGL(k_extadd_core, dim3(nkids), dim3(256), 0, s, fr, kids);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (nrows > 0) {
+    hipLaunchKernelGGL(k_extadd_panel, dim3(nrows), dim3(256), 0, s, fr, rows);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
-hipError_t launch_inverse(const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s) {
+int inverse_variant(int p) {
+  if (p <= 16) return 0;
+  if (p <= 32) return 1;
+  if (p <= 48) return 2;
+  if (p <= 64) return 3;
+  if (p <= 96) return 4;
+  if (p <= 128) return 5;
+  if (p <= 160) return 6;
+  return 7;
+}
+
+hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_inverse, dim3(n), dim3(INV_THREADS), 0, s, fr, ids, status);
+  switch (variant) {
+    case 0: hipLaunchKernelGGL((k_inverse_reg<16, 16, 1, 1>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 1: hipLaunchKernelGGL((k_inverse_reg<16, 16, 2, 2>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 2: hipLaunchKernelGGL((k_inverse_reg<16, 16, 3, 3>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 3: hipLaunchKernelGGL((k_inverse_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 4: hipLaunchKernelGGL((k_inverse_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
+    case 5: hipLaunchKernelGGL((k_inverse_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
+    case 6: hipLaunchKernelGGL((k_inverse_reg<32, 16, 5, 10>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
+    default: hipLaunchKernelGGL(k_inverse, dim3(n), dim3(INV_THREADS), 0, s, fr, ids, status); break;
+  }
   return hipGetLastError();
 }
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s) {

@@ -44,12 +44,16 @@ CASES = [
     dict(nx=3, ny=60, leaf=0, seed=2),         # narrowest periodic grid
     dict(nx=64, ny=92, leaf=64, seed=3),
     dict(nx=130, ny=60, leaf=128, seed=4),     # channel panels wider than one 64-wide tile
+    dict(nx=40, ny=140, leaf=128, seed=8),     # pivot blocks up to 140 (register-blocked inverse)
+    dict(nx=48, ny=160, leaf=96, seed=9),      # pivot blocks of 160, the largest register variant
+    dict(nx=12, ny=200, leaf=0, seed=10, layout=(20, 60, 40, 60, 20)),   # 200-row separators: fallback inverse
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c['nx']}x{c['ny']}-leaf{c['leaf']}")
 def test_S_and_grad_match_oracle_small(case):
-    prob, eps, w = inputs.tiny_problem(nx=case["nx"], ny=case["ny"], seed=case["seed"])
+    prob, eps, w = inputs.tiny_problem(nx=case["nx"], ny=case["ny"], seed=case["seed"],
+                                       layout=case.get("layout"))
     _, S, f, G, g = _run_gpu(prob, eps, w, case["leaf"])
     S_o, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
     assert _rel(S, S_o) < TOL
