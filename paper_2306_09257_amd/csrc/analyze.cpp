@@ -8,6 +8,7 @@
 // channel rows when it holds projection-row nodes; the channel-by-channel
 // block is never pivoted and is summed straight into S.
 #include <algorithm>
+#include <cstdlib>
 #include <stdexcept>
 #include <unordered_map>
 
@@ -21,7 +22,22 @@ struct Builder {
   const Desc &d;
   Symbolic &s;
   int leaf;
-  Builder(const Desc &d_, Symbolic &s_) : d(d_), s(s_), leaf(d_.leaf_size > 0 ? d_.leaf_size : 64) {}
+  std::vector<int> prefer;   // rows between the source row, the design band and the projection row
+  Builder(const Desc &d_, Symbolic &s_) : d(d_), s(s_), leaf(d_.leaf_size > 0 ? d_.leaf_size : 64) {
+    prefer.push_back((d.src_row + d.design_row0) / 2);
+    prefer.push_back((d.design_row1 - 1 + d.prj_row + 1) / 2);
+  }
+
+  // Row of a horizontal separator of [y0, y1): a row that splits the source
+  // row, the design band and the projection row from each other when one
+  // lies in the middle half of the range, else the middle row.
+  int row_cut(int y0, int y1) const {
+    const int hh = y1 - y0, mid = y0 + hh / 2;
+    int best = -1;
+    for (int r : prefer)
+      if (r >= y0 + hh / 4 && r < y1 - hh / 4 && (best < 0 || std::abs(r - mid) < std::abs(best - mid))) best = r;
+    return best >= 0 ? best : mid;
+  }
 
   int node(int x, int y) const { return y * d.nx + x; }
 
@@ -43,7 +59,7 @@ struct Builder {
       c[1] = region(xs + 1, x1, y0, y1);
       for (int y = y0; y < y1; ++y) f.piv.push_back(node(xs, y));
     } else {
-      int ys = y0 + hh / 2;
+      int ys = row_cut(y0, y1);
       c[0] = region(x0, x1, y0, ys);
       c[1] = region(x0, x1, ys + 1, y1);
       for (int x = x0; x < x1; ++x) f.piv.push_back(node(x, ys));

@@ -73,6 +73,8 @@ struct FrontDev {
   cplx *bp_piv, *bp_bnd;   // B-panel rows: p x mB and b x mB (ld mB)
   cplx *cpt_piv, *cpt_bnd; // C-panel transposed rows: p x mC and b x mC (ld mC)
   const int32_t *rmap;     // b entries: boundary -> parent-local index
+  cplx *tri;               // p x p: strict lower = L^-1 (unit diagonal implied), upper = U^-1
+  int32_t *perm;           // p entries: perm[k] = pivot-local row of elimination step k
   int32_t parent;
   int32_t pad2;
 };
@@ -95,6 +97,12 @@ enum GemmFlags : int32_t {
   G_CIN_COFF = 16,         // add the launch's column offset to Cin
   G_B_EXT = 32,            // B is the launch's external pointer (caller buffer)
   G_C_EXT = 64,            // C is the launch's external pointer (caller buffer)
+  // triangular operands stored packed in one square array (masks apply to the
+  // stored indices (r, c); zero blocks of K are skipped):
+  G_A_TRI_L = 128,         // stored A: r > c entries, unit diagonal, zero above
+  G_A_TRI_U = 256,         // stored A: r <= c entries, zero below
+  G_B_TRI_L = 512,         // stored B: r > c entries, unit diagonal, zero above
+  G_B_TRI_U = 1024,        // stored B: r <= c entries, zero below
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
@@ -103,6 +111,7 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
   const cplx *Cin;
   cplx *C;
   const int32_t *browmap;  // if set, row k of B is B + browmap[k]*ldb
+  const int32_t *crowmap;  // if set, row i of C (and of Cin) is C + crowmap[i]*ldc
   int32_t M, N, K;
   int32_t lda, ldb, ldcin, ldc;
   int32_t flags;

@@ -159,6 +159,7 @@ struct Plan {
   int device = -1;
   double gemm_cmacs_factor = 0, gemm_cmacs_schur = 0, gemm_cmacs_sweep = 0;
   cplx *ws = nullptr, *fs = nullptr, *sb = nullptr, *sc = nullptr, *X = nullptr, *V = nullptr, *aval = nullptr;
+  int32_t *perms = nullptr;   // pivot permutation of every front, at its first elimination index
   char *blob = nullptr;
   int *status = nullptr;
   double *part = nullptr;
@@ -173,14 +174,27 @@ struct Plan {
 
 double g_cmacs_acc = 0;   // executed complex MACs of the tasks added (plan building only)
 
+// Complex MACs one tile issues, over the k range that can hold nonzeros
+// (the same range the kernel visits for triangular operands).
+double tile_cmacs(const GemmTask &t, int tm, int tn) {
+  const bool tr = t.flags & G_TRANS_A;
+  int kbeg = 0, kend = t.K;
+  if (t.flags & G_A_TRI_L) { if (tr) kbeg = tm; else kend = std::min(kend, tm + GEMM_TILE); }
+  if (t.flags & G_A_TRI_U) { if (tr) kend = std::min(kend, tm + GEMM_TILE); else kbeg = tm; }
+  if (t.flags & G_B_TRI_L) kbeg = std::max(kbeg, tn);
+  if (t.flags & G_B_TRI_U) kend = std::min(kend, tn + GEMM_TILE);
+  const int mm = std::min(GEMM_TILE, t.M - tm), nn = std::min(GEMM_TILE, t.N - tn);
+  return (double)mm * nn * std::max(0, kend - kbeg);
+}
+
 void add_tiles(std::vector<GemmTask> &v, const GemmTask &t) {
   if (t.M <= 0 || t.N <= 0) return;
-  g_cmacs_acc += (double)t.M * t.N * t.K;
   for (int tm = 0; tm < t.M; tm += GEMM_TILE)
     for (int tn = 0; tn < t.N; tn += GEMM_TILE) {
       GemmTask u = t;
       u.tm = tm;
       u.tn = tn;
+      g_cmacs_acc += tile_cmacs(t, tm, tn);
       v.push_back(u);
     }
 }
@@ -188,7 +202,7 @@ void add_tiles(std::vector<GemmTask> &v, const GemmTask &t) {
 GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, int M, int N, int K, int flags,
               const cplx *Cin = nullptr, int ldcin = 0, const int32_t *browmap = nullptr) {
   GemmTask t{};
-  t.A = A; t.B = B; t.C = C; t.Cin = Cin; t.browmap = browmap;
+  t.A = A; t.B = B; t.C = C; t.Cin = Cin; t.browmap = browmap; t.crowmap = nullptr;
   t.M = M; t.N = N; t.K = K;
   t.lda = lda; t.ldb = ldb; t.ldc = ldc; t.ldcin = ldcin;
   t.flags = flags;
@@ -198,8 +212,13 @@ GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, 
 // Offsets of one front's blocks: workspace (transient) sub-blocks relative
 // to its workspace block `ws`; factor-store offsets encoded as -2 - offset
 // for blocks that live in the persistent store.
+// Offsets of one front's blocks.  Workspace (transient) sub-blocks are
+// relative to the front's workspace block `ws`; fs_* are offsets in the
+// persistent factor store (-1 if absent); sk is the front's first row in the
+// Schur operand stores (fronts holding both channel blocks).
 struct Off {
-  int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, x12 = -1, x1b = -1, y21 = -1, xc1t = -1, sk = -1;
+  int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, tri = -1, u12 = -1, l21 = -1, u1b = -1, lc1t = -1;
+  int64_t fs_x12 = -1, fs_z = -1, fs_x1b = -1, fs_xc1 = -1, sk = -1;
   int64_t wsz = 0;
 };
 
@@ -316,17 +335,22 @@ static void size_plan(apf_handle *H) {
     Off &q = o[f];
     int64_t w = 0;
     q.core = w; w += up(n * n);
-    if (mB) { q.bp = w; w += up(n * mB); }
-    if (mC && !F.sfront) { q.cpiv = w; w += up(p * mC); }
-    if (mC) { q.cbnd = w; w += up(b * mC); }
-    if (!F.sweep) { q.x12 = w; w += up(p * b); }
-    if (mB && !F.sweep && !F.sfront) { q.x1b = w; w += up(p * mB); }
+    q.tri = w; w += up(p * p);
+    if (b) { q.u12 = w; w += up(p * b); q.l21 = w; w += up(b * p); }
+    if (mB) {
+      q.bp = w; w += up(n * mB);
+      if (!F.sfront) { q.u1b = w; w += up(p * mB); }
+    }
+    if (mC) {
+      q.cpiv = w; w += up(p * mC);
+      q.cbnd = w; w += up(b * mC);
+      if (!F.sfront) { q.lc1t = w; w += up(p * mC); }
+    }
     q.wsz = w;
     if (F.sweep) {
-      q.x12 = -2 - fs; fs += up(p * b);   // negative: persistent store (decoded below)
-      q.y21 = fs; fs += up(b * p);
-      if (mB && !F.sfront) { q.x1b = -2 - fs; fs += up(p * mB); }
-      if (mC) { q.xc1t = fs; fs += up(p * mC); }
+      if (b) { q.fs_x12 = fs; fs += up(p * b); q.fs_z = fs; fs += up(b * p); }
+      if (mB) { q.fs_x1b = fs; fs += up(p * mB); }
+      if (mC) { q.fs_xc1 = fs; fs += up(p * mC); }
     }
     if (F.sfront) { q.sk = ktot; ktot += p; }
   }
@@ -362,6 +386,7 @@ static void build_plan(apf_handle *H) {
   HIPCHK(hipMalloc(&P.sb, std::max<int64_t>(ktot * Mi, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.sc, std::max<int64_t>(ktot * Mo, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.aval, (int64_t)d.nx * d.ny * 5 * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.perms, (int64_t)d.nx * d.ny * sizeof(int32_t)));
   HIPCHK(hipMalloc(&P.status, sizeof(int)));
   HIPCHK(hipMalloc(&P.part, 1024 * sizeof(double)));
   HIPCHK(hipMemset(P.status, 0, sizeof(int)));
@@ -463,25 +488,23 @@ static void build_plan(apf_handle *H) {
     D.core = WS(q.ws + q.core);
     D.bp_piv = D.mB ? WS(q.ws + q.bp) : nullptr;
     D.bp_bnd = D.mB ? WS(q.ws + q.bp) + p * D.mB : nullptr;
-    if (D.mC) {
-      D.cpt_piv = F.sfront ? P.sc + q.sk * Mo : WS(q.ws + q.cpiv);
-      D.cpt_bnd = WS(q.ws + q.cbnd);
-    } else {
-      D.cpt_piv = D.cpt_bnd = nullptr;
-    }
+    D.cpt_piv = D.mC ? WS(q.ws + q.cpiv) : nullptr;
+    D.cpt_bnd = D.mC ? WS(q.ws + q.cbnd) : nullptr;
+    D.tri = WS(q.ws + q.tri);
+    D.perm = P.perms + F.elim0;
     D.rmap = reinterpret_cast<const int32_t *>((intptr_t)rmap_off[f]);  // offset; rebased below
     D.parent = F.parent;
     (void)n;
   }
-  auto X12 = [&](int f) -> cplx * {
+  // L^-1 P^T F1B and U^-T FC1^T of fronts holding both channel blocks live in
+  // the Schur operand stores
+  auto U1B = [&](int f) -> cplx * {
     const Off &q = o[f];
-    return q.x12 <= -2 ? FSx(-2 - q.x12) : WS(q.ws + q.x12);
+    return S.fronts[f].sfront ? P.sb + q.sk * Mi : WS(q.ws + q.u1b);
   };
-  auto X1B = [&](int f) -> cplx * {
-    const Front &F = S.fronts[f];
+  auto LC1T = [&](int f) -> cplx * {
     const Off &q = o[f];
-    if (F.sfront) return P.sb + q.sk * Mi;
-    return q.x1b <= -2 ? FSx(-2 - q.x1b) : WS(q.ws + q.x1b);
+    return S.fronts[f].sfront ? P.sc + q.sk * Mo : WS(q.ws + q.lc1t);
   };
 
   std::vector<std::vector<ZeroRange>> zr(H_ + 1);
@@ -529,38 +552,60 @@ static void build_plan(apf_handle *H) {
     for (int k = 0; k < p; ++k) loc[F.piv[k]] = -1;
     for (int k = 0; k < b; ++k) loc[F.bnd[k]] = -1;
 
-    // factorization GEMMs; the pivot block holds G = F11^-1 after k_inverse
-    cplx *core = D.core;
+    // Factorization GEMMs.  After the pivot-block kernel, tri holds L^-1
+    // (strict lower, unit diagonal) and U^-1 (upper) and perm the pivot rows:
+    //   phase 1: U12 = L^-1 P^T F12, U1B = L^-1 P^T F1B, L21 = F21 U^-1, LC1T = U^-T FC1^T
+    //   phase 2: F22 -= L21 U12, F2B -= L21 U1B, FC2^T -= U12^T LC1T and, for the
+    //            fronts the gradient sweeps visit, X12 = U^-1 U12, X1B = U^-1 U1B,
+    //            Z = L21 L^-1, XC1 = L^-T LC1T.
+    const Off &q = o[f];
+    cplx *core = D.core, *tri = D.tri;
     cplx *F12 = core + p, *F21 = core + (int64_t)p * n, *F22 = core + (int64_t)p * n + p;
+    cplx *u12 = b ? WS(q.ws + q.u12) : nullptr, *l21 = b ? WS(q.ws + q.l21) : nullptr;
+    cplx *u1b = mB ? U1B(f) : nullptr, *lc1t = mC ? LC1T(f) : nullptr;
+    const int32_t *perm = D.perm;
     g_cmacs_acc = 0;
-    if (b) add_tiles(g1[lvl], gemm(core, n, F12, n, X12(f), b, p, b, p, 0));                 // X12 = G F12
-    if (F.sweep && b) add_tiles(g1[lvl], gemm(F21, n, core, n, FSx(o[f].y21), p, b, p, p, 0));  // Y21 = F21 G
-    if (mB) add_tiles(g1[lvl], gemm(core, n, D.bp_piv, mB, X1B(f), mB, p, mB, p, 0));       // X1B = G F1B
-    if (mC && F.sweep) add_tiles(g1[lvl], gemm(core, n, D.cpt_piv, mC, FSx(o[f].xc1t), mC, p, mC, p, G_TRANS_A));  // XC1T = G^T FC1^T
-    if (b) add_tiles(g2[lvl], gemm(F21, n, X12(f), b, F22, n, b, b, p, G_NEG | G_CIN, F22, n));          // F22 -= F21 X12
-    if (b && mB) add_tiles(g2[lvl], gemm(F21, n, X1B(f), mB, D.bp_bnd, mB, b, mB, p, G_NEG | G_CIN, D.bp_bnd, mB));  // F2B -= F21 X1B
-    if (b && mC) add_tiles(g2[lvl], gemm(X12(f), b, D.cpt_piv, mC, D.cpt_bnd, mC, b, mC, p, G_TRANS_A | G_NEG | G_CIN, D.cpt_bnd, mC));  // FC2^T -= X12^T FC1^T
-
+    if (b) add_tiles(g1[lvl], gemm(tri, p, F12, n, u12, b, p, b, p, G_A_TRI_L, nullptr, 0, perm));
+    if (mB) add_tiles(g1[lvl], gemm(tri, p, D.bp_piv, mB, u1b, mB, p, mB, p, G_A_TRI_L, nullptr, 0, perm));
+    if (b) add_tiles(g1[lvl], gemm(F21, n, tri, p, l21, p, b, p, p, G_B_TRI_U));
+    if (mC) add_tiles(g1[lvl], gemm(tri, p, D.cpt_piv, mC, lc1t, mC, p, mC, p, G_TRANS_A | G_A_TRI_U));
+    if (b) add_tiles(g2[lvl], gemm(l21, p, u12, b, F22, n, b, b, p, G_NEG | G_CIN, F22, n));
+    if (b && mB) add_tiles(g2[lvl], gemm(l21, p, u1b, mB, D.bp_bnd, mB, b, mB, p, G_NEG | G_CIN, D.bp_bnd, mB));
+    if (b && mC) add_tiles(g2[lvl], gemm(u12, b, lc1t, mC, D.cpt_bnd, mC, b, mC, p, G_TRANS_A | G_NEG | G_CIN, D.cpt_bnd, mC));
+    if (F.sweep) {
+      if (b) add_tiles(g2[lvl], gemm(tri, p, u12, b, FSx(q.fs_x12), b, p, b, p, G_A_TRI_U));
+      if (mB) add_tiles(g2[lvl], gemm(tri, p, u1b, mB, FSx(q.fs_x1b), mB, p, mB, p, G_A_TRI_U));
+      if (b) add_tiles(g2[lvl], gemm(l21, p, tri, p, FSx(q.fs_z), p, b, p, p, G_B_TRI_L));
+      if (mC) add_tiles(g2[lvl], gemm(tri, p, lc1t, mC, FSx(q.fs_xc1), mC, p, mC, p, G_TRANS_A | G_A_TRI_L));
+    }
     cm_factor += g_cmacs_acc;
     g_cmacs_acc = 0;
-    // gradient sweeps (root to leaves): Y_f = X1B_f - X12 Y_bnd ; Lam_f = XC1T_f G - Y21^T Lam_bnd
+    // gradient sweeps (root to leaves), with F11^-1 = U^-1 L^-1 P^T:
+    //   Y_f   = X1B_f - X12 Y_bnd
+    //   Lam_f = P (XC1 G - Z^T Lam_bnd)      (rows scattered through perm)
     if (F.sweep) {
       const int ch = P.rhs_chunk;
       cplx *Xf = P.X + (int64_t)D.sweep_row0 * ch, *Vf = P.V + (int64_t)D.sweep_row0 * ch;
       const int32_t *bm = reinterpret_cast<const int32_t *>((intptr_t)bndrow_off[f]);  // rebased below
-      GemmTask ty = gemm(X12(f), b, P.X, ch, Xf, ch, p, ch, b, G_NEG | (mB ? G_CIN | G_CIN_COFF : 0),
-                         mB ? X1B(f) : nullptr, mB, b ? bm : nullptr);
-      GemmTask tv = gemm(FSx(o[f].y21), p, P.V, ch, Vf, ch, p, ch, b, G_TRANS_A | G_NEG | (mC ? G_CIN : 0),
-                         mC ? Vf : nullptr, ch, b ? bm : nullptr);
+      GemmTask ty = gemm(b ? FSx(q.fs_x12) : nullptr, b, P.X, ch, Xf, ch, p, ch, b,
+                         G_NEG | (mB ? G_CIN | G_CIN_COFF : 0), mB ? FSx(q.fs_x1b) : nullptr, mB, b ? bm : nullptr);
+      GemmTask tv = gemm(b ? FSx(q.fs_z) : nullptr, p, P.V, ch, Vf, ch, p, ch, b,
+                         G_TRANS_A | G_NEG | (mC ? G_CIN : 0), mC ? Vf : nullptr, ch, b ? bm : nullptr);
+      tv.crowmap = perm;
       add_tiles(sw[lvl], ty);
       add_tiles(sw[lvl], tv);
-      if (mC) add_tiles(vinit, gemm(FSx(o[f].xc1t), mC, nullptr, Mi, Vf, ch, p, ch, mC, G_B_EXT | G_B_COFF));
+      if (mC) {
+        GemmTask ti = gemm(FSx(q.fs_xc1), mC, nullptr, Mi, Vf, ch, p, ch, mC, G_B_EXT | G_B_COFF);
+        ti.crowmap = perm;
+        add_tiles(vinit, ti);
+      }
     }
     cm_sweep += g_cmacs_acc * ((double)Mi / P.rhs_chunk);
   }
   P.gemm_cmacs_factor = cm_factor;
   P.gemm_cmacs_sweep = cm_sweep;
-  // S = sum over fronts holding both channel blocks of FC1 X1B = SC^T SB
+  // S = sum over fronts holding both channel blocks of FC1 F11^-1 F1B
+  //   = (U^-T FC1^T)^T (L^-1 P^T F1B) = SC^T SB
   g_cmacs_acc = 0;
   add_tiles(gS, gemm(P.sc, Mo, P.sb, Mi, nullptr, Mi, Mo, Mi, (int)ktot, G_TRANS_A | G_C_EXT));
   P.gemm_cmacs_schur = g_cmacs_acc;
@@ -603,7 +648,7 @@ static void build_plan(apf_handle *H) {
 }
 
 static void free_plan(Plan &P) {
-  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part};
+  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   P = Plan();

@@ -156,90 +156,31 @@ __global__ void k_extadd_panel(const FrontDev *fr, const int2 *tasks) {
 }
 
 // ---------------------------------------------------------------------------
-// Pivot-block inverse G = F11^-1, in place, by Gauss-Jordan elimination with
-// partial (row) pivoting.  One workgroup per front.
+// Pivot-block factorization: F11 = P L U with partial (row) pivoting, then the
+// explicit inverses of the unit lower factor L and the upper factor U.  Output
+// `tri` (p x p, rows in elimination-step order): strict lower part = L^-1
+// (unit diagonal implied), upper part = U^-1; `perm[k]` = the row of F11 that
+// step k pivoted on, so F11^-1 = U^-1 L^-1 P^T with (P^T X)[k] = X[perm[k]].
+// The products of the factorization apply the two inverses in sequence;
+// forming F11^-1 itself is avoided (it loses accuracy on nearly singular
+// pivot blocks, which the Helmholtz operator produces when an eliminated
+// subdomain is close to resonance).
+//
+// Phase A (LU): step k takes the largest not-yet-used row r of column k;
+// rows do not move: every unused row x gets l_x = a[x][k]/a[r][k] stored in
+// column k and a[x][j] -= l_x a[r][j] for j > k.
+// Phase B (inverses): in-place Gauss-Jordan on L (unit, step order) and on U
+// at once; step k updates the L triangle (i > k, j < k) with column k of L
+// and row k of L, and the U triangle (i < k, j > k) with column k of U and
+// row k of U scaled by 1/u_kk; the two touch disjoint entries.
 // ---------------------------------------------------------------------------
 constexpr int INV_THREADS = 256;
 constexpr int INV_MAXP = 1024;
 
-__device__ void gauss_jordan(cplx *a, int lda, int p, double2 *rowbuf, double2 *colbuf, int *perm,
-                             double *redv, int *redi, int *status) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < p; ++k) {
-    double bv = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < p; i += INV_THREADS) {
-      double2 v = ld2(a + (int64_t)i * lda + k);
-      double m = v.x * v.x + v.y * v.y;
-      if (m > bv) { bv = m; bi = i; }
-    }
-    redv[tid] = bv;
-    redi[tid] = bi;
-    __syncthreads();
-    for (int s = INV_THREADS / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        double ov = redv[tid + s];
-        int oi = redi[tid + s];
-        if (ov > redv[tid] || (ov == redv[tid] && oi < redi[tid])) { redv[tid] = ov; redi[tid] = oi; }
-      }
-      __syncthreads();
-    }
-    const int r = redi[0];
-    const bool zero = !(redv[0] > 0.0);
-    if (tid == 0) {
-      perm[k] = r;
-      if (zero) atomicOr(status, 1);
-    }
-    __syncthreads();
-    if (r != k) {
-      for (int j = tid; j < p; j += INV_THREADS) {
-        double2 x = ld2(a + (int64_t)k * lda + j), y = ld2(a + (int64_t)r * lda + j);
-        st2(a + (int64_t)k * lda + j, y);
-        st2(a + (int64_t)r * lda + j, x);
-      }
-    }
-    __syncthreads();
-    const double2 inv = cinv(ld2(a + (int64_t)k * lda + k));
-    for (int j = tid; j < p; j += INV_THREADS) {
-      double2 v = (j == k) ? inv : cmul(ld2(a + (int64_t)k * lda + j), inv);
-      rowbuf[j] = v;
-    }
-    for (int i = tid; i < p; i += INV_THREADS)
-      colbuf[i] = (i == k) ? make_double2(0.0, 0.0) : ld2(a + (int64_t)i * lda + k);
-    __syncthreads();
-    for (int j = tid; j < p; j += INV_THREADS) st2(a + (int64_t)k * lda + j, rowbuf[j]);
-    for (int e = tid; e < p * p; e += INV_THREADS) {
-      int i = e / p, j = e - i * p;
-      if (i == k) continue;
-      double2 old = (j == k) ? make_double2(0.0, 0.0) : ld2(a + (int64_t)i * lda + j);
-      st2(a + (int64_t)i * lda + j, csub(old, cmul(colbuf[i], rowbuf[j])));
-    }
-    __syncthreads();
-  }
-  // (P F)^-1 = F^-1 P^-1: undo the row interchanges as column interchanges
-  for (int k = p - 1; k >= 0; --k) {
-    int r = perm[k];
-    if (r != k) {
-      for (int i = tid; i < p; i += INV_THREADS) {
-        double2 x = ld2(a + (int64_t)i * lda + k), y = ld2(a + (int64_t)i * lda + r);
-        st2(a + (int64_t)i * lda + k, y);
-        st2(a + (int64_t)i * lda + r, x);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Register-blocked Gauss-Jordan for p <= min(TR*RR, TC*RC): a TR x TC thread
-// grid; thread (ti, tj) keeps entries (ti + TR*ra, tj + TC*ca) in registers.
-// Pivoting is implicit: step k takes the largest not-yet-used row r of
-// column k as its pivot row and no rows move; with pi(k) = r the array ends
-// holding B^-1 for B = rows of F in pivot order, stored at row pi(k), so
-// F^-1[i][m] = array[pi(i)][pi^-1(m)].  Each step is one uniform complex
-// FMA per owned entry (after zeroing the pivot row and column in place) and
-// two barriers.
+// Register-blocked variant for p <= TR*RR = TC*RC: thread (ti, tj) of a
+// TR x TC grid keeps entries (ti + TR*ra, tj + TC*ca) in registers.
 template <int TR, int TC, int RR, int RC>
-__global__ __launch_bounds__(TR *TC) void k_inverse_reg(const FrontDev *fr, const int32_t *ids, int *status) {
+__global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const int32_t *ids, int *status) {
   constexpr int MAXP = TR * RR;
   static_assert(TR * RR == TC * RC, "square coverage");
   static_assert(TR <= 64 && (64 % TR) == 0, "a pivot-column group must sit inside one wave");
@@ -260,10 +201,9 @@ __global__ __launch_bounds__(TR *TC) void k_inverse_reg(const FrontDev *fr, cons
       a[ra][ca] = (i < p && j < p) ? ld2(F.core + (int64_t)i * n + j) : make_double2(0.0, 0.0);
     }
   __syncthreads();
+  // ---- phase A: LU with implicit row pivoting
   for (int k = 0; k < p; ++k) {
     const int kc = k % TC, kq = k / TC;
-    // pivot search in column k among unused rows: the TR threads of column
-    // group kc are consecutive lanes of one wave
     if (tj == kc) {
       double bv = -1.0;
       int bi = p;
@@ -295,7 +235,14 @@ __global__ __launch_bounds__(TR *TC) void k_inverse_reg(const FrontDev *fr, cons
     }
     __syncthreads();
     const int r = s_r, rr = r % TR, rq = r / TR;
-    // publish the pivot row and the pivot column, then clear them in place
+    // the unused-row flags are read before the second barrier: the next
+    // step's pivot group may set its flag as soon as every thread passed it
+    bool un[RR];
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra) {
+      const int i = ti + TR * ra;
+      un[ra] = i < p && !used[i];
+    }
 #pragma unroll
     for (int ra = 0; ra < RR; ++ra) {
       if (ra == rq && ti == rr) {
@@ -303,7 +250,6 @@ __global__ __launch_bounds__(TR *TC) void k_inverse_reg(const FrontDev *fr, cons
         for (int ca = 0; ca < RC; ++ca) {
           const int j = tj + TC * ca;
           if (j < p) rowbuf[j] = a[ra][ca];
-          a[ra][ca] = make_double2(0.0, 0.0);
         }
       }
     }
@@ -314,60 +260,240 @@ __global__ __launch_bounds__(TR *TC) void k_inverse_reg(const FrontDev *fr, cons
 #pragma unroll
           for (int ra = 0; ra < RR; ++ra) {
             const int i = ti + TR * ra;
-            if (i < p && i != r) colbuf[i] = a[ra][ca];
-            a[ra][ca] = make_double2(0.0, 0.0);
+            if (i < p) colbuf[i] = a[ra][ca];
           }
         }
       }
     }
-    if (tid == 0) colbuf[r] = make_double2(-1.0, 0.0);
     __syncthreads();
-    // a[i][j] -= m_i * srow_j with srow_j = row_r[j] / piv (j != k), 1/piv (j == k)
-    // and m_r = -1: row r becomes srow, column k becomes -m_i / piv
     const double2 inv = cinv(rowbuf[k]);
-    double2 srow[RC], m[RR];
-#pragma unroll
-    for (int ca = 0; ca < RC; ++ca) {
-      const int j = tj + TC * ca;
-      srow[ca] = j < p ? cmul(rowbuf[j], inv) : make_double2(0.0, 0.0);
-      if (j == k) srow[ca] = inv;
-    }
+    double2 l[RR], u[RC];
 #pragma unroll
     for (int ra = 0; ra < RR; ++ra) {
       const int i = ti + TR * ra;
-      m[ra] = i < p ? colbuf[i] : make_double2(0.0, 0.0);
+      l[ra] = un[ra] ? cmul(colbuf[i], inv) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int ca = 0; ca < RC; ++ca) {
+      const int j = tj + TC * ca;
+      u[ca] = (j > k && j < p) ? rowbuf[j] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int ra = 0; ra < RR; ++ra)
 #pragma unroll
       for (int ca = 0; ca < RC; ++ca) {
         double2 v = a[ra][ca];
-        v.x -= m[ra].x * srow[ca].x - m[ra].y * srow[ca].y;
-        v.y -= m[ra].x * srow[ca].y + m[ra].y * srow[ca].x;
+        v.x -= l[ra].x * u[ca].x - l[ra].y * u[ca].y;
+        v.y -= l[ra].x * u[ca].y + l[ra].y * u[ca].x;
         a[ra][ca] = v;
       }
+    if (tj == kc) {
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca)
+        if (ca == kq) {
+#pragma unroll
+          for (int ra = 0; ra < RR; ++ra)
+            if (un[ra]) a[ra][ca] = l[ra];
+        }
+    }
   }
   __syncthreads();
+  // ---- phase B: in-place inverses of L and U, in step order
+  int st[RR];
+#pragma unroll
+  for (int ra = 0; ra < RR; ++ra) {
+    const int i = ti + TR * ra;
+    st[ra] = i < p ? piv_step[i] : INV_MAXP;
+  }
+  for (int k = 0; k < p; ++k) {
+    const int kc = k % TC, kq = k / TC;
+    const int r = piv_row[k], rr = r % TR, rq = r / TR;
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra) {
+      if (ra == rq && ti == rr) {
+#pragma unroll
+        for (int ca = 0; ca < RC; ++ca) {
+          const int j = tj + TC * ca;
+          if (j < p) rowbuf[j] = a[ra][ca];
+        }
+      }
+    }
+    if (tj == kc) {
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca) {
+        if (ca == kq) {
+#pragma unroll
+          for (int ra = 0; ra < RR; ++ra) {
+            const int i = ti + TR * ra;
+            if (i < p) colbuf[i] = a[ra][ca];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const double2 inv = cinv(rowbuf[k]);
+    // entry (i, j) takes c_i * s_j when i > k > j (L triangle, s_j = row_k[j])
+    // or i < k < j (U triangle, s_j = row_k[j] / u_kk): the row side and
+    // the column side must agree
+    double2 m[RR], sv[RC];
+    int rs[RR], cs[RC];
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra) {
+      const int i = ti + TR * ra;
+      m[ra] = i < p ? colbuf[i] : make_double2(0.0, 0.0);
+      rs[ra] = (st[ra] > k && st[ra] < INV_MAXP) ? 1 : (st[ra] < k ? 2 : 0);
+    }
+#pragma unroll
+    for (int ca = 0; ca < RC; ++ca) {
+      const int j = tj + TC * ca;
+      const double2 rj = j < p ? rowbuf[j] : make_double2(0.0, 0.0);
+      sv[ca] = j < k ? rj : cmul(rj, inv);
+      cs[ca] = j < k ? 1 : ((j > k && j < p) ? 2 : 0);
+    }
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra)
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca) {
+        const bool on = rs[ra] != 0 && rs[ra] == cs[ca];
+        double2 v = a[ra][ca];
+        const double px = m[ra].x * sv[ca].x - m[ra].y * sv[ca].y;
+        const double py = m[ra].x * sv[ca].y + m[ra].y * sv[ca].x;
+        v.x -= on ? px : 0.0;
+        v.y -= on ? py : 0.0;
+        a[ra][ca] = v;
+      }
+    // row k: scale its U part; column k: negate (L) or negate and scale (U)
+#pragma unroll
+    for (int ra = 0; ra < RR; ++ra) {
+      if (ra == rq && ti == rr) {
+#pragma unroll
+        for (int ca = 0; ca < RC; ++ca) {
+          const int j = tj + TC * ca;
+          if (j > k && j < p) a[ra][ca] = sv[ca];
+        }
+      }
+    }
+    if (tj == kc) {
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca)
+        if (ca == kq) {
+#pragma unroll
+          for (int ra = 0; ra < RR; ++ra) {
+            const int i = ti + TR * ra;
+            if (i < p) {
+              const double2 c = colbuf[i];
+              if (st[ra] > k) a[ra][ca] = make_double2(-c.x, -c.y);
+              else if (st[ra] < k) a[ra][ca] = make_double2(-(c.x * inv.x - c.y * inv.y), -(c.x * inv.y + c.y * inv.x));
+              else a[ra][ca] = inv;
+            }
+          }
+        }
+    }
+    __syncthreads();
+  }
   if (tid == 0 && s_bad) atomicOr(status, 1);
-  // F^-1[piv_step[x]][piv_row[y]] = array[x][y]
+  for (int k = tid; k < p; k += TR * TC) F.perm[k] = piv_row[k];
 #pragma unroll
   for (int ra = 0; ra < RR; ++ra)
 #pragma unroll
     for (int ca = 0; ca < RC; ++ca) {
       const int x = ti + TR * ra, y = tj + TC * ca;
-      if (x < p && y < p) st2(F.core + (int64_t)piv_step[x] * n + piv_row[y], a[ra][ca]);
+      if (x < p && y < p) st2(F.tri + (int64_t)st[ra] * p + y, a[ra][ca]);
     }
 }
 
-// Fallback for pivot blocks larger than the register-blocked variants cover:
-// the same elimination on the block in global memory (L2 resident).
-__global__ __launch_bounds__(INV_THREADS) void k_inverse(const FrontDev *fr, const int32_t *ids, int *status) {
+// Fallback for pivot blocks larger than the register variants cover: the same
+// two phases on a copy of the block in F.tri (global memory, L2 resident),
+// one workgroup, INV_THREADS threads striding over rows/entries.
+__global__ __launch_bounds__(INV_THREADS) void k_lu_inv_global(const FrontDev *fr, const int32_t *ids, int *status) {
   const FrontDev F = fr[ids[blockIdx.x]];
+  const int p = F.p, n = F.p + F.b, tid = threadIdx.x;
   __shared__ double2 rowbuf[INV_MAXP], colbuf[INV_MAXP];
-  __shared__ int perm[INV_MAXP];
+  __shared__ int used[INV_MAXP], piv_row[INV_MAXP], piv_step[INV_MAXP];
   __shared__ double redv[INV_THREADS];
   __shared__ int redi[INV_THREADS];
-  gauss_jordan(F.core, F.p + F.b, F.p, rowbuf, colbuf, perm, redv, redi, status);
+  cplx *a = F.tri;   // working copy, rows in F11's (natural) order
+  for (int e = tid; e < p * p; e += INV_THREADS) {
+    const int i = e / p, j = e - i * p;
+    st2(a + e, ld2(F.core + (int64_t)i * n + j));
+  }
+  for (int t = tid; t < p; t += INV_THREADS) used[t] = 0;
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < p; ++k) {
+    double bv = -1.0;
+    int bi = p;
+    for (int i = tid; i < p; i += INV_THREADS) {
+      const double2 v = ld2(a + (int64_t)i * p + k);
+      const double m = v.x * v.x + v.y * v.y;
+      if (!used[i] && (m > bv || (m == bv && i < bi))) { bv = m; bi = i; }
+    }
+    redv[tid] = bv;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int s = INV_THREADS / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double ov = redv[tid + s];
+        const int oi = redi[tid + s];
+        if (ov > redv[tid] || (ov == redv[tid] && oi < redi[tid])) { redv[tid] = ov; redi[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int r = redi[0];
+    if (!(redv[0] > 0.0)) bad = true;
+    __syncthreads();
+    if (tid == 0) { used[r] = 1; piv_row[k] = r; piv_step[r] = k; }
+    for (int j = tid; j < p; j += INV_THREADS) rowbuf[j] = ld2(a + (int64_t)r * p + j);
+    for (int i = tid; i < p; i += INV_THREADS) colbuf[i] = ld2(a + (int64_t)i * p + k);
+    __syncthreads();
+    const double2 inv = cinv(rowbuf[k]);
+    for (int e = tid; e < p * p; e += INV_THREADS) {
+      const int i = e / p, j = e - i * p;
+      if (used[i]) continue;
+      const double2 l = cmul(colbuf[i], inv);
+      if (j == k) st2(a + e, l);
+      else if (j > k) st2(a + e, csub(ld2(a + e), cmul(l, rowbuf[j])));
+    }
+    __syncthreads();
+  }
+  // phase B on the natural-order copy, rows addressed through piv_row
+  for (int k = 0; k < p; ++k) {
+    const int r = piv_row[k];
+    for (int j = tid; j < p; j += INV_THREADS) rowbuf[j] = ld2(a + (int64_t)r * p + j);
+    for (int i = tid; i < p; i += INV_THREADS) colbuf[i] = ld2(a + (int64_t)i * p + k);
+    __syncthreads();
+    const double2 inv = cinv(rowbuf[k]);
+    for (int e = tid; e < p * p; e += INV_THREADS) {
+      const int x = e / p, j = e - x * p;
+      const int i = piv_step[x];
+      const double2 c = colbuf[x];
+      if (j == k) {
+        if (i > k) st2(a + e, make_double2(-c.x, -c.y));
+        else if (i < k) st2(a + e, make_double2(-(c.x * inv.x - c.y * inv.y), -(c.x * inv.y + c.y * inv.x)));
+        else st2(a + e, inv);
+      } else if (i == k) {
+        if (j > k) st2(a + e, cmul(rowbuf[j], inv));
+      } else if (i > k && j < k) {
+        st2(a + e, csub(ld2(a + e), cmul(c, rowbuf[j])));
+      } else if (i < k && j > k) {
+        st2(a + e, csub(ld2(a + e), cmul(c, cmul(rowbuf[j], inv))));
+      }
+    }
+    __syncthreads();
+  }
+  // reorder rows into step order: stage through the core's pivot block, which
+  // is no longer needed once the copy is factored
+  for (int e = tid; e < p * p; e += INV_THREADS) {
+    const int x = e / p, j = e - x * p;
+    st2(F.core + (int64_t)piv_step[x] * n + j, ld2(a + e));
+  }
+  __syncthreads();
+  for (int e = tid; e < p * p; e += INV_THREADS) {
+    const int i = e / p, j = e - i * p;
+    st2(a + e, ld2(F.core + (int64_t)i * n + j));
+  }
+  for (int k = tid; k < p; k += INV_THREADS) F.perm[k] = piv_row[k];
+  if (tid == 0 && bad) atomicOr(status, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,6 +503,14 @@ __global__ __launch_bounds__(INV_THREADS) void k_inverse(const FrontDev *fr, con
 // v_mfma_f64_16x16x4 per complex block and k-step of 4).
 // ---------------------------------------------------------------------------
 constexpr int KT = 16;
+
+// Entry of a packed triangular operand at stored position (r, c): the strict
+// lower part with a unit diagonal (lower) or the upper part with its diagonal.
+__device__ __forceinline__ double2 tri_mask(bool lower, int r, int c, bool inside, double2 v) {
+  if (!inside) return make_double2(0.0, 0.0);
+  if (lower) return r > c ? v : (r == c ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0));
+  return r <= c ? v : make_double2(0.0, 0.0);
+}
 
 __global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext) {
   const GemmTask T = tasks[blockIdx.x];
@@ -400,7 +534,17 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, i
     }
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 
-  for (int k0 = 0; k0 < K; k0 += KT) {
+  // k range that can hold nonzeros when an operand is triangular
+  const int fl = T.flags;
+  int kbeg = 0, kend = K;
+  if (fl & G_A_TRI_L) { if (transA) kbeg = T.tm; else kend = min(kend, T.tm + 64); }
+  if (fl & G_A_TRI_U) { if (transA) kend = min(kend, T.tm + 64); else kbeg = T.tm; }
+  if (fl & G_B_TRI_L) kbeg = max(kbeg, T.tn);
+  if (fl & G_B_TRI_U) kend = min(kend, T.tn + 64);
+  kbeg = (kbeg / KT) * KT;
+  const bool triA = fl & (G_A_TRI_L | G_A_TRI_U), triB = fl & (G_B_TRI_L | G_B_TRI_U);
+
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
     double2 ra[4], rb[4];
     if (!transA) {
       const int i = tid >> 2, kq = (tid & 3) * 4;
@@ -408,6 +552,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, i
       for (int q = 0; q < 4; ++q) {
         const int gk = k0 + kq + q;
         ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gi * T.lda + gk) : make_double2(0.0, 0.0);
+        if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gi, gk, gi < M && gk < K, ra[q]);
       }
     } else {
       const int k = tid >> 4, iq = (tid & 15) * 4;
@@ -415,6 +560,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, i
       for (int q = 0; q < 4; ++q) {
         const int gi = T.tm + iq + q;
         ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gk * T.lda + gi) : make_double2(0.0, 0.0);
+        if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gk, gi, gi < M && gk < K, ra[q]);
       }
     }
     {
@@ -425,6 +571,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, i
       for (int q = 0; q < 4; ++q) {
         const int gj = T.tn + jq + q;
         rb[q] = (row && gj < N) ? ld2(row + gj) : make_double2(0.0, 0.0);
+        if (triB) rb[q] = tri_mask(fl & G_B_TRI_L, gk, gj, gk < K && gj < N, rb[q]);
       }
     }
     __syncthreads();
@@ -473,10 +620,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, i
         const int gi = T.tm + wr + 16 * r + (lane >> 4) + 4 * q;
         const int gj = T.tn + wc + 16 * c + (lane & 15);
         if (gi < M && gj < N) {
+          const int64_t oi = T.crowmap ? T.crowmap[gi] : gi;
           double2 v = make_double2(cre[r][c][q], cim[r][c][q]);
           if (neg) v = make_double2(-v.x, -v.y);
-          if (Cin) v = cadd(v, ld2(Cin + (int64_t)gi * T.ldcin + gj));
-          st2(Cp + (int64_t)gi * T.ldc + gj, v);
+          if (Cin) v = cadd(v, ld2(Cin + oi * T.ldcin + gj));
+          st2(Cp + oi * T.ldc + gj, v);
         }
       }
 }
@@ -585,17 +733,18 @@ int inverse_variant(int p) {
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s) {
   if (n == 0) return hipSuccess;
   switch (variant) {
-    case 0: hipLaunchKernelGGL((k_inverse_reg<16, 16, 1, 1>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
-    case 1: hipLaunchKernelGGL((k_inverse_reg<16, 16, 2, 2>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
-    case 2: hipLaunchKernelGGL((k_inverse_reg<16, 16, 3, 3>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
-    case 3: hipLaunchKernelGGL((k_inverse_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
-    case 4: hipLaunchKernelGGL((k_inverse_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
-    case 5: hipLaunchKernelGGL((k_inverse_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
-    case 6: hipLaunchKernelGGL((k_inverse_reg<32, 16, 5, 10>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
-    default: hipLaunchKernelGGL(k_inverse, dim3(n), dim3(INV_THREADS), 0, s, fr, ids, status); break;
+    case 0: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 1, 1>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 1: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 2, 2>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 2: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 3, 3>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 3: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 4: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
+    case 5: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
+    case 6: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 5, 10>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
+    default: hipLaunchKernelGGL(k_lu_inv_global, dim3(n), dim3(INV_THREADS), 0, s, fr, ids, status); break;
   }
   return hipGetLastError();
 }
+
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gemm, dim3(n), dim3(256), 0, s, t, coff, nlim, ext);
