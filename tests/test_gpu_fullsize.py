@@ -1,0 +1,52 @@
+"""Full-size parity: the 24000 x 160 metasurface workload (3.84M unknowns,
+2,399 x 2,399 channels, 960,000 design pixels) in the configuration bench.py
+times, against values the CPU FP64 oracle wrote once
+(tests/golden/make_metasurface_golden.py):
+
+* two full columns of S;
+* the gradient for dF/dS supported on those two input columns, at 2,000
+  seeded pixels and in 2-norm over all 960,000 pixels;
+* a property that holds at any size: passivity of the lossless structure,
+  sum_b |S_ba|^2 <= 1 for every input a (transmitted flux cannot exceed the
+  unit incident flux).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2306_09257_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "metasurface_24000x160_seed1.npz")
+TOL = 1e-10
+
+
+def test_metasurface_24000x160_against_oracle_samples():
+    from paper_2306_09257_amd import binding
+    gold = np.load(GOLDEN, allow_pickle=False)
+    prob, eps, w = inputs.metasurface_wide(seed=1)
+    print(f"[gpu] full size {prob.nx}x{prob.ny}, {prob.n_in} channels", flush=True)
+    apf = binding.APF(prob).analyze()
+    dev = torch.device("cuda:0")
+    apf.assemble(torch.as_tensor(eps, dtype=torch.float64, device=dev))
+    S = apf.factor_schur()
+    cols = gold["cols"]
+    G = torch.zeros((prob.n_out, prob.n_in), dtype=torch.complex128, device=dev)
+    G[:, torch.as_tensor(cols, device=dev)] = torch.as_tensor(gold["G_cols"], device=dev)
+    g = apf.grad(G)
+    torch.cuda.synchronize()
+    S_h = S.cpu().numpy()
+    g_h = g.cpu().numpy()
+    eS = np.linalg.norm(S_h[:, cols] - gold["S_cols"]) / np.linalg.norm(gold["S_cols"])
+    gs = g_h.ravel()[gold["pixels"]]
+    eg = np.linalg.norm(gs - gold["grad"]) / np.linalg.norm(gold["grad"])
+    en = abs(np.linalg.norm(g_h) - float(gold["grad_norm"])) / float(gold["grad_norm"])
+    print(f"[gpu] rel err S columns {eS:.2e}, sampled grad {eg:.2e}, grad norm {en:.2e}", flush=True)
+    assert eS < TOL
+    assert eg < TOL
+    assert en < TOL
+    flux = np.sum(np.abs(S_h) ** 2, axis=0)
+    assert np.all(np.isfinite(S_h)) and flux.max() <= 1.0 + 1e-9
