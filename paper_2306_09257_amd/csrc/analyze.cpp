@@ -18,6 +18,8 @@ namespace apf {
 
 namespace {
 
+constexpr int kMaxPivots = 128;   // largest pivot block of one front
+
 struct Builder {
   const Desc &d;
   Symbolic &s;
@@ -41,35 +43,52 @@ struct Builder {
 
   int node(int x, int y) const { return y * d.nx + x; }
 
+  // Emit a front over `piv` with children c0, c1; separators longer than
+  // kMaxPivots become a chain of fronts (each the parent of the previous), so
+  // that no pivot block exceeds what one workgroup factors in registers.
+  int emit(std::vector<int> &&piv, int c0, int c1, int x0, int x1, int y0, int y1) {
+    const int p = (int)piv.size();
+    const int nchunk = (p + kMaxPivots - 1) / kMaxPivots;
+    const int chunk = (p + nchunk - 1) / nchunk;
+    int prev = -1;
+    for (int j = 0; j < nchunk; ++j) {
+      Front f;
+      f.x0 = x0; f.x1 = x1; f.y0 = y0; f.y1 = y1;
+      f.piv.assign(piv.begin() + j * chunk, piv.begin() + std::min(p, (j + 1) * chunk));
+      int c[2] = {j == 0 ? c0 : prev, j == 0 ? c1 : -1};
+      for (int k = 0; k < 2; ++k)
+        if (c[k] >= 0) f.child[f.nchild++] = c[k];
+      const int id = (int)s.fronts.size();
+      s.fronts.push_back(std::move(f));
+      for (int k = 0; k < s.fronts[id].nchild; ++k) s.fronts[s.fronts[id].child[k]].parent = id;
+      prev = id;
+    }
+    return prev;
+  }
+
   // Nested dissection of the rectangle [x0,x1) x [y0,y1): cut the longer side
   // with one grid line of nodes; the two halves become children.  Children
   // are emitted before their parent, so `fronts` is a postorder.
   int region(int x0, int x1, int y0, int y1) {
     int w = x1 - x0, hh = y1 - y0;
     if (w <= 0 || hh <= 0) return -1;
-    Front f;
-    f.x0 = x0; f.x1 = x1; f.y0 = y0; f.y1 = y1;
+    std::vector<int> piv;
     int c[2] = {-1, -1};
     if ((int64_t)w * hh <= leaf) {
       for (int y = y0; y < y1; ++y)
-        for (int x = x0; x < x1; ++x) f.piv.push_back(node(x, y));
+        for (int x = x0; x < x1; ++x) piv.push_back(node(x, y));
     } else if (w >= hh) {
       int xs = x0 + w / 2;
       c[0] = region(x0, xs, y0, y1);
       c[1] = region(xs + 1, x1, y0, y1);
-      for (int y = y0; y < y1; ++y) f.piv.push_back(node(xs, y));
+      for (int y = y0; y < y1; ++y) piv.push_back(node(xs, y));
     } else {
       int ys = row_cut(y0, y1);
       c[0] = region(x0, x1, y0, ys);
       c[1] = region(x0, x1, ys + 1, y1);
-      for (int x = x0; x < x1; ++x) f.piv.push_back(node(x, ys));
+      for (int x = x0; x < x1; ++x) piv.push_back(node(x, ys));
     }
-    int id = (int)s.fronts.size();
-    for (int k = 0; k < 2; ++k)
-      if (c[k] >= 0) { f.child[f.nchild++] = c[k]; }
-    s.fronts.push_back(std::move(f));
-    for (int k = 0; k < s.fronts[id].nchild; ++k) s.fronts[s.fronts[id].child[k]].parent = id;
-    return id;
+    return emit(std::move(piv), c[0], c[1], x0, x1, y0, y1);
   }
 };
 
@@ -87,13 +106,9 @@ void analyze(const Desc &d, Symbolic &s) {
   // The periodic ring is opened by the root separator: grid column x = 0.
   int child = bld.region(1, nx, 0, ny);
   {
-    Front root;
-    root.x0 = 0; root.x1 = nx; root.y0 = 0; root.y1 = ny;
-    for (int y = 0; y < ny; ++y) root.piv.push_back(bld.node(0, y));
-    if (child >= 0) root.child[root.nchild++] = child;
-    int id = (int)s.fronts.size();
-    s.fronts.push_back(std::move(root));
-    if (child >= 0) s.fronts[child].parent = id;
+    std::vector<int> piv;
+    for (int y = 0; y < ny; ++y) piv.push_back(bld.node(0, y));
+    bld.emit(std::move(piv), child, -1, 0, nx, 0, ny);
   }
   const int nf = (int)s.fronts.size();
 
@@ -115,34 +130,35 @@ void analyze(const Desc &d, Symbolic &s) {
   }
   if (e != N) throw std::runtime_error("nested dissection does not cover the grid");
 
-  // Boundary sets: grid neighbours of the subtree's region that lie outside it.
-  // Each is a pivot of an ancestor separator (the separators split regions
-  // along full grid lines, and the periodic wrap meets the root column).
-  for (int f = 0; f < nf; ++f) {
-    Front &F = s.fronts[f];
-    if (F.parent < 0) continue;
-    std::vector<int> b;
-    int xl = (F.x0 - 1 + nx) % nx, xr = F.x1 % nx;
-    for (int y = F.y0; y < F.y1; ++y) {
-      b.push_back(bld.node(xl, y));
-      b.push_back(bld.node(xr, y));
+  // Boundary sets (symbolic factorization): the nodes a front's pivots couple
+  // to that are eliminated later, plus its children's boundaries, minus its
+  // own pivots.  With geometric dissection these are the grid neighbours of
+  // the subtree's region (ancestor separators, the periodic wrap meeting the
+  // root column) and, for a chained separator, its later parts.
+  {
+    std::vector<int> mark(N, -1);
+    for (int f = 0; f < nf; ++f) {
+      Front &F = s.fronts[f];
+      std::vector<int> keep;
+      auto add = [&](int v) {
+        if (s.node_front[v] == f || mark[v] == f) return;
+        mark[v] = f;
+        keep.push_back(v);
+      };
+      for (int u : F.piv) {
+        const int x = u % nx, y = u / nx;
+        const int nb[4] = {y * nx + (x - 1 + nx) % nx, y * nx + (x + 1) % nx, y > 0 ? u - nx : -1,
+                           y < ny - 1 ? u + nx : -1};
+        for (int v : nb)
+          if (v >= 0 && s.node_elim[v] > s.node_elim[u]) add(v);
+      }
+      for (int c = 0; c < F.nchild; ++c)
+        for (int v : s.fronts[F.child[c]].bnd) add(v);
+      std::sort(keep.begin(), keep.end(), [&](int a, int c) { return s.node_elim[a] < s.node_elim[c]; });
+      for (int v : keep)
+        if (s.node_elim[v] < F.elim0 + F.p()) throw std::runtime_error("boundary node eliminated before its front");
+      F.bnd = std::move(keep);
     }
-    if (F.y0 > 0)
-      for (int x = F.x0; x < F.x1; ++x) b.push_back(bld.node(x, F.y0 - 1));
-    if (F.y1 < ny)
-      for (int x = F.x0; x < F.x1; ++x) b.push_back(bld.node(x, F.y1));
-    std::vector<int> keep;
-    keep.reserve(b.size());
-    for (int n : b) {
-      int x = n % nx, y = n / nx;
-      bool inside = x >= F.x0 && x < F.x1 && y >= F.y0 && y < F.y1;
-      if (!inside) keep.push_back(n);
-    }
-    std::sort(keep.begin(), keep.end(), [&](int a, int c) { return s.node_elim[a] < s.node_elim[c]; });
-    keep.erase(std::unique(keep.begin(), keep.end()), keep.end());
-    for (int n : keep)
-      if (s.node_elim[n] < F.elim0 + F.p()) throw std::runtime_error("boundary node eliminated before its front");
-    F.bnd = std::move(keep);
   }
 
   // Extend-add maps: child boundary node -> parent-local index.
