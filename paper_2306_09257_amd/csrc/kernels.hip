@@ -512,7 +512,7 @@ __device__ __forceinline__ double2 tri_mask(bool lower, int r, int c, bool insid
   return r <= c ? v : make_double2(0.0, 0.0);
 }
 
-__global__ __launch_bounds__(256) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext) {
+__global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext) {
   const GemmTask T = tasks[blockIdx.x];
   const int M = T.M, K = T.K;
   const int N = T.N < nlim ? T.N : nlim;
