@@ -95,8 +95,10 @@ apf_status apf_create(const apf_problem_desc *desc, apf_handle **out);
  * (Sec. 2: one partial factorization per evaluation of S). */
 apf_status apf_analyze(apf_handle *h);
 
-/* Assemble A (the 5-point operator above with the given permittivity), B
- * and C on the GPU, straight into the frontal workspaces.
+/* Assemble A (the 5-point operator above with the given permittivity) on
+ * the GPU: its five stencil values per node, which the factorization scatters
+ * into the frontal workspaces level by level (the rows of B and C are
+ * generated there from the channel definitions).
  *   eps_dev: float64 [ny][nx] relative permittivity (real; must be nonzero
  *   and finite -- checked on the host-visible copy is not possible, so the
  *   factorization reports APF_ESINGULAR if it produces a zero pivot).
@@ -113,6 +115,22 @@ apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *stream);
  * pivot).  Requires apf_assemble since the last factorization. */
 apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev,
                             void *stream);
+
+/* Batched partial factorization of n independent problems (different grids,
+ * wavelengths and channel sets allowed): every handle must have been
+ * analysed and assembled (its own apf_assemble).  The elimination-tree levels
+ * of all problems (counted from the leaves) are merged, so each level of the
+ * whole batch is one launch per kernel; the first call on a set of handles
+ * builds the merged task lists (cached until one of the handles is
+ * destroyed), and later calls with the same handles and outputs replay a
+ * HIP graph captured from the first graph-mode call (no graph while
+ * profiling is on for hs[0]).
+ *   hs: n handle pointers (host array); S_devs: n device pointers, complex128
+ *   [n_out_i][n_in_i] each.  The factors stay on each handle for apf_grad.
+ *   Synchronises `stream` at the end; APF_ESINGULAR if any pivot block of the
+ *   batch had a zero pivot (then no handle may be used by apf_grad). */
+apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n, apf_precision prec,
+                                    double *const *S_devs, void *stream);
 
 /* Objective helper for f = sum_nm w_nm |S_nm|^2 (Sec. 2, Eq. (1) needs the
  * Wirtinger derivative dF/dS):

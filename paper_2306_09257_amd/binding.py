@@ -25,7 +25,8 @@ APF_ESTATE = -6
 APF_FP64 = 0
 APF_MIXED = 1
 
-ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_weighted_power",
+ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
+                "apf_weighted_power",
                 "apf_grad", "apf_set_profiling", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "extend_add", "inverse", "gemm_factor", "gemm_schur",
                    "gemm_sweep", "contract", "wpow")
@@ -67,6 +68,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_analyze.argtypes = [vp]
     lib.apf_assemble.argtypes = [vp, vp, vp]
     lib.apf_factor_schur.argtypes = [vp, i32, vp, vp]
+    lib.apf_factor_schur_batched.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp), vp]
     lib.apf_weighted_power.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.apf_grad.argtypes = [vp, vp, vp, vp]
     lib.apf_set_profiling.argtypes = [vp, i32]
@@ -187,6 +189,19 @@ class APF:
             self.close()
         except Exception:
             pass
+
+
+def factor_schur_batched(apfs, S_list=None, precision: int = APF_FP64):
+    """One batched partial factorization of several assembled problems.
+    Returns the list of S tensors (complex128 [n_out][n_in] each)."""
+    import torch
+    lib = load_library()
+    if S_list is None:
+        S_list = [torch.empty((a.prob.n_out, a.prob.n_in), dtype=torch.complex128, device="cuda") for a in apfs]
+    hs = (ctypes.c_void_p * len(apfs))(*[a._h.value for a in apfs])
+    ss = (ctypes.c_void_p * len(apfs))(*[S.data_ptr() for S in S_list])
+    _check(lib.apf_factor_schur_batched(hs, len(apfs), precision, ss, _stream()))
+    return S_list
 
 
 def solve(apf: APF, eps, precision: int = APF_FP64):

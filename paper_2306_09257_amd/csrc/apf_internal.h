@@ -79,14 +79,32 @@ struct FrontDev {
   int32_t pad2;
 };
 
-struct AsmEntry {          // one stencil entry of A: Aval[src] is added at dest
-  int64_t src;             // node*5 + direction (0 centre, 1 x-1, 2 x+1, 3 y-1, 4 y+1)
+// Physical parameters the assembly kernels evaluate the operator from.
+struct Phys {
+  int nx, ny;
+  double h2;                    // (k0 dx)^2
+  int npml_top, npml_bot, pml_power;
+  double alpha_top, alpha_bot;  // PML stretch amplitudes
+  double eps_src, eps_prj;      // media of the source and projection rows
+};
+
+// Channel set of one panel (device memory): the source row's inputs or the
+// projection row's outputs of one problem.
+struct ChanParams {
+  Phys P;
+  const int32_t *orders;
+  int32_t m, is_source;
+};
+
+struct AsmEntry {          // one stencil entry of A: *src is added at dest
+  const cplx *src;         // Aval + node*5 + direction (0 centre, 1 x-1, 2 x+1, 3 y-1, 4 y+1)
   cplx *dest;
 };
 
 struct PanelEntry {        // one source (B) or projection (C) node: a whole row of the panel
   int32_t node, pad;
   cplx *dest;
+  const ChanParams *cp;
 };
 
 enum GemmFlags : int32_t {

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -89,8 +91,8 @@ struct Blob {
 };
 
 struct LevelTasks {
-  int64_t zero = -1, scat = -1, pB = -1, pC = -1, ext[2] = {-1, -1}, extrow[2] = {-1, -1}, g1 = -1, g2 = -1, sw = -1;
-  int nzero = 0, nscat = 0, npB = 0, npC = 0, next[2] = {0, 0}, nextrow[2] = {0, 0}, ng1 = 0, ng2 = 0, nsw = 0;
+  int64_t zero = -1, scat = -1, pan = -1, ext[2] = {-1, -1}, extrow[2] = {-1, -1}, g1 = -1, g2 = -1, sw = -1;
+  int nzero = 0, nscat = 0, npan = 0, next[2] = {0, 0}, nextrow[2] = {0, 0}, ng1 = 0, ng2 = 0, nsw = 0;
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
   LevelTasks() {
@@ -166,7 +168,9 @@ struct Plan {
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
   int rhs_chunk = 0;
   std::vector<LevelTasks> lv;
-  int64_t gS = -1, vinit = -1, drows = -1, in_orders = -1, out_orders = -1, fronts = -1;
+  int64_t gS = -1, vinit = -1, drows = -1, fronts = -1;
+  int nfronts = 0;
+  char *chan = nullptr;       // ChanParams of the source and projection rows, then their orders
   int ngS = 0, nvinit = 0, ndesign = 0;
   template <class T>
   T *at(int64_t off) const { return off < 0 ? nullptr : reinterpret_cast<T *>(blob + off); }
@@ -433,8 +437,24 @@ static void build_plan(apf_handle *H) {
     P.ndesign = (int)dr.size();
     P.drows = ib.add(dr);
   }
-  P.in_orders = ib.add(d.in_orders);
-  P.out_orders = ib.add(d.out_orders);
+  // channel parameters of the two panels, in a small buffer of their own
+  const ChanParams *cp_src, *cp_prj;
+  {
+    std::vector<char> hb(2 * sizeof(ChanParams) + (d.n_in + d.n_out) * sizeof(int32_t));
+    HIPCHK(hipMalloc(&P.chan, hb.size()));
+    ChanParams c[2];
+    c[0].P = H->phys; c[0].m = d.n_in; c[0].is_source = 1;
+    c[0].orders = reinterpret_cast<const int32_t *>(P.chan + 2 * sizeof(ChanParams));
+    c[1].P = H->phys; c[1].m = d.n_out; c[1].is_source = 0;
+    c[1].orders = c[0].orders + d.n_in;
+    std::memcpy(hb.data(), c, sizeof c);
+    std::memcpy(hb.data() + 2 * sizeof(ChanParams), d.in_orders.data(), d.n_in * sizeof(int32_t));
+    std::memcpy(hb.data() + 2 * sizeof(ChanParams) + d.n_in * sizeof(int32_t), d.out_orders.data(),
+                d.n_out * sizeof(int32_t));
+    HIPCHK(hipMemcpy(P.chan, hb.data(), hb.size(), hipMemcpyHostToDevice));
+    cp_src = reinterpret_cast<const ChanParams *>(P.chan);
+    cp_prj = cp_src + 1;
+  }
   P.lv.assign(H_ + 1, LevelTasks());
   for (int lvl = 0; lvl <= H_; ++lvl) {
     std::vector<int32_t> kids[2], inv[N_INV_VARIANTS];
@@ -509,7 +529,7 @@ static void build_plan(apf_handle *H) {
 
   std::vector<std::vector<ZeroRange>> zr(H_ + 1);
   std::vector<std::vector<AsmEntry>> ae(H_ + 1);
-  std::vector<std::vector<PanelEntry>> pb(H_ + 1), pc(H_ + 1);
+  std::vector<std::vector<PanelEntry>> pe(H_ + 1);
   std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), sw(H_ + 1);
   std::vector<GemmTask> gS, vinit;
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
@@ -543,11 +563,12 @@ static void build_plan(apf_handle *H) {
         if (dir > 0 && S.node_elim[v] < eu) continue;   // owned by the front of v
         const int lu = loc[u], lv = loc[v];
         if (lv < 0) throw std::runtime_error("stencil neighbour outside the front");
-        ae[lvl].push_back({(int64_t)u * 5 + dir, D.core + (int64_t)lu * n + lv});
-        if (dir > 0) ae[lvl].push_back({(int64_t)u * 5 + dir, D.core + (int64_t)lv * n + lu});   // A = A^T
+        const cplx *src = P.aval + (int64_t)u * 5 + dir;
+        ae[lvl].push_back({src, D.core + (int64_t)lu * n + lv});
+        if (dir > 0) ae[lvl].push_back({src, D.core + (int64_t)lv * n + lu});   // A = A^T
       }
-      if (mB && y == d.src_row) pb[lvl].push_back({u, 0, D.bp_piv + (int64_t)k * mB});
-      if (mC && y == d.prj_row) pc[lvl].push_back({u, 0, D.cpt_piv + (int64_t)k * mC});
+      if (mB && y == d.src_row) pe[lvl].push_back({u, 0, D.bp_piv + (int64_t)k * mB, cp_src});
+      if (mC && y == d.prj_row) pe[lvl].push_back({u, 0, D.cpt_piv + (int64_t)k * mC, cp_prj});
     }
     for (int k = 0; k < p; ++k) loc[F.piv[k]] = -1;
     for (int k = 0; k < b; ++k) loc[F.bnd[k]] = -1;
@@ -616,8 +637,7 @@ static void build_plan(apf_handle *H) {
     LevelTasks &L = P.lv[lvl];
     L.zero = bl.add(zr[lvl]); L.nzero = (int)zr[lvl].size();
     L.scat = bl.add(ae[lvl]); L.nscat = (int)ae[lvl].size();
-    L.pB = bl.add(pb[lvl]); L.npB = (int)pb[lvl].size();
-    L.pC = bl.add(pc[lvl]); L.npC = (int)pc[lvl].size();
+    L.pan = bl.add(pe[lvl]); L.npan = (int)pe[lvl].size();
     L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
     L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
     L.sw = bl.add(sw[lvl]); L.nsw = (int)sw[lvl].size();
@@ -625,6 +645,7 @@ static void build_plan(apf_handle *H) {
   P.gS = bl.add(gS); P.ngS = (int)gS.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
   P.fronts = bl.add(fd);
+  P.nfronts = nf;
   HIPCHK(hipMalloc(&P.blob, bl.h.size()));
   base = P.blob;
   // rebase the pointers into the integer section
@@ -648,7 +669,7 @@ static void build_plan(apf_handle *H) {
 }
 
 static void free_plan(Plan &P) {
-  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms};
+  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   P = Plan();
@@ -688,6 +709,40 @@ extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *s
   });
 }
 
+// The level loop of the numeric factorization (leaves to root): zero the
+// level's workspaces, scatter A, generate the channel rows, extend-add the
+// children (two slots: siblings never share a launch), factor the pivot
+// blocks, then the two GEMM phases.  `blob` holds the task arrays that `lv`
+// indexes; `fr` the front descriptors.
+static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const FrontDev *fr, int *status,
+                       Profiler &pr, hipStream_t s) {
+  auto at = [&](int64_t off) -> char * { return off < 0 ? nullptr : blob + off; };
+  for (size_t lvl = 0; lvl < lv.size(); ++lvl) {
+    const LevelTasks &L = lv[lvl];
+    pr.run(P_ZERO, s, [&] { return launch_zero((const ZeroRange *)at(L.zero), L.nzero, s); });
+    pr.run(P_ASSEMBLE, s, [&] {
+      hipError_t e = launch_scatter_A((const AsmEntry *)at(L.scat), L.nscat, s);
+      if (e == hipSuccess) e = launch_assemble_panel((const PanelEntry *)at(L.pan), L.npan, s);
+      return e;
+    });
+    pr.run(P_EXTADD, s, [&] {
+      hipError_t e = hipSuccess;
+      for (int c = 0; c < 2 && e == hipSuccess; ++c)
+        e = launch_extend_add(fr, (const int32_t *)at(L.ext[c]), L.next[c], (const int2 *)at(L.extrow[c]),
+                              L.nextrow[c], s);
+      return e;
+    });
+    pr.run(P_INVERSE, s, [&] {
+      hipError_t e = hipSuccess;
+      for (int v = 0; v < N_INV_VARIANTS && e == hipSuccess; ++v)
+        e = launch_inverse(v, fr, (const int32_t *)at(L.inv[v]), L.ninv[v], status, s);
+      return e;
+    });
+    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g1), L.ng1, 0, INT_MAX, nullptr, s); });
+    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g2), L.ng2, 0, INT_MAX, nullptr, s); });
+  }
+}
+
 extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev, void *stream) {
   if (!h || !S_dev) return fail(APF_EINVAL, "null argument");
   if (prec != APF_FP64) return fail(APF_EINVAL, "only APF_FP64 is implemented");
@@ -695,35 +750,9 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     Plan &P = h->plan;
-    const FrontDev *fr = P.at<FrontDev>(P.fronts);
-    HIPCHK(hipMemsetAsync(P.status, 0, sizeof(int), s));
     Profiler &pr = h->prof;
-    for (size_t lvl = 0; lvl < P.lv.size(); ++lvl) {
-      const LevelTasks &L = P.lv[lvl];
-      pr.run(P_ZERO, s, [&] { return launch_zero(P.at<ZeroRange>(L.zero), L.nzero, s); });
-      pr.run(P_ASSEMBLE, s, [&] {
-        hipError_t e = launch_scatter_A(P.at<AsmEntry>(L.scat), L.nscat, P.aval, s);
-        if (e == hipSuccess)
-          e = launch_assemble_panel(P.at<PanelEntry>(L.pB), L.npB, h->phys, P.at<int32_t>(P.in_orders), h->d.n_in, 1, s);
-        if (e == hipSuccess)
-          e = launch_assemble_panel(P.at<PanelEntry>(L.pC), L.npC, h->phys, P.at<int32_t>(P.out_orders), h->d.n_out, 0, s);
-        return e;
-      });
-      pr.run(P_EXTADD, s, [&] {
-        hipError_t e = hipSuccess;
-        for (int c = 0; c < 2 && e == hipSuccess; ++c)
-          e = launch_extend_add(fr, P.at<int32_t>(L.ext[c]), L.next[c], P.at<int2>(L.extrow[c]), L.nextrow[c], s);
-        return e;
-      });
-      pr.run(P_INVERSE, s, [&] {
-        hipError_t e = hipSuccess;
-        for (int v = 0; v < N_INV_VARIANTS && e == hipSuccess; ++v)
-          e = launch_inverse(v, fr, P.at<int32_t>(L.inv[v]), L.ninv[v], P.status, s);
-        return e;
-      });
-      pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm(P.at<GemmTask>(L.g1), L.ng1, 0, INT_MAX, nullptr, s); });
-      pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm(P.at<GemmTask>(L.g2), L.ng2, 0, INT_MAX, nullptr, s); });
-    }
+    HIPCHK(launch_fill_int(P.status, 0, s));
+    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s);
     pr.run(P_GEMM_SCHUR, s, [&] {
       return launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s);
     });
@@ -736,6 +765,187 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
       return fail(APF_ESINGULAR, "zero pivot in a pivot block");
     }
     h->state = 2;
+    return APF_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Batched factorization of several independent problems: the level lists of
+// every handle are concatenated (level = height above the leaves), so each
+// level of the whole batch is one launch per kernel; repeated calls with the
+// same handles and outputs replay a captured HIP graph of that sequence.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchPlan {
+  std::vector<apf_handle *> hs;
+  std::vector<LevelTasks> lv;
+  char *blob = nullptr;
+  int64_t fronts = -1;
+  int *status = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;       // private stream the graph is captured on
+  std::vector<double *> graph_S;   // outputs the graph was captured with
+  ~BatchPlan() {
+    if (cap) (void)hipStreamDestroy(cap);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (blob) (void)hipFree(blob);
+    if (status) (void)hipFree(status);
+  }
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchPlan>> g_batches;
+
+template <class T>
+std::vector<T> fetch(const char *blob, int64_t off, int n) {
+  std::vector<T> v(n);
+  if (n) HIPCHK(hipMemcpy(v.data(), blob + off, n * sizeof(T), hipMemcpyDeviceToHost));
+  return v;
+}
+
+std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
+  auto B = std::make_unique<BatchPlan>();
+  B->hs = hs;
+  size_t nl = 0;
+  for (apf_handle *h : hs) nl = std::max(nl, h->plan.lv.size());
+  Blob bl;
+  {
+    const char pad[16] = {0};
+    bl.add(pad, sizeof pad);
+  }
+  std::vector<FrontDev> fd;
+  std::vector<int> base(hs.size());
+  for (size_t i = 0; i < hs.size(); ++i) {
+    const Plan &P = hs[i]->plan;
+    base[i] = (int)fd.size();
+    std::vector<FrontDev> f = fetch<FrontDev>(P.blob, P.fronts, P.nfronts);
+    for (FrontDev &x : f)
+      if (x.parent >= 0) x.parent += base[i];
+    fd.insert(fd.end(), f.begin(), f.end());
+  }
+  B->lv.assign(nl, LevelTasks());
+  for (size_t lvl = 0; lvl < nl; ++lvl) {
+    std::vector<ZeroRange> zr;
+    std::vector<AsmEntry> ae;
+    std::vector<PanelEntry> pe;
+    std::vector<int32_t> kids[2], inv[N_INV_VARIANTS];
+    std::vector<int2> rows[2];
+    std::vector<GemmTask> g1, g2;
+    for (size_t i = 0; i < hs.size(); ++i) {
+      const Plan &P = hs[i]->plan;
+      if (lvl >= P.lv.size()) continue;
+      const LevelTasks &L = P.lv[lvl];
+      auto z = fetch<ZeroRange>(P.blob, L.zero, L.nzero); zr.insert(zr.end(), z.begin(), z.end());
+      auto a = fetch<AsmEntry>(P.blob, L.scat, L.nscat); ae.insert(ae.end(), a.begin(), a.end());
+      auto pp = fetch<PanelEntry>(P.blob, L.pan, L.npan); pe.insert(pe.end(), pp.begin(), pp.end());
+      for (int c = 0; c < 2; ++c) {
+        for (int32_t k : fetch<int32_t>(P.blob, L.ext[c], L.next[c])) kids[c].push_back(k + base[i]);
+        for (int2 r : fetch<int2>(P.blob, L.extrow[c], L.nextrow[c])) rows[c].push_back(make_int2(r.x + base[i], r.y));
+      }
+      for (int v = 0; v < N_INV_VARIANTS; ++v)
+        for (int32_t k : fetch<int32_t>(P.blob, L.inv[v], L.ninv[v])) inv[v].push_back(k + base[i]);
+      auto t1 = fetch<GemmTask>(P.blob, L.g1, L.ng1); g1.insert(g1.end(), t1.begin(), t1.end());
+      auto t2 = fetch<GemmTask>(P.blob, L.g2, L.ng2); g2.insert(g2.end(), t2.begin(), t2.end());
+    }
+    LevelTasks &L = B->lv[lvl];
+    L.zero = bl.add(zr); L.nzero = (int)zr.size();
+    L.scat = bl.add(ae); L.nscat = (int)ae.size();
+    L.pan = bl.add(pe); L.npan = (int)pe.size();
+    for (int c = 0; c < 2; ++c) {
+      L.ext[c] = bl.add(kids[c]); L.next[c] = (int)kids[c].size();
+      L.extrow[c] = bl.add(rows[c]); L.nextrow[c] = (int)rows[c].size();
+    }
+    for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = bl.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
+    L.g1 = bl.add(g1); L.ng1 = (int)g1.size();
+    L.g2 = bl.add(g2); L.ng2 = (int)g2.size();
+  }
+  B->fronts = bl.add(fd);
+  HIPCHK(hipMalloc(&B->blob, bl.h.size()));
+  HIPCHK(hipMemcpy(B->blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&B->status, sizeof(int)));
+  return B;
+}
+
+void enqueue_batch(BatchPlan &B, double *const *S_devs, Profiler &pr, hipStream_t s) {
+  HIPCHK(launch_fill_int(B.status, 0, s));
+  run_levels(B.lv, B.blob, reinterpret_cast<const FrontDev *>(B.blob + B.fronts), B.status, pr, s);
+  for (size_t i = 0; i < B.hs.size(); ++i) {
+    const Plan &P = B.hs[i]->plan;
+    pr.run(P_GEMM_SCHUR, s, [&] {
+      return launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_devs[i]), s);
+    });
+  }
+}
+
+void forget_batches_of(apf_handle *h) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batches.erase(std::remove_if(g_batches.begin(), g_batches.end(),
+                                 [&](const std::unique_ptr<BatchPlan> &b) {
+                                   return std::find(b->hs.begin(), b->hs.end(), h) != b->hs.end();
+                                 }),
+                  g_batches.end());
+}
+
+}  // namespace
+
+extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n, apf_precision prec,
+                                               double *const *S_devs, void *stream) {
+  if (!hs || !S_devs || n < 1) return fail(APF_EINVAL, "need at least one handle and output");
+  if (prec != APF_FP64) return fail(APF_EINVAL, "only APF_FP64 is implemented");
+  std::vector<apf_handle *> v(hs, hs + n);
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !S_devs[i]) return fail(APF_EINVAL, "null handle or output");
+    if (hs[i]->state < 1) return fail(APF_ESTATE, "apf_assemble has not run on every handle");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(APF_EINVAL, "a handle appears twice in the batch");
+  }
+  return guarded([&]() -> apf_status {
+    hipStream_t s = (hipStream_t)stream;
+    BatchPlan *B = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      for (auto &b : g_batches)
+        if (b->hs == v) B = b.get();
+      if (!B) {
+        g_batches.push_back(build_batch(v));
+        B = g_batches.back().get();
+      }
+    }
+    Profiler &pr = hs[0]->prof;
+    const std::vector<double *> Sv(S_devs, S_devs + n);
+    if (pr.on) {
+      enqueue_batch(*B, S_devs, pr, s);   // timed launches are not captured
+    } else {
+      if (!B->exec || B->graph_S != Sv) {
+        if (B->exec) { HIPCHK(hipGraphExecDestroy(B->exec)); B->exec = nullptr; }
+        if (B->graph) { HIPCHK(hipGraphDestroy(B->graph)); B->graph = nullptr; }
+        // capture on a private stream (the caller's may be the null stream,
+        // which cannot be captured); the graph is then launched on `s`
+        if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+        try {
+          enqueue_batch(*B, S_devs, pr, B->cap);
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(B->cap, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(B->cap, &B->graph));
+        HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+        B->graph_S = Sv;
+      }
+      HIPCHK(hipGraphLaunch(B->exec, s));
+    }
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, B->status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (pr.on) pr.collect();
+    for (int i = 0; i < n; ++i) hs[i]->state = st ? 0 : 2;
+    if (st) return fail(APF_ESINGULAR, "zero pivot in a pivot block of the batch");
     return APF_OK;
   });
 }
@@ -795,6 +1005,7 @@ extern "C" apf_status apf_set_profiling(apf_handle *h, int32_t on) {
 
 extern "C" apf_status apf_destroy(apf_handle *h) {
   if (!h) return APF_OK;
+  forget_batches_of(h);
   free_plan(h->plan);
   delete h;
   return APF_OK;

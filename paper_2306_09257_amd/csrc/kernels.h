@@ -7,20 +7,11 @@
 
 namespace apf {
 
-// Physical parameters the assembly kernels evaluate the operator from.
-struct Phys {
-  int nx, ny;
-  double h2;                    // (k0 dx)^2
-  int npml_top, npml_bot, pml_power;
-  double alpha_top, alpha_bot;  // PML stretch amplitudes
-  double eps_src, eps_prj;      // media of the source and projection rows
-};
-
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s);
 hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStream_t s);
-hipError_t launch_scatter_A(const AsmEntry *e, int n, const cplx *Aval, hipStream_t s);
-hipError_t launch_assemble_panel(const PanelEntry *e, int n, const Phys &P, const int32_t *orders, int m,
-                                 int is_source, hipStream_t s);
+hipError_t launch_scatter_A(const AsmEntry *e, int n, hipStream_t s);
+hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s);
+hipError_t launch_fill_int(int *p, int v, hipStream_t s);
 hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, const int2 *rows, int nrows,
                              hipStream_t s);
 constexpr int N_INV_VARIANTS = 8;

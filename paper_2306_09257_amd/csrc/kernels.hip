@@ -82,12 +82,14 @@ __global__ void k_stencil(Phys P, const double *eps, cplx *Aval) {
 }
 
 // Scatter of the stencil values of one level's fronts into their cores.
-__global__ void k_scatter_A(const AsmEntry *e, int n, const cplx *Aval) {
+__global__ void k_scatter_A(const AsmEntry *e, int n) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const AsmEntry E = e[t];
-  st2(E.dest, cadd(ld2(E.dest), ld2(Aval + E.src)));
+  st2(E.dest, cadd(ld2(E.dest), ld2(E.src)));
 }
+
+__global__ void k_fill_int(int *p, int v) { *p = v; }
 
 // Channel value at column i of order a in a medium: sqrt(sin q) phi_a(i), with
 // q from sin^2(q/2) = h^2 eps/4 - sin^2(pi a/nx) and phi_a(i) = e^{2 pi i a i/nx}/sqrt(nx).
@@ -105,13 +107,15 @@ __device__ double2 channel_value(const Phys &P, int a, int i, double eps_medium,
 }
 
 // B rows: -2i sqrt(sin q_a) phi_a(i); C^T rows: sqrt(sin q_b) conj(phi_b(i)).
-__global__ void k_assemble_panel(const PanelEntry *e, int n, Phys P, const int32_t *orders, int m,
-                                 int is_source) {
+__global__ void k_assemble_panel(const PanelEntry *e, int n) {
   const PanelEntry E = e[blockIdx.x];
+  const ChanParams &cp = *E.cp;
+  const Phys &P = cp.P;
+  const int is_source = cp.is_source, m = cp.m;
   const int i = E.node % P.nx;
   double eps_m = is_source ? P.eps_src : P.eps_prj;
   for (int a = threadIdx.x; a < m; a += blockDim.x) {
-    double2 v = channel_value(P, orders[a], i, eps_m, !is_source);
+    double2 v = channel_value(P, cp.orders[a], i, eps_m, !is_source);
     if (is_source) v = make_double2(2.0 * v.y, -2.0 * v.x);   // times -2i
     st2(E.dest + a, cadd(ld2(E.dest + a), v));
   }
@@ -695,15 +699,18 @@ hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStrea
   hipLaunchKernelGGL(k_stencil, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, eps, Aval);
   return hipGetLastError();
 }
-hipError_t launch_scatter_A(const AsmEntry *e, int n, const cplx *Aval, hipStream_t s) {
+hipError_t launch_scatter_A(const AsmEntry *e, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_A, dim3((n + 255) / 256), dim3(256), 0, s, e, n, Aval);
+  hipLaunchKernelGGL(k_scatter_A, dim3((n + 255) / 256), dim3(256), 0, s, e, n);
   return hipGetLastError();
 }
-hipError_t launch_assemble_panel(const PanelEntry *e, int n, const Phys &P, const int32_t *orders, int m,
-                                 int is_source, hipStream_t s) {
-  if (n == 0 || m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n, P, orders, m, is_source);
+hipError_t launch_fill_int(int *p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n);
   return hipGetLastError();
 }
 hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, const int2 *rows, int nrows,

@@ -188,6 +188,26 @@ def metasurface_wide(seed: int = 1, nx: int = 24000):
     return prob, eps, w
 
 
+def batch_uneven(seed: int = 3, count: int = 64, nx_max: int = 4800, nx_step: int = 120):
+    """Independent problems of uneven size for one batched factorization: nx
+    uniform over {nx_step, 2 nx_step, ..., nx_max}, ny in {60, 92, 140},
+    wavelength lambda/lambda0 uniform in [0.9, 1.1] at dx = lambda0/20
+    (dx/lambda = 0.05/(lambda/lambda0)), eps ~ U[1, 4] on the design rows,
+    w ~ U[0, 1]; channels |a| < nx dx/lambda.  Returns a list of
+    (prob, eps, w)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        nx = int(rng.integers(1, nx_max // nx_step + 1)) * nx_step
+        ny = int(rng.choice([60, 92, 140]))
+        lam = float(rng.uniform(0.9, 1.1))
+        prob = make_problem(nx, ny, dx_over_lambda=0.05 / lam)
+        eps = eps_uniform(prob, rng)
+        w = weights_uniform(prob, rng)
+        out.append((prob, eps, w))
+    return out
+
+
 def tiny_problem(nx=24, ny=60, seed=0, layout=None, n_orders=None, **kw):
     """Small grids for oracle pins and parity tests."""
     lay = layout
