@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -152,6 +153,8 @@ def main():
     ap.add_argument("--workload", default="metasurface_24000x160", choices=sorted(WORKLOADS))
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: front GEMMs and sweeps on FP32 MFMA (FP64 storage, pivots, reductions)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the APF path here is a "
@@ -178,9 +181,11 @@ def main():
     S = torch.empty((prob.n_out, prob.n_in), dtype=torch.complex128, device=dev)
     grad = torch.empty((prob.n_design_rows, prob.nx), dtype=torch.float64, device=dev)
 
+    prec = binding.APF_MIXED if args.precision == "mixed" else binding.APF_FP64
+
     def step():
         apf.assemble(eps_d)
-        apf.factor_schur(S)
+        apf.factor_schur(S, precision=prec)
         f, G = apf.weighted_power(S, w_d)
         apf.grad(G, out=grad)
         return f
@@ -211,10 +216,12 @@ def main():
     gemm_launches = (prof["gemm_factor"][1] + prof["gemm_schur"][1] + prof["gemm_sweep"][1]) / args.steps
     gemm_flop = 8.0 * (cm["factor"] + cm["schur"] + cm["sweep"])
     achieved = gemm_flop / (gemm_ms * 1e-3) / 1e12
+    peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "mixed" else FP64_MFMA_PEAK_TFLOPS
     roofline = {
-        "kernel": "k_gemm (batched complex FP64 MFMA GEMM, all launches of a step)",
-        "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+        "kernel": "k_gemm (batched complex %s MFMA GEMM, all launches of a step)"
+                  % ("FP32" if args.precision == "mixed" else "FP64"),
+        "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak, "traffic": None,
         "flop_per_step": gemm_flop, "launches_per_step": gemm_launches,
         "avg_launch_ms": gemm_ms / max(gemm_launches, 1),
     }
@@ -227,12 +234,23 @@ def main():
         "dtype": "c128 (f64)", "data": "synthetic",
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "unknowns": prob.nx * prob.ny,
                    "n_in": prob.n_in, "n_out": prob.n_out, "design_pixels": prob.n_design_rows * prob.nx,
-                   "precision": "fp64", "leaf_size": args.leaf or 64},
+                   "precision": args.precision, "leaf_size": args.leaf or 64},
         "roofline": roofline,
         "phase_ms_per_step": phases,
         "analysis_s": t_an,
         "factor_cmacs_algorithmic": apf.query("algo_factor_cmacs"),
     }
+    if args.precision == "mixed":
+        # accuracy of the unrefined mixed result against the FP64 path
+        S_m, g_m = S.clone(), grad.clone()
+        apf.assemble(eps_d)
+        S64 = apf.factor_schur(precision=binding.APF_FP64)
+        f64, G64 = apf.weighted_power(S64, w_d)
+        g64 = apf.grad(G64)
+        torch.cuda.synchronize()
+        out["mixed_rel_err_vs_fp64"] = {
+            "S": float(torch.linalg.norm(S_m - S64) / torch.linalg.norm(S64)),
+            "grad": float(torch.linalg.norm(g_m - g64) / torch.linalg.norm(g64))}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

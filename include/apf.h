@@ -58,7 +58,12 @@ typedef enum {
 
 typedef enum {
   APF_FP64 = 0,        /* every front operation in complex FP64            */
-  APF_MIXED = 1        /* reserved: complex FP32 fronts + FP64 refinement   */
+  APF_MIXED = 1        /* front GEMMs and sweeps on FP32 MFMA (operands
+                          rounded to FP32, FP32 accumulation), pivot blocks,
+                          storage and the S / gradient reductions in FP64;
+                          no iterative refinement: the result carries the
+                          FP32 rounding amplified by ill-conditioned pivot
+                          blocks (measured 1e-4 .. 1e-2 relative)          */
 } apf_precision;
 
 typedef struct apf_handle apf_handle;
@@ -110,6 +115,8 @@ apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *stream);
 /* Numeric multifrontal partial factorization of K = [A, B; C, 0] (Sec. 2):
  * eliminates every grid unknown and writes the Schur-complement block as
  *   S_dev: complex128 [n_out][n_in],  S = C A^-1 B.
+ * prec: APF_FP64 or APF_MIXED (see apf_precision); apf_grad then runs its
+ * sweeps in the same precision.
  * The factors are kept on the handle for apf_grad.  Synchronises `stream` at
  * the end to read the pivot status word (returns APF_ESINGULAR on a zero
  * pivot).  Requires apf_assemble since the last factorization. */

@@ -101,6 +101,7 @@ struct LevelTasks {
 };
 
 constexpr int64_t ZERO_CHUNK = 8192;   // complex elements per zeroing block
+constexpr int64_t SPLIT_K = 4096;      // k rows per FP32 partial of the mixed Schur product
 
 // Per-class HIP-event timing of the launches (off unless enabled).
 enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_EXTADD, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
@@ -168,8 +169,9 @@ struct Plan {
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
   int rhs_chunk = 0;
   std::vector<LevelTasks> lv;
-  int64_t gS = -1, vinit = -1, drows = -1, fronts = -1;
-  int nfronts = 0;
+  int64_t gS = -1, vinit = -1, drows = -1, fronts = -1, gSsplit = -1;
+  int nfronts = 0, ngSsplit = 0, nseg = 0;
+  cplx *spart = nullptr;      // FP64 partial Schur blocks of the mixed path (nseg x n_out x n_in)
   char *chan = nullptr;       // ChanParams of the source and projection rows, then their orders
   int ngS = 0, nvinit = 0, ndesign = 0;
   template <class T>
@@ -237,7 +239,8 @@ struct apf_handle {
   Plan plan;
   std::vector<Off> off;
   Profiler prof;
-  int state = 0;  // 0 analysed, 1 assembled, 2 factored
+  int state = 0;
+  bool mixed = false;   // precision of the factors held (APF_MIXED)  // 0 analysed, 1 assembled, 2 factored
 };
 
 // ---------------------------------------------------------------------------
@@ -630,6 +633,17 @@ static void build_plan(apf_handle *H) {
   g_cmacs_acc = 0;
   add_tiles(gS, gemm(P.sc, Mo, P.sb, Mi, nullptr, Mi, Mo, Mi, (int)ktot, G_TRANS_A | G_C_EXT));
   P.gemm_cmacs_schur = g_cmacs_acc;
+  // mixed precision: the same product split over k segments of SPLIT_K rows,
+  // each accumulated in FP32 on MFMA and written to an FP64 partial block
+  std::vector<GemmTask> gSsplit;
+  P.nseg = (int)std::max<int64_t>(1, (ktot + SPLIT_K - 1) / SPLIT_K);
+  HIPCHK(hipMalloc(&P.spart, (int64_t)P.nseg * Mo * Mi * sizeof(cplx)));
+  for (int g = 0; g < P.nseg; ++g) {
+    const int64_t k0 = (int64_t)g * SPLIT_K;
+    const int kk = (int)std::min<int64_t>(SPLIT_K, ktot - k0);
+    add_tiles(gSsplit, gemm(P.sc + k0 * Mo, Mo, P.sb + k0 * Mi, Mi, P.spart + (int64_t)g * Mo * Mi, Mi, Mo, Mi,
+                            std::max(kk, 0), G_TRANS_A));
+  }
 
   // ---- assemble the blob ------------------------------------------------------
   Blob &bl = ib;  // continue after the integer arrays
@@ -643,6 +657,7 @@ static void build_plan(apf_handle *H) {
     L.sw = bl.add(sw[lvl]); L.nsw = (int)sw[lvl].size();
   }
   P.gS = bl.add(gS); P.ngS = (int)gS.size();
+  P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
   P.fronts = bl.add(fd);
   P.nfronts = nf;
@@ -669,7 +684,7 @@ static void build_plan(apf_handle *H) {
 }
 
 static void free_plan(Plan &P) {
-  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan};
+  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   P = Plan();
@@ -715,7 +730,7 @@ extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *s
 // blocks, then the two GEMM phases.  `blob` holds the task arrays that `lv`
 // indexes; `fr` the front descriptors.
 static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const FrontDev *fr, int *status,
-                       Profiler &pr, hipStream_t s) {
+                       Profiler &pr, hipStream_t s, bool f32) {
   auto at = [&](int64_t off) -> char * { return off < 0 ? nullptr : blob + off; };
   for (size_t lvl = 0; lvl < lv.size(); ++lvl) {
     const LevelTasks &L = lv[lvl];
@@ -738,24 +753,40 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
         e = launch_inverse(v, fr, (const int32_t *)at(L.inv[v]), L.ninv[v], status, s);
       return e;
     });
-    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g1), L.ng1, 0, INT_MAX, nullptr, s); });
-    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g2), L.ng2, 0, INT_MAX, nullptr, s); });
+    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g1), L.ng1, 0, INT_MAX, nullptr, s, f32); });
+    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g2), L.ng2, 0, INT_MAX, nullptr, s, f32); });
   }
+}
+
+// The channel-by-channel Schur block S = SC^T SB: one FP64 MFMA GEMM, or (mixed)
+// FP32-MFMA partial products over k segments summed in FP64.
+static void enqueue_schur(const Plan &P, bool f32, double *S_dev, Profiler &pr, hipStream_t s, int Mo, int Mi) {
+  if (!f32) {
+    pr.run(P_GEMM_SCHUR, s, [&] {
+      return launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s);
+    });
+    return;
+  }
+  pr.run(P_GEMM_SCHUR, s, [&] {
+    hipError_t e = launch_gemm(P.at<GemmTask>(P.gSsplit), P.ngSsplit, 0, INT_MAX, nullptr, s, true);
+    if (e == hipSuccess)
+      e = launch_sum_partials(P.spart, P.nseg, (int64_t)Mo * Mi, reinterpret_cast<cplx *>(S_dev), (int64_t)Mo * Mi, s);
+    return e;
+  });
 }
 
 extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev, void *stream) {
   if (!h || !S_dev) return fail(APF_EINVAL, "null argument");
-  if (prec != APF_FP64) return fail(APF_EINVAL, "only APF_FP64 is implemented");
+  if (prec != APF_FP64 && prec != APF_MIXED) return fail(APF_EINVAL, "unknown precision");
   if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     Plan &P = h->plan;
     Profiler &pr = h->prof;
+    const bool f32 = prec == APF_MIXED;
     HIPCHK(launch_fill_int(P.status, 0, s));
-    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s);
-    pr.run(P_GEMM_SCHUR, s, [&] {
-      return launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s);
-    });
+    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32);
+    enqueue_schur(P, f32, S_dev, pr, s, h->d.n_out, h->d.n_in);
     int st = 0;
     HIPCHK(hipMemcpyAsync(&st, P.status, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -765,6 +796,7 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
       return fail(APF_ESINGULAR, "zero pivot in a pivot block");
     }
     h->state = 2;
+    h->mixed = f32;
     return APF_OK;
   });
 }
@@ -787,6 +819,7 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;       // private stream the graph is captured on
   std::vector<double *> graph_S;   // outputs the graph was captured with
+  bool graph_f32 = false;          // and its precision
   ~BatchPlan() {
     if (cap) (void)hipStreamDestroy(cap);
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -869,15 +902,11 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
   return B;
 }
 
-void enqueue_batch(BatchPlan &B, double *const *S_devs, Profiler &pr, hipStream_t s) {
+void enqueue_batch(BatchPlan &B, double *const *S_devs, Profiler &pr, hipStream_t s, bool f32) {
   HIPCHK(launch_fill_int(B.status, 0, s));
-  run_levels(B.lv, B.blob, reinterpret_cast<const FrontDev *>(B.blob + B.fronts), B.status, pr, s);
-  for (size_t i = 0; i < B.hs.size(); ++i) {
-    const Plan &P = B.hs[i]->plan;
-    pr.run(P_GEMM_SCHUR, s, [&] {
-      return launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_devs[i]), s);
-    });
-  }
+  run_levels(B.lv, B.blob, reinterpret_cast<const FrontDev *>(B.blob + B.fronts), B.status, pr, s, f32);
+  for (size_t i = 0; i < B.hs.size(); ++i)
+    enqueue_schur(B.hs[i]->plan, f32, S_devs[i], pr, s, B.hs[i]->d.n_out, B.hs[i]->d.n_in);
 }
 
 void forget_batches_of(apf_handle *h) {
@@ -894,7 +923,8 @@ void forget_batches_of(apf_handle *h) {
 extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n, apf_precision prec,
                                                double *const *S_devs, void *stream) {
   if (!hs || !S_devs || n < 1) return fail(APF_EINVAL, "need at least one handle and output");
-  if (prec != APF_FP64) return fail(APF_EINVAL, "only APF_FP64 is implemented");
+  if (prec != APF_FP64 && prec != APF_MIXED) return fail(APF_EINVAL, "unknown precision");
+  const bool f32 = prec == APF_MIXED;
   std::vector<apf_handle *> v(hs, hs + n);
   for (int i = 0; i < n; ++i) {
     if (!hs[i] || !S_devs[i]) return fail(APF_EINVAL, "null handle or output");
@@ -917,9 +947,9 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
     Profiler &pr = hs[0]->prof;
     const std::vector<double *> Sv(S_devs, S_devs + n);
     if (pr.on) {
-      enqueue_batch(*B, S_devs, pr, s);   // timed launches are not captured
+      enqueue_batch(*B, S_devs, pr, s, f32);   // timed launches are not captured
     } else {
-      if (!B->exec || B->graph_S != Sv) {
+      if (!B->exec || B->graph_S != Sv || B->graph_f32 != f32) {
         if (B->exec) { HIPCHK(hipGraphExecDestroy(B->exec)); B->exec = nullptr; }
         if (B->graph) { HIPCHK(hipGraphDestroy(B->graph)); B->graph = nullptr; }
         // capture on a private stream (the caller's may be the null stream,
@@ -927,7 +957,7 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
         if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
         try {
-          enqueue_batch(*B, S_devs, pr, B->cap);
+          enqueue_batch(*B, S_devs, pr, B->cap, f32);
         } catch (...) {
           hipGraph_t g = nullptr;
           (void)hipStreamEndCapture(B->cap, &g);
@@ -937,6 +967,7 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
         HIPCHK(hipStreamEndCapture(B->cap, &B->graph));
         HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
         B->graph_S = Sv;
+        B->graph_f32 = f32;
       }
       HIPCHK(hipGraphLaunch(B->exec, s));
     }
@@ -944,7 +975,10 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
     HIPCHK(hipMemcpyAsync(&st, B->status, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (pr.on) pr.collect();
-    for (int i = 0; i < n; ++i) hs[i]->state = st ? 0 : 2;
+    for (int i = 0; i < n; ++i) {
+      hs[i]->state = st ? 0 : 2;
+      hs[i]->mixed = f32;
+    }
     if (st) return fail(APF_ESINGULAR, "zero pivot in a pivot block of the batch");
     return APF_OK;
   });
@@ -980,10 +1014,11 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     for (int m0 = 0, c = 0; m0 < Mi; m0 += ch, ++c) {
       const int w = std::min(ch, Mi - m0);
       Profiler &pr = h->prof;
-      pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s); });
+      const bool f32 = h->mixed;
+      pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32); });
       for (int lvl = (int)P.lv.size() - 1; lvl >= 0; --lvl) {
         const LevelTasks &L = P.lv[lvl];
-        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(L.sw), L.nsw, m0, w, nullptr, s); });
+        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(L.sw), L.nsw, m0, w, nullptr, s, f32); });
       }
       pr.run(P_CONTRACT, s, [&] {
         return launch_contract(P.at<int32_t>(P.drows), P.ndesign, P.X, P.V, ch, w, two_h2, grad_dev, c > 0, s);

@@ -10,6 +10,7 @@
 namespace apf {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -516,7 +517,39 @@ __device__ __forceinline__ double2 tri_mask(bool lower, int r, int c, bool insid
   return r <= c ? v : make_double2(0.0, 0.0);
 }
 
+// MFMA flavours of the GEMM: FP64 (v_mfma_f64_16x16x4) or FP32 with FP32
+// accumulation (v_mfma_f32_16x16x4) on operands rounded to FP32 when they are
+// staged in LDS; memory operands and results stay FP64 either way.
+template <bool F32>
+struct GemmPrec;
+template <>
+struct GemmPrec<false> {
+  typedef double2 lds_t;
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // D layout: lane l, element q -> row (l/16) + 4q, column l%16
+  static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+  static __device__ __forceinline__ lds_t cvt(double2 v) { return v; }
+};
+template <>
+struct GemmPrec<true> {
+  typedef float2 lds_t;
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // D layout: lane l, element q -> row 4(l/16) + q, column l%16
+  static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+  static __device__ __forceinline__ lds_t cvt(double2 v) { return make_float2((float)v.x, (float)v.y); }
+};
+
+template <bool F32>
 __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext) {
+  typedef GemmPrec<F32> GP;
+  typedef typename GP::lds_t lds_t;
+  typedef typename GP::acc_t acc_t;
   const GemmTask T = tasks[blockIdx.x];
   const int M = T.M, K = T.K;
   const int N = T.N < nlim ? T.N : nlim;
@@ -527,14 +560,14 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   if (T.flags & G_B_COFF) Bp += coff;
   cplx *Cp = (T.flags & G_C_EXT) ? const_cast<cplx *>(ext) : T.C;
 
-  __shared__ double2 As[KT][64];
-  __shared__ double2 Bs[KT][64];
+  __shared__ lds_t As[KT][64];
+  __shared__ lds_t Bs[KT][64];
 
-  d4 cre[2][2], cim[2][2];
+  acc_t cre[2][2], cim[2][2];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
-      cre[r][c] = d4{0.0, 0.0, 0.0, 0.0};
-      cim[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+      cre[r][c] = acc_t{0, 0, 0, 0};
+      cim[r][c] = acc_t{0, 0, 0, 0};
     }
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 
@@ -581,20 +614,20 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
     __syncthreads();
     if (!transA) {
       const int i = tid >> 2, kq = (tid & 3) * 4;
-      for (int q = 0; q < 4; ++q) As[kq + q][i] = ra[q];
+      for (int q = 0; q < 4; ++q) As[kq + q][i] = GP::cvt(ra[q]);
     } else {
       const int k = tid >> 4, iq = (tid & 15) * 4;
-      for (int q = 0; q < 4; ++q) As[k][iq + q] = ra[q];
+      for (int q = 0; q < 4; ++q) As[k][iq + q] = GP::cvt(ra[q]);
     }
     {
       const int k = tid >> 4, jq = (tid & 15) * 4;
-      for (int q = 0; q < 4; ++q) Bs[k][jq + q] = rb[q];
+      for (int q = 0; q < 4; ++q) Bs[k][jq + q] = GP::cvt(rb[q]);
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       const int kx = kk + (lane >> 4);
-      double2 a[2], b[2];
+      lds_t a[2], b[2];
       a[0] = As[kx][wr + (lane & 15)];
       a[1] = As[kx][wr + 16 + (lane & 15)];
       b[0] = Bs[kx][wc + (lane & 15)];
@@ -603,15 +636,14 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].x, cre[r][c], 0, 0, 0);
-          cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[r].y, b[c].y, cre[r][c], 0, 0, 0);
-          cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].y, cim[r][c], 0, 0, 0);
-          cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].y, b[c].x, cim[r][c], 0, 0, 0);
+          cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
+          cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
+          cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
+          cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
         }
     }
   }
 
-  // D layout of v_mfma_f64_16x16x4: lane l, element q -> row (l/16) + 4q, column l%16.
   const bool neg = T.flags & G_NEG;
   const cplx *Cin = (T.flags & G_CIN) ? T.Cin : nullptr;
   if (Cin && (T.flags & G_CIN_COFF)) Cin += coff;
@@ -621,11 +653,11 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int gi = T.tm + wr + 16 * r + (lane >> 4) + 4 * q;
+        const int gi = T.tm + wr + 16 * r + GP::row(lane, q);
         const int gj = T.tn + wc + 16 * c + (lane & 15);
         if (gi < M && gj < N) {
           const int64_t oi = T.crowmap ? T.crowmap[gi] : gi;
-          double2 v = make_double2(cre[r][c][q], cim[r][c][q]);
+          double2 v = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
           if (neg) v = make_double2(-v.x, -v.y);
           if (Cin) v = cadd(v, ld2(Cin + oi * T.ldcin + gj));
           st2(Cp + oi * T.ldc + gj, v);
@@ -752,9 +784,28 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s) {
+hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm, dim3(n), dim3(256), 0, s, t, coff, nlim, ext);
+  if (f32)
+    hipLaunchKernelGGL(k_gemm<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext);
+  else
+    hipLaunchKernelGGL(k_gemm<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext);
+  return hipGetLastError();
+}
+
+// S = sum over nseg partial products (FP64), one thread per entry.
+__global__ void k_sum_partials(const double2 *part, int nseg, int64_t stride, double2 *S, int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double2 v = part[t];
+  for (int k = 1; k < nseg; ++k) v = cadd(v, part[t + k * stride]);
+  S[t] = v;
+}
+
+hipError_t launch_sum_partials(const cplx *part, int nseg, int64_t stride, cplx *S, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double2 *>(part), nseg, stride, reinterpret_cast<double2 *>(S), n);
   return hipGetLastError();
 }
 hipError_t launch_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
