@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--workload", default="metasurface_24000x160", choices=sorted(WORKLOADS))
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: front GEMMs and sweeps on FP32 MFMA (FP64 storage, pivots, reductions)")
     args = ap.parse_args()
@@ -168,6 +171,14 @@ def main():
     import numpy as np
     import torch
     from paper_2306_09257_amd import binding
+
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     prob, eps, w = make_workload(args.workload)
     print(f"[bench] workload {args.workload}: {prob.nx}x{prob.ny}, {prob.n_in}x{prob.n_out} channels",

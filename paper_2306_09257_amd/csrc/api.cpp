@@ -169,7 +169,10 @@ struct Plan {
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
   int rhs_chunk = 0;
   std::vector<LevelTasks> lv;
-  int64_t gS = -1, vinit = -1, drows = -1, fronts = -1, gSsplit = -1;
+  int64_t gS = -1, vinit = -1, drows = -1, fronts = -1, gSsplit = -1, vmap_base = -1, vmap_pidx = -1;
+  int64_t xc_rows = 0;        // rows of the weighted-adjoint operand store (sweep fronts with C rows)
+  cplx *xc = nullptr;         // L^-T U^-T FC1^T of those fronts, stacked: xc_rows x n_out
+  int32_t *vmap = nullptr;    // V row of every xc row (rebuilt from the pivot permutations per call)
   int nfronts = 0, ngSsplit = 0, nseg = 0;
   cplx *spart = nullptr;      // FP64 partial Schur blocks of the mixed path (nseg x n_out x n_in)
   char *chan = nullptr;       // ChanParams of the source and projection rows, then their orders
@@ -205,6 +208,53 @@ void add_tiles(std::vector<GemmTask> &v, const GemmTask &t) {
     }
 }
 
+// Tiles of one large GEMM in an order that suits the 8 XCDs (each with its
+// own L2): workgroup b runs on XCD b % 8, so the list interleaves eight
+// queues.  The tile grid is cut into eight equal rectangular regions (the
+// split of 8 into row x column groups that keeps regions squarest), one per
+// XCD, so that an XCD's tiles share A row panels and B column panels; each
+// region is walked in 8 x 8 sub-blocks, the tiles that run side by side.
+// Queues are padded with empty tasks (M = N = 0, which the kernel skips).
+constexpr int N_XCD = 8, SUB = 8;
+
+void add_tiles_xcd(std::vector<GemmTask> &v, const GemmTask &t) {
+  if (t.M <= 0 || t.N <= 0) return;
+  const int nm = (t.M + GEMM_TILE - 1) / GEMM_TILE, nn = (t.N + GEMM_TILE - 1) / GEMM_TILE;
+  int RB = 1, CB = 8;
+  double best = 1e30;
+  for (int rb : {1, 2, 4, 8}) {
+    const int cb = N_XCD / rb;
+    if (rb > nm || cb > nn) continue;
+    const double h = (double)nm / rb, w = (double)nn / cb;
+    const double score = std::max(h / w, w / h);
+    if (score < best) { best = score; RB = rb; CB = cb; }
+  }
+  if (best == 1e30) { RB = std::min(nm, N_XCD); CB = 1; }
+  std::vector<std::vector<GemmTask>> q(N_XCD);
+  for (int rb = 0; rb < RB; ++rb)
+    for (int cb = 0; cb < CB; ++cb) {
+      std::vector<GemmTask> &qq = q[(rb * CB + cb) % N_XCD];
+      const int m0 = rb * nm / RB, m1 = (rb + 1) * nm / RB, n0 = cb * nn / CB, n1 = (cb + 1) * nn / CB;
+      for (int sm = m0; sm < m1; sm += SUB)
+        for (int sn = n0; sn < n1; sn += SUB)
+          for (int im = sm; im < std::min(m1, sm + SUB); ++im)
+            for (int in = sn; in < std::min(n1, sn + SUB); ++in) {
+              GemmTask u = t;
+              u.tm = im * GEMM_TILE;
+              u.tn = in * GEMM_TILE;
+              g_cmacs_acc += tile_cmacs(t, u.tm, u.tn);
+              qq.push_back(u);
+            }
+    }
+  size_t len = 0;
+  for (auto &qq : q) len = std::max(len, qq.size());
+  GemmTask empty = t;
+  empty.M = empty.N = 0;
+  empty.tm = empty.tn = 0;
+  for (size_t k = 0; k < len; ++k)
+    for (int x = 0; x < N_XCD; ++x) v.push_back(k < q[x].size() ? q[x][k] : empty);
+}
+
 GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, int M, int N, int K, int flags,
               const cplx *Cin = nullptr, int ldcin = 0, const int32_t *browmap = nullptr) {
   GemmTask t{};
@@ -224,7 +274,7 @@ GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, 
 // Schur operand stores (fronts holding both channel blocks).
 struct Off {
   int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, tri = -1, u12 = -1, l21 = -1, u1b = -1, lc1t = -1;
-  int64_t fs_x12 = -1, fs_z = -1, fs_x1b = -1, fs_xc1 = -1, sk = -1;
+  int64_t fs_x12 = -1, fs_z = -1, fs_x1b = -1, xk = -1, sk = -1;
   int64_t wsz = 0;
 };
 
@@ -335,7 +385,7 @@ static void size_plan(apf_handle *H) {
   o.assign(nf, Off());
   Arena ar;
   std::vector<std::vector<int>> release_at(H_ + 2);
-  int64_t fs = 0, ktot = 0;
+  int64_t fs = 0, ktot = 0, xck = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
     int64_t p = F.p(), b = F.b(), n = p + b, mB = F.hasB ? Mi : 0, mC = F.hasC ? Mo : 0;
@@ -357,7 +407,7 @@ static void size_plan(apf_handle *H) {
     if (F.sweep) {
       if (b) { q.fs_x12 = fs; fs += up(p * b); q.fs_z = fs; fs += up(b * p); }
       if (mB) { q.fs_x1b = fs; fs += up(p * mB); }
-      if (mC) { q.fs_xc1 = fs; fs += up(p * mC); }
+      if (mC) { q.xk = xck; xck += p; }
     }
     if (F.sfront) { q.sk = ktot; ktot += p; }
   }
@@ -373,6 +423,7 @@ static void size_plan(apf_handle *H) {
   }
   P.ws_elems = std::max<int64_t>(ar.top, 1);
   P.fs_elems = std::max<int64_t>(fs, 1);
+  P.xc_rows = xck;
   S.k_total = ktot;
 }
 
@@ -394,6 +445,8 @@ static void build_plan(apf_handle *H) {
   HIPCHK(hipMalloc(&P.sc, std::max<int64_t>(ktot * Mo, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.aval, (int64_t)d.nx * d.ny * 5 * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.perms, (int64_t)d.nx * d.ny * sizeof(int32_t)));
+  HIPCHK(hipMalloc(&P.xc, std::max<int64_t>(P.xc_rows * Mo, 1) * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.vmap, std::max<int64_t>(P.xc_rows, 1) * sizeof(int32_t)));
   HIPCHK(hipMalloc(&P.status, sizeof(int)));
   HIPCHK(hipMalloc(&P.part, 1024 * sizeof(double)));
   HIPCHK(hipMemset(P.status, 0, sizeof(int)));
@@ -535,6 +588,7 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<PanelEntry>> pe(H_ + 1);
   std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), sw(H_ + 1);
   std::vector<GemmTask> gS, vinit;
+  std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
   double cm_factor = 0, cm_sweep = 0;
   for (int f = 0; f < nf; ++f) {
@@ -600,7 +654,7 @@ static void build_plan(apf_handle *H) {
       if (b) add_tiles(g2[lvl], gemm(tri, p, u12, b, FSx(q.fs_x12), b, p, b, p, G_A_TRI_U));
       if (mB) add_tiles(g2[lvl], gemm(tri, p, u1b, mB, FSx(q.fs_x1b), mB, p, mB, p, G_A_TRI_U));
       if (b) add_tiles(g2[lvl], gemm(l21, p, tri, p, FSx(q.fs_z), p, b, p, p, G_B_TRI_L));
-      if (mC) add_tiles(g2[lvl], gemm(tri, p, lc1t, mC, FSx(q.fs_xc1), mC, p, mC, p, G_TRANS_A | G_A_TRI_L));
+      if (mC) add_tiles(g2[lvl], gemm(tri, p, lc1t, mC, P.xc + q.xk * Mo, mC, p, mC, p, G_TRANS_A | G_A_TRI_L));
     }
     cm_factor += g_cmacs_acc;
     g_cmacs_acc = 0;
@@ -618,12 +672,21 @@ static void build_plan(apf_handle *H) {
       tv.crowmap = perm;
       add_tiles(sw[lvl], ty);
       add_tiles(sw[lvl], tv);
-      if (mC) {
-        GemmTask ti = gemm(FSx(q.fs_xc1), mC, nullptr, Mi, Vf, ch, p, ch, mC, G_B_EXT | G_B_COFF);
-        ti.crowmap = perm;
-        add_tiles(vinit, ti);
-      }
+      if (mC)
+        for (int k = 0; k < p; ++k) {   // V row of xc row xk + k: sweep_row0 + perm[k]
+          vmap_base[q.xk + k] = D.sweep_row0;
+          vmap_pidx[q.xk + k] = (int32_t)(F.elim0 + k);
+        }
     }
+    cm_sweep += g_cmacs_acc * ((double)Mi / P.rhs_chunk);
+  }
+  // weighted adjoint source of every sweep front with C rows in one GEMM:
+  // V[vmap[r]] = XC[r] G, rows scattered through the permutation map
+  if (P.xc_rows) {
+    g_cmacs_acc = 0;
+    GemmTask ti = gemm(P.xc, Mo, nullptr, Mi, P.V, P.rhs_chunk, (int)P.xc_rows, P.rhs_chunk, Mo, G_B_EXT | G_B_COFF);
+    ti.crowmap = P.vmap;
+    add_tiles_xcd(vinit, ti);
     cm_sweep += g_cmacs_acc * ((double)Mi / P.rhs_chunk);
   }
   P.gemm_cmacs_factor = cm_factor;
@@ -631,7 +694,7 @@ static void build_plan(apf_handle *H) {
   // S = sum over fronts holding both channel blocks of FC1 F11^-1 F1B
   //   = (U^-T FC1^T)^T (L^-1 P^T F1B) = SC^T SB
   g_cmacs_acc = 0;
-  add_tiles(gS, gemm(P.sc, Mo, P.sb, Mi, nullptr, Mi, Mo, Mi, (int)ktot, G_TRANS_A | G_C_EXT));
+  add_tiles_xcd(gS, gemm(P.sc, Mo, P.sb, Mi, nullptr, Mi, Mo, Mi, (int)ktot, G_TRANS_A | G_C_EXT));
   P.gemm_cmacs_schur = g_cmacs_acc;
   // mixed precision: the same product split over k segments of SPLIT_K rows,
   // each accumulated in FP32 on MFMA and written to an FP64 partial block
@@ -641,8 +704,8 @@ static void build_plan(apf_handle *H) {
   for (int g = 0; g < P.nseg; ++g) {
     const int64_t k0 = (int64_t)g * SPLIT_K;
     const int kk = (int)std::min<int64_t>(SPLIT_K, ktot - k0);
-    add_tiles(gSsplit, gemm(P.sc + k0 * Mo, Mo, P.sb + k0 * Mi, Mi, P.spart + (int64_t)g * Mo * Mi, Mi, Mo, Mi,
-                            std::max(kk, 0), G_TRANS_A));
+    add_tiles_xcd(gSsplit, gemm(P.sc + k0 * Mo, Mo, P.sb + k0 * Mi, Mi, P.spart + (int64_t)g * Mo * Mi, Mi, Mo, Mi,
+                                std::max(kk, 0), G_TRANS_A));
   }
 
   // ---- assemble the blob ------------------------------------------------------
@@ -659,6 +722,8 @@ static void build_plan(apf_handle *H) {
   P.gS = bl.add(gS); P.ngS = (int)gS.size();
   P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
+  P.vmap_base = bl.add(vmap_base);
+  P.vmap_pidx = bl.add(vmap_pidx);
   P.fronts = bl.add(fd);
   P.nfronts = nf;
   HIPCHK(hipMalloc(&P.blob, bl.h.size()));
@@ -684,7 +749,8 @@ static void build_plan(apf_handle *H) {
 }
 
 static void free_plan(Plan &P) {
-  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart};
+  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
+                  P.xc, P.vmap};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   P = Plan();
@@ -1011,6 +1077,7 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     const int Mi = h->d.n_in, ch = P.rhs_chunk;
     const cplx *G = reinterpret_cast<const cplx *>(dfdS_dev);
     const double two_h2 = 2.0 * h->phys.h2;
+    HIPCHK(launch_row_map(P.vmap, P.at<int32_t>(P.vmap_base), P.at<int32_t>(P.vmap_pidx), P.perms, P.xc_rows, s));
     for (int m0 = 0, c = 0; m0 < Mi; m0 += ch, ++c) {
       const int w = std::min(ch, Mi - m0);
       Profiler &pr = h->prof;
@@ -1065,6 +1132,7 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
     for (const Front &F : S.fronts) c += F.sweep;
     *value = c;
   } else if (k == "k_total") *value = (double)S.k_total;
+  else if (k == "xc_rows") *value = (double)h->plan.xc_rows;
   else if (k == "ws_bytes") *value = (double)h->plan.ws_elems * sizeof(cplx);
   else if (k == "factor_bytes") *value = (double)h->plan.fs_elems * sizeof(cplx);
   else if (k == "schur_store_bytes") *value = (double)S.k_total * (h->d.n_in + h->d.n_out) * sizeof(cplx);

@@ -19,6 +19,8 @@ int inverse_variant(int p);   // kernel variant of a pivot block of size p
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
                        bool f32 = false);
+hipError_t launch_row_map(int32_t *map, const int32_t *base, const int32_t *pidx, const int32_t *perm, int64_t n,
+                          hipStream_t s);
 hipError_t launch_sum_partials(const cplx *part, int nseg, int64_t stride, cplx *S, int64_t n, hipStream_t s);
 hipError_t launch_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
                            double two_h2, double *grad, int accumulate, hipStream_t s);

@@ -793,6 +793,20 @@ hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx 
   return hipGetLastError();
 }
 
+// map[r] = base[r] + perm[pidx[r]]: destination rows of a GEMM whose output
+// rows follow the pivot permutations computed by the factorization.
+__global__ void k_row_map(int32_t *map, const int32_t *base, const int32_t *pidx, const int32_t *perm, int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) map[t] = base[t] + perm[pidx[t]];
+}
+
+hipError_t launch_row_map(int32_t *map, const int32_t *base, const int32_t *pidx, const int32_t *perm, int64_t n,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_map, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, map, base, pidx, perm, n);
+  return hipGetLastError();
+}
+
 // S = sum over nseg partial products (FP64), one thread per entry.
 __global__ void k_sum_partials(const double2 *part, int nseg, int64_t stride, double2 *S, int64_t n) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
