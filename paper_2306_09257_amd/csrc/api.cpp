@@ -824,17 +824,13 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
   }
 }
 
-// The channel-by-channel Schur block S = SC^T SB: one FP64 MFMA GEMM, or (mixed)
-// FP32-MFMA partial products over k segments summed in FP64.
+// The channel-by-channel Schur block S = SC^T SB: partial products over k
+// segments (FP64 MFMA, or FP32 MFMA on the mixed path) summed in FP64.
 static void enqueue_schur(const Plan &P, bool f32, double *S_dev, Profiler &pr, hipStream_t s, int Mo, int Mi) {
-  if (!f32) {
-    pr.run(P_GEMM_SCHUR, s, [&] {
-      return launch_gemm(P.at<GemmTask>(P.gS), P.ngS, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s);
-    });
-    return;
-  }
+  // k split into segments of SPLIT_K rows: shorter, more numerous tasks than
+  // one K_total-deep tile each, summed in FP64 afterwards
   pr.run(P_GEMM_SCHUR, s, [&] {
-    hipError_t e = launch_gemm(P.at<GemmTask>(P.gSsplit), P.ngSsplit, 0, INT_MAX, nullptr, s, true);
+    hipError_t e = launch_gemm(P.at<GemmTask>(P.gSsplit), P.ngSsplit, 0, INT_MAX, nullptr, s, f32);
     if (e == hipSuccess)
       e = launch_sum_partials(P.spart, P.nseg, (int64_t)Mo * Mi, reinterpret_cast<cplx *>(S_dev), (int64_t)Mo * Mi, s);
     return e;

@@ -769,12 +769,14 @@ int inverse_variant(int p) {
   return 7;
 }
 
+// Small blocks (p <= 48, the leaves and short separators) run on one wave:
+// the per-step barriers are then free and more fronts fit on a CU.
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s) {
   if (n == 0) return hipSuccess;
   switch (variant) {
-    case 0: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 1, 1>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
-    case 1: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 2, 2>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
-    case 2: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 3, 3>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
+    case 0: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 2, 2>), dim3(n), dim3(64), 0, s, fr, ids, status); break;
+    case 1: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 4, 4>), dim3(n), dim3(64), 0, s, fr, ids, status); break;
+    case 2: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 6, 6>), dim3(n), dim3(64), 0, s, fr, ids, status); break;
     case 3: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
     case 4: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
     case 5: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
