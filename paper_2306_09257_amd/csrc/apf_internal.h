@@ -96,12 +96,18 @@ struct ChanParams {
   int32_t m, is_source;
 };
 
+// Extend-add row task (child, row | flags) of the channel panels: the first
+// writer of a parent panel row stores, later writers add.
+constexpr int32_t EXT_STORE_B = 1 << 30;   // store this row of the B panel
+constexpr int32_t EXT_STORE_C = 1 << 29;   // store this row of the C^T panel
+constexpr int32_t EXT_ROW_MASK = EXT_STORE_C - 1;
+
 struct AsmEntry {          // one stencil entry of A: *src is added at dest
   const cplx *src;         // Aval + node*5 + direction (0 centre, 1 x-1, 2 x+1, 3 y-1, 4 y+1)
   cplx *dest;
 };
 
-struct PanelEntry {        // one source (B) or projection (C) node: a whole row of the panel
+struct PanelEntry {        // one source (B) or projection (C) node: a whole row of the panel, stored
   int32_t node, pad;
   cplx *dest;
   const ChanParams *cp;

@@ -511,18 +511,44 @@ static void build_plan(apf_handle *H) {
     cp_src = reinterpret_cast<const ChanParams *>(P.chan);
     cp_prj = cp_src + 1;
   }
+  // Channel panel rows: the first writer of a row stores, later writers add.
+  // In launch order the writers are the channel assembly (pivot rows on the
+  // source or projection row), the children of slot 0, those of slot 1.
+  // wrB/wrC[f][k] marks row k of front f as written by one of them.
+  std::vector<std::vector<uint8_t>> wrB(nf), wrC(nf);
   P.lv.assign(H_ + 1, LevelTasks());
   for (int lvl = 0; lvl <= H_; ++lvl) {
     std::vector<int32_t> kids[2], inv[N_INV_VARIANTS];
     std::vector<int2> rows[2];
     for (int f : S.levels[lvl]) {
       const Front &F = S.fronts[f];
+      std::vector<uint8_t> &wb = wrB[f], &wc = wrC[f];
+      if (F.hasB) wb.assign(F.p() + F.b(), 0);
+      if (F.hasC) wc.assign(F.p() + F.b(), 0);
+      for (int k = 0; k < F.p(); ++k) {
+        const int y = F.piv[k] / d.nx;
+        if (F.hasB && y == d.src_row) wb[k] = 1;
+        if (F.hasC && y == d.prj_row) wc[k] = 1;
+      }
       for (int c = 0; c < F.nchild; ++c) {
         const Front &Ch = S.fronts[F.child[c]];
         if (Ch.b() == 0) continue;
+        if ((Ch.hasB && !F.hasB) || (Ch.hasC && !F.hasC)) throw std::runtime_error("child panel without parent panel");
         kids[c].push_back(F.child[c]);
         if (Ch.hasB || Ch.hasC)
-          for (int r = 0; r < Ch.b(); ++r) rows[c].push_back(make_int2(F.child[c], r));
+          for (int r = 0; r < Ch.b(); ++r) {
+            const int pr = Ch.rmap[r];
+            int32_t flag = 0;
+            if (Ch.hasB) {
+              if (!wb[pr]) flag |= EXT_STORE_B;
+              wb[pr] = 1;
+            }
+            if (Ch.hasC) {
+              if (!wc[pr]) flag |= EXT_STORE_C;
+              wc[pr] = 1;
+            }
+            rows[c].push_back(make_int2(F.child[c], r | flag));
+          }
       }
       if (F.p() > 0) inv[inverse_variant(F.p())].push_back(f);
     }
@@ -600,11 +626,23 @@ static void build_plan(apf_handle *H) {
       for (int64_t o0 = 0; o0 < cnt; o0 += ZERO_CHUNK) zr[lvl].push_back({ptr + o0, std::min(ZERO_CHUNK, cnt - o0)});
     };
     zero(D.core, (int64_t)n * n);
-    if (mB) zero(D.bp_piv, (int64_t)n * mB);
-    if (mC) {
-      zero(D.cpt_piv, (int64_t)p * mC);
-      if (b) zero(D.cpt_bnd, (int64_t)b * mC);
-    }
+    // Channel panel rows no writer touches are zeroed: pivot rows always (the
+    // phase-1 products read them), boundary rows only when some boundary row
+    // is written; otherwise the phase-2 update does not read them (no Cin).
+    auto zero_rows = [&](cplx *piv0, cplx *bnd0, int m, const std::vector<uint8_t> &w) {
+      bool bnd_read = false;
+      for (int k = p; k < n; ++k) bnd_read = bnd_read || w[k];
+      for (int k = 0; k < n;) {
+        if (w[k] || (k >= p && !bnd_read)) { ++k; continue; }
+        int e = k + 1;
+        while (e < n && e != p && !w[e]) ++e;
+        zero(k < p ? piv0 + (int64_t)k * m : bnd0 + (int64_t)(k - p) * m, (int64_t)(e - k) * m);
+        k = e;
+      }
+      return bnd_read;
+    };
+    const bool cinB = mB ? zero_rows(D.bp_piv, D.bp_bnd, mB, wrB[f]) : false;
+    const bool cinC = mC ? zero_rows(D.cpt_piv, D.cpt_bnd, mC, wrC[f]) : false;
     // stencil entries owned by this front (the earlier-eliminated end of each edge)
     for (int k = 0; k < p; ++k) loc[F.piv[k]] = k;
     for (int k = 0; k < b; ++k) loc[F.bnd[k]] = p + k;
@@ -648,8 +686,12 @@ static void build_plan(apf_handle *H) {
     if (b) add_tiles(g1[lvl], gemm(F21, n, tri, p, l21, p, b, p, p, G_B_TRI_U));
     if (mC) add_tiles(g1[lvl], gemm(tri, p, D.cpt_piv, mC, lc1t, mC, p, mC, p, G_TRANS_A | G_A_TRI_U));
     if (b) add_tiles(g2[lvl], gemm(l21, p, u12, b, F22, n, b, b, p, G_NEG | G_CIN, F22, n));
-    if (b && mB) add_tiles(g2[lvl], gemm(l21, p, u1b, mB, D.bp_bnd, mB, b, mB, p, G_NEG | G_CIN, D.bp_bnd, mB));
-    if (b && mC) add_tiles(g2[lvl], gemm(u12, b, lc1t, mC, D.cpt_bnd, mC, b, mC, p, G_TRANS_A | G_NEG | G_CIN, D.cpt_bnd, mC));
+    if (b && mB)
+      add_tiles(g2[lvl], gemm(l21, p, u1b, mB, D.bp_bnd, mB, b, mB, p, G_NEG | (cinB ? G_CIN : 0),
+                              cinB ? D.bp_bnd : nullptr, mB));
+    if (b && mC)
+      add_tiles(g2[lvl], gemm(u12, b, lc1t, mC, D.cpt_bnd, mC, b, mC, p, G_TRANS_A | G_NEG | (cinC ? G_CIN : 0),
+                              cinC ? D.cpt_bnd : nullptr, mC));
     if (F.sweep) {
       if (b) add_tiles(g2[lvl], gemm(tri, p, u12, b, FSx(q.fs_x12), b, p, b, p, G_A_TRI_U));
       if (mB) add_tiles(g2[lvl], gemm(tri, p, u1b, mB, FSx(q.fs_x1b), mB, p, mB, p, G_A_TRI_U));

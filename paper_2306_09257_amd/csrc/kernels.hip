@@ -108,6 +108,7 @@ __device__ double2 channel_value(const Phys &P, int a, int i, double eps_medium,
 }
 
 // B rows: -2i sqrt(sin q_a) phi_a(i); C^T rows: sqrt(sin q_b) conj(phi_b(i)).
+// Each row is stored whole: the assembly is the first writer of its rows.
 __global__ void k_assemble_panel(const PanelEntry *e, int n) {
   const PanelEntry E = e[blockIdx.x];
   const ChanParams &cp = *E.cp;
@@ -118,7 +119,7 @@ __global__ void k_assemble_panel(const PanelEntry *e, int n) {
   for (int a = threadIdx.x; a < m; a += blockDim.x) {
     double2 v = channel_value(P, cp.orders[a], i, eps_m, !is_source);
     if (is_source) v = make_double2(2.0 * v.y, -2.0 * v.x);   // times -2i
-    st2(E.dest + a, cadd(ld2(E.dest + a), v));
+    st2(E.dest + a, v);
   }
 }
 
@@ -126,7 +127,8 @@ __global__ void k_assemble_panel(const PanelEntry *e, int n) {
 // Extend-add: scatter-add one child's contribution block into its parent.
 // k_extadd_core: one block per child, the b x b core block.
 // k_extadd_panel: one block per (child, boundary row) of a child that carries
-// channel panels: its B row and C^T row.
+// channel panels: its B row and C^T row, stored or added as the task's flags
+// say.
 // Children of one parent are processed in separate launches (slots), so no
 // two blocks of a launch write the same parent entry.
 // ---------------------------------------------------------------------------
@@ -142,21 +144,40 @@ __global__ void k_extadd_core(const FrontDev *fr, const int32_t *kids) {
   }
 }
 
+// Moves one panel row: d = s (store) or d += s.  Four loads per thread are
+// issued before any store, so that the row's latency overlaps.
+__device__ __forceinline__ void row_extadd(cplx *__restrict__ d, const cplx *__restrict__ src, int m, bool store) {
+  for (int b0 = threadIdx.x; b0 < m; b0 += 4 * blockDim.x) {
+    double2 v[4], w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = b0 + u * blockDim.x;
+      v[u] = i < m ? ld2(src + i) : make_double2(0.0, 0.0);
+      w[u] = (i < m && !store) ? ld2(d + i) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = b0 + u * blockDim.x;
+      if (i < m) st2(d + i, cadd(v[u], w[u]));
+    }
+  }
+}
+
 __global__ void k_extadd_panel(const FrontDev *fr, const int2 *tasks) {
   const int2 t = tasks[blockIdx.x];
   const FrontDev C = fr[t.x];
   const FrontDev P = fr[C.parent];
-  const int r = t.y;
+  const int r = t.y & EXT_ROW_MASK;
   const int pr = C.rmap[r];
   if (C.mB) {
     const cplx *sb = C.bp_bnd + (int64_t)r * C.mB;
     cplx *db = pr < P.p ? P.bp_piv + (int64_t)pr * P.mB : P.bp_bnd + (int64_t)(pr - P.p) * P.mB;
-    for (int s = threadIdx.x; s < C.mB; s += blockDim.x) st2(db + s, cadd(ld2(db + s), ld2(sb + s)));
+    row_extadd(db, sb, C.mB, t.y & EXT_STORE_B);
   }
   if (C.mC) {
     const cplx *sc = C.cpt_bnd + (int64_t)r * C.mC;
     cplx *dc = pr < P.p ? P.cpt_piv + (int64_t)pr * P.mC : P.cpt_bnd + (int64_t)(pr - P.p) * P.mC;
-    for (int s = threadIdx.x; s < C.mC; s += blockDim.x) st2(dc + s, cadd(ld2(dc + s), ld2(sc + s)));
+    row_extadd(dc, sc, C.mC, t.y & EXT_STORE_C);
   }
 }
 
