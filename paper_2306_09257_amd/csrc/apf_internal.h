@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/apf.h"
 
 namespace apf {
@@ -101,6 +103,11 @@ struct ChanParams {
 constexpr int32_t EXT_STORE_B = 1 << 30;   // store this row of the B panel
 constexpr int32_t EXT_STORE_C = 1 << 29;   // store this row of the C^T panel
 constexpr int32_t EXT_ROW_MASK = EXT_STORE_C - 1;
+
+// Core extend-add tasks (child, first row): a task moves core_rows_per_task(b)
+// consecutive rows of the child's b x b contribution block.
+constexpr int EXT_CORE_ELEMS = 4096;
+inline __host__ __device__ int core_rows_per_task(int b) { return b >= EXT_CORE_ELEMS ? 1 : EXT_CORE_ELEMS / b; }
 
 struct AsmEntry {          // one stencil entry of A: *src is added at dest
   const cplx *src;         // Aval + node*5 + direction (0 centre, 1 x-1, 2 x+1, 3 y-1, 4 y+1)

@@ -518,8 +518,8 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<uint8_t>> wrB(nf), wrC(nf);
   P.lv.assign(H_ + 1, LevelTasks());
   for (int lvl = 0; lvl <= H_; ++lvl) {
-    std::vector<int32_t> kids[2], inv[N_INV_VARIANTS];
-    std::vector<int2> rows[2];
+    std::vector<int32_t> inv[N_INV_VARIANTS];
+    std::vector<int2> kids[2], rows[2];
     for (int f : S.levels[lvl]) {
       const Front &F = S.fronts[f];
       std::vector<uint8_t> &wb = wrB[f], &wc = wrC[f];
@@ -534,7 +534,7 @@ static void build_plan(apf_handle *H) {
         const Front &Ch = S.fronts[F.child[c]];
         if (Ch.b() == 0) continue;
         if ((Ch.hasB && !F.hasB) || (Ch.hasC && !F.hasC)) throw std::runtime_error("child panel without parent panel");
-        kids[c].push_back(F.child[c]);
+        for (int r0 = 0; r0 < Ch.b(); r0 += core_rows_per_task(Ch.b())) kids[c].push_back(make_int2(F.child[c], r0));
         if (Ch.hasB || Ch.hasC)
           for (int r = 0; r < Ch.b(); ++r) {
             const int pr = Ch.rmap[r];
@@ -851,7 +851,7 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     pr.run(P_EXTADD, s, [&] {
       hipError_t e = hipSuccess;
       for (int c = 0; c < 2 && e == hipSuccess; ++c)
-        e = launch_extend_add(fr, (const int32_t *)at(L.ext[c]), L.next[c], (const int2 *)at(L.extrow[c]),
+        e = launch_extend_add(fr, (const int2 *)at(L.ext[c]), L.next[c], (const int2 *)at(L.extrow[c]),
                               L.nextrow[c], s);
       return e;
     });
@@ -968,8 +968,8 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     std::vector<ZeroRange> zr;
     std::vector<AsmEntry> ae;
     std::vector<PanelEntry> pe;
-    std::vector<int32_t> kids[2], inv[N_INV_VARIANTS];
-    std::vector<int2> rows[2];
+    std::vector<int32_t> inv[N_INV_VARIANTS];
+    std::vector<int2> kids[2], rows[2];
     std::vector<GemmTask> g1, g2;
     for (size_t i = 0; i < hs.size(); ++i) {
       const Plan &P = hs[i]->plan;
@@ -979,7 +979,7 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
       auto a = fetch<AsmEntry>(P.blob, L.scat, L.nscat); ae.insert(ae.end(), a.begin(), a.end());
       auto pp = fetch<PanelEntry>(P.blob, L.pan, L.npan); pe.insert(pe.end(), pp.begin(), pp.end());
       for (int c = 0; c < 2; ++c) {
-        for (int32_t k : fetch<int32_t>(P.blob, L.ext[c], L.next[c])) kids[c].push_back(k + base[i]);
+        for (int2 k : fetch<int2>(P.blob, L.ext[c], L.next[c])) kids[c].push_back(make_int2(k.x + base[i], k.y));
         for (int2 r : fetch<int2>(P.blob, L.extrow[c], L.nextrow[c])) rows[c].push_back(make_int2(r.x + base[i], r.y));
       }
       for (int v = 0; v < N_INV_VARIANTS; ++v)

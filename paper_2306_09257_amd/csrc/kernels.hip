@@ -125,22 +125,33 @@ __global__ void k_assemble_panel(const PanelEntry *e, int n) {
 
 // ---------------------------------------------------------------------------
 // Extend-add: scatter-add one child's contribution block into its parent.
-// k_extadd_core: one block per child, the b x b core block.
+// k_extadd_core: one block per (child, group of rows) of the b x b core block.
 // k_extadd_panel: one block per (child, boundary row) of a child that carries
 // channel panels: its B row and C^T row, stored or added as the task's flags
 // say.
 // Children of one parent are processed in separate launches (slots), so no
 // two blocks of a launch write the same parent entry.
 // ---------------------------------------------------------------------------
-__global__ void k_extadd_core(const FrontDev *fr, const int32_t *kids) {
-  const FrontDev C = fr[kids[blockIdx.x]];
+__global__ void k_extadd_core(const FrontDev *fr, const int2 *tasks) {
+  const int2 t = tasks[blockIdx.x];
+  const FrontDev C = fr[t.x];
   const FrontDev P = fr[C.parent];
   const int nc = C.p + C.b, np = P.p + P.b, b = C.b;
-  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-    const int r = e / b, c = e - r * b;
-    const cplx *src = C.core + (int64_t)(C.p + r) * nc + C.p + c;
-    cplx *d = P.core + (int64_t)C.rmap[r] * np + C.rmap[c];
-    st2(d, cadd(ld2(d), ld2(src)));
+  const int r0 = t.y, ne = min(core_rows_per_task(b), b - r0) * b;
+  for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+    double2 v[4], w[4];
+    cplx *d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * blockDim.x;
+      const int r = r0 + e / b, c = e - (e / b) * b;
+      d[u] = P.core + (int64_t)C.rmap[e < ne ? r : r0] * np + C.rmap[e < ne ? c : 0];
+      v[u] = e < ne ? ld2(C.core + (int64_t)(C.p + r) * nc + C.p + c) : make_double2(0.0, 0.0);
+      w[u] = e < ne ? ld2(d[u]) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + u * blockDim.x < ne) st2(d[u], cadd(v[u], w[u]));
   }
 }
 
@@ -766,7 +777,7 @@ hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n);
   return hipGetLastError();
 }
-hipError_t launch_extend_add(const FrontDev *fr, const int32_t *kids, int nkids, const int2 *rows, int nrows,
+hipError_t launch_extend_add(const FrontDev *fr, const int2 *kids, int nkids, const int2 *rows, int nrows,
                              hipStream_t s) {
   if (nkids > 0) {
     hipLaunchKernelGGL(k_extadd_core, dim3(nkids), dim3(256), 0, s, fr, kids);
