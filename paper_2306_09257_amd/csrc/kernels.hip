@@ -564,6 +564,8 @@ struct GemmPrec<false> {
   // D layout: lane l, element q -> row (l/16) + 4q, column l%16
   static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
   static __device__ __forceinline__ lds_t cvt(double2 v) { return v; }
+  // LDS column swizzle of A (16-byte entries, 8 per 128-byte bank row)
+  static __device__ __forceinline__ int swz(int k) { return ((k >> 2) & 3) << 1; }
 };
 template <>
 struct GemmPrec<true> {
@@ -575,6 +577,8 @@ struct GemmPrec<true> {
   // D layout: lane l, element q -> row 4(l/16) + q, column l%16
   static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
   static __device__ __forceinline__ lds_t cvt(double2 v) { return make_float2((float)v.x, (float)v.y); }
+  // LDS column swizzle of A (8-byte entries, 16 per 128-byte bank row)
+  static __device__ __forceinline__ int swz(int k) { return ((k >> 2) & 3) << 2; }
 };
 
 template <bool F32>
@@ -624,44 +628,48 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
         if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gi, gk, gi < M && gk < K, ra[q]);
       }
     } else {
-      const int k = tid >> 4, iq = (tid & 15) * 4;
+      // stored k-major: 16 lanes read 16 consecutive entries of one row
+      const int k = tid >> 4, i0 = tid & 15;
       const int gk = k0 + k;
       for (int q = 0; q < 4; ++q) {
-        const int gi = T.tm + iq + q;
+        const int gi = T.tm + i0 + 16 * q;
         ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gk * T.lda + gi) : make_double2(0.0, 0.0);
         if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gk, gi, gi < M && gk < K, ra[q]);
       }
     }
     {
-      const int k = tid >> 4, jq = (tid & 15) * 4;
+      const int k = tid >> 4, j0 = tid & 15;
       const int gk = k0 + k;
       const cplx *row = nullptr;
       if (gk < K) row = Bp + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb;
       for (int q = 0; q < 4; ++q) {
-        const int gj = T.tn + jq + q;
+        const int gj = T.tn + j0 + 16 * q;
         rb[q] = (row && gj < N) ? ld2(row + gj) : make_double2(0.0, 0.0);
         if (triB) rb[q] = tri_mask(fl & G_B_TRI_L, gk, gj, gk < K && gj < N, rb[q]);
       }
     }
     __syncthreads();
+    // As columns are XOR-swizzled by GP::swz(k): the transposing stores of a
+    // row-major A then spread over all LDS banks, and a row read stays
+    // conflict-free (the swizzle permutes within aligned groups of columns)
     if (!transA) {
       const int i = tid >> 2, kq = (tid & 3) * 4;
-      for (int q = 0; q < 4; ++q) As[kq + q][i] = GP::cvt(ra[q]);
+      for (int q = 0; q < 4; ++q) As[kq + q][i ^ GP::swz(kq + q)] = GP::cvt(ra[q]);
     } else {
-      const int k = tid >> 4, iq = (tid & 15) * 4;
-      for (int q = 0; q < 4; ++q) As[k][iq + q] = GP::cvt(ra[q]);
+      const int k = tid >> 4, i0 = tid & 15;
+      for (int q = 0; q < 4; ++q) As[k][(i0 + 16 * q) ^ GP::swz(k)] = GP::cvt(ra[q]);
     }
     {
-      const int k = tid >> 4, jq = (tid & 15) * 4;
-      for (int q = 0; q < 4; ++q) Bs[k][jq + q] = GP::cvt(rb[q]);
+      const int k = tid >> 4, j0 = tid & 15;
+      for (int q = 0; q < 4; ++q) Bs[k][j0 + 16 * q] = GP::cvt(rb[q]);
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       const int kx = kk + (lane >> 4);
       lds_t a[2], b[2];
-      a[0] = As[kx][wr + (lane & 15)];
-      a[1] = As[kx][wr + 16 + (lane & 15)];
+      a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
+      a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
       b[0] = Bs[kx][wc + (lane & 15)];
       b[1] = Bs[kx][wc + 16 + (lane & 15)];
 #pragma unroll
