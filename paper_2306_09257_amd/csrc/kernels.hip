@@ -31,6 +31,15 @@ __device__ __forceinline__ double2 csel(bool c, double2 a, double2 b) {
   return make_double2(c ? a.x : b.x, c ? a.y : b.y);
 }
 __device__ __forceinline__ double2 ld2(const cplx *p) { return *reinterpret_cast<const double2 *>(p); }
+// the same memory seen through the global address space (global_load
+// instead of flat_load)
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const dvec2 gcplx;
+__device__ __forceinline__ gcplx *as_global(const cplx *p) { return (gcplx *)p; }
+__device__ __forceinline__ double2 ldg(gcplx *p) {
+  const dvec2 v = *p;
+  return make_double2(v.x, v.y);
+}
 __device__ __forceinline__ void st2(cplx *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
 
 // ---------------------------------------------------------------------------
@@ -617,9 +626,26 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   kbeg = (kbeg / KT) * KT;
   const bool triA = fl & (G_A_TRI_L | G_A_TRI_U), triB = fl & (G_B_TRI_L | G_B_TRI_U);
 
+  // interior tiles (no edge in M or N, no triangular mask) load their k
+  // slabs without per-element conditions while the slab is full in K
+  const bool full_mn = T.tm + 64 <= M && T.tn + 64 <= N && !triA && !triB;
   for (int k0 = kbeg; k0 < kend; k0 += KT) {
     double2 ra[4], rb[4];
-    if (!transA) {
+    if (full_mn && k0 + KT <= K) {
+      if (!transA) {
+        const int i = tid >> 2, kq = (tid & 3) * 4;
+        const gcplx *a = as_global(T.A) + (int64_t)(T.tm + i) * T.lda + k0 + kq;
+        for (int q = 0; q < 4; ++q) ra[q] = ldg(a + q);
+      } else {
+        const int k = tid >> 4, i0 = tid & 15;
+        const gcplx *a = as_global(T.A) + (int64_t)(k0 + k) * T.lda + T.tm + i0;
+        for (int q = 0; q < 4; ++q) ra[q] = ldg(a + 16 * q);
+      }
+      const int k = tid >> 4, j0 = tid & 15;
+      const int gk = k0 + k;
+      const gcplx *b = as_global(Bp) + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j0;
+      for (int q = 0; q < 4; ++q) rb[q] = ldg(b + 16 * q);
+    } else if (!transA) {
       const int i = tid >> 2, kq = (tid & 3) * 4;
       const int gi = T.tm + i;
       for (int q = 0; q < 4; ++q) {
