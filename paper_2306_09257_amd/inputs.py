@@ -208,6 +208,19 @@ def batch_uneven(seed: int = 3, count: int = 64, nx_max: int = 4800, nx_step: in
     return out
 
 
+def design_loop(seed: int = 4, nx: int = 12000):
+    """Differentiation-in-the-loop workload: 12,000 x 140 grid (1.68M unknowns),
+    1,199 x 1,199 channels, 480,000 design pixels.  Initial design
+    eps = 2.5 + 0.1 N(0,1) clipped to [1, 4]; w ~ U[0,1]."""
+    prob = make_problem(nx, 140)
+    rng = np.random.default_rng(seed)
+    eps = prob.background_eps()
+    eps[prob.design_row0:prob.design_row1, :] = np.clip(
+        2.5 + 0.1 * rng.standard_normal((prob.n_design_rows, prob.nx)), 1.0, 4.0)
+    w = weights_uniform(prob, rng)
+    return prob, eps, w
+
+
 def tiny_problem(nx=24, ny=60, seed=0, layout=None, n_orders=None, **kw):
     """Small grids for oracle pins and parity tests."""
     lay = layout
