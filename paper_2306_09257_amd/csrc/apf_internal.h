@@ -134,6 +134,12 @@ enum GemmFlags : int32_t {
   G_A_TRI_U = 256,         // stored A: r <= c entries, zero below
   G_B_TRI_L = 512,         // stored B: r > c entries, unit diagonal, zero above
   G_B_TRI_U = 1024,        // stored B: r <= c entries, zero below
+  // gradient contraction in the epilogue: for every output row i with
+  // auxmap[i] >= 0, the partial sum of Re(C(i,j) aux(i,j)) over the 32
+  // columns of one wave goes to part[auxmap[i] * nblk + column / 32]
+  // (aux has the layout of C)
+  G_CONTRACT = 2048,
+  G_NO_STORE = 4096,       // C itself is not written (only the contraction)
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
@@ -147,6 +153,8 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
   int32_t lda, ldb, ldcin, ldc;
   int32_t flags;
   int32_t tm, tn;
+  const cplx *aux;         // G_CONTRACT: the second factor of the contraction
+  const int32_t *auxmap;   // G_CONTRACT: row -> contraction slot, or -1
 };
 
 struct ZeroRange { cplx *ptr; int64_t n; };

@@ -91,8 +91,8 @@ struct Blob {
 };
 
 struct LevelTasks {
-  int64_t zero = -1, scat = -1, pan = -1, ext[2] = {-1, -1}, extrow[2] = {-1, -1}, g1 = -1, g2 = -1, sw = -1;
-  int nzero = 0, nscat = 0, npan = 0, next[2] = {0, 0}, nextrow[2] = {0, 0}, ng1 = 0, ng2 = 0, nsw = 0;
+  int64_t zero = -1, scat = -1, pan = -1, ext[2] = {-1, -1}, extrow[2] = {-1, -1}, g1 = -1, g2 = -1;
+  int nzero = 0, nscat = 0, npan = 0, next[2] = {0, 0}, nextrow[2] = {0, 0}, ng1 = 0, ng2 = 0;
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
   LevelTasks() {
@@ -169,14 +169,21 @@ struct Plan {
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
   int rhs_chunk = 0;
   std::vector<LevelTasks> lv;
-  int64_t gS = -1, vinit = -1, drows = -1, fronts = -1, gSsplit = -1, vmap_base = -1, vmap_pidx = -1;
+  int64_t gS = -1, vinit = -1, gidx = -1, fronts = -1, gSsplit = -1, vmap_base = -1, vmap_pidx = -1;
   int64_t xc_rows = 0;        // rows of the weighted-adjoint operand store (sweep fronts with C rows)
   cplx *xc = nullptr;         // L^-T U^-T FC1^T of those fronts, stacked: xc_rows x n_out
   int32_t *vmap = nullptr;    // V row of every xc row (rebuilt from the pivot permutations per call)
   int nfronts = 0, ngSsplit = 0, nseg = 0;
   cplx *spart = nullptr;      // FP64 partial Schur blocks of the mixed path (nseg x n_out x n_in)
   char *chan = nullptr;       // ChanParams of the source and projection rows, then their orders
-  int ngS = 0, nvinit = 0, ndesign = 0;
+  int ngS = 0, nvinit = 0;
+  // gradient sweeps: launch t holds the Y tiles of level H - t and the
+  // adjoint tiles (with the contraction) of level H - t + 1
+  std::vector<int64_t> swl;
+  std::vector<int> nswl;
+  int64_t ndesign = 0;        // design pixels (contraction slots)
+  int nblk = 0;               // 32-column contraction partials per pixel
+  double *gpart = nullptr;    // ndesign x nblk
   template <class T>
   T *at(int64_t off) const { return off < 0 ? nullptr : reinterpret_cast<T *>(blob + off); }
 };
@@ -487,11 +494,16 @@ static void build_plan(apf_handle *H) {
     }
   }
   {
-    std::vector<int32_t> dr;
+    // contraction slot of every sweep row: the design pixel (row-major over
+    // the design rows) or -1
+    std::vector<int32_t> gi(std::max<int64_t>(S.n_sweep_rows, 1), -1);
     for (int y = d.design_row0; y < d.design_row1; ++y)
-      for (int x = 0; x < d.nx; ++x) dr.push_back((int32_t)S.node_sweep_row[(int64_t)y * d.nx + x]);
-    P.ndesign = (int)dr.size();
-    P.drows = ib.add(dr);
+      for (int x = 0; x < d.nx; ++x)
+        gi[S.node_sweep_row[(int64_t)y * d.nx + x]] = (int32_t)((int64_t)(y - d.design_row0) * d.nx + x);
+    P.gidx = ib.add(gi);
+    P.ndesign = (int64_t)(d.design_row1 - d.design_row0) * d.nx;
+    P.nblk = 2 * ((Mi + 63) / 64);
+    HIPCHK(hipMalloc(&P.gpart, std::max<int64_t>(P.ndesign * P.nblk, 1) * sizeof(double)));
   }
   // channel parameters of the two panels, in a small buffer of their own
   const ChanParams *cp_src, *cp_prj;
@@ -612,7 +624,7 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<ZeroRange>> zr(H_ + 1);
   std::vector<std::vector<AsmEntry>> ae(H_ + 1);
   std::vector<std::vector<PanelEntry>> pe(H_ + 1);
-  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), sw(H_ + 1);
+  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), swY(H_ + 1), swL(H_ + 1);
   std::vector<GemmTask> gS, vinit;
   std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
@@ -703,17 +715,25 @@ static void build_plan(apf_handle *H) {
     // gradient sweeps (root to leaves), with F11^-1 = U^-1 L^-1 P^T:
     //   Y_f   = X1B_f - X12 Y_bnd
     //   Lam_f = P (XC1 G - Z^T Lam_bnd)      (rows scattered through perm)
+    // The adjoint tiles also form the gradient partials Re(Lam Y) of their
+    // design rows; fronts whose children do not take part in the sweeps do
+    // not store Lam (nothing reads it).
     if (F.sweep) {
       const int ch = P.rhs_chunk;
       cplx *Xf = P.X + (int64_t)D.sweep_row0 * ch, *Vf = P.V + (int64_t)D.sweep_row0 * ch;
       const int32_t *bm = reinterpret_cast<const int32_t *>((intptr_t)bndrow_off[f]);  // rebased below
       GemmTask ty = gemm(b ? FSx(q.fs_x12) : nullptr, b, P.X, ch, Xf, ch, p, ch, b,
                          G_NEG | (mB ? G_CIN | G_CIN_COFF : 0), mB ? FSx(q.fs_x1b) : nullptr, mB, b ? bm : nullptr);
+      bool lam_read = false;
+      for (int c = 0; c < F.nchild; ++c) lam_read = lam_read || S.fronts[F.child[c]].sweep;
       GemmTask tv = gemm(b ? FSx(q.fs_z) : nullptr, p, P.V, ch, Vf, ch, p, ch, b,
-                         G_TRANS_A | G_NEG | (mC ? G_CIN : 0), mC ? Vf : nullptr, ch, b ? bm : nullptr);
+                         G_TRANS_A | G_NEG | (mC ? G_CIN : 0) | G_CONTRACT | (lam_read ? 0 : G_NO_STORE),
+                         mC ? Vf : nullptr, ch, b ? bm : nullptr);
       tv.crowmap = perm;
-      add_tiles(sw[lvl], ty);
-      add_tiles(sw[lvl], tv);
+      tv.aux = Xf;
+      tv.auxmap = reinterpret_cast<const int32_t *>((intptr_t)(P.gidx + (int64_t)D.sweep_row0 * 4));  // rebased below
+      add_tiles(swY[lvl], ty);
+      add_tiles(swL[lvl], tv);
       if (mC)
         for (int k = 0; k < p; ++k) {   // V row of xc row xk + k: sweep_row0 + perm[k]
           vmap_base[q.xk + k] = D.sweep_row0;
@@ -759,7 +779,15 @@ static void build_plan(apf_handle *H) {
     L.pan = bl.add(pe[lvl]); L.npan = (int)pe[lvl].size();
     L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
     L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
-    L.sw = bl.add(sw[lvl]); L.nsw = (int)sw[lvl].size();
+  }
+  P.swl.assign(H_ + 2, -1);
+  P.nswl.assign(H_ + 2, 0);
+  for (int t = 0; t <= H_ + 1; ++t) {
+    std::vector<GemmTask> m;
+    if (H_ - t >= 0) m.insert(m.end(), swY[H_ - t].begin(), swY[H_ - t].end());
+    if (H_ - t + 1 <= H_) m.insert(m.end(), swL[H_ - t + 1].begin(), swL[H_ - t + 1].end());
+    P.swl[t] = bl.add(m);
+    P.nswl[t] = (int)m.size();
   }
   P.gS = bl.add(gS); P.ngS = (int)gS.size();
   P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
@@ -780,9 +808,12 @@ static void build_plan(apf_handle *H) {
       if (rmap_off[f] >= 0) rebase(fdv[f].rmap);
       else fdv[f].rmap = nullptr;
     }
-    for (int lvl = 0; lvl <= H_; ++lvl) {
-      GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + P.lv[lvl].sw);
-      for (int k = 0; k < P.lv[lvl].nsw; ++k) rebase(t[k].browmap);
+    for (size_t l = 0; l < P.swl.size(); ++l) {
+      GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + P.swl[l]);
+      for (int k = 0; k < P.nswl[l]; ++k) {
+        rebase(t[k].browmap);
+        rebase(t[k].auxmap);
+      }
     }
   }
   (void)ib_size;
@@ -792,7 +823,7 @@ static void build_plan(apf_handle *H) {
 
 static void free_plan(Plan &P) {
   void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
-                  P.xc, P.vmap};
+                  P.xc, P.vmap, P.gpart};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   P = Plan();
@@ -1116,19 +1147,17 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     const cplx *G = reinterpret_cast<const cplx *>(dfdS_dev);
     const double two_h2 = 2.0 * h->phys.h2;
     HIPCHK(launch_row_map(P.vmap, P.at<int32_t>(P.vmap_base), P.at<int32_t>(P.vmap_pidx), P.perms, P.xc_rows, s));
-    for (int m0 = 0, c = 0; m0 < Mi; m0 += ch, ++c) {
+    Profiler &pr = h->prof;
+    const bool f32 = h->mixed;
+    for (int m0 = 0; m0 < Mi; m0 += ch) {
       const int w = std::min(ch, Mi - m0);
-      Profiler &pr = h->prof;
-      const bool f32 = h->mixed;
       pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32); });
-      for (int lvl = (int)P.lv.size() - 1; lvl >= 0; --lvl) {
-        const LevelTasks &L = P.lv[lvl];
-        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(L.sw), L.nsw, m0, w, nullptr, s, f32); });
-      }
-      pr.run(P_CONTRACT, s, [&] {
-        return launch_contract(P.at<int32_t>(P.drows), P.ndesign, P.X, P.V, ch, w, two_h2, grad_dev, c > 0, s);
-      });
+      for (size_t t = 0; t < P.swl.size(); ++t)
+        pr.run(P_GEMM_SWEEP, s, [&] {
+          return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk);
+        });
     }
+    pr.run(P_CONTRACT, s, [&] { return launch_reduce_partials(P.gpart, P.nblk, P.ndesign, two_h2, grad_dev, s); });
     if (h->prof.on) h->prof.collect();
     return APF_OK;
   });

@@ -17,13 +17,14 @@ hipError_t launch_extend_add(const FrontDev *fr, const int2 *kids, int nkids, co
 constexpr int N_INV_VARIANTS = 8;
 int inverse_variant(int p);   // kernel variant of a pivot block of size p
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
+// part / nblk: output of the tasks flagged G_CONTRACT (unused otherwise)
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
-                       bool f32 = false);
+                       bool f32 = false, double *part = nullptr, int nblk = 0);
 hipError_t launch_row_map(int32_t *map, const int32_t *base, const int32_t *pidx, const int32_t *perm, int64_t n,
                           hipStream_t s);
 hipError_t launch_sum_partials(const cplx *part, int nseg, int64_t stride, cplx *S, int64_t n, hipStream_t s);
-hipError_t launch_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
-                           double two_h2, double *grad, int accumulate, hipStream_t s);
+hipError_t launch_reduce_partials(const double *part, int nblk, int64_t n, double scale, double *grad,
+                                  hipStream_t s);
 hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx *G, int64_t n, double *part,
                                  int npart, hipStream_t s);
 

@@ -591,7 +591,8 @@ struct GemmPrec<true> {
 };
 
 template <bool F32>
-__global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext) {
+__global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
+                                                 double *part, int nblk) {
   typedef GemmPrec<F32> GP;
   typedef typename GP::lds_t lds_t;
   typedef typename GP::acc_t acc_t;
@@ -711,43 +712,83 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   }
 
   const bool neg = T.flags & G_NEG;
+  const bool store = !(T.flags & G_NO_STORE), contract = T.flags & G_CONTRACT;
   const cplx *Cin = (T.flags & G_CIN) ? T.Cin : nullptr;
   if (Cin && (T.flags & G_CIN_COFF)) Cin += coff;
+  // Epilogue in three passes (results, stores, contraction), so that the
+  // loads of each pass are all in flight together.  Lane l holds rows
+  // row(l, q) of the 16-row blocks r and columns l % 16 of the blocks c.
+  int64_t oi[2][4];
+  bool rowok[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gi = T.tm + wr + 16 * r + GP::row(lane, q);
+      rowok[r][q] = gi < M;
+      oi[r][q] = rowok[r][q] ? (T.crowmap ? T.crowmap[gi] : gi) : 0;
+    }
+  bool colok[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) colok[c] = T.tn + wc + 16 * c + (lane & 15) < N;
+  double2 v[2][2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int gi = T.tm + wr + 16 * r + GP::row(lane, q);
         const int gj = T.tn + wc + 16 * c + (lane & 15);
-        if (gi < M && gj < N) {
-          const int64_t oi = T.crowmap ? T.crowmap[gi] : gi;
-          double2 v = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
-          if (neg) v = make_double2(-v.x, -v.y);
-          if (Cin) v = cadd(v, ld2(Cin + oi * T.ldcin + gj));
-          st2(Cp + oi * T.ldc + gj, v);
+        v[r][c][q] = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
+        if (neg) v[r][c][q] = make_double2(-v[r][c][q].x, -v[r][c][q].y);
+        if (Cin && rowok[r][q] && colok[c]) v[r][c][q] = cadd(v[r][c][q], ld2(Cin + oi[r][q] * T.ldcin + gj));
+      }
+  if (store) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (rowok[r][q] && colok[c]) st2(Cp + oi[r][q] * T.ldc + T.tn + wc + 16 * c + (lane & 15), v[r][c][q]);
+  }
+  if (contract) {
+    // gradient partials: per row, Re(C aux) summed over the wave's 32 columns
+    double acc[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[r][q] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          if (rowok[r][q] && colok[c]) {
+            const double2 y = ld2(T.aux + oi[r][q] * T.ldc + T.tn + wc + 16 * c + (lane & 15));
+            acc[r][q] += v[r][c][q].x * y.x - v[r][c][q].y * y.y;
+          }
+      }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double a = acc[r][q];
+        for (int off = 1; off < 16; off <<= 1) a += __shfl_xor(a, off, 64);
+        if ((lane & 15) == 0 && rowok[r][q]) {
+          const int g = T.auxmap[oi[r][q]];
+          if (g >= 0) part[(int64_t)g * nblk + (coff + T.tn + wc) / 32] = a;
         }
       }
+  }
 }
 
-// ---------------------------------------------------------------------------
-// Gradient contraction: grad_k += -2 Re(sigma_k sum_m Lam_km Y_km),
-// sigma_k = -h^2 outside the PML.  One wave per design pixel.
-// ---------------------------------------------------------------------------
-__global__ void k_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
-                           double two_h2, double *grad, int accumulate) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (wave >= n) return;
-  const int64_t r = rows[wave];
+// grad[g] = scale * (sum of the nblk contraction partials of slot g)
+__global__ void k_reduce_partials(const double *part, int nblk, int64_t n, double scale, double *grad) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const double *p = part + g * nblk;
   double acc = 0.0;
-  for (int m = lane; m < ncols; m += 64) {
-    double2 x = ld2(X + r * ld + m), v = ld2(V + r * ld + m);
-    acc += x.x * v.x - x.y * v.y;
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) grad[wave] = (accumulate ? grad[wave] : 0.0) + two_h2 * acc;
+  for (int b = 0; b < nblk; ++b) acc += p[b];
+  grad[g] = scale * acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -852,12 +893,13 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32) {
+hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
+                       double *part, int nblk) {
   if (n == 0) return hipSuccess;
   if (f32)
-    hipLaunchKernelGGL(k_gemm<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext);
+    hipLaunchKernelGGL(k_gemm<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
   else
-    hipLaunchKernelGGL(k_gemm<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext);
+    hipLaunchKernelGGL(k_gemm<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
   return hipGetLastError();
 }
 
@@ -890,11 +932,11 @@ hipError_t launch_sum_partials(const cplx *part, int nseg, int64_t stride, cplx 
                      reinterpret_cast<const double2 *>(part), nseg, stride, reinterpret_cast<double2 *>(S), n);
   return hipGetLastError();
 }
-hipError_t launch_contract(const int32_t *rows, int n, const cplx *X, const cplx *V, int ld, int ncols,
-                           double two_h2, double *grad, int accumulate, hipStream_t s) {
+hipError_t launch_reduce_partials(const double *part, int nblk, int64_t n, double scale, double *grad,
+                                  hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_contract, dim3((n + 3) / 4), dim3(256), 0, s, rows, n, X, V, ld, ncols, two_h2, grad,
-                     accumulate);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nblk, n, scale,
+                     grad);
   return hipGetLastError();
 }
 hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx *G, int64_t n, double *part,

@@ -14,12 +14,15 @@ Function over the C ABI:
 Finite differences.  The fourth-order central difference
   (8 [f(x+h) - f(x-h)] - [f(x+2h) - f(x-2h)]) / (12 h),  h = 1e-2,
 has a truncation error of order h^4 |f^(5)| / 30 and a rounding error of
-about 3 e_f / (2 h), e_f being the absolute error of one evaluation of f.
-e_f grows as the optimised structure becomes more resonant (measured: about
-1e-13 |f| at the start, 5e-12 |f| after 180 steps), which at h = 1e-3 already
-leaves ~1e-6 of the gradient; at h = 1e-2 both terms stay near 1e-7, checked
-at 1e-6.  The plain central difference at h = 1e-6 is rounding-limited,
-e_f / h ~ 1e-5 of the gradient at the start, checked there at 1e-4.
+about 3 e_f / (2 h), e_f being the absolute rounding error of one evaluation
+of f (measured here: e_f ~ 5e-12, i.e. 1e-14 |f|, from the FD error at
+h = 1e-3).  That floor, ~5e-10 per pixel, is absolute, while the gradient
+shrinks as the optimisation converges (|dF/deps| per pixel falls from ~3e-3
+to ~4e-5 over the 200 steps).  The check therefore bounds the error of the
+32 sampled entries by 1e-6 of max(|g_32|, |g_32 at step 0|): strictly
+relative at the start, relative to the initial gradient scale later.  The
+plain central difference at h = 1e-6 is rounding-limited (e_f / h ~ 5e-6 per
+pixel, ~1e-5 of the initial gradient) and is checked at the start at 1e-4.
 """
 import os
 
@@ -76,7 +79,7 @@ def test_design_loop_12000x140_adam_with_finite_difference_checks():
     x = torch.as_tensor(eps[r0:r1], dtype=torch.float64, device=dev).clone().requires_grad_(True)
     opt = torch.optim.Adam([x], lr=0.02)
     pix = np.random.default_rng(7).choice(x.numel(), size=32, replace=False)
-    f_hist, fd_err = [], []
+    f_hist, fd_err, g_ref = [], [], None
     for step in range(200):
         opt.zero_grad()
         S = Fn.apply(x, apf, eps_bg)
@@ -104,9 +107,13 @@ def test_design_loop_12000x140_adam_with_finite_difference_checks():
                     else:
                         h = 1e-6
                         g_fd[n] = (f_at(h) - f_at(-h)) / (2 * h)
-                err = float(np.linalg.norm(g_fd - g_adj) / np.linalg.norm(g_adj))
+                if g_ref is None:
+                    g_ref = float(np.linalg.norm(g_adj))
+                err = float(np.linalg.norm(g_fd - g_adj) / max(np.linalg.norm(g_adj), g_ref))
                 fd_err.append((step, kind, err))
-                print(f"[gpu] step {step} f {f_hist[-1]:.6f} FD {kind}: rel err {err:.2e}", flush=True)
+                print(f"[gpu] step {step} f {f_hist[-1]:.6f} FD {kind}: err {err:.2e} "
+                      f"(|g_32| {np.linalg.norm(g_adj):.3e}, max abs err {np.abs(g_fd - g_adj).max():.3e})",
+                      flush=True)
         opt.step()
         with torch.no_grad():
             x.clamp_(1.0, 4.0)
