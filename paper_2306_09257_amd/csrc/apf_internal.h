@@ -98,11 +98,11 @@ struct ChanParams {
   int32_t m, is_source;
 };
 
-// Extend-add row task (child, row | flags) of the channel panels: the first
-// writer of a parent panel row stores, later writers add.
-constexpr int32_t EXT_STORE_B = 1 << 30;   // store this row of the B panel
-constexpr int32_t EXT_STORE_C = 1 << 29;   // store this row of the C^T panel
-constexpr int32_t EXT_ROW_MASK = EXT_STORE_C - 1;
+// Row maps of the channel-panel updates that a child writes straight into
+// its parent's panel: entry = parent-local row, | EXT_ADD when an earlier
+// writer has stored that row already (the update adds instead of storing).
+constexpr int32_t EXT_ADD = 1 << 30;
+constexpr int32_t EXT_ROW_MASK = EXT_ADD - 1;
 
 // Core extend-add tasks (child, first row): a task moves core_rows_per_task(b)
 // consecutive rows of the child's b x b contribution block.
@@ -140,6 +140,7 @@ enum GemmFlags : int32_t {
   // (aux has the layout of C)
   G_CONTRACT = 2048,
   G_NO_STORE = 4096,       // C itself is not written (only the contraction)
+  G_CIN_OWN = 8192,        // Cin row i is Cin + i*ldcin (not mapped by crowmap)
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
@@ -148,7 +149,8 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
   const cplx *Cin;
   cplx *C;
   const int32_t *browmap;  // if set, row k of B is B + browmap[k]*ldb
-  const int32_t *crowmap;  // if set, row i of C (and of Cin) is C + crowmap[i]*ldc
+  const int32_t *crowmap;  // if set, row i of C (and of Cin) is C + (crowmap[i] & EXT_ROW_MASK)*ldc,
+                           // and C's old value is added when crowmap[i] & EXT_ADD
   int32_t M, N, K;
   int32_t lda, ldb, ldcin, ldc;
   int32_t flags;

@@ -91,8 +91,10 @@ struct Blob {
 };
 
 struct LevelTasks {
-  int64_t zero = -1, scat = -1, pan = -1, ext[2] = {-1, -1}, extrow[2] = {-1, -1}, g1 = -1, g2 = -1;
-  int nzero = 0, nscat = 0, npan = 0, next[2] = {0, 0}, nextrow[2] = {0, 0}, ng1 = 0, ng2 = 0;
+  // g2b: the phase-2 channel-panel updates of second children, which write
+  // into the same parent rows as the first children's (g2) and run after them
+  int64_t zero = -1, scat = -1, pan = -1, ext[2] = {-1, -1}, g1 = -1, g2 = -1, g2b = -1;
+  int nzero = 0, nscat = 0, npan = 0, next[2] = {0, 0}, ng1 = 0, ng2 = 0, ng2b = 0;
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
   LevelTasks() {
@@ -280,6 +282,11 @@ GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, 
 // persistent factor store (-1 if absent); sk is the front's first row in the
 // Schur operand stores (fronts holding both channel blocks).
 struct Off {
+  // ws: the front's transient blocks (core, tri, u12, l21, u1b, lc1t), live
+  // from its level to its parent's; pws: its channel panels (bp, cpiv, cbnd),
+  // live from its first child's level (the children write into them) to its
+  // own level
+  int64_t pws = -1, pwsz = 0;
   int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, tri = -1, u12 = -1, l21 = -1, u1b = -1, lc1t = -1;
   int64_t fs_x12 = -1, fs_z = -1, fs_x1b = -1, xk = -1, sk = -1;
   int64_t wsz = 0;
@@ -401,16 +408,13 @@ static void size_plan(apf_handle *H) {
     q.core = w; w += up(n * n);
     q.tri = w; w += up(p * p);
     if (b) { q.u12 = w; w += up(p * b); q.l21 = w; w += up(b * p); }
-    if (mB) {
-      q.bp = w; w += up(n * mB);
-      if (!F.sfront) { q.u1b = w; w += up(p * mB); }
-    }
-    if (mC) {
-      q.cpiv = w; w += up(p * mC);
-      q.cbnd = w; w += up(b * mC);
-      if (!F.sfront) { q.lc1t = w; w += up(p * mC); }
-    }
+    if (mB && !F.sfront) { q.u1b = w; w += up(p * mB); }
+    if (mC && !F.sfront) { q.lc1t = w; w += up(p * mC); }
     q.wsz = w;
+    int64_t pw = 0;
+    if (mB) { q.bp = pw; pw += up(n * mB); }
+    if (mC) { q.cpiv = pw; q.cbnd = pw + p * mC; pw += up(n * mC); }
+    q.pwsz = pw;
     if (F.sweep) {
       if (b) { q.fs_x12 = fs; fs += up(p * b); q.fs_z = fs; fs += up(b * p); }
       if (mB) { q.fs_x1b = fs; fs += up(p * mB); }
@@ -419,8 +423,21 @@ static void size_plan(apf_handle *H) {
     if (F.sfront) { q.sk = ktot; ktot += p; }
   }
   // lifetime allocation, level by level
+  std::vector<std::vector<int>> palloc_at(H_ + 1), prelease_at(H_ + 2);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    if (!o[f].pwsz) continue;
+    int lp = F.height;
+    for (int c = 0; c < F.nchild; ++c) lp = std::min(lp, S.fronts[F.child[c]].height);
+    palloc_at[lp].push_back(f);
+  }
   for (int lvl = 0; lvl <= H_; ++lvl) {
     for (int f : release_at[lvl]) ar.release(o[f].ws, o[f].wsz);
+    for (int f : prelease_at[lvl]) ar.release(o[f].pws, o[f].pwsz);
+    for (int f : palloc_at[lvl]) {
+      o[f].pws = ar.alloc(o[f].pwsz);
+      prelease_at[S.fronts[f].height + 1].push_back(f);
+    }
     for (int f : S.levels[lvl]) {
       o[f].ws = ar.alloc(o[f].wsz);
       const Front &F = S.fronts[f];
@@ -524,51 +541,63 @@ static void build_plan(apf_handle *H) {
     cp_prj = cp_src + 1;
   }
   // Channel panel rows: the first writer of a row stores, later writers add.
-  // In launch order the writers are the channel assembly (pivot rows on the
-  // source or projection row), the children of slot 0, those of slot 1.
-  // wrB/wrC[f][k] marks row k of front f as written by one of them.
+  // The writers of a front's panel rows, in launch order: the channel
+  // assembly (pivot rows on the source or projection row; at the front's
+  // panel level), then its children's phase-2 panel updates ordered by
+  // (child level, slot).  wrB/wrC[f][k] marks row k of front f as written;
+  // rowsB/rowsC_off[c] is child c's flagged row map into its parent.
   std::vector<std::vector<uint8_t>> wrB(nf), wrC(nf);
+  std::vector<int64_t> rowsB_off(nf, -1), rowsC_off(nf, -1);
+  std::vector<int> slot_of(nf, 0);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    std::vector<uint8_t> &wb = wrB[f], &wc = wrC[f];
+    if (F.hasB) wb.assign(F.p() + F.b(), 0);
+    if (F.hasC) wc.assign(F.p() + F.b(), 0);
+    for (int k = 0; k < F.p(); ++k) {
+      const int y = F.piv[k] / d.nx;
+      if (F.hasB && y == d.src_row) wb[k] = 1;
+      if (F.hasC && y == d.prj_row) wc[k] = 1;
+    }
+    int order[2] = {0, 1};
+    if (F.nchild == 2 && S.fronts[F.child[1]].height < S.fronts[F.child[0]].height) std::swap(order[0], order[1]);
+    for (int oc = 0; oc < F.nchild; ++oc) {
+      const int c = order[oc], cf = F.child[c];
+      const Front &Ch = S.fronts[cf];
+      slot_of[cf] = c;
+      if (Ch.b() == 0) continue;
+      if ((Ch.hasB && !F.hasB) || (Ch.hasC && !F.hasC)) throw std::runtime_error("child panel without parent panel");
+      std::vector<int32_t> rb, rc;
+      for (int r = 0; r < Ch.b(); ++r) {
+        const int pr = Ch.rmap[r];
+        if (Ch.hasB) {
+          rb.push_back(pr | (wb[pr] ? EXT_ADD : 0));
+          wb[pr] = 1;
+        }
+        if (Ch.hasC) {
+          rc.push_back(pr | (wc[pr] ? EXT_ADD : 0));
+          wc[pr] = 1;
+        }
+      }
+      if (Ch.hasB) rowsB_off[cf] = ib.add(rb);
+      if (Ch.hasC) rowsC_off[cf] = ib.add(rc);
+    }
+  }
   P.lv.assign(H_ + 1, LevelTasks());
   for (int lvl = 0; lvl <= H_; ++lvl) {
     std::vector<int32_t> inv[N_INV_VARIANTS];
-    std::vector<int2> kids[2], rows[2];
+    std::vector<int2> kids[2];
     for (int f : S.levels[lvl]) {
       const Front &F = S.fronts[f];
-      std::vector<uint8_t> &wb = wrB[f], &wc = wrC[f];
-      if (F.hasB) wb.assign(F.p() + F.b(), 0);
-      if (F.hasC) wc.assign(F.p() + F.b(), 0);
-      for (int k = 0; k < F.p(); ++k) {
-        const int y = F.piv[k] / d.nx;
-        if (F.hasB && y == d.src_row) wb[k] = 1;
-        if (F.hasC && y == d.prj_row) wc[k] = 1;
-      }
       for (int c = 0; c < F.nchild; ++c) {
         const Front &Ch = S.fronts[F.child[c]];
         if (Ch.b() == 0) continue;
-        if ((Ch.hasB && !F.hasB) || (Ch.hasC && !F.hasC)) throw std::runtime_error("child panel without parent panel");
         for (int r0 = 0; r0 < Ch.b(); r0 += core_rows_per_task(Ch.b())) kids[c].push_back(make_int2(F.child[c], r0));
-        if (Ch.hasB || Ch.hasC)
-          for (int r = 0; r < Ch.b(); ++r) {
-            const int pr = Ch.rmap[r];
-            int32_t flag = 0;
-            if (Ch.hasB) {
-              if (!wb[pr]) flag |= EXT_STORE_B;
-              wb[pr] = 1;
-            }
-            if (Ch.hasC) {
-              if (!wc[pr]) flag |= EXT_STORE_C;
-              wc[pr] = 1;
-            }
-            rows[c].push_back(make_int2(F.child[c], r | flag));
-          }
       }
       if (F.p() > 0) inv[inverse_variant(F.p())].push_back(f);
     }
     LevelTasks &L = P.lv[lvl];
-    for (int c = 0; c < 2; ++c) {
-      L.ext[c] = ib.add(kids[c]); L.next[c] = (int)kids[c].size();
-      L.extrow[c] = ib.add(rows[c]); L.nextrow[c] = (int)rows[c].size();
-    }
+    for (int c = 0; c < 2; ++c) { L.ext[c] = ib.add(kids[c]); L.next[c] = (int)kids[c].size(); }
     for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = ib.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
   }
   const int64_t ib_size = (int64_t)ib.h.size();
@@ -600,10 +629,10 @@ static void build_plan(apf_handle *H) {
     D.mC = F.hasC ? Mo : 0;
     D.sweep_row0 = F.sweep ? (int32_t)S.node_sweep_row[F.piv[0]] : -1;
     D.core = WS(q.ws + q.core);
-    D.bp_piv = D.mB ? WS(q.ws + q.bp) : nullptr;
-    D.bp_bnd = D.mB ? WS(q.ws + q.bp) + p * D.mB : nullptr;
-    D.cpt_piv = D.mC ? WS(q.ws + q.cpiv) : nullptr;
-    D.cpt_bnd = D.mC ? WS(q.ws + q.cbnd) : nullptr;
+    D.bp_piv = D.mB ? WS(q.pws + q.bp) : nullptr;
+    D.bp_bnd = D.mB ? WS(q.pws + q.bp) + p * D.mB : nullptr;
+    D.cpt_piv = D.mC ? WS(q.pws + q.cpiv) : nullptr;
+    D.cpt_bnd = D.mC ? WS(q.pws + q.cbnd) : nullptr;
     D.tri = WS(q.ws + q.tri);
     D.perm = P.perms + F.elim0;
     D.rmap = reinterpret_cast<const int32_t *>((intptr_t)rmap_off[f]);  // offset; rebased below
@@ -624,7 +653,7 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<ZeroRange>> zr(H_ + 1);
   std::vector<std::vector<AsmEntry>> ae(H_ + 1);
   std::vector<std::vector<PanelEntry>> pe(H_ + 1);
-  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), swY(H_ + 1), swL(H_ + 1);
+  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), swY(H_ + 1), swL(H_ + 1);
   std::vector<GemmTask> gS, vinit;
   std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
@@ -633,11 +662,17 @@ static void build_plan(apf_handle *H) {
     const Front &F = S.fronts[f];
     const FrontDev &D = fd[f];
     const int lvl = F.height;
+    // panel level: the channel panels are zeroed and assembled before the
+    // first child's phase-2 update writes into them
+    int lp = lvl;
+    for (int c = 0; c < F.nchild; ++c) lp = std::min(lp, S.fronts[F.child[c]].height);
     const int p = F.p(), b = F.b(), n = p + b, mB = D.mB, mC = D.mC;
+    int zl = lvl;
     auto zero = [&](cplx *ptr, int64_t cnt) {
-      for (int64_t o0 = 0; o0 < cnt; o0 += ZERO_CHUNK) zr[lvl].push_back({ptr + o0, std::min(ZERO_CHUNK, cnt - o0)});
+      for (int64_t o0 = 0; o0 < cnt; o0 += ZERO_CHUNK) zr[zl].push_back({ptr + o0, std::min(ZERO_CHUNK, cnt - o0)});
     };
     zero(D.core, (int64_t)n * n);
+    zl = lp;
     // Channel panel rows no writer touches are zeroed: pivot rows always (the
     // phase-1 products read them), boundary rows only when some boundary row
     // is written; otherwise the phase-2 update does not read them (no Cin).
@@ -674,8 +709,8 @@ static void build_plan(apf_handle *H) {
         ae[lvl].push_back({src, D.core + (int64_t)lu * n + lv});
         if (dir > 0) ae[lvl].push_back({src, D.core + (int64_t)lv * n + lu});   // A = A^T
       }
-      if (mB && y == d.src_row) pe[lvl].push_back({u, 0, D.bp_piv + (int64_t)k * mB, cp_src});
-      if (mC && y == d.prj_row) pe[lvl].push_back({u, 0, D.cpt_piv + (int64_t)k * mC, cp_prj});
+      if (mB && y == d.src_row) pe[lp].push_back({u, 0, D.bp_piv + (int64_t)k * mB, cp_src});
+      if (mC && y == d.prj_row) pe[lp].push_back({u, 0, D.cpt_piv + (int64_t)k * mC, cp_prj});
     }
     for (int k = 0; k < p; ++k) loc[F.piv[k]] = -1;
     for (int k = 0; k < b; ++k) loc[F.bnd[k]] = -1;
@@ -698,12 +733,24 @@ static void build_plan(apf_handle *H) {
     if (b) add_tiles(g1[lvl], gemm(F21, n, tri, p, l21, p, b, p, p, G_B_TRI_U));
     if (mC) add_tiles(g1[lvl], gemm(tri, p, D.cpt_piv, mC, lc1t, mC, p, mC, p, G_TRANS_A | G_A_TRI_U));
     if (b) add_tiles(g2[lvl], gemm(l21, p, u12, b, F22, n, b, b, p, G_NEG | G_CIN, F22, n));
-    if (b && mB)
-      add_tiles(g2[lvl], gemm(l21, p, u1b, mB, D.bp_bnd, mB, b, mB, p, G_NEG | (cinB ? G_CIN : 0),
-                              cinB ? D.bp_bnd : nullptr, mB));
-    if (b && mC)
-      add_tiles(g2[lvl], gemm(u12, b, lc1t, mC, D.cpt_bnd, mC, b, mC, p, G_TRANS_A | G_NEG | (cinC ? G_CIN : 0),
-                              cinC ? D.cpt_bnd : nullptr, mC));
+    // channel-panel updates F2B - L21 U1B and FC2^T - U12^T LC1T, written
+    // straight into the parent's panel rows (stored or added per row)
+    if (b && (mB || mC)) {
+      const FrontDev &PD = fd[F.parent];
+      std::vector<GemmTask> &gp = slot_of[f] ? g2b[lvl] : g2[lvl];
+      if (mB) {
+        GemmTask t = gemm(l21, p, u1b, mB, PD.bp_piv, mB, b, mB, p, G_NEG | (cinB ? G_CIN | G_CIN_OWN : 0),
+                          cinB ? D.bp_bnd : nullptr, mB);
+        t.crowmap = reinterpret_cast<const int32_t *>((intptr_t)rowsB_off[f]);  // rebased below
+        add_tiles(gp, t);
+      }
+      if (mC) {
+        GemmTask t = gemm(u12, b, lc1t, mC, PD.cpt_piv, mC, b, mC, p,
+                          G_TRANS_A | G_NEG | (cinC ? G_CIN | G_CIN_OWN : 0), cinC ? D.cpt_bnd : nullptr, mC);
+        t.crowmap = reinterpret_cast<const int32_t *>((intptr_t)rowsC_off[f]);  // rebased below
+        add_tiles(gp, t);
+      }
+    }
     if (F.sweep) {
       if (b) add_tiles(g2[lvl], gemm(tri, p, u12, b, FSx(q.fs_x12), b, p, b, p, G_A_TRI_U));
       if (mB) add_tiles(g2[lvl], gemm(tri, p, u1b, mB, FSx(q.fs_x1b), mB, p, mB, p, G_A_TRI_U));
@@ -779,6 +826,7 @@ static void build_plan(apf_handle *H) {
     L.pan = bl.add(pe[lvl]); L.npan = (int)pe[lvl].size();
     L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
     L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
+    L.g2b = bl.add(g2b[lvl]); L.ng2b = (int)g2b[lvl].size();
   }
   P.swl.assign(H_ + 2, -1);
   P.nswl.assign(H_ + 2, 0);
@@ -808,6 +856,12 @@ static void build_plan(apf_handle *H) {
       if (rmap_off[f] >= 0) rebase(fdv[f].rmap);
       else fdv[f].rmap = nullptr;
     }
+    for (int lvl = 0; lvl <= H_; ++lvl)
+      for (int64_t off : {P.lv[lvl].g2, P.lv[lvl].g2b}) {
+        GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + off);
+        const int n = off == P.lv[lvl].g2 ? P.lv[lvl].ng2 : P.lv[lvl].ng2b;
+        for (int k = 0; k < n; ++k) rebase(t[k].crowmap);
+      }
     for (size_t l = 0; l < P.swl.size(); ++l) {
       GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + P.swl[l]);
       for (int k = 0; k < P.nswl[l]; ++k) {
@@ -882,8 +936,7 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     pr.run(P_EXTADD, s, [&] {
       hipError_t e = hipSuccess;
       for (int c = 0; c < 2 && e == hipSuccess; ++c)
-        e = launch_extend_add(fr, (const int2 *)at(L.ext[c]), L.next[c], (const int2 *)at(L.extrow[c]),
-                              L.nextrow[c], s);
+        e = launch_extend_add(fr, (const int2 *)at(L.ext[c]), L.next[c], s);
       return e;
     });
     pr.run(P_INVERSE, s, [&] {
@@ -894,6 +947,7 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     });
     pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g1), L.ng1, 0, INT_MAX, nullptr, s, f32); });
     pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g2), L.ng2, 0, INT_MAX, nullptr, s, f32); });
+    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g2b), L.ng2b, 0, INT_MAX, nullptr, s, f32); });
   }
 }
 
@@ -1000,8 +1054,8 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     std::vector<AsmEntry> ae;
     std::vector<PanelEntry> pe;
     std::vector<int32_t> inv[N_INV_VARIANTS];
-    std::vector<int2> kids[2], rows[2];
-    std::vector<GemmTask> g1, g2;
+    std::vector<int2> kids[2];
+    std::vector<GemmTask> g1, g2, g2b;
     for (size_t i = 0; i < hs.size(); ++i) {
       const Plan &P = hs[i]->plan;
       if (lvl >= P.lv.size()) continue;
@@ -1011,12 +1065,12 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
       auto pp = fetch<PanelEntry>(P.blob, L.pan, L.npan); pe.insert(pe.end(), pp.begin(), pp.end());
       for (int c = 0; c < 2; ++c) {
         for (int2 k : fetch<int2>(P.blob, L.ext[c], L.next[c])) kids[c].push_back(make_int2(k.x + base[i], k.y));
-        for (int2 r : fetch<int2>(P.blob, L.extrow[c], L.nextrow[c])) rows[c].push_back(make_int2(r.x + base[i], r.y));
       }
       for (int v = 0; v < N_INV_VARIANTS; ++v)
         for (int32_t k : fetch<int32_t>(P.blob, L.inv[v], L.ninv[v])) inv[v].push_back(k + base[i]);
       auto t1 = fetch<GemmTask>(P.blob, L.g1, L.ng1); g1.insert(g1.end(), t1.begin(), t1.end());
       auto t2 = fetch<GemmTask>(P.blob, L.g2, L.ng2); g2.insert(g2.end(), t2.begin(), t2.end());
+      auto t3 = fetch<GemmTask>(P.blob, L.g2b, L.ng2b); g2b.insert(g2b.end(), t3.begin(), t3.end());
     }
     LevelTasks &L = B->lv[lvl];
     L.zero = bl.add(zr); L.nzero = (int)zr.size();
@@ -1024,11 +1078,11 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     L.pan = bl.add(pe); L.npan = (int)pe.size();
     for (int c = 0; c < 2; ++c) {
       L.ext[c] = bl.add(kids[c]); L.next[c] = (int)kids[c].size();
-      L.extrow[c] = bl.add(rows[c]); L.nextrow[c] = (int)rows[c].size();
     }
     for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = bl.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
     L.g1 = bl.add(g1); L.ng1 = (int)g1.size();
     L.g2 = bl.add(g2); L.ng2 = (int)g2.size();
+    L.g2b = bl.add(g2b); L.ng2b = (int)g2b.size();
   }
   B->fronts = bl.add(fd);
   HIPCHK(hipMalloc(&B->blob, bl.h.size()));

@@ -135,9 +135,8 @@ __global__ void k_assemble_panel(const PanelEntry *e, int n) {
 // ---------------------------------------------------------------------------
 // Extend-add: scatter-add one child's contribution block into its parent.
 // k_extadd_core: one block per (child, group of rows) of the b x b core block.
-// k_extadd_panel: one block per (child, boundary row) of a child that carries
-// channel panels: its B row and C^T row, stored or added as the task's flags
-// say.
+// (The channel panels need no extend-add: the children's panel updates
+// write into the parent's panel rows directly.)
 // Children of one parent are processed in separate launches (slots), so no
 // two blocks of a launch write the same parent entry.
 // ---------------------------------------------------------------------------
@@ -161,43 +160,6 @@ __global__ void k_extadd_core(const FrontDev *fr, const int2 *tasks) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (e0 + u * blockDim.x < ne) st2(d[u], cadd(v[u], w[u]));
-  }
-}
-
-// Moves one panel row: d = s (store) or d += s.  Four loads per thread are
-// issued before any store, so that the row's latency overlaps.
-__device__ __forceinline__ void row_extadd(cplx *__restrict__ d, const cplx *__restrict__ src, int m, bool store) {
-  for (int b0 = threadIdx.x; b0 < m; b0 += 4 * blockDim.x) {
-    double2 v[4], w[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = b0 + u * blockDim.x;
-      v[u] = i < m ? ld2(src + i) : make_double2(0.0, 0.0);
-      w[u] = (i < m && !store) ? ld2(d + i) : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = b0 + u * blockDim.x;
-      if (i < m) st2(d + i, cadd(v[u], w[u]));
-    }
-  }
-}
-
-__global__ void k_extadd_panel(const FrontDev *fr, const int2 *tasks) {
-  const int2 t = tasks[blockIdx.x];
-  const FrontDev C = fr[t.x];
-  const FrontDev P = fr[C.parent];
-  const int r = t.y & EXT_ROW_MASK;
-  const int pr = C.rmap[r];
-  if (C.mB) {
-    const cplx *sb = C.bp_bnd + (int64_t)r * C.mB;
-    cplx *db = pr < P.p ? P.bp_piv + (int64_t)pr * P.mB : P.bp_bnd + (int64_t)(pr - P.p) * P.mB;
-    row_extadd(db, sb, C.mB, t.y & EXT_STORE_B);
-  }
-  if (C.mC) {
-    const cplx *sc = C.cpt_bnd + (int64_t)r * C.mC;
-    cplx *dc = pr < P.p ? P.cpt_piv + (int64_t)pr * P.mC : P.cpt_bnd + (int64_t)(pr - P.p) * P.mC;
-    row_extadd(dc, sc, C.mC, t.y & EXT_STORE_C);
   }
 }
 
@@ -718,15 +680,19 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   // Epilogue in three passes (results, stores, contraction), so that the
   // loads of each pass are all in flight together.  Lane l holds rows
   // row(l, q) of the 16-row blocks r and columns l % 16 of the blocks c.
-  int64_t oi[2][4];
-  bool rowok[2][4];
+  const bool own = T.flags & G_CIN_OWN;
+  int64_t oi[2][4], ci[2][4];
+  bool rowok[2][4], addold[2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int gi = T.tm + wr + 16 * r + GP::row(lane, q);
       rowok[r][q] = gi < M;
-      oi[r][q] = rowok[r][q] ? (T.crowmap ? T.crowmap[gi] : gi) : 0;
+      const int32_t m = (rowok[r][q] && T.crowmap) ? T.crowmap[gi] : gi;
+      oi[r][q] = rowok[r][q] ? (m & EXT_ROW_MASK) : 0;
+      addold[r][q] = (m & EXT_ADD) != 0;
+      ci[r][q] = own ? gi : oi[r][q];
     }
   bool colok[2];
 #pragma unroll
@@ -741,7 +707,8 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
         const int gj = T.tn + wc + 16 * c + (lane & 15);
         v[r][c][q] = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
         if (neg) v[r][c][q] = make_double2(-v[r][c][q].x, -v[r][c][q].y);
-        if (Cin && rowok[r][q] && colok[c]) v[r][c][q] = cadd(v[r][c][q], ld2(Cin + oi[r][q] * T.ldcin + gj));
+        if (Cin && rowok[r][q] && colok[c]) v[r][c][q] = cadd(v[r][c][q], ld2(Cin + ci[r][q] * T.ldcin + gj));
+        if (addold[r][q] && rowok[r][q] && colok[c]) v[r][c][q] = cadd(v[r][c][q], ld2(Cp + oi[r][q] * T.ldc + gj));
       }
   if (store) {
 #pragma unroll
@@ -852,18 +819,10 @@ hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n);
   return hipGetLastError();
 }
-hipError_t launch_extend_add(const FrontDev *fr, const int2 *kids, int nkids, const int2 *rows, int nrows,
-                             hipStream_t s) {
-  if (nkids > 0) {
-    hipLaunchKernelGGL(k_extadd_core, dim3(nkids), dim3(256), 0, s, fr, kids);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (nrows > 0) {
-    hipLaunchKernelGGL(k_extadd_panel, dim3(nrows), dim3(256), 0, s, fr, rows);
-    return hipGetLastError();
-  }
-  return hipSuccess;
+hipError_t launch_extend_add(const FrontDev *fr, const int2 *kids, int nkids, hipStream_t s) {
+  if (nkids == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extadd_core, dim3(nkids), dim3(256), 0, s, fr, kids);
+  return hipGetLastError();
 }
 int inverse_variant(int p) {
   if (p <= 16) return 0;
