@@ -592,6 +592,13 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   // interior tiles (no edge in M or N, no triangular mask) load their k
   // slabs without per-element conditions while the slab is full in K
   const bool full_mn = T.tm + 64 <= M && T.tn + 64 <= N && !triA && !triB;
+  // 16x16 output blocks of this wave that hold any output entry
+  bool blk_ok[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) blk_ok[r][c] = T.tm + wr + 16 * r < M && T.tn + wc + 16 * c < N;
+  const bool blk_all = blk_ok[0][0] && blk_ok[0][1] && blk_ok[1][0] && blk_ok[1][1];
   for (int k0 = kbeg; k0 < kend; k0 += KT) {
     double2 ra[4], rb[4];
     if (full_mn && k0 + KT <= K) {
@@ -653,23 +660,48 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
       for (int q = 0; q < 4; ++q) Bs[k][j0 + 16 * q] = GP::cvt(rb[q]);
     }
     __syncthreads();
+    if (blk_all && k0 + KT <= kend) {
 #pragma unroll
-    for (int kk = 0; kk < KT; kk += 4) {
-      const int kx = kk + (lane >> 4);
-      lds_t a[2], b[2];
-      a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
-      a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
-      b[0] = Bs[kx][wc + (lane & 15)];
-      b[1] = Bs[kx][wc + 16 + (lane & 15)];
+      for (int kk = 0; kk < KT; kk += 4) {
+        const int kx = kk + (lane >> 4);
+        lds_t a[2], b[2];
+        a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
+        a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
+        b[0] = Bs[kx][wc + (lane & 15)];
+        b[1] = Bs[kx][wc + 16 + (lane & 15)];
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
-          cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
-          cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
-          cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
-        }
+          for (int c = 0; c < 2; ++c) {
+            cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
+            cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
+            cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
+            cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+          }
+      }
+    } else {
+      // edge tile or last slab: skip the 16x16 blocks that lie outside the
+      // output and the k steps past the end of the k range (wave-uniform)
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 4) {
+        if (k0 + kk >= kend) break;
+        const int kx = kk + (lane >> 4);
+        lds_t a[2], b[2];
+        a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
+        a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
+        b[0] = Bs[kx][wc + (lane & 15)];
+        b[1] = Bs[kx][wc + 16 + (lane & 15)];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            if (blk_ok[r][c]) {
+              cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
+              cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
+              cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
+              cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+            }
+      }
     }
   }
 
