@@ -186,7 +186,10 @@ constexpr int INV_THREADS = 256;
 constexpr int INV_MAXP = 1024;
 
 // Register-blocked variant for p <= TR*RR = TC*RC: thread (ti, tj) of a
-// TR x TC grid keeps entries (ti + TR*ra, tj + TC*ca) in registers.
+// TR x TC grid keeps entries (ti + TR*ra, tj + TC*ca) in registers.  Steps
+// run as k = kq*TC + kc with kq unrolled, so the pivot column k is register
+// column kq (a compile-time index) in the threads with tj == kc; only the
+// pivot row, found at run time, needs a run-time register choice.
 template <int TR, int TC, int RR, int RC>
 __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const int32_t *ids, int *status) {
   constexpr int MAXP = TR * RR;
@@ -196,113 +199,100 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
   const int p = F.p, n = F.p + F.b;
   const int tid = threadIdx.x, ti = tid % TR, tj = tid / TR;
   __shared__ double2 rowbuf[MAXP], colbuf[MAXP];
-  __shared__ int used[MAXP], piv_row[MAXP], piv_step[MAXP];
+  __shared__ int piv_row[MAXP], piv_step[MAXP];
   __shared__ int s_r, s_bad;
-  for (int t = tid; t < MAXP; t += TR * TC) used[t] = 0;
   if (tid == 0) s_bad = 0;
   double2 a[RR][RC];
+  bool un[RR];   // this thread's rows not pivoted yet
 #pragma unroll
-  for (int ra = 0; ra < RR; ++ra)
-#pragma unroll
-    for (int ca = 0; ca < RC; ++ca) {
-      const int i = ti + TR * ra, j = tj + TC * ca;
-      a[ra][ca] = (i < p && j < p) ? ld2(F.core + (int64_t)i * n + j) : make_double2(0.0, 0.0);
-    }
-  __syncthreads();
-  // ---- phase A: LU with implicit row pivoting
-  for (int k = 0; k < p; ++k) {
-    const int kc = k % TC, kq = k / TC;
-    if (tj == kc) {
-      double bv = -1.0;
-      int bi = p;
-#pragma unroll
-      for (int ca = 0; ca < RC; ++ca) {
-        if (ca == kq) {
-#pragma unroll
-          for (int ra = 0; ra < RR; ++ra) {
-            const int i = ti + TR * ra;
-            const double2 v = a[ra][ca];
-            const double m = v.x * v.x + v.y * v.y;
-            if (i < p && !used[i] && (m > bv || (m == bv && i < bi))) { bv = m; bi = i; }
-          }
-        }
-      }
-#pragma unroll
-      for (int off = TR / 2; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off, TR);
-        const int oi = __shfl_xor(bi, off, TR);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
-      if (ti == 0) {
-        if (!(bv > 0.0)) s_bad = 1;
-        s_r = bi;
-        used[bi] = 1;
-        piv_row[k] = bi;
-        piv_step[bi] = k;
-      }
-    }
-    __syncthreads();
-    const int r = s_r, rr = r % TR, rq = r / TR;
-    // the unused-row flags are read before the second barrier: the next
-    // step's pivot group may set its flag as soon as every thread passed it
-    bool un[RR];
-#pragma unroll
-    for (int ra = 0; ra < RR; ++ra) {
-      const int i = ti + TR * ra;
-      un[ra] = i < p && !used[i];
-    }
-#pragma unroll
-    for (int ra = 0; ra < RR; ++ra) {
-      if (ra == rq && ti == rr) {
-#pragma unroll
-        for (int ca = 0; ca < RC; ++ca) {
-          const int j = tj + TC * ca;
-          if (j < p) rowbuf[j] = a[ra][ca];
-        }
-      }
-    }
-    if (tj == kc) {
-#pragma unroll
-      for (int ca = 0; ca < RC; ++ca) {
-        if (ca == kq) {
-#pragma unroll
-          for (int ra = 0; ra < RR; ++ra) {
-            const int i = ti + TR * ra;
-            if (i < p) colbuf[i] = a[ra][ca];
-          }
-        }
-      }
-    }
-    __syncthreads();
-    const double2 inv = cinv(rowbuf[k]);
-    double2 l[RR], u[RC];
-#pragma unroll
-    for (int ra = 0; ra < RR; ++ra) {
-      const int i = ti + TR * ra;
-      l[ra] = un[ra] ? cmul(colbuf[i], inv) : make_double2(0.0, 0.0);
-    }
+  for (int ra = 0; ra < RR; ++ra) {
+    const int i = ti + TR * ra;
+    un[ra] = i < p;
 #pragma unroll
     for (int ca = 0; ca < RC; ++ca) {
       const int j = tj + TC * ca;
-      u[ca] = (j > k && j < p) ? rowbuf[j] : make_double2(0.0, 0.0);
+      a[ra][ca] = (i < p && j < p) ? ld2(F.core + (int64_t)i * n + j) : make_double2(0.0, 0.0);
     }
+  }
+  __syncthreads();
+  // ---- phase A: LU with implicit row pivoting
 #pragma unroll
-    for (int ra = 0; ra < RR; ++ra)
+  for (int kq = 0; kq < RC; ++kq) {
+    for (int kc = 0; kc < TC; ++kc) {
+      const int k = kq * TC + kc;
+      if (k >= p) break;
+      if (tj == kc) {
+        // largest unused row of column k (ties: lowest row)
+        double bv = -1.0;
+        int bi = p;
 #pragma unroll
-      for (int ca = 0; ca < RC; ++ca) {
-        double2 v = a[ra][ca];
-        v.x -= l[ra].x * u[ca].x - l[ra].y * u[ca].y;
-        v.y -= l[ra].x * u[ca].y + l[ra].y * u[ca].x;
-        a[ra][ca] = v;
-      }
-    if (tj == kc) {
-#pragma unroll
-      for (int ca = 0; ca < RC; ++ca)
-        if (ca == kq) {
-#pragma unroll
-          for (int ra = 0; ra < RR; ++ra)
-            if (un[ra]) a[ra][ca] = l[ra];
+        for (int ra = 0; ra < RR; ++ra) {
+          const double2 v = a[ra][kq];
+          const double m = v.x * v.x + v.y * v.y;
+          if (un[ra] && m > bv) { bv = m; bi = ti + TR * ra; }
         }
+#pragma unroll
+        for (int off = TR / 2; off > 0; off >>= 1) {
+          const double ov = __shfl_xor(bv, off, TR);
+          const int oi = __shfl_xor(bi, off, TR);
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (ti == 0) {
+          if (!(bv > 0.0)) s_bad = 1;
+          s_r = bi;
+          piv_row[k] = bi;
+          piv_step[bi] = k;
+        }
+      }
+      __syncthreads();
+      // the pivot column and row go through LDS between the two barriers (the
+      // previous step's reads of both buffers finished before the first)
+      const int r = s_r, rr = r % TR, rq = r / TR;
+      if (tj == kc) {
+#pragma unroll
+        for (int ra = 0; ra < RR; ++ra) {
+          const int i = ti + TR * ra;
+          if (i < p) colbuf[i] = a[ra][kq];
+        }
+      }
+      if (ti == rr) {
+#pragma unroll
+        for (int ra = 0; ra < RR; ++ra)
+          if (ra == rq) {
+#pragma unroll
+            for (int ca = 0; ca < RC; ++ca) {
+              const int j = tj + TC * ca;
+              if (j < p) rowbuf[j] = a[ra][ca];
+            }
+          }
+      }
+#pragma unroll
+      for (int ra = 0; ra < RR; ++ra) un[ra] = un[ra] && (ti + TR * ra != r);
+      __syncthreads();
+      const double2 inv = cinv(rowbuf[k]);
+      double2 l[RR], u[RC];
+#pragma unroll
+      for (int ra = 0; ra < RR; ++ra) l[ra] = un[ra] ? cmul(colbuf[ti + TR * ra], inv) : make_double2(0.0, 0.0);
+      // register columns ca < kq hold only j < k: nothing to update there
+#pragma unroll
+      for (int ca = kq; ca < RC; ++ca) {
+        const int j = tj + TC * ca;
+        u[ca] = (j > k && j < p) ? rowbuf[j] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int ra = 0; ra < RR; ++ra)
+#pragma unroll
+        for (int ca = kq; ca < RC; ++ca) {
+          double2 v = a[ra][ca];
+          v.x = fma(-l[ra].x, u[ca].x, fma(l[ra].y, u[ca].y, v.x));
+          v.y = fma(-l[ra].x, u[ca].y, fma(-l[ra].y, u[ca].x, v.y));
+          a[ra][ca] = v;
+        }
+      if (tj == kc) {
+#pragma unroll
+        for (int ra = 0; ra < RR; ++ra)
+          if (un[ra]) a[ra][kq] = l[ra];
+      }
     }
   }
   __syncthreads();
@@ -313,91 +303,93 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
     const int i = ti + TR * ra;
     st[ra] = i < p ? piv_step[i] : INV_MAXP;
   }
-  for (int k = 0; k < p; ++k) {
-    const int kc = k % TC, kq = k / TC;
-    const int r = piv_row[k], rr = r % TR, rq = r / TR;
 #pragma unroll
-    for (int ra = 0; ra < RR; ++ra) {
-      if (ra == rq && ti == rr) {
+  for (int kq = 0; kq < RC; ++kq) {
+    for (int kc = 0; kc < TC; ++kc) {
+      const int k = kq * TC + kc;
+      if (k >= p) break;
+      const int r = piv_row[k], rr = r % TR, rq = r / TR;
+      if (ti == rr) {
 #pragma unroll
-        for (int ca = 0; ca < RC; ++ca) {
-          const int j = tj + TC * ca;
-          if (j < p) rowbuf[j] = a[ra][ca];
-        }
-      }
-    }
-    if (tj == kc) {
+        for (int ra = 0; ra < RR; ++ra)
+          if (ra == rq) {
 #pragma unroll
-      for (int ca = 0; ca < RC; ++ca) {
-        if (ca == kq) {
-#pragma unroll
-          for (int ra = 0; ra < RR; ++ra) {
-            const int i = ti + TR * ra;
-            if (i < p) colbuf[i] = a[ra][ca];
-          }
-        }
-      }
-    }
-    __syncthreads();
-    const double2 inv = cinv(rowbuf[k]);
-    // entry (i, j) takes c_i * s_j when i > k > j (L triangle, s_j = row_k[j])
-    // or i < k < j (U triangle, s_j = row_k[j] / u_kk): the row side and
-    // the column side must agree
-    double2 m[RR], sv[RC];
-    int rs[RR], cs[RC];
-#pragma unroll
-    for (int ra = 0; ra < RR; ++ra) {
-      const int i = ti + TR * ra;
-      m[ra] = i < p ? colbuf[i] : make_double2(0.0, 0.0);
-      rs[ra] = (st[ra] > k && st[ra] < INV_MAXP) ? 1 : (st[ra] < k ? 2 : 0);
-    }
-#pragma unroll
-    for (int ca = 0; ca < RC; ++ca) {
-      const int j = tj + TC * ca;
-      const double2 rj = j < p ? rowbuf[j] : make_double2(0.0, 0.0);
-      sv[ca] = j < k ? rj : cmul(rj, inv);
-      cs[ca] = j < k ? 1 : ((j > k && j < p) ? 2 : 0);
-    }
-#pragma unroll
-    for (int ra = 0; ra < RR; ++ra)
-#pragma unroll
-      for (int ca = 0; ca < RC; ++ca) {
-        const bool on = rs[ra] != 0 && rs[ra] == cs[ca];
-        double2 v = a[ra][ca];
-        const double px = m[ra].x * sv[ca].x - m[ra].y * sv[ca].y;
-        const double py = m[ra].x * sv[ca].y + m[ra].y * sv[ca].x;
-        v.x -= on ? px : 0.0;
-        v.y -= on ? py : 0.0;
-        a[ra][ca] = v;
-      }
-    // row k: scale its U part; column k: negate (L) or negate and scale (U)
-#pragma unroll
-    for (int ra = 0; ra < RR; ++ra) {
-      if (ra == rq && ti == rr) {
-#pragma unroll
-        for (int ca = 0; ca < RC; ++ca) {
-          const int j = tj + TC * ca;
-          if (j > k && j < p) a[ra][ca] = sv[ca];
-        }
-      }
-    }
-    if (tj == kc) {
-#pragma unroll
-      for (int ca = 0; ca < RC; ++ca)
-        if (ca == kq) {
-#pragma unroll
-          for (int ra = 0; ra < RR; ++ra) {
-            const int i = ti + TR * ra;
-            if (i < p) {
-              const double2 c = colbuf[i];
-              if (st[ra] > k) a[ra][ca] = make_double2(-c.x, -c.y);
-              else if (st[ra] < k) a[ra][ca] = make_double2(-(c.x * inv.x - c.y * inv.y), -(c.x * inv.y + c.y * inv.x));
-              else a[ra][ca] = inv;
+            for (int ca = 0; ca < RC; ++ca) {
+              const int j = tj + TC * ca;
+              if (j < p) rowbuf[j] = a[ra][ca];
             }
           }
+      }
+      if (tj == kc) {
+#pragma unroll
+        for (int ra = 0; ra < RR; ++ra) {
+          const int i = ti + TR * ra;
+          if (i < p) colbuf[i] = a[ra][kq];
         }
+      }
+      __syncthreads();
+      const double2 inv = cinv(rowbuf[k]);
+      // entry (i, j) takes c_i * s_j when i > k > j (L triangle, s_j = row_k[j])
+      // or i < k < j (U triangle, s_j = row_k[j] / u_kk): the row side and
+      // the column side must agree
+      // register columns ca < kq hold j < k (L side), ca > kq hold j > k (U
+      // side); column kq holds j = tj + TC kq, on either side of k.  mL / mU:
+      // the column factor c_i of rows that take the L / U update (zero else);
+      // entries j >= p have s_j = 0.
+      double2 mL[RR], mU[RR], sv[RC];
+#pragma unroll
+      for (int ra = 0; ra < RR; ++ra) {
+        const int i = ti + TR * ra;
+        const double2 c = i < p ? colbuf[i] : make_double2(0.0, 0.0);
+        const bool lrow = st[ra] > k && st[ra] < INV_MAXP, urow = st[ra] < k;
+        mL[ra] = lrow ? c : make_double2(0.0, 0.0);
+        mU[ra] = urow ? c : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int ca = 0; ca < RC; ++ca) {
+        const int j = tj + TC * ca;
+        const double2 rj = j < p ? rowbuf[j] : make_double2(0.0, 0.0);
+        sv[ca] = j < k ? rj : cmul(rj, inv);
+      }
+#pragma unroll
+      for (int ra = 0; ra < RR; ++ra)
+#pragma unroll
+        for (int ca = 0; ca < RC; ++ca) {
+          double2 m;
+          if (ca < kq) m = mL[ra];
+          else if (ca > kq) m = mU[ra];
+          else m = tj < kc ? mL[ra] : (tj > kc ? mU[ra] : make_double2(0.0, 0.0));
+          double2 v = a[ra][ca];
+          v.x = fma(-m.x, sv[ca].x, fma(m.y, sv[ca].y, v.x));
+          v.y = fma(-m.x, sv[ca].y, fma(-m.y, sv[ca].x, v.y));
+          a[ra][ca] = v;
+        }
+      // row k: scale its U part; column k: negate (L) or negate and scale (U)
+      if (ti == rr) {
+#pragma unroll
+        for (int ra = 0; ra < RR; ++ra)
+          if (ra == rq) {
+#pragma unroll
+            for (int ca = 0; ca < RC; ++ca) {
+              const int j = tj + TC * ca;
+              if (j > k && j < p) a[ra][ca] = sv[ca];
+            }
+          }
+      }
+      if (tj == kc) {
+#pragma unroll
+        for (int ra = 0; ra < RR; ++ra) {
+          const int i = ti + TR * ra;
+          if (i < p) {
+            const double2 c = colbuf[i];
+            if (st[ra] > k) a[ra][kq] = make_double2(-c.x, -c.y);
+            else if (st[ra] < k) a[ra][kq] = make_double2(-(c.x * inv.x - c.y * inv.y), -(c.x * inv.y + c.y * inv.x));
+            else a[ra][kq] = inv;
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (tid == 0 && s_bad) atomicOr(status, 1);
   for (int k = tid; k < p; k += TR * TC) F.perm[k] = piv_row[k];
