@@ -14,12 +14,16 @@ Gaussian, f = sum w |S|^2 with w ~ U[0, 1].  Synthetic, seeded.
 
 Prints one JSON line.  The roofline block is for the batched complex FP64
 MFMA GEMM kernel (k_gemm): its algorithmic flops (8 per complex MAC of the
-M x N x K products the tasks specify) over its HIP-event time in the timed
-region.  The cpu_baseline block times the CPU FP64 oracle on a bounded
-narrow-strip sample of the same workload and scales it by the oracle's cost
-model to the full workload.
+M x N x K products the tasks specify, a triangular factor counting only its
+stored triangle) over its HIP-event time in the timed region; traffic is
+the kernel's HBM bytes per launch from the committed counter summary under
+profiles/, or null when that summary was taken on other sources.  The
+cpu_baseline block times the CPU FP64 oracle on a bounded narrow-strip
+sample of the same workload and scales it by the oracle's cost model to the
+full workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -45,6 +49,43 @@ def make_workload(name):
     if spec["kind"] == "wide":
         return inputs.metasurface_wide(seed=spec["seed"], nx=spec["nx"])
     return inputs.metasurface_small(seed=spec["seed"])
+
+
+SOURCE_DIRS = ("paper_2306_09257_amd/csrc", "include")
+
+
+def sources_digest():
+    """sha256 over the library sources (kernels, plan building, headers): the
+    identity of the code whose hardware counters a profile summary records."""
+    h = hashlib.sha256()
+    for d in SOURCE_DIRS:
+        for name in sorted(os.listdir(os.path.join(ROOT, d))):
+            if name.endswith((".hip", ".cpp", ".h")):
+                with open(os.path.join(ROOT, d, name), "rb") as f:
+                    h.update(name.encode())
+                    h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload, precision):
+    """HBM bytes per k_gemm launch recorded by the committed counter summary
+    profiles/k_gemm_<workload>_<precision>.md (FETCH_SIZE and WRITE_SIZE
+    passes, scaled by a plain copy's counts), if it was taken on the current
+    sources.  Returns (bytes or None, note)."""
+    path = os.path.join(ROOT, "profiles", f"k_gemm_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None, f"no counter summary {os.path.relpath(path, ROOT)}"
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            for key in ("traffic_bytes_per_launch", "sources_sha256"):
+                if line.startswith(key + ":"):
+                    fields[key] = line.split(":", 1)[1].strip()
+    if "traffic_bytes_per_launch" not in fields or "sources_sha256" not in fields:
+        return None, f"{os.path.relpath(path, ROOT)} records no traffic"
+    if fields["sources_sha256"] != sources_digest():
+        return None, f"{os.path.relpath(path, ROOT)} was taken on other sources"
+    return float(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
 
 
 def oracle_cost_model(nx, ny, m):
@@ -228,11 +269,13 @@ def main():
     gemm_flop = 8.0 * (cm["factor"] + cm["schur"] + cm["sweep"])
     achieved = gemm_flop / (gemm_ms * 1e-3) / 1e12
     peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "mixed" else FP64_MFMA_PEAK_TFLOPS
+    traffic, traffic_note = profiled_traffic(args.workload, args.precision)
     roofline = {
         "kernel": "k_gemm (batched complex %s MFMA GEMM, all launches of a step)"
                   % ("FP32" if args.precision == "mixed" else "FP64"),
         "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-        "frac": achieved / peak, "traffic": None,
+        "frac": achieved / peak, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+        "traffic_source": traffic_note,
         "flop_per_step": gemm_flop, "launches_per_step": gemm_launches,
         "avg_launch_ms": gemm_ms / max(gemm_launches, 1),
     }

@@ -179,8 +179,9 @@ const char *apf_last_error(void);
  *   peak), "factor_bytes", "schur_store_bytes", "n_sweep_rows",
  *   "n_sweep_fronts", "k_total";
  *   after the first apf_assemble: "rhs_chunk", "gemm_cmacs_factor",
- *   "gemm_cmacs_schur", "gemm_cmacs_sweep" (complex multiply-adds issued to
- *   the GEMM kernel per call);
+ *   "gemm_cmacs_schur", "gemm_cmacs_sweep" (complex multiply-adds of the
+ *   GEMM tasks of one call whose operands are structurally nonzero: the
+ *   stored triangle of a triangular factor, no tile padding);
  *   with profiling on: "ms_<class>" and "launches_<class>", the summed
  *   HIP-event time and launch count since profiling was enabled, for the
  *   classes stencil, zero, assemble, extend_add, inverse, gemm_factor,

@@ -192,18 +192,36 @@ struct Plan {
 
 double g_cmacs_acc = 0;   // executed complex MACs of the tasks added (plan building only)
 
-// Complex MACs one tile issues, over the k range that can hold nonzeros
-// (the same range the kernel visits for triangular operands).
+// Complex MACs of one tile whose operands are both structurally nonzero: a
+// triangular operand contributes only its stored triangle (diagonal
+// included), everything else the full k range.  This is the algorithmic work
+// of the tile, not counting the zeros the MFMA tiles multiply.
 double tile_cmacs(const GemmTask &t, int tm, int tn) {
   const bool tr = t.flags & G_TRANS_A;
-  int kbeg = 0, kend = t.K;
-  if (t.flags & G_A_TRI_L) { if (tr) kbeg = tm; else kend = std::min(kend, tm + GEMM_TILE); }
-  if (t.flags & G_A_TRI_U) { if (tr) kend = std::min(kend, tm + GEMM_TILE); else kbeg = tm; }
-  if (t.flags & G_B_TRI_L) kbeg = std::max(kbeg, tn);
-  if (t.flags & G_B_TRI_U) kend = std::min(kend, tn + GEMM_TILE);
   const int mm = std::min(GEMM_TILE, t.M - tm), nn = std::min(GEMM_TILE, t.N - tn);
-  return (double)mm * nn * std::max(0, kend - kbeg);
+  if (mm <= 0 || nn <= 0 || t.K <= 0) return 0.0;
+  // nonzero k count for an index x of the triangular operand: k <= x (kind 1)
+  // or k >= x (kind 2), within [0, K)
+  auto cnt = [&](int kind, int x) -> double {
+    if (kind == 1) return std::max(0, std::min(t.K, x + 1));
+    return std::max(0, t.K - std::max(0, x));
+  };
+  const bool triA = t.flags & (G_A_TRI_L | G_A_TRI_U), triB = t.flags & (G_B_TRI_L | G_B_TRI_U);
+  double s = 0.0;
+  if (triA) {
+    // stored (r, c) = (i, k) or, transposed, (k, i); L keeps r >= c, U r <= c
+    const int kind = (((t.flags & G_A_TRI_L) != 0) != tr) ? 1 : 2;
+    for (int i = tm; i < tm + mm; ++i) s += cnt(kind, i);
+    return s * nn;
+  }
+  if (triB) {
+    const int kind = (t.flags & G_B_TRI_L) ? 2 : 1;   // stored (k, j)
+    for (int j = tn; j < tn + nn; ++j) s += cnt(kind, j);
+    return s * mm;
+  }
+  return (double)mm * nn * t.K;
 }
+
 
 void add_tiles(std::vector<GemmTask> &v, const GemmTask &t) {
   if (t.M <= 0 || t.N <= 0) return;
@@ -945,9 +963,13 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
         e = launch_inverse(v, fr, (const int32_t *)at(L.inv[v]), L.ninv[v], status, s);
       return e;
     });
-    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g1), L.ng1, 0, INT_MAX, nullptr, s, f32); });
-    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g2), L.ng2, 0, INT_MAX, nullptr, s, f32); });
-    pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(L.g2b), L.ng2b, 0, INT_MAX, nullptr, s, f32); });
+    // (empty task lists launch nothing and are not counted)
+    for (int g = 0; g < 3; ++g) {
+      const int64_t off = g == 0 ? L.g1 : (g == 1 ? L.g2 : L.g2b);
+      const int n = g == 0 ? L.ng1 : (g == 1 ? L.ng2 : L.ng2b);
+      if (n > 0)
+        pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32); });
+    }
   }
 }
 
@@ -1205,11 +1227,13 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     const bool f32 = h->mixed;
     for (int m0 = 0; m0 < Mi; m0 += ch) {
       const int w = std::min(ch, Mi - m0);
-      pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32); });
+      if (P.nvinit > 0)
+        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32); });
       for (size_t t = 0; t < P.swl.size(); ++t)
-        pr.run(P_GEMM_SWEEP, s, [&] {
-          return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk);
-        });
+        if (P.nswl[t] > 0)
+          pr.run(P_GEMM_SWEEP, s, [&] {
+            return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk);
+          });
     }
     pr.run(P_CONTRACT, s, [&] { return launch_reduce_partials(P.gpart, P.nblk, P.ndesign, two_h2, grad_dev, s); });
     if (h->prof.on) h->prof.collect();
