@@ -544,24 +544,22 @@ struct GemmPrec<true> {
   static __device__ __forceinline__ int swz(int k) { return ((k >> 2) & 3) << 2; }
 };
 
-template <bool F32>
-__global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
-                                                 double *part, int nblk) {
+// One 64x64 output tile.  TRI: the task has a triangular operand (masked
+// loads, zero blocks of the triangle skipped); the other instantiation has
+// none of that code.
+template <bool F32, bool TRI>
+__device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, const cplx *ext, double *part,
+                                          int nblk, typename GemmPrec<F32>::lds_t (*As)[64],
+                                          typename GemmPrec<F32>::lds_t (*Bs)[64]) {
   typedef GemmPrec<F32> GP;
   typedef typename GP::lds_t lds_t;
   typedef typename GP::acc_t acc_t;
-  const GemmTask T = tasks[blockIdx.x];
   const int M = T.M, K = T.K;
-  const int N = T.N < nlim ? T.N : nlim;
-  if (T.tn >= N) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool transA = T.flags & G_TRANS_A;
   const cplx *Bp = (T.flags & G_B_EXT) ? ext : T.B;
   if (T.flags & G_B_COFF) Bp += coff;
   cplx *Cp = (T.flags & G_C_EXT) ? const_cast<cplx *>(ext) : T.C;
-
-  __shared__ lds_t As[KT][64];
-  __shared__ lds_t Bs[KT][64];
 
   acc_t cre[2][2], cim[2][2];
   for (int r = 0; r < 2; ++r)
@@ -579,11 +577,22 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   if (fl & G_B_TRI_L) kbeg = max(kbeg, T.tn);
   if (fl & G_B_TRI_U) kend = min(kend, T.tn + 64);
   kbeg = (kbeg / KT) * KT;
-  const bool triA = fl & (G_A_TRI_L | G_A_TRI_U), triB = fl & (G_B_TRI_L | G_B_TRI_U);
+  const bool triA = TRI && (fl & (G_A_TRI_L | G_A_TRI_U)), triB = TRI && (fl & (G_B_TRI_L | G_B_TRI_U));
+  // nonzero pattern of a triangular operand in (i, k) / (k, j) terms:
+  // 1 = nonzero only for k <= i (k <= j), 2 = only for k >= i (k >= j)
+  const int akind = !triA ? 0 : ((((fl & G_A_TRI_L) != 0) != transA) ? 1 : 2);
+  const int bkind = !triB ? 0 : ((fl & G_B_TRI_L) ? 2 : 1);
 
-  // interior tiles (no edge in M or N, no triangular mask) load their k
-  // slabs without per-element conditions while the slab is full in K
-  const bool full_mn = T.tm + 64 <= M && T.tn + 64 <= N && !triA && !triB;
+  // interior tiles (no edge in M or N) load a k slab without per-element
+  // conditions when the slab is full in K and, for a triangular operand,
+  // lies strictly on the nonzero side of its diagonal (raw stored values)
+  const bool interior = T.tm + 64 <= M && T.tn + 64 <= N;
+  auto slab_raw = [&](int k0) -> bool {
+    if (!interior || k0 + KT > K) return false;
+    if (triA && !(akind == 1 ? k0 + KT - 1 < T.tm : k0 > T.tm + 63)) return false;
+    if (triB && !(bkind == 1 ? k0 + KT - 1 < T.tn : k0 > T.tn + 63)) return false;
+    return true;
+  };
   // 16x16 output blocks of this wave that hold any output entry
   bool blk_ok[2][2];
 #pragma unroll
@@ -593,7 +602,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   const bool blk_all = blk_ok[0][0] && blk_ok[0][1] && blk_ok[1][0] && blk_ok[1][1];
   for (int k0 = kbeg; k0 < kend; k0 += KT) {
     double2 ra[4], rb[4];
-    if (full_mn && k0 + KT <= K) {
+    if (slab_raw(k0)) {
       if (!transA) {
         const int i = tid >> 2, kq = (tid & 3) * 4;
         const gcplx *a = as_global(T.A) + (int64_t)(T.tm + i) * T.lda + k0 + kq;
@@ -652,7 +661,24 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
       for (int q = 0; q < 4; ++q) Bs[k][j0 + 16 * q] = GP::cvt(rb[q]);
     }
     __syncthreads();
-    if (blk_all && k0 + KT <= kend) {
+    // 16x16 blocks that take part in this slab: inside the output and, for a
+    // triangular operand, not zero over the whole slab (wave-uniform)
+    bool ok[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        ok[r][c] = blk_ok[r][c];
+        if (TRI) {
+          const int i0 = T.tm + wr + 16 * r, j0 = T.tn + wc + 16 * c, k1 = k0 + KT - 1;
+          if (akind == 1 && k0 > i0 + 15) ok[r][c] = false;
+          if (akind == 2 && k1 < i0) ok[r][c] = false;
+          if (bkind == 1 && k0 > j0 + 15) ok[r][c] = false;
+          if (bkind == 2 && k1 < j0) ok[r][c] = false;
+        }
+      }
+    const bool ok_all = ok[0][0] && ok[0][1] && ok[1][0] && ok[1][1];
+    if (ok_all && k0 + KT <= kend) {
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
         const int kx = kk + (lane >> 4);
@@ -672,8 +698,8 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
           }
       }
     } else {
-      // edge tile or last slab: skip the 16x16 blocks that lie outside the
-      // output and the k steps past the end of the k range (wave-uniform)
+      // edge tile, zero triangle blocks or last slab: skip the blocks that do
+      // not take part and the k steps past the end of the k range
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
         if (k0 + kk >= kend) break;
@@ -687,7 +713,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
         for (int r = 0; r < 2; ++r)
 #pragma unroll
           for (int c = 0; c < 2; ++c)
-            if (blk_ok[r][c]) {
+            if (ok[r][c]) {
               cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
               cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
               cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
@@ -770,6 +796,20 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
         }
       }
   }
+}
+
+template <bool F32>
+__global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
+                                                 double *part, int nblk) {
+  __shared__ typename GemmPrec<F32>::lds_t As[KT][64];
+  __shared__ typename GemmPrec<F32>::lds_t Bs[KT][64];
+  const GemmTask T = tasks[blockIdx.x];
+  const int N = T.N < nlim ? T.N : nlim;
+  if (T.tn >= N) return;
+  if (T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U))
+    gemm_tile<F32, true>(T, coff, N, ext, part, nblk, As, Bs);
+  else
+    gemm_tile<F32, false>(T, coff, N, ext, part, nblk, As, Bs);
 }
 
 // grad[g] = scale * (sum of the nblk contraction partials of slot g)
