@@ -616,25 +616,25 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
       const int gk = k0 + k;
       const gcplx *b = as_global(Bp) + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j0;
       for (int q = 0; q < 4; ++q) rb[q] = ldg(b + 16 * q);
-    } else if (!transA) {
-      const int i = tid >> 2, kq = (tid & 3) * 4;
-      const int gi = T.tm + i;
-      for (int q = 0; q < 4; ++q) {
-        const int gk = k0 + kq + q;
-        ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gi * T.lda + gk) : make_double2(0.0, 0.0);
-        if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gi, gk, gi < M && gk < K, ra[q]);
-      }
     } else {
-      // stored k-major: 16 lanes read 16 consecutive entries of one row
-      const int k = tid >> 4, i0 = tid & 15;
-      const int gk = k0 + k;
-      for (int q = 0; q < 4; ++q) {
-        const int gi = T.tm + i0 + 16 * q;
-        ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gk * T.lda + gi) : make_double2(0.0, 0.0);
-        if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gk, gi, gi < M && gk < K, ra[q]);
+      if (!transA) {
+        const int i = tid >> 2, kq = (tid & 3) * 4;
+        const int gi = T.tm + i;
+        for (int q = 0; q < 4; ++q) {
+          const int gk = k0 + kq + q;
+          ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gi * T.lda + gk) : make_double2(0.0, 0.0);
+          if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gi, gk, gi < M && gk < K, ra[q]);
+        }
+      } else {
+        // stored k-major: 16 lanes read 16 consecutive entries of one row
+        const int k = tid >> 4, i0 = tid & 15;
+        const int gk = k0 + k;
+        for (int q = 0; q < 4; ++q) {
+          const int gi = T.tm + i0 + 16 * q;
+          ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gk * T.lda + gi) : make_double2(0.0, 0.0);
+          if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gk, gi, gi < M && gk < K, ra[q]);
+        }
       }
-    }
-    {
       const int k = tid >> 4, j0 = tid & 15;
       const int gk = k0 + k;
       const cplx *row = nullptr;
