@@ -184,8 +184,9 @@ const char *apf_last_error(void);
  *   stored triangle of a triangular factor, no tile padding);
  *   with profiling on: "ms_<class>" and "launches_<class>", the summed
  *   HIP-event time and launch count since profiling was enabled, for the
- *   classes stencil, zero, assemble, extend_add, inverse, gemm_factor,
- *   gemm_schur, gemm_sweep, contract, wpow. */
+ *   classes stencil, zero, assemble, inverse, gemm_factor, gemm_schur,
+ *   gemm_sweep, contract, wpow (the children's contribution blocks are
+ *   added into their parents by the gemm_factor launches). */
 apf_status apf_query(apf_handle *h, const char *key, double *value);
 
 /* Structure export for host-side validation (host only, after apf_analyze).

@@ -28,8 +28,8 @@ APF_MIXED = 1
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
                 "apf_weighted_power",
                 "apf_grad", "apf_set_profiling", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
-PROFILE_CLASSES = ("stencil", "zero", "assemble", "extend_add", "inverse", "gemm_factor", "gemm_schur",
-                   "gemm_sweep", "contract", "wpow")
+PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
+                   "contract", "wpow")
 
 
 class APFError(RuntimeError):

@@ -104,11 +104,6 @@ struct ChanParams {
 constexpr int32_t EXT_ADD = 1 << 30;
 constexpr int32_t EXT_ROW_MASK = EXT_ADD - 1;
 
-// Core extend-add tasks (child, first row): a task moves core_rows_per_task(b)
-// consecutive rows of the child's b x b contribution block.
-constexpr int EXT_CORE_ELEMS = 4096;
-inline __host__ __device__ int core_rows_per_task(int b) { return b >= EXT_CORE_ELEMS ? 1 : EXT_CORE_ELEMS / b; }
-
 struct AsmEntry {          // one stencil entry of A: *src is added at dest
   const cplx *src;         // Aval + node*5 + direction (0 centre, 1 x-1, 2 x+1, 3 y-1, 4 y+1)
   cplx *dest;
@@ -140,7 +135,8 @@ enum GemmFlags : int32_t {
   // (aux has the layout of C)
   G_CONTRACT = 2048,
   G_NO_STORE = 4096,       // C itself is not written (only the contraction)
-  G_CIN_OWN = 8192,        // Cin row i is Cin + i*ldcin (not mapped by crowmap)
+  G_CIN_OWN = 8192,        // Cin entry (i, j) is Cin[i*ldcin + j] (not mapped by crowmap / ccolmap)
+  G_C_ACC = 16384,         // C's old value is added to every entry (as EXT_ADD for all rows)
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
@@ -157,6 +153,7 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
   int32_t tm, tn;
   const cplx *aux;         // G_CONTRACT: the second factor of the contraction
   const int32_t *auxmap;   // G_CONTRACT: row -> contraction slot, or -1
+  const int32_t *ccolmap;  // if set, column j of C is column ccolmap[j]
 };
 
 struct ZeroRange { cplx *ptr; int64_t n; };

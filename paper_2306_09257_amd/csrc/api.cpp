@@ -93,8 +93,8 @@ struct Blob {
 struct LevelTasks {
   // g2b: the phase-2 channel-panel updates of second children, which write
   // into the same parent rows as the first children's (g2) and run after them
-  int64_t zero = -1, scat = -1, pan = -1, ext[2] = {-1, -1}, g1 = -1, g2 = -1, g2b = -1;
-  int nzero = 0, nscat = 0, npan = 0, next[2] = {0, 0}, ng1 = 0, ng2 = 0, ng2b = 0;
+  int64_t zero = -1, scat = -1, pan = -1, g1 = -1, g2 = -1, g2b = -1;
+  int nzero = 0, nscat = 0, npan = 0, ng1 = 0, ng2 = 0, ng2b = 0;
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
   LevelTasks() {
@@ -106,10 +106,10 @@ constexpr int64_t ZERO_CHUNK = 8192;   // complex elements per zeroing block
 constexpr int64_t SPLIT_K = 4096;      // k rows per FP32 partial of the mixed Schur product
 
 // Per-class HIP-event timing of the launches (off unless enabled).
-enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_EXTADD, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
+enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
                  P_CONTRACT, P_WPOW, P_NCLASS };
-const char *const kProfNames[P_NCLASS] = {"stencil", "zero", "assemble", "extend_add", "inverse",
-                                          "gemm_factor", "gemm_schur", "gemm_sweep", "contract", "wpow"};
+const char *const kProfNames[P_NCLASS] = {"stencil", "zero", "assemble", "inverse", "gemm_factor",
+                                          "gemm_schur", "gemm_sweep", "contract", "wpow"};
 
 struct Profiler {
   bool on = false;
@@ -300,10 +300,10 @@ GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, 
 // persistent factor store (-1 if absent); sk is the front's first row in the
 // Schur operand stores (fronts holding both channel blocks).
 struct Off {
-  // ws: the front's transient blocks (core, tri, u12, l21, u1b, lc1t), live
-  // from its level to its parent's; pws: its channel panels (bp, cpiv, cbnd),
-  // live from its first child's level (the children write into them) to its
-  // own level
+  // Transient blocks, two arena allocations that both end after the front's
+  // own level.  pws: the core and the channel panels (bp, cpiv, cbnd), taken
+  // at the first child's level (the children write their contribution blocks
+  // into them); ws: tri, u12, l21, u1b, lc1t, taken at the front's level.
   int64_t pws = -1, pwsz = 0;
   int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, tri = -1, u12 = -1, l21 = -1, u1b = -1, lc1t = -1;
   int64_t fs_x12 = -1, fs_z = -1, fs_x1b = -1, xk = -1, sk = -1;
@@ -423,13 +423,13 @@ static void size_plan(apf_handle *H) {
     int64_t p = F.p(), b = F.b(), n = p + b, mB = F.hasB ? Mi : 0, mC = F.hasC ? Mo : 0;
     Off &q = o[f];
     int64_t w = 0;
-    q.core = w; w += up(n * n);
     q.tri = w; w += up(p * p);
     if (b) { q.u12 = w; w += up(p * b); q.l21 = w; w += up(b * p); }
     if (mB && !F.sfront) { q.u1b = w; w += up(p * mB); }
     if (mC && !F.sfront) { q.lc1t = w; w += up(p * mC); }
     q.wsz = w;
     int64_t pw = 0;
+    q.core = pw; pw += up(n * n);
     if (mB) { q.bp = pw; pw += up(n * mB); }
     if (mC) { q.cpiv = pw; q.cbnd = pw + p * mC; pw += up(n * mC); }
     q.pwsz = pw;
@@ -440,27 +440,24 @@ static void size_plan(apf_handle *H) {
     }
     if (F.sfront) { q.sk = ktot; ktot += p; }
   }
-  // lifetime allocation, level by level
-  std::vector<std::vector<int>> palloc_at(H_ + 1), prelease_at(H_ + 2);
+  // lifetime allocation, level by level: a front's workspace is taken at its
+  // first child's level and given back after its own level
+  std::vector<std::vector<int>> alloc_at(H_ + 1);
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
-    if (!o[f].pwsz) continue;
     int lp = F.height;
     for (int c = 0; c < F.nchild; ++c) lp = std::min(lp, S.fronts[F.child[c]].height);
-    palloc_at[lp].push_back(f);
+    alloc_at[lp].push_back(f);
   }
   for (int lvl = 0; lvl <= H_; ++lvl) {
-    for (int f : release_at[lvl]) ar.release(o[f].ws, o[f].wsz);
-    for (int f : prelease_at[lvl]) ar.release(o[f].pws, o[f].pwsz);
-    for (int f : palloc_at[lvl]) {
-      o[f].pws = ar.alloc(o[f].pwsz);
-      prelease_at[S.fronts[f].height + 1].push_back(f);
+    for (int f : release_at[lvl]) {
+      ar.release(o[f].ws, o[f].wsz);
+      ar.release(o[f].pws, o[f].pwsz);
     }
+    for (int f : alloc_at[lvl]) o[f].pws = ar.alloc(o[f].pwsz);
     for (int f : S.levels[lvl]) {
       o[f].ws = ar.alloc(o[f].wsz);
-      const Front &F = S.fronts[f];
-      int end = F.parent >= 0 ? S.fronts[F.parent].height : H_;
-      release_at[end + 1].push_back(f);
+      release_at[lvl + 1].push_back(f);
     }
   }
   P.ws_elems = std::max<int64_t>(ar.top, 1);
@@ -604,18 +601,11 @@ static void build_plan(apf_handle *H) {
   P.lv.assign(H_ + 1, LevelTasks());
   for (int lvl = 0; lvl <= H_; ++lvl) {
     std::vector<int32_t> inv[N_INV_VARIANTS];
-    std::vector<int2> kids[2];
     for (int f : S.levels[lvl]) {
       const Front &F = S.fronts[f];
-      for (int c = 0; c < F.nchild; ++c) {
-        const Front &Ch = S.fronts[F.child[c]];
-        if (Ch.b() == 0) continue;
-        for (int r0 = 0; r0 < Ch.b(); r0 += core_rows_per_task(Ch.b())) kids[c].push_back(make_int2(F.child[c], r0));
-      }
       if (F.p() > 0) inv[inverse_variant(F.p())].push_back(f);
     }
     LevelTasks &L = P.lv[lvl];
-    for (int c = 0; c < 2; ++c) { L.ext[c] = ib.add(kids[c]); L.next[c] = (int)kids[c].size(); }
     for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = ib.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
   }
   const int64_t ib_size = (int64_t)ib.h.size();
@@ -646,7 +636,7 @@ static void build_plan(apf_handle *H) {
     D.mB = F.hasB ? Mi : 0;
     D.mC = F.hasC ? Mo : 0;
     D.sweep_row0 = F.sweep ? (int32_t)S.node_sweep_row[F.piv[0]] : -1;
-    D.core = WS(q.ws + q.core);
+    D.core = WS(q.pws + q.core);
     D.bp_piv = D.mB ? WS(q.pws + q.bp) : nullptr;
     D.bp_bnd = D.mB ? WS(q.pws + q.bp) + p * D.mB : nullptr;
     D.cpt_piv = D.mC ? WS(q.pws + q.cpiv) : nullptr;
@@ -680,17 +670,15 @@ static void build_plan(apf_handle *H) {
     const Front &F = S.fronts[f];
     const FrontDev &D = fd[f];
     const int lvl = F.height;
-    // panel level: the channel panels are zeroed and assembled before the
-    // first child's phase-2 update writes into them
+    // panel level: the core and the channel panels are zeroed and assembled
+    // before the first child's phase-2 update writes into them
     int lp = lvl;
     for (int c = 0; c < F.nchild; ++c) lp = std::min(lp, S.fronts[F.child[c]].height);
     const int p = F.p(), b = F.b(), n = p + b, mB = D.mB, mC = D.mC;
-    int zl = lvl;
     auto zero = [&](cplx *ptr, int64_t cnt) {
-      for (int64_t o0 = 0; o0 < cnt; o0 += ZERO_CHUNK) zr[zl].push_back({ptr + o0, std::min(ZERO_CHUNK, cnt - o0)});
+      for (int64_t o0 = 0; o0 < cnt; o0 += ZERO_CHUNK) zr[lp].push_back({ptr + o0, std::min(ZERO_CHUNK, cnt - o0)});
     };
     zero(D.core, (int64_t)n * n);
-    zl = lp;
     // Channel panel rows no writer touches are zeroed: pivot rows always (the
     // phase-1 products read them), boundary rows only when some boundary row
     // is written; otherwise the phase-2 update does not read them (no Cin).
@@ -724,8 +712,8 @@ static void build_plan(apf_handle *H) {
         const int lu = loc[u], lv = loc[v];
         if (lv < 0) throw std::runtime_error("stencil neighbour outside the front");
         const cplx *src = P.aval + (int64_t)u * 5 + dir;
-        ae[lvl].push_back({src, D.core + (int64_t)lu * n + lv});
-        if (dir > 0) ae[lvl].push_back({src, D.core + (int64_t)lv * n + lu});   // A = A^T
+        ae[lp].push_back({src, D.core + (int64_t)lu * n + lv});
+        if (dir > 0) ae[lp].push_back({src, D.core + (int64_t)lv * n + lu});   // A = A^T
       }
       if (mB && y == d.src_row) pe[lp].push_back({u, 0, D.bp_piv + (int64_t)k * mB, cp_src});
       if (mC && y == d.prj_row) pe[lp].push_back({u, 0, D.cpt_piv + (int64_t)k * mC, cp_prj});
@@ -750,12 +738,20 @@ static void build_plan(apf_handle *H) {
     if (mB) add_tiles(g1[lvl], gemm(tri, p, D.bp_piv, mB, u1b, mB, p, mB, p, G_A_TRI_L, nullptr, 0, perm));
     if (b) add_tiles(g1[lvl], gemm(F21, n, tri, p, l21, p, b, p, p, G_B_TRI_U));
     if (mC) add_tiles(g1[lvl], gemm(tri, p, D.cpt_piv, mC, lc1t, mC, p, mC, p, G_TRANS_A | G_A_TRI_U));
-    if (b) add_tiles(g2[lvl], gemm(l21, p, u12, b, F22, n, b, b, p, G_NEG | G_CIN, F22, n));
-    // channel-panel updates F2B - L21 U1B and FC2^T - U12^T LC1T, written
-    // straight into the parent's panel rows (stored or added per row)
-    if (b && (mB || mC)) {
+    // contribution blocks, written straight into the parent: the core update
+    // F22 - L21 U12 is added at (rmap[r], rmap[c]) of the parent's core; the
+    // channel-panel updates F2B - L21 U1B and FC2^T - U12^T LC1T go to the
+    // parent's panel rows (stored or added per row).  Second children run in
+    // the g2b launch, after the first children of the same level.
+    if (b) {
       const FrontDev &PD = fd[F.parent];
       std::vector<GemmTask> &gp = slot_of[f] ? g2b[lvl] : g2[lvl];
+      {
+        GemmTask t = gemm(l21, p, u12, b, PD.core, PD.p + PD.b, b, b, p, G_NEG | G_CIN | G_CIN_OWN | G_C_ACC, F22, n);
+        t.crowmap = reinterpret_cast<const int32_t *>((intptr_t)rmap_off[f]);  // rebased below
+        t.ccolmap = t.crowmap;
+        add_tiles(gp, t);
+      }
       if (mB) {
         GemmTask t = gemm(l21, p, u1b, mB, PD.bp_piv, mB, b, mB, p, G_NEG | (cinB ? G_CIN | G_CIN_OWN : 0),
                           cinB ? D.bp_bnd : nullptr, mB);
@@ -878,7 +874,10 @@ static void build_plan(apf_handle *H) {
       for (int64_t off : {P.lv[lvl].g2, P.lv[lvl].g2b}) {
         GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + off);
         const int n = off == P.lv[lvl].g2 ? P.lv[lvl].ng2 : P.lv[lvl].ng2b;
-        for (int k = 0; k < n; ++k) rebase(t[k].crowmap);
+        for (int k = 0; k < n; ++k) {
+          rebase(t[k].crowmap);
+          rebase(t[k].ccolmap);
+        }
       }
     for (size_t l = 0; l < P.swl.size(); ++l) {
       GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + P.swl[l]);
@@ -949,12 +948,6 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     pr.run(P_ASSEMBLE, s, [&] {
       hipError_t e = launch_scatter_A((const AsmEntry *)at(L.scat), L.nscat, s);
       if (e == hipSuccess) e = launch_assemble_panel((const PanelEntry *)at(L.pan), L.npan, s);
-      return e;
-    });
-    pr.run(P_EXTADD, s, [&] {
-      hipError_t e = hipSuccess;
-      for (int c = 0; c < 2 && e == hipSuccess; ++c)
-        e = launch_extend_add(fr, (const int2 *)at(L.ext[c]), L.next[c], s);
       return e;
     });
     pr.run(P_INVERSE, s, [&] {
@@ -1076,7 +1069,6 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     std::vector<AsmEntry> ae;
     std::vector<PanelEntry> pe;
     std::vector<int32_t> inv[N_INV_VARIANTS];
-    std::vector<int2> kids[2];
     std::vector<GemmTask> g1, g2, g2b;
     for (size_t i = 0; i < hs.size(); ++i) {
       const Plan &P = hs[i]->plan;
@@ -1085,9 +1077,6 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
       auto z = fetch<ZeroRange>(P.blob, L.zero, L.nzero); zr.insert(zr.end(), z.begin(), z.end());
       auto a = fetch<AsmEntry>(P.blob, L.scat, L.nscat); ae.insert(ae.end(), a.begin(), a.end());
       auto pp = fetch<PanelEntry>(P.blob, L.pan, L.npan); pe.insert(pe.end(), pp.begin(), pp.end());
-      for (int c = 0; c < 2; ++c) {
-        for (int2 k : fetch<int2>(P.blob, L.ext[c], L.next[c])) kids[c].push_back(make_int2(k.x + base[i], k.y));
-      }
       for (int v = 0; v < N_INV_VARIANTS; ++v)
         for (int32_t k : fetch<int32_t>(P.blob, L.inv[v], L.ninv[v])) inv[v].push_back(k + base[i]);
       auto t1 = fetch<GemmTask>(P.blob, L.g1, L.ng1); g1.insert(g1.end(), t1.begin(), t1.end());
@@ -1098,9 +1087,6 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     L.zero = bl.add(zr); L.nzero = (int)zr.size();
     L.scat = bl.add(ae); L.nscat = (int)ae.size();
     L.pan = bl.add(pe); L.npan = (int)pe.size();
-    for (int c = 0; c < 2; ++c) {
-      L.ext[c] = bl.add(kids[c]); L.next[c] = (int)kids[c].size();
-    }
     for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = bl.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
     L.g1 = bl.add(g1); L.ng1 = (int)g1.size();
     L.g2 = bl.add(g2); L.ng2 = (int)g2.size();

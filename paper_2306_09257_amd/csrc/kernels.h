@@ -12,7 +12,6 @@ hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStrea
 hipError_t launch_scatter_A(const AsmEntry *e, int n, hipStream_t s);
 hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, hipStream_t s);
-hipError_t launch_extend_add(const FrontDev *fr, const int2 *kids, int nkids, hipStream_t s);
 constexpr int N_INV_VARIANTS = 8;
 int inverse_variant(int p);   // kernel variant of a pivot block of size p
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);

@@ -133,37 +133,6 @@ __global__ void k_assemble_panel(const PanelEntry *e, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Extend-add: scatter-add one child's contribution block into its parent.
-// k_extadd_core: one block per (child, group of rows) of the b x b core block.
-// (The channel panels need no extend-add: the children's panel updates
-// write into the parent's panel rows directly.)
-// Children of one parent are processed in separate launches (slots), so no
-// two blocks of a launch write the same parent entry.
-// ---------------------------------------------------------------------------
-__global__ void k_extadd_core(const FrontDev *fr, const int2 *tasks) {
-  const int2 t = tasks[blockIdx.x];
-  const FrontDev C = fr[t.x];
-  const FrontDev P = fr[C.parent];
-  const int nc = C.p + C.b, np = P.p + P.b, b = C.b;
-  const int r0 = t.y, ne = min(core_rows_per_task(b), b - r0) * b;
-  for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
-    double2 v[4], w[4];
-    cplx *d[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * blockDim.x;
-      const int r = r0 + e / b, c = e - (e / b) * b;
-      d[u] = P.core + (int64_t)C.rmap[e < ne ? r : r0] * np + C.rmap[e < ne ? c : 0];
-      v[u] = e < ne ? ld2(C.core + (int64_t)(C.p + r) * nc + C.p + c) : make_double2(0.0, 0.0);
-      w[u] = e < ne ? ld2(d[u]) : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (e0 + u * blockDim.x < ne) st2(d[u], cadd(v[u], w[u]));
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Pivot-block factorization: F11 = P L U with partial (row) pivoting, then the
 // explicit inverses of the unit lower factor L and the upper factor U.  Output
 // `tri` (p x p, rows in elimination-step order): strict lower part = L^-1
@@ -745,8 +714,14 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
       ci[r][q] = own ? gi : oi[r][q];
     }
   bool colok[2];
+  int oj[2];   // output column (mapped through ccolmap)
+  const bool cacc = T.flags & G_C_ACC;
 #pragma unroll
-  for (int c = 0; c < 2; ++c) colok[c] = T.tn + wc + 16 * c + (lane & 15) < N;
+  for (int c = 0; c < 2; ++c) {
+    const int gj = T.tn + wc + 16 * c + (lane & 15);
+    colok[c] = gj < N;
+    oj[c] = (colok[c] && T.ccolmap) ? T.ccolmap[gj] : gj;
+  }
   double2 v[2][2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
@@ -757,8 +732,10 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
         const int gj = T.tn + wc + 16 * c + (lane & 15);
         v[r][c][q] = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
         if (neg) v[r][c][q] = make_double2(-v[r][c][q].x, -v[r][c][q].y);
-        if (Cin && rowok[r][q] && colok[c]) v[r][c][q] = cadd(v[r][c][q], ld2(Cin + ci[r][q] * T.ldcin + gj));
-        if (addold[r][q] && rowok[r][q] && colok[c]) v[r][c][q] = cadd(v[r][c][q], ld2(Cp + oi[r][q] * T.ldc + gj));
+        if (Cin && rowok[r][q] && colok[c])
+          v[r][c][q] = cadd(v[r][c][q], ld2(Cin + ci[r][q] * T.ldcin + (own ? gj : oj[c])));
+        if ((addold[r][q] || cacc) && rowok[r][q] && colok[c])
+          v[r][c][q] = cadd(v[r][c][q], ld2(Cp + oi[r][q] * T.ldc + oj[c]));
       }
   if (store) {
 #pragma unroll
@@ -767,7 +744,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (rowok[r][q] && colok[c]) st2(Cp + oi[r][q] * T.ldc + T.tn + wc + 16 * c + (lane & 15), v[r][c][q]);
+          if (rowok[r][q] && colok[c]) st2(Cp + oi[r][q] * T.ldc + oj[c], v[r][c][q]);
   }
   if (contract) {
     // gradient partials: per row, Re(C aux) summed over the wave's 32 columns
@@ -881,11 +858,6 @@ hipError_t launch_fill_int(int *p, int v, hipStream_t s) {
 hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n);
-  return hipGetLastError();
-}
-hipError_t launch_extend_add(const FrontDev *fr, const int2 *kids, int nkids, hipStream_t s) {
-  if (nkids == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_extadd_core, dim3(nkids), dim3(256), 0, s, fr, kids);
   return hipGetLastError();
 }
 int inverse_variant(int p) {
