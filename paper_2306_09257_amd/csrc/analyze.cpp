@@ -20,14 +20,15 @@ namespace {
 
 constexpr int kMaxPivots = 128;   // largest pivot block of one front
 // A region is cut by a vertical separator (a full column of its height) only
-// while it is at least kAspect times wider than tall; narrower regions are
-// cut horizontally.  Vertical separators of the strip span the source and
-// the projection rows, so each one is a front that holds both channel
-// blocks and adds its pivots to the Schur product's k dimension; with
-// kAspect = 2 there are half as many of them (24000 x 160 against
-// kAspect = 1: k_total 64,704 -> 44,352, factorization work -24%, gradient
-// work -13%, workspace 55 -> 37 GB).
-constexpr double kAspect = 2.0;
+// while it is at least kAspectPart times wider than tall; narrower regions
+// are cut horizontally.  A vertical separator of a region that spans both the
+// source and the projection row is a front that holds both channel blocks
+// and adds its pivots to the Schur product's k dimension, so such regions
+// keep being cut horizontally up to kAspectFull (24000 x 160 against a
+// uniform aspect of 1: k_total 64,704 -> 34,176, factorization work -30%,
+// gradient work -21%, workspace 55 -> 37 GB).
+constexpr double kAspectFull = 3.0;   // regions holding both channel rows
+constexpr double kAspectPart = 1.5;   // the others
 
 struct Builder {
   const Desc &d;
@@ -76,7 +77,7 @@ struct Builder {
   }
 
   // Nested dissection of the rectangle [x0,x1) x [y0,y1): cut it with one
-  // grid line of nodes (vertically while w >= kAspect h, else horizontally);
+  // grid line of nodes (vertically while w >= aspect x h, else horizontally);
   // the two parts become children.  Children are emitted before their
   // parent, so `fronts` is a postorder.
   int region(int x0, int x1, int y0, int y1) {
@@ -87,7 +88,7 @@ struct Builder {
     if ((int64_t)w * hh <= leaf) {
       for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x) piv.push_back(node(x, y));
-    } else if (w >= kAspect * hh) {
+    } else if (w >= ((y0 <= d.src_row && d.prj_row < y1) ? kAspectFull : kAspectPart) * hh) {
       int xs = x0 + w / 2;
       c[0] = region(x0, xs, y0, y1);
       c[1] = region(xs + 1, x1, y0, y1);
