@@ -24,11 +24,12 @@ constexpr int kMaxPivots = 128;   // largest pivot block of one front
 // are cut horizontally.  A vertical separator of a region that spans both the
 // source and the projection row is a front that holds both channel blocks
 // and adds its pivots to the Schur product's k dimension, so such regions
-// keep being cut horizontally up to kAspectFull (24000 x 160 against a
-// uniform aspect of 1: k_total 64,704 -> 34,176, factorization work -30%,
-// gradient work -21%, workspace 55 -> 37 GB).
+// keep being cut horizontally up to kAspectFull.  (24000 x 160 against a
+// uniform aspect of 1, with the band-edge row cuts below: k_total 64,704 ->
+// 34,176, factorization work -31%, gradient work -32%, workspace 55 -> 21 GB;
+// measured 1.5 and 2 for kAspectPart, 2 to 4 for kAspectFull.)
 constexpr double kAspectFull = 3.0;   // regions holding both channel rows
-constexpr double kAspectPart = 1.5;   // the others
+constexpr double kAspectPart = 2.0;   // the others
 
 struct Builder {
   const Desc &d;
