@@ -137,6 +137,9 @@ enum GemmFlags : int32_t {
   G_NO_STORE = 4096,       // C itself is not written (only the contraction)
   G_CIN_OWN = 8192,        // Cin entry (i, j) is Cin[i*ldcin + j] (not mapped by crowmap / ccolmap)
   G_C_ACC = 16384,         // C's old value is added to every entry (as EXT_ADD for all rows)
+  G_TRANS_B = 32768,       // B(k, j) = B[j*ldb + k]; browmap then maps j (stored row of B)
+  G_K_LIM = 65536,         // K is limited to the launch's column limit (a right-hand-side chunk)
+  G_ACC_CHUNK = 131072,    // C's old value is added when the launch's column offset is > 0
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
@@ -154,9 +157,23 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
   const cplx *aux;         // G_CONTRACT: the second factor of the contraction
   const int32_t *auxmap;   // G_CONTRACT: row -> contraction slot, or -1
   const int32_t *ccolmap;  // if set, column j of C is column ccolmap[j]
+  const int32_t *arowmap;  // if set, row i of a non-transposed A is A + arowmap[i]*lda
 };
 
 struct ZeroRange { cplx *ptr; int64_t n; };
+
+// A front of the gradient sweeps none of whose children take part in them and
+// that holds no channel rows: its forward and adjoint fields are needed only
+// for the gradient of its own pixels, which follows from the b x b product
+// W = Lam_bnd Y_bnd^T of its boundary fields.
+struct LowRankFront {
+  const cplx *W;          // b x b
+  const cplx *X12;        // p x b (U^-1 L^-1 P^T F12)
+  const cplx *Z;          // b x p (L21 L^-1)
+  const int32_t *perm;    // p pivot rows in step order
+  const int32_t *gidx;    // p design-pixel indices (by pivot), or -1
+  int32_t p, b;
+};
 
 constexpr int GEMM_TILE = 64;
 

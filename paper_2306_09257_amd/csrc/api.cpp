@@ -183,6 +183,14 @@ struct Plan {
   // adjoint tiles (with the contraction) of level H - t + 1
   std::vector<int64_t> swl;
   std::vector<int> nswl;
+  // low-rank sweep fronts (no sweep children, no channel rows): instead of
+  // Y and Lam tiles, launch t is followed by the W = Lam_bnd Y_bnd^T tasks of
+  // level H - t + 1 (swtb), and their pixels' gradient is formed at the end
+  std::vector<int64_t> swtb;
+  std::vector<int> nswtb;
+  int64_t lrfronts = -1;
+  int nlr = 0;
+  cplx *lrW = nullptr;        // their W blocks, b x b each
   int64_t ndesign = 0;        // design pixels (contraction slots)
   int nblk = 0;               // 32-column contraction partials per pixel
   double *gpart = nullptr;    // ndesign x nblk
@@ -536,6 +544,25 @@ static void build_plan(apf_handle *H) {
     P.ndesign = (int64_t)(d.design_row1 - d.design_row0) * d.nx;
     P.nblk = 2 * ((Mi + 63) / 64);
     HIPCHK(hipMalloc(&P.gpart, std::max<int64_t>(P.ndesign * P.nblk, 1) * sizeof(double)));
+    // slots of low-rank fronts' pixels are never written: keep them zero
+    HIPCHK(hipMemset(P.gpart, 0, std::max<int64_t>(P.ndesign * P.nblk, 1) * sizeof(double)));
+  }
+  // low-rank sweep fronts and their W blocks
+  std::vector<char> lowrank(nf, 0);
+  std::vector<int64_t> lr_woff(nf, -1);
+  {
+    int64_t wtot = 0;
+    for (int f = 0; f < nf; ++f) {
+      const Front &F = S.fronts[f];
+      if (!F.sweep || F.hasB || F.hasC || F.b() == 0 || F.b() > 64 || F.p() > 64) continue;
+      bool kid_sweeps = false;
+      for (int c = 0; c < F.nchild; ++c) kid_sweeps = kid_sweeps || S.fronts[F.child[c]].sweep;
+      if (kid_sweeps) continue;
+      lowrank[f] = 1;
+      lr_woff[f] = wtot;
+      wtot += (int64_t)F.b() * F.b();
+    }
+    HIPCHK(hipMalloc(&P.lrW, std::max<int64_t>(wtot, 1) * sizeof(cplx)));
   }
   // channel parameters of the two panels, in a small buffer of their own
   const ChanParams *cp_src, *cp_prj;
@@ -661,7 +688,8 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<ZeroRange>> zr(H_ + 1);
   std::vector<std::vector<AsmEntry>> ae(H_ + 1);
   std::vector<std::vector<PanelEntry>> pe(H_ + 1);
-  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), swY(H_ + 1), swL(H_ + 1);
+  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), swY(H_ + 1), swL(H_ + 1), swW(H_ + 1);
+  std::vector<LowRankFront> lrf;
   std::vector<GemmTask> gS, vinit;
   std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
@@ -793,8 +821,26 @@ static void build_plan(apf_handle *H) {
       tv.crowmap = perm;
       tv.aux = Xf;
       tv.auxmap = reinterpret_cast<const int32_t *>((intptr_t)(P.gidx + (int64_t)D.sweep_row0 * 4));  // rebased below
-      add_tiles(swY[lvl], ty);
-      add_tiles(swL[lvl], tv);
+      if (lowrank[f]) {
+        // W = Lam_bnd Y_bnd^T over the right-hand-side columns (summed over
+        // chunks): A = boundary rows of V, B = the same rows of X transposed
+        GemmTask tw = gemm(P.V, ch, P.X, ch, P.lrW + lr_woff[f], b, b, b, ch, G_TRANS_B | G_K_LIM | G_ACC_CHUNK);
+        tw.arowmap = bm;
+        tw.browmap = bm;
+        add_tiles(swW[lvl], tw);
+        LowRankFront L{};
+        L.W = P.lrW + lr_woff[f];
+        L.X12 = FSx(q.fs_x12);
+        L.Z = FSx(q.fs_z);
+        L.perm = perm;
+        L.gidx = reinterpret_cast<const int32_t *>((intptr_t)(P.gidx + (int64_t)D.sweep_row0 * 4));  // rebased below
+        L.p = p;
+        L.b = b;
+        lrf.push_back(L);
+      } else {
+        add_tiles(swY[lvl], ty);
+        add_tiles(swL[lvl], tv);
+      }
       if (mC)
         for (int k = 0; k < p; ++k) {   // V row of xc row xk + k: sweep_row0 + perm[k]
           vmap_base[q.xk + k] = D.sweep_row0;
@@ -851,6 +897,14 @@ static void build_plan(apf_handle *H) {
     P.swl[t] = bl.add(m);
     P.nswl[t] = (int)m.size();
   }
+  P.swtb.assign(H_ + 2, -1);
+  P.nswtb.assign(H_ + 2, 0);
+  for (int t = 1; t <= H_ + 1; ++t) {
+    P.swtb[t] = bl.add(swW[H_ - t + 1]);
+    P.nswtb[t] = (int)swW[H_ - t + 1].size();
+  }
+  P.lrfronts = bl.add(lrf);
+  P.nlr = (int)lrf.size();
   P.gS = bl.add(gS); P.ngS = (int)gS.size();
   P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
@@ -885,7 +939,16 @@ static void build_plan(apf_handle *H) {
         rebase(t[k].browmap);
         rebase(t[k].auxmap);
       }
+      if (P.nswtb[l] > 0) {
+        GemmTask *w = reinterpret_cast<GemmTask *>(bl.h.data() + P.swtb[l]);
+        for (int k = 0; k < P.nswtb[l]; ++k) {
+          rebase(w[k].browmap);
+          rebase(w[k].arowmap);
+        }
+      }
     }
+    LowRankFront *lr = reinterpret_cast<LowRankFront *>(bl.h.data() + P.lrfronts);
+    for (int k = 0; k < P.nlr; ++k) rebase(lr[k].gidx);
   }
   (void)ib_size;
   HIPCHK(hipMemcpy(P.blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
@@ -894,7 +957,7 @@ static void build_plan(apf_handle *H) {
 
 static void free_plan(Plan &P) {
   void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
-                  P.xc, P.vmap, P.gpart};
+                  P.xc, P.vmap, P.gpart, P.lrW};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   P = Plan();
@@ -1215,13 +1278,20 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
       const int w = std::min(ch, Mi - m0);
       if (P.nvinit > 0)
         pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32); });
-      for (size_t t = 0; t < P.swl.size(); ++t)
+      for (size_t t = 0; t < P.swl.size(); ++t) {
         if (P.nswl[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] {
             return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk);
           });
+        if (P.nswtb[t] > 0)
+          pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm_tb(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s, f32); });
+      }
     }
-    pr.run(P_CONTRACT, s, [&] { return launch_reduce_partials(P.gpart, P.nblk, P.ndesign, two_h2, grad_dev, s); });
+    pr.run(P_CONTRACT, s, [&] {
+      hipError_t e = launch_reduce_partials(P.gpart, P.nblk, P.ndesign, two_h2, grad_dev, s);
+      if (e == hipSuccess) e = launch_lowrank_grad(P.at<LowRankFront>(P.lrfronts), P.nlr, two_h2, grad_dev, s);
+      return e;
+    });
     if (h->prof.on) h->prof.collect();
     return APF_OK;
   });

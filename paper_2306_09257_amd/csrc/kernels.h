@@ -18,6 +18,9 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
 // part / nblk: output of the tasks flagged G_CONTRACT (unused otherwise)
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
                        bool f32 = false, double *part = nullptr, int nblk = 0);
+// tasks with a stored-transposed B (G_TRANS_B) in their own kernel
+hipError_t launch_gemm_tb(const GemmTask *t, int n, int coff, int nlim, hipStream_t s, bool f32);
+hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, double *grad, hipStream_t s);
 hipError_t launch_row_map(int32_t *map, const int32_t *base, const int32_t *pidx, const int32_t *perm, int64_t n,
                           hipStream_t s);
 hipError_t launch_sum_partials(const cplx *part, int nseg, int64_t stride, cplx *S, int64_t n, hipStream_t s);

@@ -516,14 +516,14 @@ struct GemmPrec<true> {
 // One 64x64 output tile.  TRI: the task has a triangular operand (masked
 // loads, zero blocks of the triangle skipped); the other instantiation has
 // none of that code.
-template <bool F32, bool TRI>
-__device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, const cplx *ext, double *part,
-                                          int nblk, typename GemmPrec<F32>::lds_t (*As)[64],
+template <bool F32, bool TRI, bool TB>
+__device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, int nlimk, const cplx *ext,
+                                          double *part, int nblk, typename GemmPrec<F32>::lds_t (*As)[64],
                                           typename GemmPrec<F32>::lds_t (*Bs)[64]) {
   typedef GemmPrec<F32> GP;
   typedef typename GP::lds_t lds_t;
   typedef typename GP::acc_t acc_t;
-  const int M = T.M, K = T.K;
+  const int M = T.M, K = ((T.flags & G_K_LIM) && nlimk < T.K) ? nlimk : T.K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool transA = T.flags & G_TRANS_A;
   const cplx *Bp = (T.flags & G_B_EXT) ? ext : T.B;
@@ -574,24 +574,34 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
     if (slab_raw(k0)) {
       if (!transA) {
         const int i = tid >> 2, kq = (tid & 3) * 4;
-        const gcplx *a = as_global(T.A) + (int64_t)(T.tm + i) * T.lda + k0 + kq;
+        const int ar = (TB && T.arowmap) ? T.arowmap[T.tm + i] : T.tm + i;
+        const gcplx *a = as_global(T.A) + (int64_t)ar * T.lda + k0 + kq;
         for (int q = 0; q < 4; ++q) ra[q] = ldg(a + q);
       } else {
         const int k = tid >> 4, i0 = tid & 15;
         const gcplx *a = as_global(T.A) + (int64_t)(k0 + k) * T.lda + T.tm + i0;
         for (int q = 0; q < 4; ++q) ra[q] = ldg(a + 16 * q);
       }
-      const int k = tid >> 4, j0 = tid & 15;
-      const int gk = k0 + k;
-      const gcplx *b = as_global(Bp) + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j0;
-      for (int q = 0; q < 4; ++q) rb[q] = ldg(b + 16 * q);
+      if (TB) {
+        // B stored transposed: thread reads 4 consecutive k of stored row j
+        const int j = tid >> 2, kq = (tid & 3) * 4;
+        const int br = T.browmap ? T.browmap[T.tn + j] : T.tn + j;
+        const gcplx *b = as_global(Bp) + (int64_t)br * T.ldb + k0 + kq;
+        for (int q = 0; q < 4; ++q) rb[q] = ldg(b + q);
+      } else {
+        const int k = tid >> 4, j0 = tid & 15;
+        const int gk = k0 + k;
+        const gcplx *b = as_global(Bp) + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j0;
+        for (int q = 0; q < 4; ++q) rb[q] = ldg(b + 16 * q);
+      }
     } else {
       if (!transA) {
         const int i = tid >> 2, kq = (tid & 3) * 4;
         const int gi = T.tm + i;
         for (int q = 0; q < 4; ++q) {
           const int gk = k0 + kq + q;
-          ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gi * T.lda + gk) : make_double2(0.0, 0.0);
+          ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)((TB && T.arowmap) ? T.arowmap[gi] : gi) * T.lda + gk)
+                                     : make_double2(0.0, 0.0);
           if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gi, gk, gi < M && gk < K, ra[q]);
         }
       } else {
@@ -604,14 +614,24 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
           if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gk, gi, gi < M && gk < K, ra[q]);
         }
       }
-      const int k = tid >> 4, j0 = tid & 15;
-      const int gk = k0 + k;
-      const cplx *row = nullptr;
-      if (gk < K) row = Bp + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb;
-      for (int q = 0; q < 4; ++q) {
-        const int gj = T.tn + j0 + 16 * q;
-        rb[q] = (row && gj < N) ? ld2(row + gj) : make_double2(0.0, 0.0);
-        if (triB) rb[q] = tri_mask(fl & G_B_TRI_L, gk, gj, gk < K && gj < N, rb[q]);
+      if (TB) {
+        const int j = tid >> 2, kq = (tid & 3) * 4;
+        const int gj = T.tn + j;
+        const cplx *row = gj < N ? Bp + (int64_t)(T.browmap ? T.browmap[gj] : gj) * T.ldb : nullptr;
+        for (int q = 0; q < 4; ++q) {
+          const int gk = k0 + kq + q;
+          rb[q] = (row && gk < K) ? ld2(row + gk) : make_double2(0.0, 0.0);
+        }
+      } else {
+        const int k = tid >> 4, j0 = tid & 15;
+        const int gk = k0 + k;
+        const cplx *row = nullptr;
+        if (gk < K) row = Bp + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb;
+        for (int q = 0; q < 4; ++q) {
+          const int gj = T.tn + j0 + 16 * q;
+          rb[q] = (row && gj < N) ? ld2(row + gj) : make_double2(0.0, 0.0);
+          if (triB) rb[q] = tri_mask(fl & G_B_TRI_L, gk, gj, gk < K && gj < N, rb[q]);
+        }
       }
     }
     __syncthreads();
@@ -625,7 +645,12 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
       const int k = tid >> 4, i0 = tid & 15;
       for (int q = 0; q < 4; ++q) As[k][(i0 + 16 * q) ^ GP::swz(k)] = GP::cvt(ra[q]);
     }
-    {
+    // a transposed B is transposed into LDS like a row-major A, with the
+    // same column swizzle
+    if (TB) {
+      const int j = tid >> 2, kq = (tid & 3) * 4;
+      for (int q = 0; q < 4; ++q) Bs[kq + q][j ^ GP::swz(kq + q)] = GP::cvt(rb[q]);
+    } else {
       const int k = tid >> 4, j0 = tid & 15;
       for (int q = 0; q < 4; ++q) Bs[k][j0 + 16 * q] = GP::cvt(rb[q]);
     }
@@ -654,8 +679,8 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
         lds_t a[2], b[2];
         a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
         a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
-        b[0] = Bs[kx][wc + (lane & 15)];
-        b[1] = Bs[kx][wc + 16 + (lane & 15)];
+        b[0] = Bs[kx][(wc + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
+        b[1] = Bs[kx][(wc + 16 + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -676,8 +701,8 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
         lds_t a[2], b[2];
         a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
         a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
-        b[0] = Bs[kx][wc + (lane & 15)];
-        b[1] = Bs[kx][wc + 16 + (lane & 15)];
+        b[0] = Bs[kx][(wc + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
+        b[1] = Bs[kx][(wc + 16 + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -715,7 +740,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, co
     }
   bool colok[2];
   int oj[2];   // output column (mapped through ccolmap)
-  const bool cacc = T.flags & G_C_ACC;
+  const bool cacc = (T.flags & G_C_ACC) || ((T.flags & G_ACC_CHUNK) && coff > 0);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int gj = T.tn + wc + 16 * c + (lane & 15);
@@ -781,12 +806,67 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   __shared__ typename GemmPrec<F32>::lds_t As[KT][64];
   __shared__ typename GemmPrec<F32>::lds_t Bs[KT][64];
   const GemmTask T = tasks[blockIdx.x];
-  const int N = T.N < nlim ? T.N : nlim;
+  // the launch's column limit applies to N, or to K for G_K_LIM tasks
+  const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
   if (T.tn >= N) return;
   if (T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U))
-    gemm_tile<F32, true>(T, coff, N, ext, part, nblk, As, Bs);
+    gemm_tile<F32, true, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
   else
-    gemm_tile<F32, false>(T, coff, N, ext, part, nblk, As, Bs);
+    gemm_tile<F32, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+}
+
+// Tasks with a stored-transposed B (G_TRANS_B, with an optional row gather of
+// A): a kernel of their own, so that the main kernel carries none of it.
+template <bool F32>
+__global__ __launch_bounds__(256, 4) void k_gemm_tb(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
+                                                    double *part, int nblk) {
+  __shared__ typename GemmPrec<F32>::lds_t As[KT][64];
+  __shared__ typename GemmPrec<F32>::lds_t Bs[KT][64];
+  const GemmTask T = tasks[blockIdx.x];
+  const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
+  if (T.tn >= N) return;
+  gemm_tile<F32, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+}
+
+// Gradient of the pixels of the low-rank sweep fronts: with
+//   Y_f = -X12 Y_bnd,  Lam_f[perm[k]] = -(Z^T Lam_bnd)[k],  W = Lam_bnd Y_bnd^T,
+// grad_i = scale * Re sum_{a,c} Z[a][kinv(i)] W[a][c] X12[i][c]
+// (kinv(i): the step whose pivot row is i).  One workgroup per front; thread
+// (i, g) of a 64 x 4 grid takes the rows a = g, g + 4, ... of W for pivot i,
+// and the four partial sums of a pivot meet in LDS.
+__global__ __launch_bounds__(256) void k_lowrank_grad(const LowRankFront *fr, double scale, double *grad) {
+  const LowRankFront F = fr[blockIdx.x];
+  __shared__ int kinv[64];
+  __shared__ double part[4][64];
+  const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
+  if (g == 0 && i < F.p) kinv[F.perm[i]] = i;
+  __syncthreads();
+  double acc = 0.0;
+  if (i < F.p) {
+    const int k = kinv[i], b = F.b;
+    const cplx *x = F.X12 + (int64_t)i * b;
+    for (int a = g; a < b; a += 4) {
+      const cplx *w = F.W + (int64_t)a * b;
+      // four independent partial sums keep several loads in flight
+      double2 t[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                      make_double2(0.0, 0.0)};
+      int c = 0;
+      for (; c + 4 <= b; c += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = cadd(t[u], cmul(ld2(w + c + u), ld2(x + c + u)));
+      }
+      for (; c < b; ++c) t[0] = cadd(t[0], cmul(ld2(w + c), ld2(x + c)));
+      const double2 ts = cadd(cadd(t[0], t[1]), cadd(t[2], t[3]));
+      const double2 z = ld2(F.Z + (int64_t)a * F.p + k);
+      acc += z.x * ts.x - z.y * ts.y;
+    }
+  }
+  part[g][i] = acc;
+  __syncthreads();
+  if (g == 0 && i < F.p) {
+    const int gi = F.gidx[i];
+    if (gi >= 0) grad[gi] = scale * (part[0][i] + part[1][i] + part[2][i] + part[3][i]);
+  }
 }
 
 // grad[g] = scale * (sum of the nblk contraction partials of slot g)
@@ -888,6 +968,19 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
   return hipGetLastError();
 }
 
+hipError_t launch_gemm_tb(const GemmTask *t, int n, int coff, int nlim, hipStream_t s, bool f32) {
+  if (n == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_gemm_tb<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, nullptr, nullptr, 0);
+  else
+    hipLaunchKernelGGL(k_gemm_tb<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, nullptr, nullptr, 0);
+  return hipGetLastError();
+}
+hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, double *grad, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lowrank_grad, dim3(n), dim3(256), 0, s, f, scale, grad);
+  return hipGetLastError();
+}
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
                        double *part, int nblk) {
   if (n == 0) return hipSuccess;
