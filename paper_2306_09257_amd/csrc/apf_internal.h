@@ -140,6 +140,7 @@ enum GemmFlags : int32_t {
   G_TRANS_B = 32768,       // B(k, j) = B[j*ldb + k]; browmap then maps j (stored row of B)
   G_K_LIM = 65536,         // K is limited to the launch's column limit (a right-hand-side chunk)
   G_ACC_CHUNK = 131072,    // C's old value is added when the launch's column offset is > 0
+  G_K3 = 262144,           // complex products in the three-product form (launched on the deep-K kernel)
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B

@@ -95,6 +95,7 @@ struct LevelTasks {
   // into the same parent rows as the first children's (g2) and run after them
   int64_t zero = -1, scat = -1, pan = -1, g1 = -1, g2 = -1, g2b = -1;
   int nzero = 0, nscat = 0, npan = 0, ng1 = 0, ng2 = 0, ng2b = 0;
+  bool deep1 = false, deep2 = false, deep2b = false;   // lists run by the three-product kernel
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
   LevelTasks() {
@@ -186,6 +187,7 @@ struct Plan {
   // low-rank sweep fronts (no sweep children, no channel rows): instead of
   // Y and Lam tiles, launch t is followed by the W = Lam_bnd Y_bnd^T tasks of
   // level H - t + 1 (swtb), and their pixels' gradient is formed at the end
+  std::vector<char> swl_deep;
   std::vector<int64_t> swtb;
   std::vector<int> nswtb;
   int64_t lrfronts = -1;
@@ -472,6 +474,41 @@ static void size_plan(apf_handle *H) {
   P.fs_elems = std::max<int64_t>(fs, 1);
   P.xc_rows = xck;
   S.k_total = ktot;
+}
+
+// Mean k extent of a GEMM task list's tiles (the k range a tile runs, as the
+// kernel narrows it for triangular operands).  Lists whose tiles are deep
+// enough to be MFMA-bound run on the three-product kernel.
+static double mean_tile_k(const std::vector<GemmTask> &v) {
+  if (v.empty()) return 0.0;
+  double sum = 0.0;
+  for (const GemmTask &T : v) {
+    int kb = 0, ke = T.K;
+    const bool ta = T.flags & G_TRANS_A;
+    if (T.flags & G_A_TRI_L) { if (ta) kb = T.tm; else ke = std::min(ke, T.tm + 64); }
+    if (T.flags & G_A_TRI_U) { if (ta) ke = std::min(ke, T.tm + 64); else kb = T.tm; }
+    if (T.flags & G_B_TRI_L) kb = std::max(kb, T.tn);
+    if (T.flags & G_B_TRI_U) ke = std::min(ke, T.tn + 64);
+    sum += std::max(0, ke - kb);
+  }
+  return sum / (double)v.size();
+}
+// Threshold measured at 24000x160: lists with a mean k extent of 96 or more
+// run faster on the three-product kernel (fewer MFMAs) despite its lower
+// occupancy; shallower lists are bound by their loads and epilogues.
+constexpr double kDeepMeanK = 96.0;
+// Flags every task of a deep list for the three-product form.  The flag is
+// per task, so a task rounds the same way in any launch that holds it
+// (single problems and merged batches alike).
+static bool mark_deep(std::vector<GemmTask> &v) {
+  if (mean_tile_k(v) < kDeepMeanK) return false;
+  for (GemmTask &T : v) T.flags |= G_K3;
+  return true;
+}
+static bool any_k3(const std::vector<GemmTask> &v) {
+  for (const GemmTask &T : v)
+    if (T.flags & G_K3) return true;
+  return false;
 }
 
 static void build_plan(apf_handle *H) {
@@ -884,16 +921,21 @@ static void build_plan(apf_handle *H) {
     L.zero = bl.add(zr[lvl]); L.nzero = (int)zr[lvl].size();
     L.scat = bl.add(ae[lvl]); L.nscat = (int)ae[lvl].size();
     L.pan = bl.add(pe[lvl]); L.npan = (int)pe[lvl].size();
+    L.deep1 = mark_deep(g1[lvl]);
+    L.deep2 = mark_deep(g2[lvl]);
+    L.deep2b = mark_deep(g2b[lvl]);
     L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
     L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
     L.g2b = bl.add(g2b[lvl]); L.ng2b = (int)g2b[lvl].size();
   }
   P.swl.assign(H_ + 2, -1);
   P.nswl.assign(H_ + 2, 0);
+  P.swl_deep.assign(H_ + 2, 0);
   for (int t = 0; t <= H_ + 1; ++t) {
     std::vector<GemmTask> m;
     if (H_ - t >= 0) m.insert(m.end(), swY[H_ - t].begin(), swY[H_ - t].end());
     if (H_ - t + 1 <= H_) m.insert(m.end(), swL[H_ - t + 1].begin(), swL[H_ - t + 1].end());
+    P.swl_deep[t] = mark_deep(m);
     P.swl[t] = bl.add(m);
     P.nswl[t] = (int)m.size();
   }
@@ -906,6 +948,10 @@ static void build_plan(apf_handle *H) {
   P.lrfronts = bl.add(lrf);
   P.nlr = (int)lrf.size();
   P.gS = bl.add(gS); P.ngS = (int)gS.size();
+  // the Schur partials and the weighted adjoint source are K_total / M_out
+  // deep: always the three-product form
+  for (GemmTask &T : gSsplit) T.flags |= G_K3;
+  for (GemmTask &T : vinit) T.flags |= G_K3;
   P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
   P.vmap_base = bl.add(vmap_base);
@@ -1023,8 +1069,9 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     for (int g = 0; g < 3; ++g) {
       const int64_t off = g == 0 ? L.g1 : (g == 1 ? L.g2 : L.g2b);
       const int n = g == 0 ? L.ng1 : (g == 1 ? L.ng2 : L.ng2b);
+      const bool deep = g == 0 ? L.deep1 : (g == 1 ? L.deep2 : L.deep2b);
       if (n > 0)
-        pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32); });
+        pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32, nullptr, 0, deep); });
     }
   }
 }
@@ -1035,7 +1082,7 @@ static void enqueue_schur(const Plan &P, bool f32, double *S_dev, Profiler &pr, 
   // k split into segments of SPLIT_K rows: shorter, more numerous tasks than
   // one K_total-deep tile each, summed in FP64 afterwards
   pr.run(P_GEMM_SCHUR, s, [&] {
-    hipError_t e = launch_gemm(P.at<GemmTask>(P.gSsplit), P.ngSsplit, 0, INT_MAX, nullptr, s, f32);
+    hipError_t e = launch_gemm(P.at<GemmTask>(P.gSsplit), P.ngSsplit, 0, INT_MAX, nullptr, s, f32, nullptr, 0, true);
     if (e == hipSuccess)
       e = launch_sum_partials(P.spart, P.nseg, (int64_t)Mo * Mi, reinterpret_cast<cplx *>(S_dev), (int64_t)Mo * Mi, s);
     return e;
@@ -1154,6 +1201,9 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     L.g1 = bl.add(g1); L.ng1 = (int)g1.size();
     L.g2 = bl.add(g2); L.ng2 = (int)g2.size();
     L.g2b = bl.add(g2b); L.ng2b = (int)g2b.size();
+    L.deep1 = any_k3(g1);
+    L.deep2 = any_k3(g2);
+    L.deep2b = any_k3(g2b);
   }
   B->fronts = bl.add(fd);
   HIPCHK(hipMalloc(&B->blob, bl.h.size()));
@@ -1277,11 +1327,11 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     for (int m0 = 0; m0 < Mi; m0 += ch) {
       const int w = std::min(ch, Mi - m0);
       if (P.nvinit > 0)
-        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32); });
+        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32, nullptr, 0, true); });
       for (size_t t = 0; t < P.swl.size(); ++t) {
         if (P.nswl[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] {
-            return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk);
+            return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk, P.swl_deep[t] != 0);
           });
         if (P.nswtb[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm_tb(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s, f32); });

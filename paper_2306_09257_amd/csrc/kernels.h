@@ -15,9 +15,10 @@ hipError_t launch_fill_int(int *p, int v, hipStream_t s);
 constexpr int N_INV_VARIANTS = 8;
 int inverse_variant(int p);   // kernel variant of a pivot block of size p
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
-// part / nblk: output of the tasks flagged G_CONTRACT (unused otherwise)
+// part / nblk: output of the tasks flagged G_CONTRACT (unused otherwise);
+// deep: MFMA-bound deep-K task list (three-product complex form on FP64)
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
-                       bool f32 = false, double *part = nullptr, int nblk = 0);
+                       bool f32 = false, double *part = nullptr, int nblk = 0, bool deep = false);
 // tasks with a stored-transposed B (G_TRANS_B) in their own kernel
 hipError_t launch_gemm_tb(const GemmTask *t, int n, int coff, int nlim, hipStream_t s, bool f32);
 hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, double *grad, hipStream_t s);

@@ -515,8 +515,13 @@ struct GemmPrec<true> {
 
 // One 64x64 output tile.  TRI: the task has a triangular operand (masked
 // loads, zero blocks of the triangle skipped); the other instantiation has
-// none of that code.
-template <bool F32, bool TRI, bool TB>
+// none of that code.  K3 (FP64 only): complex products from three real
+// products instead of four (Karatsuba): with a = ar + i ai, b = br + i bi,
+//   k1 = (ar + ai) br,  k2 = ar (bi - br),  k3 = ai (br + bi),
+//   re(ab) = k1 - k3,   im(ab) = k1 + k2,
+// each k summed over K in its own accumulator; a quarter fewer MFMAs for
+// a third more accumulator registers.
+template <bool F32, bool TRI, bool TB, bool K3 = false>
 __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, int nlimk, const cplx *ext,
                                           double *part, int nblk, typename GemmPrec<F32>::lds_t (*As)[64],
                                           typename GemmPrec<F32>::lds_t (*Bs)[64]) {
@@ -530,11 +535,14 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   if (T.flags & G_B_COFF) Bp += coff;
   cplx *Cp = (T.flags & G_C_EXT) ? const_cast<cplx *>(ext) : T.C;
 
-  acc_t cre[2][2], cim[2][2];
+  static_assert(!(K3 && F32), "the three-product form is for the FP64 path");
+  // four-product form: cre, cim; three-product form: k1 -> cre, k2 -> cim, k3
+  acc_t cre[2][2], cim[2][2], ck3[2][2];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
       cre[r][c] = acc_t{0, 0, 0, 0};
       cim[r][c] = acc_t{0, 0, 0, 0};
+      ck3[r][c] = acc_t{0, 0, 0, 0};
     }
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 
@@ -681,15 +689,34 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
         a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
         b[0] = Bs[kx][(wc + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
         b[1] = Bs[kx][(wc + 16 + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
+        if constexpr (K3) {
+          double as[2], bd[2], bs[2];
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+          for (int r = 0; r < 2; ++r) as[r] = a[r].x + a[r].y;
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
-            cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
-            cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
-            cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+            bd[c] = b[c].y - b[c].x;
+            bs[c] = b[c].x + b[c].y;
           }
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              cre[r][c] = GP::mfma(as[r], b[c].x, cre[r][c]);
+              cim[r][c] = GP::mfma(a[r].x, bd[c], cim[r][c]);
+              ck3[r][c] = GP::mfma(a[r].y, bs[c], ck3[r][c]);
+            }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
+              cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
+              cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
+              cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+            }
+        }
       }
     } else {
       // edge tile, zero triangle blocks or last slab: skip the blocks that do
@@ -708,10 +735,16 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
 #pragma unroll
           for (int c = 0; c < 2; ++c)
             if (ok[r][c]) {
-              cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
-              cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
-              cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
-              cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+              if constexpr (K3) {
+                cre[r][c] = GP::mfma(a[r].x + a[r].y, b[c].x, cre[r][c]);
+                cim[r][c] = GP::mfma(a[r].x, b[c].y - b[c].x, cim[r][c]);
+                ck3[r][c] = GP::mfma(a[r].y, b[c].x + b[c].y, ck3[r][c]);
+              } else {
+                cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
+                cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
+                cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
+                cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+              }
             }
       }
     }
@@ -755,7 +788,10 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gj = T.tn + wc + 16 * c + (lane & 15);
-        v[r][c][q] = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
+        if constexpr (K3)
+          v[r][c][q] = make_double2(cre[r][c][q] - ck3[r][c][q], cre[r][c][q] + cim[r][c][q]);
+        else
+          v[r][c][q] = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
         if (neg) v[r][c][q] = make_double2(-v[r][c][q].x, -v[r][c][q].y);
         if (Cin && rowok[r][q] && colok[c])
           v[r][c][q] = cadd(v[r][c][q], ld2(Cin + ci[r][q] * T.ldcin + (own ? gj : oj[c])));
@@ -813,6 +849,33 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
     gemm_tile<F32, true, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
   else
     gemm_tile<F32, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+}
+
+// Launches that hold deep-K tasks (Schur partials, weighted adjoint source,
+// the upper levels' fronts and sweeps): MFMA-bound, so the tasks flagged
+// G_K3 take the three-product complex form, at three workgroups per CU for
+// its accumulators.  Unflagged tasks of such a launch (other problems of a
+// merged batch) keep the four-product form, so that every task rounds the
+// same way whichever launch runs it.
+__global__ __launch_bounds__(256, 3) void k_gemm_k3(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
+                                                   double *part, int nblk) {
+  __shared__ double2 As[KT][64];
+  __shared__ double2 Bs[KT][64];
+  const GemmTask T = tasks[blockIdx.x];
+  const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
+  if (T.tn >= N) return;
+  const bool tri = T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U);
+  if (T.flags & G_K3) {
+    if (tri)
+      gemm_tile<false, true, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+    else
+      gemm_tile<false, false, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+  } else {
+    if (tri)
+      gemm_tile<false, true, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+    else
+      gemm_tile<false, false, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+  }
 }
 
 // Tasks with a stored-transposed B (G_TRANS_B, with an optional row gather of
@@ -982,9 +1045,11 @@ hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, doubl
   return hipGetLastError();
 }
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
-                       double *part, int nblk) {
+                       double *part, int nblk, bool deep) {
   if (n == 0) return hipSuccess;
-  if (f32)
+  if (deep && !f32)
+    hipLaunchKernelGGL(k_gemm_k3, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
+  else if (f32)
     hipLaunchKernelGGL(k_gemm<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
   else
     hipLaunchKernelGGL(k_gemm<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
