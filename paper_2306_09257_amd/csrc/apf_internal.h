@@ -137,13 +137,13 @@ enum GemmFlags : int32_t {
   G_NO_STORE = 4096,       // C itself is not written (only the contraction)
   G_CIN_OWN = 8192,        // Cin entry (i, j) is Cin[i*ldcin + j] (not mapped by crowmap / ccolmap)
   G_C_ACC = 16384,         // C's old value is added to every entry (as EXT_ADD for all rows)
-  G_TRANS_B = 32768,       // B(k, j) = B[j*ldb + k]; browmap then maps j (stored row of B)
+  G_TRANS_B = 32768,       // B(k, j) = B[j*ldb + k]; browmap then maps j (low-rank W tasks only)
   G_K_LIM = 65536,         // K is limited to the launch's column limit (a right-hand-side chunk)
   G_ACC_CHUNK = 131072,    // C's old value is added when the launch's column offset is > 0
   G_K3 = 262144,           // complex products in the three-product form (launched on the deep-K kernel)
 };
 
-struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
+struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B (a 32 x 32 quadrant for W tasks)
   const cplx *A;
   const cplx *B;
   const cplx *Cin;
@@ -158,7 +158,7 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B
   const cplx *aux;         // G_CONTRACT: the second factor of the contraction
   const int32_t *auxmap;   // G_CONTRACT: row -> contraction slot, or -1
   const int32_t *ccolmap;  // if set, column j of C is column ccolmap[j]
-  const int32_t *arowmap;  // if set, row i of a non-transposed A is A + arowmap[i]*lda
+  const int32_t *arowmap;  // W tasks: row i of A is A + arowmap[i]*lda
 };
 
 struct ZeroRange { cplx *ptr; int64_t n; };

@@ -185,8 +185,9 @@ struct Plan {
   std::vector<int64_t> swl;
   std::vector<int> nswl;
   // low-rank sweep fronts (no sweep children, no channel rows): instead of
-  // Y and Lam tiles, launch t is followed by the W = Lam_bnd Y_bnd^T tasks of
-  // level H - t + 1 (swtb), and their pixels' gradient is formed at the end
+  // Y and Lam tiles, launch t is followed by the W = Lam_bnd Y_bnd^T quadrant
+  // tasks of level H - t + 1 (swtb), and their pixels' gradient is formed at
+  // the end
   std::vector<char> swl_deep;
   std::vector<int64_t> swtb;
   std::vector<int> nswtb;
@@ -860,11 +861,19 @@ static void build_plan(apf_handle *H) {
       tv.auxmap = reinterpret_cast<const int32_t *>((intptr_t)(P.gidx + (int64_t)D.sweep_row0 * 4));  // rebased below
       if (lowrank[f]) {
         // W = Lam_bnd Y_bnd^T over the right-hand-side columns (summed over
-        // chunks): A = boundary rows of V, B = the same rows of X transposed
+        // chunks): A = boundary rows of V, B = the same rows of X, both
+        // k-contiguous; one task per 32 x 32 quadrant
         GemmTask tw = gemm(P.V, ch, P.X, ch, P.lrW + lr_woff[f], b, b, b, ch, G_TRANS_B | G_K_LIM | G_ACC_CHUNK);
         tw.arowmap = bm;
         tw.browmap = bm;
-        add_tiles(swW[lvl], tw);
+        for (int tm = 0; tm < b; tm += 32)
+          for (int tn = 0; tn < b; tn += 32) {
+            GemmTask u = tw;
+            u.tm = tm;
+            u.tn = tn;
+            g_cmacs_acc += (double)std::min(32, b - tm) * std::min(32, b - tn) * ch;
+            swW[lvl].push_back(u);
+          }
         LowRankFront L{};
         L.W = P.lrW + lr_woff[f];
         L.X12 = FSx(q.fs_x12);
@@ -1334,7 +1343,7 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
             return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk, P.swl_deep[t] != 0);
           });
         if (P.nswtb[t] > 0)
-          pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm_tb(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s, f32); });
+          pr.run(P_GEMM_SWEEP, s, [&] { return launch_lowrank_w(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s); });
       }
     }
     pr.run(P_CONTRACT, s, [&] {

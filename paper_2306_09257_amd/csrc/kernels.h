@@ -19,8 +19,9 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
 // deep: MFMA-bound deep-K task list (three-product complex form on FP64)
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
                        bool f32 = false, double *part = nullptr, int nblk = 0, bool deep = false);
-// tasks with a stored-transposed B (G_TRANS_B) in their own kernel
-hipError_t launch_gemm_tb(const GemmTask *t, int n, int coff, int nlim, hipStream_t s, bool f32);
+// W = Lam_bnd Y_bnd^T of the low-rank sweep fronts: one task per 32 x 32
+// quadrant (tm, tn), one wave per task; nlim: the chunk's width (k extent)
+hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStream_t s);
 hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, double *grad, hipStream_t s);
 hipError_t launch_row_map(int32_t *map, const int32_t *base, const int32_t *pidx, const int32_t *perm, int64_t n,
                           hipStream_t s);

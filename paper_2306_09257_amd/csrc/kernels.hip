@@ -521,7 +521,7 @@ struct GemmPrec<true> {
 //   re(ab) = k1 - k3,   im(ab) = k1 + k2,
 // each k summed over K in its own accumulator; a quarter fewer MFMAs for
 // a third more accumulator registers.
-template <bool F32, bool TRI, bool TB, bool K3 = false>
+template <bool F32, bool TRI, bool K3 = false>
 __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, int nlimk, const cplx *ext,
                                           double *part, int nblk, typename GemmPrec<F32>::lds_t (*As)[64],
                                           typename GemmPrec<F32>::lds_t (*Bs)[64]) {
@@ -582,21 +582,14 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
     if (slab_raw(k0)) {
       if (!transA) {
         const int i = tid >> 2, kq = (tid & 3) * 4;
-        const int ar = (TB && T.arowmap) ? T.arowmap[T.tm + i] : T.tm + i;
-        const gcplx *a = as_global(T.A) + (int64_t)ar * T.lda + k0 + kq;
+        const gcplx *a = as_global(T.A) + (int64_t)(T.tm + i) * T.lda + k0 + kq;
         for (int q = 0; q < 4; ++q) ra[q] = ldg(a + q);
       } else {
         const int k = tid >> 4, i0 = tid & 15;
         const gcplx *a = as_global(T.A) + (int64_t)(k0 + k) * T.lda + T.tm + i0;
         for (int q = 0; q < 4; ++q) ra[q] = ldg(a + 16 * q);
       }
-      if (TB) {
-        // B stored transposed: thread reads 4 consecutive k of stored row j
-        const int j = tid >> 2, kq = (tid & 3) * 4;
-        const int br = T.browmap ? T.browmap[T.tn + j] : T.tn + j;
-        const gcplx *b = as_global(Bp) + (int64_t)br * T.ldb + k0 + kq;
-        for (int q = 0; q < 4; ++q) rb[q] = ldg(b + q);
-      } else {
+      {
         const int k = tid >> 4, j0 = tid & 15;
         const int gk = k0 + k;
         const gcplx *b = as_global(Bp) + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j0;
@@ -608,8 +601,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
         const int gi = T.tm + i;
         for (int q = 0; q < 4; ++q) {
           const int gk = k0 + kq + q;
-          ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)((TB && T.arowmap) ? T.arowmap[gi] : gi) * T.lda + gk)
-                                     : make_double2(0.0, 0.0);
+          ra[q] = (gi < M && gk < K) ? ld2(T.A + (int64_t)gi * T.lda + gk) : make_double2(0.0, 0.0);
           if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gi, gk, gi < M && gk < K, ra[q]);
         }
       } else {
@@ -622,15 +614,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
           if (triA) ra[q] = tri_mask(fl & G_A_TRI_L, gk, gi, gi < M && gk < K, ra[q]);
         }
       }
-      if (TB) {
-        const int j = tid >> 2, kq = (tid & 3) * 4;
-        const int gj = T.tn + j;
-        const cplx *row = gj < N ? Bp + (int64_t)(T.browmap ? T.browmap[gj] : gj) * T.ldb : nullptr;
-        for (int q = 0; q < 4; ++q) {
-          const int gk = k0 + kq + q;
-          rb[q] = (row && gk < K) ? ld2(row + gk) : make_double2(0.0, 0.0);
-        }
-      } else {
+      {
         const int k = tid >> 4, j0 = tid & 15;
         const int gk = k0 + k;
         const cplx *row = nullptr;
@@ -653,12 +637,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
       const int k = tid >> 4, i0 = tid & 15;
       for (int q = 0; q < 4; ++q) As[k][(i0 + 16 * q) ^ GP::swz(k)] = GP::cvt(ra[q]);
     }
-    // a transposed B is transposed into LDS like a row-major A, with the
-    // same column swizzle
-    if (TB) {
-      const int j = tid >> 2, kq = (tid & 3) * 4;
-      for (int q = 0; q < 4; ++q) Bs[kq + q][j ^ GP::swz(kq + q)] = GP::cvt(rb[q]);
-    } else {
+    {
       const int k = tid >> 4, j0 = tid & 15;
       for (int q = 0; q < 4; ++q) Bs[k][j0 + 16 * q] = GP::cvt(rb[q]);
     }
@@ -687,8 +666,8 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
         lds_t a[2], b[2];
         a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
         a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
-        b[0] = Bs[kx][(wc + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
-        b[1] = Bs[kx][(wc + 16 + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
+        b[0] = Bs[kx][wc + (lane & 15)];
+        b[1] = Bs[kx][wc + 16 + (lane & 15)];
         if constexpr (K3) {
           double as[2], bd[2], bs[2];
 #pragma unroll
@@ -728,8 +707,8 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
         lds_t a[2], b[2];
         a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
         a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
-        b[0] = Bs[kx][(wc + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
-        b[1] = Bs[kx][(wc + 16 + (lane & 15)) ^ (TB ? GP::swz(kx) : 0)];
+        b[0] = Bs[kx][wc + (lane & 15)];
+        b[1] = Bs[kx][wc + 16 + (lane & 15)];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -846,9 +825,9 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
   if (T.tn >= N) return;
   if (T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U))
-    gemm_tile<F32, true, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+    gemm_tile<F32, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
   else
-    gemm_tile<F32, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+    gemm_tile<F32, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
 }
 
 // Launches that hold deep-K tasks (Schur partials, weighted adjoint source,
@@ -867,28 +846,103 @@ __global__ __launch_bounds__(256, 3) void k_gemm_k3(const GemmTask *tasks, int c
   const bool tri = T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U);
   if (T.flags & G_K3) {
     if (tri)
-      gemm_tile<false, true, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, true, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
     else
-      gemm_tile<false, false, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
   } else {
     if (tri)
-      gemm_tile<false, true, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, true, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
     else
-      gemm_tile<false, false, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
   }
 }
 
-// Tasks with a stored-transposed B (G_TRANS_B, with an optional row gather of
-// A): a kernel of their own, so that the main kernel carries none of it.
-template <bool F32>
-__global__ __launch_bounds__(256, 4) void k_gemm_tb(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
-                                                    double *part, int nblk) {
-  __shared__ typename GemmPrec<F32>::lds_t As[KT][64];
-  __shared__ typename GemmPrec<F32>::lds_t Bs[KT][64];
-  const GemmTask T = tasks[blockIdx.x];
-  const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
-  if (T.tn >= N) return;
-  gemm_tile<F32, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+// W = Lam_bnd Y_bnd^T of the low-rank sweep fronts: a b x b product (b <= 64)
+// over the right-hand-side columns, both operands gathered rows of the sweep
+// arrays (A = V rows arowmap, B = X rows browmap, each row k-contiguous).
+// Each task is one 32 x 32 quadrant (tm, tn) of one front and runs on one
+// wave; a workgroup holds four independent tasks, with no LDS and no
+// barrier.  Lane l takes row (l % 16) of a 16-row block and the four
+// consecutive k = 4 (l / 16) + j of each 16-k slab, so each lane loads 64
+// contiguous bytes per row and MFMA step j pairs A and B entries of the same
+// k.  Rows past the front's size are clamped to a valid row (their outputs
+// are not stored); k past the chunk's width reads zeros.  The chunk's sum is
+// stored, or added for column offsets > 0 (later chunks).
+__global__ __launch_bounds__(256, 3) void k_lowrank_w(const GemmTask *tasks, int n, int coff, int nlimk) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + wave;
+  if (idx >= n) return;
+  const GemmTask T = tasks[idx];
+  const int M = T.M, N = T.N, K = nlimk < T.K ? nlimk : T.K;
+  const int r = lane & 15, g = lane >> 4;
+  const cplx *pa[2], *pb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ia = min(T.tm + 16 * h + r, M - 1), jb = min(T.tn + 16 * h + r, N - 1);
+    pa[h] = T.A + (int64_t)T.arowmap[ia] * T.lda + 4 * g;
+    pb[h] = T.B + (int64_t)T.browmap[jb] * T.ldb + 4 * g;
+  }
+  d4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      cre[a][c] = d4{0, 0, 0, 0};
+      cim[a][c] = d4{0, 0, 0, 0};
+    }
+  auto step = [&](const double2 (&ra)[2][4], const double2 (&rb)[2][4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          cre[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a][j].x, rb[c][j].x, cre[a][c], 0, 0, 0);
+          cre[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ra[a][j].y, rb[c][j].y, cre[a][c], 0, 0, 0);
+          cim[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a][j].x, rb[c][j].y, cim[a][c], 0, 0, 0);
+          cim[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a][j].y, rb[c][j].x, cim[a][c], 0, 0, 0);
+        }
+  };
+  const int kfull = K & ~15;
+  for (int k0 = 0; k0 < kfull; k0 += 16) {
+    double2 ra[2][4], rb[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ra[h][j] = ldg(as_global(pa[h]) + k0 + j);
+        rb[h][j] = ldg(as_global(pb[h]) + k0 + j);
+      }
+    step(ra, rb);
+  }
+  if (kfull < K) {
+    double2 ra[2][4], rb[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool in = kfull + 4 * g + j < K;
+        ra[h][j] = in ? ld2(pa[h] + kfull + j) : make_double2(0.0, 0.0);
+        rb[h][j] = in ? ld2(pb[h] + kfull + j) : make_double2(0.0, 0.0);
+      }
+    step(ra, rb);
+  }
+  // D layout: lane l, element q -> row (l / 16) + 4 q, column l % 16
+  const bool acc = coff > 0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = T.tm + 16 * a + g + 4 * q, jj = T.tn + 16 * c + r;
+        if (i < M && jj < N) {
+          cplx *w = T.C + (int64_t)i * T.ldc + jj;
+          double2 v = make_double2(cre[a][c][q], cim[a][c][q]);
+          if (acc) v = cadd(v, ld2(w));
+          st2(w, v);
+        }
+      }
 }
 
 // Gradient of the pixels of the low-rank sweep fronts: with
@@ -1031,12 +1085,9 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_tb(const GemmTask *t, int n, int coff, int nlim, hipStream_t s, bool f32) {
+hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (f32)
-    hipLaunchKernelGGL(k_gemm_tb<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, nullptr, nullptr, 0);
-  else
-    hipLaunchKernelGGL(k_gemm_tb<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, nullptr, nullptr, 0);
+  hipLaunchKernelGGL(k_lowrank_w, dim3((n + 3) / 4), dim3(256), 0, s, t, n, coff, nlim);
   return hipGetLastError();
 }
 hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, double *grad, hipStream_t s) {
