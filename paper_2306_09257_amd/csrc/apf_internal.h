@@ -163,17 +163,27 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B (a 
 
 struct ZeroRange { cplx *ptr; int64_t n; };
 
-// A front of the gradient sweeps none of whose children take part in them and
-// that holds no channel rows: its forward and adjoint fields are needed only
-// for the gradient of its own pixels, which follows from the b x b product
-// W = Lam_bnd Y_bnd^T of its boundary fields.
-struct LowRankFront {
-  const cplx *W;          // b x b
-  const cplx *X12;        // p x b (U^-1 L^-1 P^T F12)
-  const cplx *Z;          // b x p (L21 L^-1)
+// A front of a low-rank sweep subtree.  A sweep front whose subtree holds no
+// channel rows has Y_piv = -X12 Y_bnd and Lam_piv[perm[k]] = -(Z^T Lam_bnd)[k]
+// (no source terms), so every product of its fields over the right-hand-side
+// columns follows from the b x b matrix Wt = Y_bnd Lam_bnd^T: with
+// U1t = Wt Z and Qt = X12 [U1t | Wt], the matrix Rt = Y Lam^T over the
+// front's rows (pivots, then boundary) is
+//   Rt[j][perm[k]] = Qt[j][k],      Rt[j][p + a] = -Qt[j][p + a],
+//   Rt[p + c][perm[k]] = -U1t[c][k], Rt[p + c][p + a] = Wt[c][a].
+// Its diagonal at the pivots gives the gradient of the front's pixels, and
+// each child's Wt is Rt restricted to the child's boundary (through the
+// child's row map).  Only the subtree's root forms Wt from the sweep fields.
+struct WFront {
+  const cplx *Qt;         // p x (p + b)
+  const cplx *Bf;         // b x (p + b): [U1t | Wt]
   const int32_t *perm;    // p pivot rows in step order
   const int32_t *gidx;    // p design-pixel indices (by pivot), or -1
   int32_t p, b;
+  int32_t nch;            // children in low-rank subtrees (0..2)
+  int32_t pc[2], bc[2];   // their pivot and boundary counts
+  cplx *dst[2];           // their Wt (b_c x b_c, ld p_c + b_c)
+  const int32_t *rmap[2]; // their boundary -> this front's local row
 };
 
 constexpr int GEMM_TILE = 64;

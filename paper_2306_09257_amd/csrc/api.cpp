@@ -184,16 +184,18 @@ struct Plan {
   // adjoint tiles (with the contraction) of level H - t + 1
   std::vector<int64_t> swl;
   std::vector<int> nswl;
-  // low-rank sweep fronts (no sweep children, no channel rows): instead of
-  // Y and Lam tiles, launch t is followed by the W = Lam_bnd Y_bnd^T quadrant
-  // tasks of level H - t + 1 (swtb), and their pixels' gradient is formed at
-  // the end
+  // low-rank sweep subtrees (no channel rows): instead of Y and Lam tiles,
+  // launch t is followed by the Wt = Y_bnd Lam_bnd^T quadrant tasks of the
+  // subtree roots of level H - t + 1 (swtb); after the sweeps, level by level
+  // from the top, the U1t and Qt products (wu, wq) and the gather of the
+  // children's Wt with the fronts' gradient (wp)
   std::vector<char> swl_deep;
   std::vector<int64_t> swtb;
   std::vector<int> nswtb;
-  int64_t lrfronts = -1;
-  int nlr = 0;
-  cplx *lrW = nullptr;        // their W blocks, b x b each
+  std::vector<int64_t> wu, wq, wp;
+  std::vector<int> nwu, nwq, nwp;
+  std::vector<char> wu_deep, wq_deep;
+  cplx *lrW = nullptr;        // per front: Bf (b x (p+b)) and Qt (p x (p+b))
   int64_t ndesign = 0;        // design pixels (contraction slots)
   int nblk = 0;               // 32-column contraction partials per pixel
   double *gpart = nullptr;    // ndesign x nblk
@@ -498,6 +500,7 @@ static double mean_tile_k(const std::vector<GemmTask> &v) {
 // run faster on the three-product kernel (fewer MFMAs) despite its lower
 // occupancy; shallower lists are bound by their loads and epilogues.
 constexpr double kDeepMeanK = 96.0;
+constexpr int kWMaxLevels = 3;   // levels of a low-rank sweep subtree
 // Flags every task of a deep list for the three-product form.  The flag is
 // per task, so a task rounds the same way in any launch that holds it
 // (single problems and merged batches alike).
@@ -585,20 +588,63 @@ static void build_plan(apf_handle *H) {
     // slots of low-rank fronts' pixels are never written: keep them zero
     HIPCHK(hipMemset(P.gpart, 0, std::max<int64_t>(P.ndesign * P.nblk, 1) * sizeof(double)));
   }
-  // low-rank sweep fronts and their W blocks
-  std::vector<char> lowrank(nf, 0);
-  std::vector<int64_t> lr_woff(nf, -1);
+  // Low-rank sweep subtrees.  For a sweep front f without channel rows the
+  // sweeps cost 2 p b M complex MACs (Y and Lam rows, M right-hand sides)
+  // plus its sweep children's costs; forming Wt = Y_bnd Lam_bnd^T instead
+  // costs b^2 M, after which the whole subtree is served by small dense
+  // products (b^2 p + p b (p + b) per front, independent of M).  The cheaper
+  // choice is taken bottom-up (fronts are in postorder); a chosen front with
+  // no chosen ancestor is a subtree root.  Subtrees span at most
+  // kWMaxLevels levels: the rounding error of the dense propagation grows by
+  // the cancellation factor of both field reconstructions at every level,
+  // where the sweeps add it once per level (24000 x 160, sampled gradient
+  // against the oracle: 5.6e-13 for 1 or 2 levels, 1.7e-11 for 3, 2.3e-10
+  // for 5, 1.4e-10 unlimited).
+  std::vector<char> wcov(nf, 0), wroot(nf, 0);
+  std::vector<int64_t> bf_off(nf, -1), qt_off(nf, -1);
   {
-    int64_t wtot = 0;
+    const double M = (double)Mi;
+    std::vector<double> cost(nf, 0.0), dense(nf, 0.0);
+    std::vector<char> pick(nf, 0);
+    std::vector<int> sdepth(nf, 0);   // levels of sweep fronts below f
     for (int f = 0; f < nf; ++f) {
       const Front &F = S.fronts[f];
-      if (!F.sweep || F.hasB || F.hasC || F.b() == 0 || F.b() > 64 || F.p() > 64) continue;
-      bool kid_sweeps = false;
-      for (int c = 0; c < F.nchild; ++c) kid_sweeps = kid_sweeps || S.fronts[F.child[c]].sweep;
-      if (kid_sweeps) continue;
-      lowrank[f] = 1;
-      lr_woff[f] = wtot;
-      wtot += (int64_t)F.b() * F.b();
+      if (!F.sweep) continue;
+      const double p = F.p(), b = F.b();
+      double direct = 2.0 * p * b * M, dsub = b * b * p + p * b * (p + b);
+      bool ok = !F.hasB && !F.hasC && F.b() > 0;
+      for (int c = 0; c < F.nchild; ++c) {
+        const int ch = F.child[c];
+        if (!S.fronts[ch].sweep) continue;
+        direct += cost[ch];
+        dsub += dense[ch];
+        sdepth[f] = std::max(sdepth[f], sdepth[ch] + 1);
+      }
+      ok = ok && sdepth[f] < kWMaxLevels;
+      dense[f] = dsub;
+      const double viaW = b * b * M + dsub;
+      pick[f] = ok && viaW < direct;
+      cost[f] = pick[f] ? viaW : direct;
+    }
+    // a chosen front covers its whole sweep subtree (parents come after their
+    // children, so walk down from the root)
+    for (int f = nf - 1; f >= 0; --f) {
+      const Front &F = S.fronts[f];
+      if (!F.sweep) continue;
+      const bool pc = F.parent >= 0 && wcov[F.parent];
+      wcov[f] = pc || pick[f];
+      wroot[f] = !pc && pick[f];
+    }
+    int64_t wtot = 0;
+    for (int f = 0; f < nf; ++f) {
+      if (!wcov[f]) continue;
+      const Front &F = S.fronts[f];
+      if (F.p() > 128) throw std::runtime_error("pivot block larger than 128 in a low-rank sweep subtree");
+      const int64_t n = F.p() + F.b();
+      bf_off[f] = wtot;
+      wtot += (int64_t)F.b() * n;
+      qt_off[f] = wtot;
+      wtot += (int64_t)F.p() * n;
     }
     HIPCHK(hipMalloc(&P.lrW, std::max<int64_t>(wtot, 1) * sizeof(cplx)));
   }
@@ -727,11 +773,12 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<AsmEntry>> ae(H_ + 1);
   std::vector<std::vector<PanelEntry>> pe(H_ + 1);
   std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), swY(H_ + 1), swL(H_ + 1), swW(H_ + 1);
-  std::vector<LowRankFront> lrf;
+  std::vector<std::vector<GemmTask>> wuL(H_ + 1), wqL(H_ + 1);
+  std::vector<std::vector<WFront>> wpL(H_ + 1);
   std::vector<GemmTask> gS, vinit;
   std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
-  double cm_factor = 0, cm_sweep = 0;
+  double cm_factor = 0, cm_sweep = 0, cm_wprop = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
     const FrontDev &D = fd[f];
@@ -859,11 +906,12 @@ static void build_plan(apf_handle *H) {
       tv.crowmap = perm;
       tv.aux = Xf;
       tv.auxmap = reinterpret_cast<const int32_t *>((intptr_t)(P.gidx + (int64_t)D.sweep_row0 * 4));  // rebased below
-      if (lowrank[f]) {
-        // W = Lam_bnd Y_bnd^T over the right-hand-side columns (summed over
-        // chunks): A = boundary rows of V, B = the same rows of X, both
-        // k-contiguous; one task per 32 x 32 quadrant
-        GemmTask tw = gemm(P.V, ch, P.X, ch, P.lrW + lr_woff[f], b, b, b, ch, G_TRANS_B | G_K_LIM | G_ACC_CHUNK);
+      if (wroot[f]) {
+        // Wt = Y_bnd Lam_bnd^T over the right-hand-side columns (summed over
+        // chunks): A = boundary rows of X, B = the same rows of V, both
+        // k-contiguous; one task per 32 x 32 quadrant, written into the Wt
+        // columns of the front's Bf
+        GemmTask tw = gemm(P.X, ch, P.V, ch, P.lrW + bf_off[f] + p, n, b, b, ch, G_TRANS_B | G_K_LIM | G_ACC_CHUNK);
         tw.arowmap = bm;
         tw.browmap = bm;
         for (int tm = 0; tm < b; tm += 32)
@@ -874,15 +922,33 @@ static void build_plan(apf_handle *H) {
             g_cmacs_acc += (double)std::min(32, b - tm) * std::min(32, b - tn) * ch;
             swW[lvl].push_back(u);
           }
-        LowRankFront L{};
-        L.W = P.lrW + lr_woff[f];
-        L.X12 = FSx(q.fs_x12);
-        L.Z = FSx(q.fs_z);
-        L.perm = perm;
-        L.gidx = reinterpret_cast<const int32_t *>((intptr_t)(P.gidx + (int64_t)D.sweep_row0 * 4));  // rebased below
-        L.p = p;
-        L.b = b;
-        lrf.push_back(L);
+      }
+      if (wcov[f]) {
+        // U1t = Wt Z into the first p columns of Bf; Qt = X12 [U1t | Wt]
+        cplx *bf = P.lrW + bf_off[f], *qt = P.lrW + qt_off[f];
+        const double acc0 = g_cmacs_acc;
+        add_tiles(wuL[lvl], gemm(bf + p, n, FSx(q.fs_z), p, bf, n, b, p, b, 0));
+        add_tiles(wqL[lvl], gemm(FSx(q.fs_x12), b, bf, n, qt, n, p, n, b, 0));
+        cm_wprop += g_cmacs_acc - acc0;
+        g_cmacs_acc = acc0;
+        WFront W{};
+        W.Qt = qt;
+        W.Bf = bf;
+        W.perm = perm;
+        W.gidx = reinterpret_cast<const int32_t *>((intptr_t)(P.gidx + (int64_t)D.sweep_row0 * 4));  // rebased below
+        W.p = p;
+        W.b = b;
+        for (int c = 0; c < F.nchild; ++c) {
+          const int cf = F.child[c];
+          if (!S.fronts[cf].sweep) continue;
+          const int pc = S.fronts[cf].p(), bc = S.fronts[cf].b();
+          W.pc[W.nch] = pc;
+          W.bc[W.nch] = bc;
+          W.dst[W.nch] = P.lrW + bf_off[cf] + pc;
+          W.rmap[W.nch] = reinterpret_cast<const int32_t *>((intptr_t)rmap_off[cf]);  // rebased below
+          ++W.nch;
+        }
+        wpL[lvl].push_back(W);
       } else {
         add_tiles(swY[lvl], ty);
         add_tiles(swL[lvl], tv);
@@ -905,7 +971,7 @@ static void build_plan(apf_handle *H) {
     cm_sweep += g_cmacs_acc * ((double)Mi / P.rhs_chunk);
   }
   P.gemm_cmacs_factor = cm_factor;
-  P.gemm_cmacs_sweep = cm_sweep;
+  P.gemm_cmacs_sweep = cm_sweep + cm_wprop;
   // S = sum over fronts holding both channel blocks of FC1 F11^-1 F1B
   //   = (U^-T FC1^T)^T (L^-1 P^T F1B) = SC^T SB
   g_cmacs_acc = 0;
@@ -954,8 +1020,16 @@ static void build_plan(apf_handle *H) {
     P.swtb[t] = bl.add(swW[H_ - t + 1]);
     P.nswtb[t] = (int)swW[H_ - t + 1].size();
   }
-  P.lrfronts = bl.add(lrf);
-  P.nlr = (int)lrf.size();
+  P.wu.assign(H_ + 1, -1); P.wq.assign(H_ + 1, -1); P.wp.assign(H_ + 1, -1);
+  P.nwu.assign(H_ + 1, 0); P.nwq.assign(H_ + 1, 0); P.nwp.assign(H_ + 1, 0);
+  P.wu_deep.assign(H_ + 1, 0); P.wq_deep.assign(H_ + 1, 0);
+  for (int l = 0; l <= H_; ++l) {
+    P.wu_deep[l] = mark_deep(wuL[l]);
+    P.wq_deep[l] = mark_deep(wqL[l]);
+    P.wu[l] = bl.add(wuL[l]); P.nwu[l] = (int)wuL[l].size();
+    P.wq[l] = bl.add(wqL[l]); P.nwq[l] = (int)wqL[l].size();
+    P.wp[l] = bl.add(wpL[l]); P.nwp[l] = (int)wpL[l].size();
+  }
   P.gS = bl.add(gS); P.ngS = (int)gS.size();
   // the Schur partials and the weighted adjoint source are K_total / M_out
   // deep: always the three-product form
@@ -1002,8 +1076,13 @@ static void build_plan(apf_handle *H) {
         }
       }
     }
-    LowRankFront *lr = reinterpret_cast<LowRankFront *>(bl.h.data() + P.lrfronts);
-    for (int k = 0; k < P.nlr; ++k) rebase(lr[k].gidx);
+    for (int l = 0; l <= H_; ++l) {
+      WFront *wf = reinterpret_cast<WFront *>(bl.h.data() + P.wp[l]);
+      for (int k = 0; k < P.nwp[l]; ++k) {
+        rebase(wf[k].gidx);
+        for (int c = 0; c < wf[k].nch; ++c) rebase(wf[k].rmap[c]);
+      }
+    }
   }
   (void)ib_size;
   HIPCHK(hipMemcpy(P.blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
@@ -1347,10 +1426,22 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
       }
     }
     pr.run(P_CONTRACT, s, [&] {
-      hipError_t e = launch_reduce_partials(P.gpart, P.nblk, P.ndesign, two_h2, grad_dev, s);
-      if (e == hipSuccess) e = launch_lowrank_grad(P.at<LowRankFront>(P.lrfronts), P.nlr, two_h2, grad_dev, s);
-      return e;
+      return launch_reduce_partials(P.gpart, P.nblk, P.ndesign, two_h2, grad_dev, s);
     });
+    // low-rank sweep subtrees, from the top: U1t, Qt, then the gradient of
+    // the level's fronts and their children's Wt
+    for (int l = (int)P.wp.size() - 1; l >= 0; --l) {
+      if (P.nwp[l] == 0) continue;
+      if (P.nwu[l] > 0)
+        pr.run(P_GEMM_SWEEP, s, [&] {
+          return launch_gemm(P.at<GemmTask>(P.wu[l]), P.nwu[l], 0, INT_MAX, nullptr, s, f32, nullptr, 0, P.wu_deep[l] != 0);
+        });
+      if (P.nwq[l] > 0)
+        pr.run(P_GEMM_SWEEP, s, [&] {
+          return launch_gemm(P.at<GemmTask>(P.wq[l]), P.nwq[l], 0, INT_MAX, nullptr, s, f32, nullptr, 0, P.wq_deep[l] != 0);
+        });
+      pr.run(P_CONTRACT, s, [&] { return launch_wprop(P.at<WFront>(P.wp[l]), P.nwp[l], two_h2, grad_dev, s); });
+    }
     if (h->prof.on) h->prof.collect();
     return APF_OK;
   });

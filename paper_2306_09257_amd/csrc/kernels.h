@@ -22,7 +22,8 @@ hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx 
 // W = Lam_bnd Y_bnd^T of the low-rank sweep fronts: one task per 32 x 32
 // quadrant (tm, tn), one wave per task; nlim: the chunk's width (k extent)
 hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStream_t s);
-hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, double *grad, hipStream_t s);
+// one workgroup per front of a low-rank sweep subtree (gradient + children's Wt)
+hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipStream_t s);
 hipError_t launch_row_map(int32_t *map, const int32_t *base, const int32_t *pidx, const int32_t *perm, int64_t n,
                           hipStream_t s);
 hipError_t launch_sum_partials(const cplx *part, int nseg, int64_t stride, cplx *S, int64_t n, hipStream_t s);

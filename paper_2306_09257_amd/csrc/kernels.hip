@@ -945,44 +945,38 @@ __global__ __launch_bounds__(256, 3) void k_lowrank_w(const GemmTask *tasks, int
       }
 }
 
-// Gradient of the pixels of the low-rank sweep fronts: with
-//   Y_f = -X12 Y_bnd,  Lam_f[perm[k]] = -(Z^T Lam_bnd)[k],  W = Lam_bnd Y_bnd^T,
-// grad_i = scale * Re sum_{a,c} Z[a][kinv(i)] W[a][c] X12[i][c]
-// (kinv(i): the step whose pivot row is i).  One workgroup per front; thread
-// (i, g) of a 64 x 4 grid takes the rows a = g, g + 4, ... of W for pivot i,
-// and the four partial sums of a pivot meet in LDS.
-__global__ __launch_bounds__(256) void k_lowrank_grad(const LowRankFront *fr, double scale, double *grad) {
-  const LowRankFront F = fr[blockIdx.x];
-  __shared__ int kinv[64];
-  __shared__ double part[4][64];
-  const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
-  if (g == 0 && i < F.p) kinv[F.perm[i]] = i;
+// One front of a low-rank sweep subtree (one workgroup): the gradient of its
+// pixels, grad_i = scale * Re Rt[i][i] = scale * Re Qt[i][kinv(i)], and the
+// Wt of its children in low-rank subtrees, gathered from Rt through their row
+// maps (kinv(i): the step whose pivot row is i).
+__global__ __launch_bounds__(256) void k_wprop(const WFront *fr, double scale, double *grad) {
+  const WFront F = fr[blockIdx.x];
+  __shared__ int kinv[128];
+  const int p = F.p, ld = F.p + F.b;
+  for (int k = threadIdx.x; k < p; k += blockDim.x) kinv[F.perm[k]] = k;
   __syncthreads();
-  double acc = 0.0;
-  if (i < F.p) {
-    const int k = kinv[i], b = F.b;
-    const cplx *x = F.X12 + (int64_t)i * b;
-    for (int a = g; a < b; a += 4) {
-      const cplx *w = F.W + (int64_t)a * b;
-      // four independent partial sums keep several loads in flight
-      double2 t[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
-                      make_double2(0.0, 0.0)};
-      int c = 0;
-      for (; c + 4 <= b; c += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = cadd(t[u], cmul(ld2(w + c + u), ld2(x + c + u)));
-      }
-      for (; c < b; ++c) t[0] = cadd(t[0], cmul(ld2(w + c), ld2(x + c)));
-      const double2 ts = cadd(cadd(t[0], t[1]), cadd(t[2], t[3]));
-      const double2 z = ld2(F.Z + (int64_t)a * F.p + k);
-      acc += z.x * ts.x - z.y * ts.y;
-    }
-  }
-  part[g][i] = acc;
-  __syncthreads();
-  if (g == 0 && i < F.p) {
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
     const int gi = F.gidx[i];
-    if (gi >= 0) grad[gi] = scale * (part[0][i] + part[1][i] + part[2][i] + part[3][i]);
+    if (gi >= 0) grad[gi] = scale * F.Qt[(int64_t)i * ld + kinv[i]].re;
+  }
+  for (int c = 0; c < F.nch; ++c) {
+    const int bc = F.bc[c], ldd = F.pc[c] + bc;
+    const int32_t *rm = F.rmap[c];
+    cplx *dst = F.dst[c];
+    for (int e = threadIdx.x; e < bc * bc; e += blockDim.x) {
+      const int y = e / bc, x = e - y * bc;
+      const int ry = rm[y], rx = rm[x];
+      double2 v;
+      if (ry < p) {
+        v = rx < p ? ld2(F.Qt + (int64_t)ry * ld + kinv[rx]) : ld2(F.Qt + (int64_t)ry * ld + rx);
+        if (rx >= p) v = make_double2(-v.x, -v.y);
+      } else {
+        const cplx *row = F.Bf + (int64_t)(ry - p) * ld;
+        v = rx < p ? ld2(row + kinv[rx]) : ld2(row + rx);
+        if (rx < p) v = make_double2(-v.x, -v.y);
+      }
+      st2(dst + (int64_t)y * ldd + x, v);
+    }
   }
 }
 
@@ -1090,9 +1084,9 @@ hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStr
   hipLaunchKernelGGL(k_lowrank_w, dim3((n + 3) / 4), dim3(256), 0, s, t, n, coff, nlim);
   return hipGetLastError();
 }
-hipError_t launch_lowrank_grad(const LowRankFront *f, int n, double scale, double *grad, hipStream_t s) {
+hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lowrank_grad, dim3(n), dim3(256), 0, s, f, scale, grad);
+  hipLaunchKernelGGL(k_wprop, dim3(n), dim3(256), 0, s, f, scale, grad);
   return hipGetLastError();
 }
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
