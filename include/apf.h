@@ -147,6 +147,46 @@ apf_status apf_weighted_power(apf_handle *h, const double *S_dev,
                               const double *w_dev, double *f_dev,
                               double *dfdS_dev, void *stream);
 
+/* Objective helper for the beam-splitter figure of merit (Sec. 3, Eq. (5)):
+ *   f = sum_nm (|S_nm|^2 - t_nm)^2,  t_nm = t1 where the output order minus
+ *   the input order is +-1 (the +-1 diffraction orders; the paper's t1 is
+ *   1/2), 0 elsewhere;  dF/dS = 2 (|S|^2 - t) conj(S) (the paper's df/dT).
+ *   S_dev, dfdS_dev: complex128 [n_out][n_in]; f_dev: one float64.
+ * Requires apf_assemble since the handle was analysed (APF_ESTATE). */
+apf_status apf_splitter_fom(apf_handle *h, const double *S_dev, double t1,
+                            double *f_dev, double *dfdS_dev, void *stream);
+
+/* Ridge parameterization of the design rows (Sec. 3: edge positions as the
+ * design parameters, mirror symmetry about the central plane):
+ *   edges_dev: float64 [n_edges] ascending edge positions in grid units
+ *     along the periodic axis (node j stands for the cell [j-1/2, j+1/2));
+ *     ridges are consecutive pairs (x1, x2), (x3, x4), ...  With mirror = 1
+ *     these are the first half period's edges and the period continues with
+ *     nx - x_n, ..., nx - x_1 (the reflection about x = nx/2).
+ *   eps_dev: float64 [ny][nx]; only the design rows are written: every design
+ *     row of column j gets eps_gap + (eps_ridge - eps_gap) * (fraction of
+ *     cell j covered by ridges, periodic images included).
+ * Ridges are assumed disjoint (overlaps add up); edges outside the period
+ * wrap.  APF_EINVAL for a null pointer, mirror not 0/1, n_edges <= 0 or an
+ * odd number of edges in the period. */
+apf_status apf_ridges_eps(apf_handle *h, const double *edges_dev, int32_t n_edges,
+                          int32_t mirror, double eps_ridge, double eps_gap,
+                          double *eps_dev, void *stream);
+
+/* Chain rule from the permittivity gradient to the edge positions (Sec. 2:
+ * dA/dp_k touches only the pixels p_k modifies): with the covered fraction
+ * of the cell holding an edge changing by -1 (left edge) or +1 (right edge)
+ * per unit move, and an image edge nx - x moving by -1,
+ *   grad_edges[k] = sum over design rows of grad_eps at the cells of edge k
+ *                   (and of its image) times -/+(eps_ridge - eps_gap).
+ *   grad_eps_dev: float64 [design_row1 - design_row0][nx] (as from apf_grad);
+ *   grad_edges_dev: float64 [n_edges].  Same arguments and errors as
+ *   apf_ridges_eps. */
+apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, int32_t n_edges,
+                           int32_t mirror, double eps_ridge, double eps_gap,
+                           const double *grad_eps_dev, double *grad_edges_dev,
+                           void *stream);
+
 /* Gradient of a real objective f(S) with respect to the permittivity of every
  * design pixel (Sec. 2, Eq. (1) with dS/deps_k of Eq. (3), U_k = e_k and
  * Sigma_k = dA_kk/deps_k = -h^2):

@@ -26,7 +26,7 @@ APF_FP64 = 0
 APF_MIXED = 1
 
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
-                "apf_weighted_power",
+                "apf_weighted_power", "apf_splitter_fom", "apf_ridges_eps", "apf_ridges_grad",
                 "apf_grad", "apf_set_profiling", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow")
@@ -70,6 +70,9 @@ def load_library(path: str = LIB_PATH):
     lib.apf_factor_schur.argtypes = [vp, i32, vp, vp]
     lib.apf_factor_schur_batched.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp), vp]
     lib.apf_weighted_power.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.apf_splitter_fom.argtypes = [vp, vp, dbl, vp, vp, vp]
+    lib.apf_ridges_eps.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
+    lib.apf_ridges_grad.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp, vp]
     lib.apf_grad.argtypes = [vp, vp, vp, vp]
     lib.apf_set_profiling.argtypes = [vp, i32]
     lib.apf_destroy.argtypes = [vp]
@@ -170,6 +173,36 @@ class APF:
         assert w.dtype == torch.float64 and w.is_contiguous() and S.is_contiguous()
         _check(self._lib.apf_weighted_power(self._h, _ptr(S), _ptr(w), _ptr(f), _ptr(G), _stream()))
         return f, G
+
+    def splitter_fom(self, S, t1: float = 0.5):
+        """Eq. (5) figure of merit and dF/dS (device tensors)."""
+        import torch
+        assert S.dtype == torch.complex128 and S.is_contiguous()
+        f = torch.empty((), dtype=torch.float64, device=S.device)
+        G = torch.empty_like(S)
+        _check(self._lib.apf_splitter_fom(self._h, _ptr(S), float(t1), _ptr(f), _ptr(G), _stream()))
+        return f, G
+
+    def ridges_eps(self, edges, eps, mirror: bool, eps_ridge: float, eps_gap: float):
+        """Writes the design rows of eps ([ny][nx] float64, device) from the
+        edge positions (float64 device tensor, grid units)."""
+        import torch
+        assert edges.dtype == torch.float64 and edges.is_contiguous() and edges.is_cuda
+        assert eps.dtype == torch.float64 and eps.is_contiguous() and tuple(eps.shape) == (self.prob.ny, self.prob.nx)
+        _check(self._lib.apf_ridges_eps(self._h, _ptr(edges), edges.numel(), int(mirror), float(eps_ridge),
+                                        float(eps_gap), _ptr(eps), _stream()))
+        return eps
+
+    def ridges_grad(self, edges, grad_eps, mirror: bool, eps_ridge: float, eps_gap: float):
+        """df/d(edges) from df/deps of the design rows."""
+        import torch
+        assert edges.dtype == torch.float64 and edges.is_contiguous() and edges.is_cuda
+        assert grad_eps.dtype == torch.float64 and grad_eps.is_contiguous()
+        assert tuple(grad_eps.shape) == (self.prob.n_design_rows, self.prob.nx)
+        out = torch.empty_like(edges)
+        _check(self._lib.apf_ridges_grad(self._h, _ptr(edges), edges.numel(), int(mirror), float(eps_ridge),
+                                         float(eps_gap), _ptr(grad_eps), _ptr(out), _stream()))
+        return out
 
     def grad(self, dfdS, out=None):
         import torch

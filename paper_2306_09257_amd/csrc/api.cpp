@@ -1400,6 +1400,58 @@ extern "C" apf_status apf_weighted_power(apf_handle *h, const double *S_dev, con
   });
 }
 
+extern "C" apf_status apf_splitter_fom(apf_handle *h, const double *S_dev, double t1, double *f_dev,
+                                       double *dfdS_dev, void *stream) {
+  if (!h || !S_dev || !f_dev || !dfdS_dev) return fail(APF_EINVAL, "null argument");
+  if (!h->planned) return fail(APF_ESTATE, "apf_assemble has not run");
+  return guarded([&]() -> apf_status {
+    const int Mi = h->d.n_in, Mo = h->d.n_out;
+    const int64_t n = (int64_t)Mi * Mo;
+    const int npart = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t *in_ord = reinterpret_cast<const int32_t *>(h->plan.chan + 2 * sizeof(ChanParams));
+    Profiler &pr = h->prof;
+    pr.run(P_WPOW, s, [&] {
+      return launch_splitter_fom(reinterpret_cast<const cplx *>(S_dev), in_ord, in_ord + Mi, Mi, Mo, t1, f_dev,
+                                 reinterpret_cast<cplx *>(dfdS_dev), h->plan.part, npart, s);
+    });
+    if (pr.on) pr.collect();
+    return APF_OK;
+  });
+}
+
+static apf_status check_ridges(apf_handle *h, const double *edges_dev, int32_t n_edges, int32_t mirror) {
+  if (!h || !edges_dev) return fail(APF_EINVAL, "null argument");
+  if (mirror != 0 && mirror != 1) return fail(APF_EINVAL, "mirror must be 0 or 1");
+  if (n_edges <= 0 || ((mirror ? 2 * (int64_t)n_edges : n_edges) % 2) != 0)
+    return fail(APF_EINVAL, "the edges of the period must form pairs");
+  if (h->d.design_row1 <= h->d.design_row0) return fail(APF_EINVAL, "no design rows");
+  return APF_OK;
+}
+
+extern "C" apf_status apf_ridges_eps(apf_handle *h, const double *edges_dev, int32_t n_edges, int32_t mirror,
+                                     double eps_ridge, double eps_gap, double *eps_dev, void *stream) {
+  if (apf_status st = check_ridges(h, edges_dev, n_edges, mirror)) return st;
+  if (!eps_dev) return fail(APF_EINVAL, "null argument");
+  return guarded([&]() -> apf_status {
+    HIPCHK(launch_ridges_eps(edges_dev, n_edges, mirror, h->d.nx, h->d.design_row0,
+                             h->d.design_row1 - h->d.design_row0, eps_ridge, eps_gap, eps_dev, (hipStream_t)stream));
+    return APF_OK;
+  });
+}
+
+extern "C" apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, int32_t n_edges, int32_t mirror,
+                                      double eps_ridge, double eps_gap, const double *grad_eps_dev,
+                                      double *grad_edges_dev, void *stream) {
+  if (apf_status st = check_ridges(h, edges_dev, n_edges, mirror)) return st;
+  if (!grad_eps_dev || !grad_edges_dev) return fail(APF_EINVAL, "null argument");
+  return guarded([&]() -> apf_status {
+    HIPCHK(launch_ridges_grad(edges_dev, n_edges, mirror, h->d.nx, h->d.design_row1 - h->d.design_row0, eps_ridge,
+                              eps_gap, grad_eps_dev, grad_edges_dev, (hipStream_t)stream));
+    return APF_OK;
+  });
+}
+
 extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev, void *stream) {
   if (!h || !dfdS_dev || !grad_dev) return fail(APF_EINVAL, "null argument");
   if (h->state != 2) return fail(APF_ESTATE, "apf_factor_schur has not run since the last assembly");

@@ -32,4 +32,13 @@ hipError_t launch_reduce_partials(const double *part, int nblk, int64_t n, doubl
 hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx *G, int64_t n, double *part,
                                  int npart, hipStream_t s);
 
+// beam-splitter workload: Eq. (5) figure of merit, ridge permittivity and
+// the chain rule to the edge positions (see include/apf.h)
+hipError_t launch_splitter_fom(const cplx *S, const int32_t *in_ord, const int32_t *out_ord, int n_in, int n_out,
+                               double t1, double *f, cplx *G, double *part, int npart, hipStream_t s);
+hipError_t launch_ridges_eps(const double *edges, int n, int mirror, int nx, int row0, int nrows, double eps_ridge,
+                             double eps_gap, double *eps, hipStream_t s);
+hipError_t launch_ridges_grad(const double *edges, int n, int mirror, int nx, int nrows, double eps_ridge,
+                              double eps_gap, const double *grad_eps, double *grad_edges, hipStream_t s);
+
 }  // namespace apf

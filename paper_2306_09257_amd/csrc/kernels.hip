@@ -1025,6 +1025,98 @@ __global__ void k_wpow_final(const double *part, int n, double *f) {
 }
 
 // ---------------------------------------------------------------------------
+// Beam-splitter figure of merit (Eq. (5)): f = sum (|S|^2 - t)^2 with
+// t = t1 where the output order differs from the input order by +-1, else 0;
+// dF/dS = 2 (|S|^2 - t) conj(S).  Block partial sums, then k_wpow_final.
+// ---------------------------------------------------------------------------
+__global__ void k_splitter_partial(const double2 *S, const int32_t *in_ord, const int32_t *out_ord, int n_in,
+                                   double t1, double2 *G, int64_t n, double *part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(e / n_in), m = (int)(e - (int64_t)o * n_in);
+    const int d = out_ord[o] - in_ord[m];
+    const double t = (d == 1 || d == -1) ? t1 : 0.0;
+    const double2 v = S[e];
+    const double r = v.x * v.x + v.y * v.y - t;
+    acc += r * r;
+    G[e] = make_double2(2.0 * r * v.x, -2.0 * r * v.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Ridge permittivity from edge positions (grid units along the periodic axis,
+// node j = cell [j - 1/2, j + 1/2)); with mirror symmetry the given edges are
+// the first half period's and the full list continues with nx - x in
+// reverse order.  Ridges are consecutive edge pairs; a cell's permittivity
+// is eps_gap + (eps_ridge - eps_gap) * (covered fraction), on every design
+// row.  One thread per cell.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ridge_edge(const double *e, int n, int mirror, int nx, int q) {
+  return (!mirror || q < n) ? e[q] : (double)nx - e[2 * n - 1 - q];
+}
+
+__global__ void k_ridges_eps(const double *edges, int n, int mirror, int nx, int row0, int nrows, double eps_ridge,
+                             double eps_gap, double *eps) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nx) return;
+  const int nfull = mirror ? 2 * n : n;
+  const double lo = (double)j - 0.5, hi = lo + 1.0;
+  double frac = 0.0;
+  for (int r = 0; r + 1 < nfull; r += 2) {
+    const double a = ridge_edge(edges, n, mirror, nx, r), b = ridge_edge(edges, n, mirror, nx, r + 1);
+    for (int sh = -1; sh <= 1; ++sh) {
+      const double c = fmin(hi, b + sh * (double)nx) - fmax(lo, a + sh * (double)nx);
+      if (c > 0.0) frac += c;
+    }
+  }
+  const double v = eps_gap + (eps_ridge - eps_gap) * frac;
+  for (int i = 0; i < nrows; ++i) eps[(int64_t)(row0 + i) * nx + j] = v;
+}
+
+// df/dx_k for the free edges: the cell holding an edge changes its covered
+// length by -1 (left edge, even place in the full list) or +1 (right edge)
+// per unit move; an image edge nx - x moves by -1.  grad_eps: [nrows][nx].
+// One workgroup per free edge: the column sums over the design rows.
+__device__ double column_sum(const double *g, int nx, int nrows, int j, double *red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nrows; i += blockDim.x) acc += g[(int64_t)i * nx + j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double v = red[0];
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_ridges_grad(const double *edges, int n, int mirror, int nx, int nrows,
+                                                    double eps_ridge, double eps_gap, const double *grad_eps,
+                                                    double *grad_edges) {
+  __shared__ double red[64];
+  const int k = blockIdx.x;
+  const double de = eps_ridge - eps_gap;
+  const int nfull = mirror ? 2 * n : n;
+  auto cell = [&](double x) { int c = (int)floor(x + 0.5) % nx; return c < 0 ? c + nx : c; };
+  double g = (k % 2 == 0 ? -de : de) * column_sum(grad_eps, nx, nrows, cell(edges[k]), red);
+  if (mirror) {
+    const int q = nfull - 1 - k;
+    const double sq = q % 2 == 0 ? -de : de;
+    g -= sq * column_sum(grad_eps, nx, nrows, cell(ridge_edge(edges, n, mirror, nx, q)), red);
+  }
+  if (threadIdx.x == 0) grad_edges[k] = g;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
@@ -1144,6 +1236,30 @@ hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_wpow_final, dim3(1), dim3(256), 0, s, part, npart, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_splitter_fom(const cplx *S, const int32_t *in_ord, const int32_t *out_ord, int n_in, int n_out,
+                               double t1, double *f, cplx *G, double *part, int npart, hipStream_t s) {
+  const int64_t n = (int64_t)n_in * n_out;
+  hipLaunchKernelGGL(k_splitter_partial, dim3(npart), dim3(256), 0, s, reinterpret_cast<const double2 *>(S), in_ord,
+                     out_ord, n_in, t1, reinterpret_cast<double2 *>(G), n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wpow_final, dim3(1), dim3(256), 0, s, part, npart, f);
+  return hipGetLastError();
+}
+hipError_t launch_ridges_eps(const double *edges, int n, int mirror, int nx, int row0, int nrows, double eps_ridge,
+                             double eps_gap, double *eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_ridges_eps, dim3((nx + 255) / 256), dim3(256), 0, s, edges, n, mirror, nx, row0, nrows,
+                     eps_ridge, eps_gap, eps);
+  return hipGetLastError();
+}
+hipError_t launch_ridges_grad(const double *edges, int n, int mirror, int nx, int nrows, double eps_ridge,
+                              double eps_gap, const double *grad_eps, double *grad_edges, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ridges_grad, dim3(n), dim3(64), 0, s, edges, n, mirror, nx, nrows, eps_ridge, eps_gap,
+                     grad_eps, grad_edges);
   return hipGetLastError();
 }
 

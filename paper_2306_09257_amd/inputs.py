@@ -235,3 +235,61 @@ def tiny_problem(nx=24, ny=60, seed=0, layout=None, n_orders=None, **kw):
     eps = eps_uniform(prob, rng)
     w = weights_uniform(prob, rng)
     return prob, eps, w
+
+
+# ----------------------------------------------------------------------------
+# beam-splitter workload (Sec. 3): period W = 24 um, wavelength 0.94 um,
+# a-Si ridges (n = 3.70) of height 0.56 um on silica (n = 1.45) in air, light
+# incident from the substrate, inputs |a| < W/(2 lambda) (within +-30 degrees
+# in air), outputs |a| < W/lambda (all outgoing orders in air)
+# ----------------------------------------------------------------------------
+
+SPLITTER_W_UM = 24.0
+SPLITTER_LAMBDA_UM = 0.94
+SPLITTER_RIDGE_H_UM = 0.56
+SPLITTER_EPS_RIDGE = 3.70 ** 2
+SPLITTER_EPS_SUBSTRATE = 1.45 ** 2
+SPLITTER_EPS_AIR = 1.0
+SPLITTER_MIN_GAP_UM = 0.04
+
+
+def splitter_problem(nx: int = 1024, npml: int = 20, spacer: int = 12) -> Problem:
+    """Grid of one period: nx cells across W, the ridge band rounded to whole
+    rows (24 at nx = 1024, dx = 23.4 nm = lambda / 40.1); rows: PML |
+    substrate (source side) | ridges | air (projection side) | PML."""
+    dx_um = SPLITTER_W_UM / nx
+    rows = int(round(SPLITTER_RIDGE_H_UM / dx_um))
+    lay = (npml, spacer, rows, spacer, npml)
+    dxl = dx_um / SPLITTER_LAMBDA_UM
+    return make_problem(nx, sum(lay), dx_over_lambda=dxl, layout=lay,
+                        in_orders=channel_orders(nx, dxl, sin_max=0.5),
+                        out_orders=channel_orders(nx, dxl),
+                        eps_top=SPLITTER_EPS_SUBSTRATE, eps_bot=SPLITTER_EPS_AIR)
+
+
+def splitter_edges_to_grid(y_um, nx: int) -> np.ndarray:
+    """Edge positions y in [-W/2, W/2] (microns, central plane at 0) to grid
+    units x = (y / W + 1/2) nx along the periodic axis."""
+    return (np.asarray(y_um, dtype=np.float64) / SPLITTER_W_UM + 0.5) * nx
+
+
+def splitter_random_edges(nx: int, rng: np.random.Generator, n_ridges_half: int = 40) -> np.ndarray:
+    """2 n_ridges_half ascending edges of the first half period [0, nx/2] (grid
+    units) with every ridge width and gap (the ends included) at least
+    40 nm: gaps = minimum + the rest split by a flat Dirichlet draw."""
+    n = 2 * n_ridges_half
+    half = nx / 2.0
+    m = SPLITTER_MIN_GAP_UM / (SPLITTER_W_UM / nx)
+    spare = half - (n + 1) * m
+    if spare <= 0:
+        raise ValueError("grid too coarse for the minimum gap")
+    g = m + spare * rng.dirichlet(np.ones(n + 1))
+    return np.cumsum(g)[:n]
+
+
+def beam_splitter(seed: int = 6, nx: int = 1024):
+    """The beam-splitter problem with a seeded random initial design:
+    (prob, background eps, first-half-period edges in grid units)."""
+    prob = splitter_problem(nx)
+    rng = np.random.default_rng(seed)
+    return prob, prob.background_eps(), splitter_random_edges(nx, rng)
