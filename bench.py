@@ -13,10 +13,11 @@ Workload (default): 1,200-wavelength metasurface, 24,000 x 160 grid
 Gaussian, f = sum w |S|^2 with w ~ U[0, 1].  Synthetic, seeded.
 
 Prints one JSON line.  The roofline block is for the batched complex FP64
-MFMA GEMM kernel (k_gemm): its algorithmic flops (8 per complex MAC of the
+MFMA GEMM kernels (k_gemm, its three-product variant k_gemm_k3 and the
+low-rank k_lowrank_w): their algorithmic flops (8 per complex MAC of the
 M x N x K products the tasks specify, a triangular factor counting only its
-stored triangle) over its HIP-event time in the timed region; traffic is
-the kernel's HBM bytes per launch from the committed counter summary under
+stored triangle) over their HIP-event time in the timed region; traffic is
+their HBM bytes per launch from the committed counter summary under
 profiles/, or null when that summary was taken on other sources.  The
 cpu_baseline block times the CPU FP64 oracle on a bounded narrow-strip
 sample of the same workload and scales it by the oracle's cost model to the
@@ -271,7 +272,7 @@ def main():
     peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "mixed" else FP64_MFMA_PEAK_TFLOPS
     traffic, traffic_note = profiled_traffic(args.workload, args.precision)
     roofline = {
-        "kernel": "k_gemm (batched complex %s MFMA GEMM, all launches of a step)"
+        "kernel": "k_gemm / k_gemm_k3 / k_lowrank_w (batched complex %s MFMA GEMMs, all launches of a step)"
                   % ("FP32" if args.precision == "mixed" else "FP64"),
         "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
         "frac": achieved / peak, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
@@ -288,7 +289,7 @@ def main():
         "dtype": "c128 (f64)", "data": "synthetic",
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "unknowns": prob.nx * prob.ny,
                    "n_in": prob.n_in, "n_out": prob.n_out, "design_pixels": prob.n_design_rows * prob.nx,
-                   "precision": args.precision, "leaf_size": args.leaf or 64},
+                   "precision": args.precision, "leaf_size": args.leaf or 48},
         "roofline": roofline,
         "phase_ms_per_step": phases,
         "analysis_s": t_an,

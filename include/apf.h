@@ -87,7 +87,7 @@ typedef struct {
   int32_t n_in, n_out;
   const int32_t *in_orders;   /* n_in channel orders a (source row)       */
   const int32_t *out_orders;  /* n_out channel orders b (projection row)  */
-  int32_t leaf_size;          /* max nodes of a nested-dissection leaf; 0 = default (64) */
+  int32_t leaf_size;          /* max nodes of a nested-dissection leaf; 0 = default (48) */
 } apf_problem_desc;
 
 /* Validate the descriptor and create a handle (host only, no GPU work). */
