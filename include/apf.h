@@ -221,7 +221,9 @@ const char *apf_last_error(void);
  *   after the first apf_assemble: "rhs_chunk", "gemm_cmacs_factor",
  *   "gemm_cmacs_schur", "gemm_cmacs_sweep" (complex multiply-adds of the
  *   GEMM tasks of one call whose operands are structurally nonzero: the
- *   stored triangle of a triangular factor, no tile padding);
+ *   stored triangle of a triangular factor, no tile padding),
+ *   "lowrank_fronts" and "lowrank_roots" (sweep fronts served by the
+ *   low-rank subtree products, and the subtrees' roots);
  *   with profiling on: "ms_<class>" and "launches_<class>", the summed
  *   HIP-event time and launch count since profiling was enabled, for the
  *   classes stencil, zero, assemble, inverse, gemm_factor, gemm_schur,

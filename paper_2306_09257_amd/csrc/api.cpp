@@ -196,6 +196,7 @@ struct Plan {
   std::vector<int> nwu, nwq, nwp;
   std::vector<char> wu_deep, wq_deep;
   cplx *lrW = nullptr;        // per front: Bf (b x (p+b)) and Qt (p x (p+b))
+  int n_wfronts = 0, n_wroots = 0;   // fronts of low-rank sweep subtrees, their roots
   int64_t ndesign = 0;        // design pixels (contraction slots)
   int nblk = 0;               // 32-column contraction partials per pixel
   double *gpart = nullptr;    // ndesign x nblk
@@ -637,7 +638,9 @@ static void build_plan(apf_handle *H) {
     }
     int64_t wtot = 0;
     for (int f = 0; f < nf; ++f) {
+      P.n_wroots += wroot[f];
       if (!wcov[f]) continue;
+      ++P.n_wfronts;
       const Front &F = S.fronts[f];
       if (F.p() > 128) throw std::runtime_error("pivot block larger than 128 in a low-rank sweep subtree");
       const int64_t n = F.p() + F.b();
@@ -1540,6 +1543,8 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
   else if (k == "factor_bytes") *value = (double)h->plan.fs_elems * sizeof(cplx);
   else if (k == "schur_store_bytes") *value = (double)S.k_total * (h->d.n_in + h->d.n_out) * sizeof(cplx);
   else if (k == "rhs_chunk") *value = h->planned ? (double)h->plan.rhs_chunk : -1.0;
+  else if (k == "lowrank_fronts") *value = h->planned ? (double)h->plan.n_wfronts : -1.0;
+  else if (k == "lowrank_roots") *value = h->planned ? (double)h->plan.n_wroots : -1.0;
   else if (k == "gemm_cmacs_factor") *value = h->planned ? h->plan.gemm_cmacs_factor : -1.0;
   else if (k == "gemm_cmacs_schur") *value = h->planned ? h->plan.gemm_cmacs_schur : -1.0;
   else if (k == "gemm_cmacs_sweep") *value = h->planned ? h->plan.gemm_cmacs_sweep : -1.0;

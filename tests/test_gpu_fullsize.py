@@ -44,7 +44,10 @@ def test_metasurface_24000x160_against_oracle_samples():
     gs = g_h.ravel()[gold["pixels"]]
     eg = np.linalg.norm(gs - gold["grad"]) / np.linalg.norm(gold["grad"])
     en = abs(np.linalg.norm(g_h) - float(gold["grad_norm"])) / float(gold["grad_norm"])
-    print(f"[gpu] rel err S columns {eS:.2e}, sampled grad {eg:.2e}, grad norm {en:.2e}", flush=True)
+    nlr, nroot = apf.query("lowrank_fronts"), apf.query("lowrank_roots")
+    print(f"[gpu] rel err S columns {eS:.2e}, sampled grad {eg:.2e}, grad norm {en:.2e}; "
+          f"{nlr:.0f} fronts in {nroot:.0f} low-rank sweep subtrees", flush=True)
+    assert nroot > 0 and nlr > nroot      # the subtree products take part
     assert eS < TOL
     assert eg < TOL
     assert en < TOL
