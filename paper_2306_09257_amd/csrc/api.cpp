@@ -1056,10 +1056,13 @@ static void build_plan(apf_handle *H) {
       if (rmap_off[f] >= 0) rebase(fdv[f].rmap);
       else fdv[f].rmap = nullptr;
     }
+    // (an empty list and the next one can share an offset: take each list's
+    // own count, never look the count up by offset)
     for (int lvl = 0; lvl <= H_; ++lvl)
-      for (int64_t off : {P.lv[lvl].g2, P.lv[lvl].g2b}) {
-        GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + off);
-        const int n = off == P.lv[lvl].g2 ? P.lv[lvl].ng2 : P.lv[lvl].ng2b;
+      for (int which = 0; which < 2; ++which) {
+        const LevelTasks &L = P.lv[lvl];
+        GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + (which ? L.g2b : L.g2));
+        const int n = which ? L.ng2b : L.ng2;
         for (int k = 0; k < n; ++k) {
           rebase(t[k].crowmap);
           rebase(t[k].ccolmap);
