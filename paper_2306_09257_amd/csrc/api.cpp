@@ -912,19 +912,14 @@ static void build_plan(apf_handle *H) {
       if (wroot[f]) {
         // Wt = Y_bnd Lam_bnd^T over the right-hand-side columns (summed over
         // chunks): A = boundary rows of X, B = the same rows of V, both
-        // k-contiguous; one task per 32 x 32 quadrant, written into the Wt
-        // columns of the front's Bf
+        // k-contiguous; one task per root, written into the Wt columns of
+        // the front's Bf
+        if (b > 64) throw std::runtime_error("low-rank subtree root with more than 64 boundary nodes");
         GemmTask tw = gemm(P.X, ch, P.V, ch, P.lrW + bf_off[f] + p, n, b, b, ch, G_TRANS_B | G_K_LIM | G_ACC_CHUNK);
         tw.arowmap = bm;
         tw.browmap = bm;
-        for (int tm = 0; tm < b; tm += 32)
-          for (int tn = 0; tn < b; tn += 32) {
-            GemmTask u = tw;
-            u.tm = tm;
-            u.tn = tn;
-            g_cmacs_acc += (double)std::min(32, b - tm) * std::min(32, b - tn) * ch;
-            swW[lvl].push_back(u);
-          }
+        g_cmacs_acc += (double)b * b * ch;
+        swW[lvl].push_back(tw);
       }
       if (wcov[f]) {
         // U1t = Wt Z into the first p columns of Bf; Qt = X12 [U1t | Wt]

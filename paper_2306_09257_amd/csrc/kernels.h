@@ -19,8 +19,8 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
 // deep: MFMA-bound deep-K task list (three-product complex form on FP64)
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
                        bool f32 = false, double *part = nullptr, int nblk = 0, bool deep = false);
-// W = Lam_bnd Y_bnd^T of the low-rank sweep fronts: one task per 32 x 32
-// quadrant (tm, tn), one wave per task; nlim: the chunk's width (k extent)
+// Wt = Y_bnd Lam_bnd^T of the low-rank subtree roots: one task (b <= 64) per
+// root, one workgroup per task; nlim: the chunk's width (k extent)
 hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStream_t s);
 // one workgroup per front of a low-rank sweep subtree (gradient + children's Wt)
 hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipStream_t s);

@@ -857,88 +857,95 @@ __global__ __launch_bounds__(256, 3) void k_gemm_k3(const GemmTask *tasks, int c
   }
 }
 
-// W = Lam_bnd Y_bnd^T of the low-rank sweep fronts: a b x b product (b <= 64)
-// over the right-hand-side columns, both operands gathered rows of the sweep
-// arrays (A = V rows arowmap, B = X rows browmap, each row k-contiguous).
-// Each task is one 32 x 32 quadrant (tm, tn) of one front and runs on one
-// wave; a workgroup holds four independent tasks, with no LDS and no
-// barrier.  Lane l takes row (l % 16) of a 16-row block and the four
-// consecutive k = 4 (l / 16) + j of each 16-k slab, so each lane loads 64
-// contiguous bytes per row and MFMA step j pairs A and B entries of the same
-// k.  Rows past the front's size are clamped to a valid row (their outputs
-// are not stored); k past the chunk's width reads zeros.  The chunk's sum is
-// stored, or added for column offsets > 0 (later chunks).
-__global__ __launch_bounds__(256, 3) void k_lowrank_w(const GemmTask *tasks, int n, int coff, int nlimk) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int idx = blockIdx.x * 4 + wave;
-  if (idx >= n) return;
-  const GemmTask T = tasks[idx];
+// Wt = Y_bnd Lam_bnd^T of the roots of the low-rank sweep subtrees: a b x b
+// product (b <= 64) over the right-hand-side columns whose operands are
+// gathered rows of the sweep arrays (A rows arowmap, B rows browmap, each
+// row k-contiguous).  One workgroup per root, each wave one 32 x 32
+// quadrant; every 16-k slab of the 64 A rows and 64 B rows is read from HBM
+// once and shared through LDS, and the next slab's loads are issued before
+// the current slab's MFMAs so that they are in flight meanwhile.  Rows past
+// the front's size are clamped to its last row (their outputs are not
+// stored); k past the chunk's width reads zeros.  The chunk's sum is stored,
+// or added for column offsets > 0 (later chunks).
+__global__ __launch_bounds__(256, 2) void k_lowrank_w(const GemmTask *tasks, int coff, int nlimk) {
+  typedef GemmPrec<false> GP;
+  __shared__ double2 As[16][64];
+  __shared__ double2 Bs[16][64];
+  const GemmTask T = tasks[blockIdx.x];
   const int M = T.M, N = T.N, K = nlimk < T.K ? nlimk : T.K;
-  const int r = lane & 15, g = lane >> 4;
-  const cplx *pa[2], *pb[2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // loader: thread -> (row, 4 consecutive k) of the slab, for A and for B
+  const int lr = tid >> 2, lk = (tid & 3) * 4;
+  const cplx *pa = T.A + (int64_t)T.arowmap[min(lr, M - 1)] * T.lda;
+  const cplx *pb = T.B + (int64_t)T.browmap[min(lr, N - 1)] * T.ldb;
+  double2 ra[4], rb[4];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int ia = min(T.tm + 16 * h + r, M - 1), jb = min(T.tn + 16 * h + r, N - 1);
-    pa[h] = T.A + (int64_t)T.arowmap[ia] * T.lda + 4 * g;
-    pb[h] = T.B + (int64_t)T.browmap[jb] * T.ldb + 4 * g;
-  }
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + lk + q;
+      ra[q] = k < K ? ld2(pa + k) : make_double2(0.0, 0.0);
+      rb[q] = k < K ? ld2(pb + k) : make_double2(0.0, 0.0);
+    }
+  };
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const bool active = wr < M && wc < N;
+  bool blk[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) blk[r][c] = wr + 16 * r < M && wc + 16 * c < N;
   d4 cre[2][2], cim[2][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      cre[a][c] = d4{0, 0, 0, 0};
-      cim[a][c] = d4{0, 0, 0, 0};
+      cre[r][c] = d4{0, 0, 0, 0};
+      cim[r][c] = d4{0, 0, 0, 0};
     }
-  auto step = [&](const double2 (&ra)[2][4], const double2 (&rb)[2][4]) {
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    __syncthreads();   // the previous slab's MFMA reads are done
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int q = 0; q < 4; ++q) {
+      As[lk + q][lr ^ GP::swz(lk + q)] = ra[q];
+      Bs[lk + q][lr ^ GP::swz(lk + q)] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + 16 < K) load(k0 + 16);
+    if (active) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int kx = kk + (lane >> 4);
+        double2 a[2], b[2];
+        a[0] = As[kx][(wr + (lane & 15)) ^ GP::swz(kx)];
+        a[1] = As[kx][(wr + 16 + (lane & 15)) ^ GP::swz(kx)];
+        b[0] = Bs[kx][(wc + (lane & 15)) ^ GP::swz(kx)];
+        b[1] = Bs[kx][(wc + 16 + (lane & 15)) ^ GP::swz(kx)];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          cre[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a][j].x, rb[c][j].x, cre[a][c], 0, 0, 0);
-          cre[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ra[a][j].y, rb[c][j].y, cre[a][c], 0, 0, 0);
-          cim[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a][j].x, rb[c][j].y, cim[a][c], 0, 0, 0);
-          cim[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a][j].y, rb[c][j].x, cim[a][c], 0, 0, 0);
-        }
-  };
-  const int kfull = K & ~15;
-  for (int k0 = 0; k0 < kfull; k0 += 16) {
-    double2 ra[2][4], rb[2][4];
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        ra[h][j] = ldg(as_global(pa[h]) + k0 + j);
-        rb[h][j] = ldg(as_global(pb[h]) + k0 + j);
+          for (int c = 0; c < 2; ++c)
+            if (blk[r][c]) {
+              cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
+              cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
+              cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
+              cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+            }
       }
-    step(ra, rb);
+    }
   }
-  if (kfull < K) {
-    double2 ra[2][4], rb[2][4];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bool in = kfull + 4 * g + j < K;
-        ra[h][j] = in ? ld2(pa[h] + kfull + j) : make_double2(0.0, 0.0);
-        rb[h][j] = in ? ld2(pb[h] + kfull + j) : make_double2(0.0, 0.0);
-      }
-    step(ra, rb);
-  }
-  // D layout: lane l, element q -> row (l / 16) + 4 q, column l % 16
+  if (!active) return;
   const bool acc = coff > 0;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = T.tm + 16 * a + g + 4 * q, jj = T.tn + 16 * c + r;
-        if (i < M && jj < N) {
-          cplx *w = T.C + (int64_t)i * T.ldc + jj;
-          double2 v = make_double2(cre[a][c][q], cim[a][c][q]);
+        const int i = wr + 16 * r + GP::row(lane, q), j = wc + 16 * c + (lane & 15);
+        if (i < M && j < N) {
+          cplx *w = T.C + (int64_t)i * T.ldc + j;
+          double2 v = make_double2(cre[r][c][q], cim[r][c][q]);
           if (acc) v = cadd(v, ld2(w));
           st2(w, v);
         }
@@ -1173,7 +1180,7 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
 
 hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lowrank_w, dim3((n + 3) / 4), dim3(256), 0, s, t, n, coff, nlim);
+  hipLaunchKernelGGL(k_lowrank_w, dim3(n), dim3(256), 0, s, t, coff, nlim);
   return hipGetLastError();
 }
 hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipStream_t s) {
