@@ -72,6 +72,25 @@ def test_metasurface_240x92_matches_oracle():
     assert _rel(g, g_o) < TOL
 
 
+def test_lowrank_subtrees_match_oracle_1200x92():
+    """1200 x 92 grid, 119 x 119 channels: enough right-hand sides for the
+    channel-free sweep subtrees to take the low-rank route (Wt = Y_bnd
+    Lam_bnd^T at their roots, dense propagation below); every pixel's
+    gradient against the oracle, and the subtree fronts' share checked."""
+    prob = inputs.make_problem(1200, 92)
+    rng = np.random.default_rng(11)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    w = inputs.weights_uniform(prob, rng)
+    apf, S, f, G, g = _run_gpu(prob, eps, w)
+    nlr, nroot = apf.query("lowrank_fronts"), apf.query("lowrank_roots")
+    S_o, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
+    print(f"[gpu] 1200x92 ({prob.n_in} channels): {nlr:.0f} fronts in {nroot:.0f} low-rank subtrees; "
+          f"rel err S {_rel(S, S_o):.2e} grad {_rel(g, g_o):.2e}", flush=True)
+    assert nroot > 0 and nlr > nroot
+    assert _rel(S, S_o) < TOL
+    assert _rel(g, g_o) < TOL
+
+
 def test_repeat_is_bitwise_deterministic_and_reassembles():
     prob, eps, w = inputs.tiny_problem(nx=40, ny=60, seed=5)
     from paper_2306_09257_amd import binding
