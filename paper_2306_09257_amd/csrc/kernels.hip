@@ -867,7 +867,7 @@ __global__ __launch_bounds__(256, 3) void k_gemm_k3(const GemmTask *tasks, int c
 // the front's size are clamped to its last row (their outputs are not
 // stored); k past the chunk's width reads zeros.  The chunk's sum is stored,
 // or added for column offsets > 0 (later chunks).
-__global__ __launch_bounds__(256, 2) void k_lowrank_w(const GemmTask *tasks, int coff, int nlimk) {
+__global__ __launch_bounds__(256, 3) void k_lowrank_w(const GemmTask *tasks, int coff, int nlimk) {
   typedef GemmPrec<false> GP;
   __shared__ double2 As[16][64];
   __shared__ double2 Bs[16][64];
@@ -894,13 +894,15 @@ __global__ __launch_bounds__(256, 2) void k_lowrank_w(const GemmTask *tasks, int
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) blk[r][c] = wr + 16 * r < M && wc + 16 * c < N;
-  d4 cre[2][2], cim[2][2];
+  // three-product complex form (see gemm_tile): k1 -> cre, k2 -> cim, k3
+  d4 cre[2][2], cim[2][2], ck3[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       cre[r][c] = d4{0, 0, 0, 0};
       cim[r][c] = d4{0, 0, 0, 0};
+      ck3[r][c] = d4{0, 0, 0, 0};
     }
   load(0);
   for (int k0 = 0; k0 < K; k0 += 16) {
@@ -926,10 +928,9 @@ __global__ __launch_bounds__(256, 2) void k_lowrank_w(const GemmTask *tasks, int
 #pragma unroll
           for (int c = 0; c < 2; ++c)
             if (blk[r][c]) {
-              cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
-              cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
-              cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
-              cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+              cre[r][c] = GP::mfma(a[r].x + a[r].y, b[c].x, cre[r][c]);
+              cim[r][c] = GP::mfma(a[r].x, b[c].y - b[c].x, cim[r][c]);
+              ck3[r][c] = GP::mfma(a[r].y, b[c].x + b[c].y, ck3[r][c]);
             }
       }
     }
@@ -945,7 +946,7 @@ __global__ __launch_bounds__(256, 2) void k_lowrank_w(const GemmTask *tasks, int
         const int i = wr + 16 * r + GP::row(lane, q), j = wc + 16 * c + (lane & 15);
         if (i < M && j < N) {
           cplx *w = T.C + (int64_t)i * T.ldc + j;
-          double2 v = make_double2(cre[r][c][q], cim[r][c][q]);
+          double2 v = make_double2(cre[r][c][q] - ck3[r][c][q], cre[r][c][q] + cim[r][c][q]);
           if (acc) v = cadd(v, ld2(w));
           st2(w, v);
         }
