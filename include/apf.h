@@ -156,6 +156,19 @@ apf_status apf_weighted_power(apf_handle *h, const double *S_dev,
 apf_status apf_splitter_fom(apf_handle *h, const double *S_dev, double t1,
                             double *f_dev, double *dfdS_dev, void *stream);
 
+/* Objective helper for the multi-angle splitter: for input a the targets
+ * T(a) are the outputs whose order differs from a's by g * delta, |g| <= gmax
+ * (a supercell's diffraction orders, Sec. 3); with p = |S|^2 and mu_a the
+ * mean of p over T(a),
+ *   f = sum_a sum_{t in T(a)} [ -p_ta + (p_ta - mu_a)^2 ]
+ * (transmit into the target orders, evenly), and
+ *   dF/dS_ta = (-1 + 2 (p_ta - mu_a)) conj(S_ta) on the targets, 0 elsewhere.
+ *   S_dev, dfdS_dev: complex128 [n_out][n_in]; f_dev: one float64.
+ * APF_EINVAL for delta <= 0, gmax < 0 or more than 262,144 inputs;
+ * APF_ESTATE before the first apf_assemble. */
+apf_status apf_group_fom(apf_handle *h, const double *S_dev, int32_t delta, int32_t gmax,
+                         double *f_dev, double *dfdS_dev, void *stream);
+
 /* Ridge parameterization of the design rows (Sec. 3: edge positions as the
  * design parameters, mirror symmetry about the central plane):
  *   edges_dev: float64 [n_edges] ascending edge positions in grid units
@@ -198,6 +211,14 @@ apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, int32_t n_edg
  * Uses the factors of the last apf_factor_schur (else APF_ESTATE). */
 apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev,
                     void *stream);
+
+/* Cap the right-hand-side chunk of the gradient sweeps (0: the default, as
+ * many columns as half of the free device memory holds).  The sweep arrays
+ * X and V hold one row per sweep pivot and `chunk` columns each; apf_grad
+ * runs the sweeps once per chunk of inputs.  For callers that must bound the
+ * memory the handle takes.  Call before the first apf_assemble (else
+ * APF_ESTATE); APF_EINVAL unless max_chunk is 0 or a positive multiple of 64. */
+apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk);
 
 /* Enable (on != 0) or disable per-class HIP-event timing of every launch
  * the handle makes (counters reset).  When on, each call waits for its own

@@ -26,8 +26,8 @@ APF_FP64 = 0
 APF_MIXED = 1
 
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
-                "apf_weighted_power", "apf_splitter_fom", "apf_ridges_eps", "apf_ridges_grad",
-                "apf_grad", "apf_set_profiling", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
+                "apf_weighted_power", "apf_splitter_fom", "apf_group_fom", "apf_ridges_eps", "apf_ridges_grad",
+                "apf_grad", "apf_set_rhs_chunk", "apf_set_profiling", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow")
 
@@ -71,10 +71,12 @@ def load_library(path: str = LIB_PATH):
     lib.apf_factor_schur_batched.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp), vp]
     lib.apf_weighted_power.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.apf_splitter_fom.argtypes = [vp, vp, dbl, vp, vp, vp]
+    lib.apf_group_fom.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     lib.apf_ridges_eps.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
     lib.apf_ridges_grad.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp, vp]
     lib.apf_grad.argtypes = [vp, vp, vp, vp]
     lib.apf_set_profiling.argtypes = [vp, i32]
+    lib.apf_set_rhs_chunk.argtypes = [vp, i32]
     lib.apf_destroy.argtypes = [vp]
     lib.apf_last_error.argtypes = []
     lib.apf_last_error.restype = ctypes.c_char_p
@@ -134,6 +136,11 @@ class APF:
         _check(self._lib.apf_query(self._h, key.encode(), ctypes.byref(v)))
         return v.value
 
+    def set_rhs_chunk(self, max_chunk: int):
+        """Cap the sweeps' right-hand-side chunk (before the first assemble)."""
+        _check(self._lib.apf_set_rhs_chunk(self._h, int(max_chunk)))
+        return self
+
     def set_profiling(self, on: bool):
         _check(self._lib.apf_set_profiling(self._h, 1 if on else 0))
 
@@ -181,6 +188,15 @@ class APF:
         f = torch.empty((), dtype=torch.float64, device=S.device)
         G = torch.empty_like(S)
         _check(self._lib.apf_splitter_fom(self._h, _ptr(S), float(t1), _ptr(f), _ptr(G), _stream()))
+        return f, G
+
+    def group_fom(self, S, delta: int, gmax: int = 2):
+        """Grouped multi-angle objective and dF/dS (device tensors)."""
+        import torch
+        assert S.dtype == torch.complex128 and S.is_contiguous()
+        f = torch.empty((), dtype=torch.float64, device=S.device)
+        G = torch.empty_like(S)
+        _check(self._lib.apf_group_fom(self._h, _ptr(S), int(delta), int(gmax), _ptr(f), _ptr(G), _stream()))
         return f, G
 
     def ridges_eps(self, edges, eps, mirror: bool, eps_ridge: float, eps_gap: float):

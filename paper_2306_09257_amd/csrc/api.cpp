@@ -335,8 +335,9 @@ struct apf_handle {
   Plan plan;
   std::vector<Off> off;
   Profiler prof;
-  int state = 0;
-  bool mixed = false;   // precision of the factors held (APF_MIXED)  // 0 analysed, 1 assembled, 2 factored
+  int state = 0;        // 0 analysed, 1 assembled, 2 factored
+  bool mixed = false;   // precision of the factors held (APF_MIXED)
+  int max_chunk = 0;    // cap on the right-hand-side chunk of the sweeps (0: memory decides)
 };
 
 // ---------------------------------------------------------------------------
@@ -548,6 +549,7 @@ static void build_plan(apf_handle *H) {
     double budget = 0.5 * (double)fr;
     int64_t chunk = (int64_t)(budget / (2.0 * rows * sizeof(cplx)));
     chunk = std::min<int64_t>(chunk, Mi);
+    if (H->max_chunk > 0) chunk = std::min<int64_t>(chunk, H->max_chunk);
     if (chunk < Mi) chunk = std::max<int64_t>(64, chunk / 64 * 64);
     P.rhs_chunk = (int)std::max<int64_t>(chunk, 1);
     P.x_elems = rows * P.rhs_chunk;
@@ -1421,6 +1423,26 @@ extern "C" apf_status apf_splitter_fom(apf_handle *h, const double *S_dev, doubl
   });
 }
 
+extern "C" apf_status apf_group_fom(apf_handle *h, const double *S_dev, int32_t delta, int32_t gmax, double *f_dev,
+                                    double *dfdS_dev, void *stream) {
+  if (!h || !S_dev || !f_dev || !dfdS_dev) return fail(APF_EINVAL, "null argument");
+  if (delta <= 0 || gmax < 0) return fail(APF_EINVAL, "delta must be positive and gmax non-negative");
+  if (!h->planned) return fail(APF_ESTATE, "apf_assemble has not run");
+  return guarded([&]() -> apf_status {
+    const int Mi = h->d.n_in, Mo = h->d.n_out;
+    if ((Mi + 255) / 256 > 1024) return fail(APF_EINVAL, "more than 262,144 inputs");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t *in_ord = reinterpret_cast<const int32_t *>(h->plan.chan + 2 * sizeof(ChanParams));
+    Profiler &pr = h->prof;
+    pr.run(P_WPOW, s, [&] {
+      return launch_group_fom(reinterpret_cast<const cplx *>(S_dev), in_ord, in_ord + Mi, Mi, Mo, delta, gmax,
+                              f_dev, reinterpret_cast<cplx *>(dfdS_dev), h->plan.part, s);
+    });
+    if (pr.on) pr.collect();
+    return APF_OK;
+  });
+}
+
 static apf_status check_ridges(apf_handle *h, const double *edges_dev, int32_t n_edges, int32_t mirror) {
   if (!h || !edges_dev) return fail(APF_EINVAL, "null argument");
   if (mirror != 0 && mirror != 1) return fail(APF_EINVAL, "mirror must be 0 or 1");
@@ -1498,6 +1520,15 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     if (h->prof.on) h->prof.collect();
     return APF_OK;
   });
+}
+
+extern "C" apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  if (max_chunk < 0 || (max_chunk > 0 && max_chunk % 64 != 0))
+    return fail(APF_EINVAL, "the chunk cap must be 0 or a positive multiple of 64");
+  if (h->planned) return fail(APF_ESTATE, "the sweep arrays are already sized (apf_assemble has run)");
+  h->max_chunk = max_chunk;
+  return APF_OK;
 }
 
 extern "C" apf_status apf_set_profiling(apf_handle *h, int32_t on) {

@@ -36,6 +36,8 @@ hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx
 // the chain rule to the edge positions (see include/apf.h)
 hipError_t launch_splitter_fom(const cplx *S, const int32_t *in_ord, const int32_t *out_ord, int n_in, int n_out,
                                double t1, double *f, cplx *G, double *part, int npart, hipStream_t s);
+hipError_t launch_group_fom(const cplx *S, const int32_t *in_ord, const int32_t *out_ord, int n_in, int n_out,
+                            int delta, int gmax, double *f, cplx *G, double *part, hipStream_t s);
 hipError_t launch_ridges_eps(const double *edges, int n, int mirror, int nx, int row0, int nrows, double eps_ridge,
                              double eps_gap, double *eps, hipStream_t s);
 hipError_t launch_ridges_grad(const double *edges, int n, int mirror, int nx, int nrows, double eps_ridge,

@@ -4,6 +4,8 @@
 // each kernel below; the host plan holds the per-level task arrays.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "apf_internal.h"
 #include "kernels.h"
 
@@ -1060,6 +1062,61 @@ __global__ void k_splitter_partial(const double2 *S, const int32_t *in_ord, cons
 }
 
 // ---------------------------------------------------------------------------
+// Grouped objective of the multi-angle splitter: for input a the targets are
+// the outputs whose order differs by g * delta, |g| <= gmax; with p = |S|^2
+// and mu_a the mean of p over a's targets,
+//   f = sum_a sum_t [ -p_ta + (p_ta - mu_a)^2 ],
+//   dF/dS_ta = (-1 + 2 (p_ta - mu_a)) conj(S_ta) on the targets, 0 elsewhere.
+// k_group_zero clears dF/dS; k_group_partial takes one input column per
+// thread (two passes over the outputs: the mean, then f and dF/dS) and sums
+// its block's f into part[]; k_wpow_final adds the parts.
+// ---------------------------------------------------------------------------
+__global__ void k_group_zero(double2 *G, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    G[e] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_group_partial(const double2 *S, const int32_t *in_ord, const int32_t *out_ord, int n_in,
+                                int n_out, int delta, int gmax, double2 *G, double *part) {
+  __shared__ double red[256];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (a < n_in) {
+    const int oa = in_ord[a];
+    auto is_target = [&](int t) {
+      const int d = out_ord[t] - oa;
+      return d % delta == 0 && d <= gmax * delta && -d <= gmax * delta;
+    };
+    double sum = 0.0;
+    int cnt = 0;
+    for (int t = 0; t < n_out; ++t)
+      if (is_target(t)) {
+        const double2 v = S[(int64_t)t * n_in + a];
+        sum += v.x * v.x + v.y * v.y;
+        ++cnt;
+      }
+    if (cnt > 0) {
+      const double mu = sum / cnt;
+      for (int t = 0; t < n_out; ++t)
+        if (is_target(t)) {
+          const double2 v = S[(int64_t)t * n_in + a];
+          const double p = v.x * v.x + v.y * v.y, dev = p - mu;
+          acc += -p + dev * dev;
+          const double df = -1.0 + 2.0 * dev;
+          G[(int64_t)t * n_in + a] = make_double2(df * v.x, -df * v.y);
+        }
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
 // Ridge permittivity from edge positions (grid units along the periodic axis,
 // node j = cell [j - 1/2, j + 1/2)); with mirror symmetry the given edges are
 // the first half period's and the full list continues with nx - x in
@@ -1255,6 +1312,21 @@ hipError_t launch_splitter_fom(const cplx *S, const int32_t *in_ord, const int32
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_wpow_final, dim3(1), dim3(256), 0, s, part, npart, f);
+  return hipGetLastError();
+}
+hipError_t launch_group_fom(const cplx *S, const int32_t *in_ord, const int32_t *out_ord, int n_in, int n_out,
+                            int delta, int gmax, double *f, cplx *G, double *part, hipStream_t s) {
+  const int64_t n = (int64_t)n_in * n_out;
+  hipLaunchKernelGGL(k_group_zero, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<double2 *>(G), n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nb = (n_in + 255) / 256;
+  hipLaunchKernelGGL(k_group_partial, dim3(nb), dim3(256), 0, s, reinterpret_cast<const double2 *>(S), in_ord,
+                     out_ord, n_in, n_out, delta, gmax, reinterpret_cast<double2 *>(G), part);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wpow_final, dim3(1), dim3(256), 0, s, part, nb, f);
   return hipGetLastError();
 }
 hipError_t launch_ridges_eps(const double *edges, int n, int mirror, int nx, int row0, int nrows, double eps_ridge,

@@ -293,3 +293,19 @@ def beam_splitter(seed: int = 6, nx: int = 1024):
     prob = splitter_problem(nx)
     rng = np.random.default_rng(seed)
     return prob, prob.background_eps(), splitter_random_edges(nx, rng)
+
+
+def metasurface_multiangle(seed: int = 2, nx: int = 48000):
+    """Multi-angle splitter workload: 48,000 x 160 grid (7.68M unknowns),
+    inputs |a| < 0.95 nx dx/lambda (4,559 at nx = 48,000) and the same output
+    orders, 1.92M design pixels of binary {1, 4} permittivity smoothed by a
+    3-px-FWHM Gaussian.  The objective groups, for each input, the outputs at
+    order differences g * delta (|g| <= 2) with delta = nx dx / (24 lambda)
+    (a 24-wavelength supercell: 100 orders at nx = 48,000).  Returns
+    (prob, eps, delta)."""
+    orders = channel_orders(nx, 0.05, sin_max=0.95)
+    prob = make_problem(nx, 160, in_orders=orders, out_orders=orders)
+    rng = np.random.default_rng(seed)
+    eps = eps_binary_smoothed(prob, rng)
+    delta = int(round(nx * 0.05 / 24.0))
+    return prob, eps, delta

@@ -91,6 +91,32 @@ def test_lowrank_subtrees_match_oracle_1200x92():
     assert _rel(g, g_o) < TOL
 
 
+def test_chunked_sweeps_match_oracle_1200x92():
+    """The same 1200 x 92 problem (119 inputs) with the right-hand-side chunk
+    capped at 64: two sweep passes, the low-rank products and the contraction
+    partials accumulated across chunks."""
+    from paper_2306_09257_amd import binding
+    prob = inputs.make_problem(1200, 92)
+    rng = np.random.default_rng(11)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    w = inputs.weights_uniform(prob, rng)
+    apf = binding.APF(prob).analyze().set_rhs_chunk(64)
+    with pytest.raises(binding.APFError):
+        binding.APF(prob).analyze().set_rhs_chunk(100)
+    apf.assemble(_dev(eps, torch.float64))
+    assert apf.query("rhs_chunk") == 64
+    with pytest.raises(binding.APFError):
+        apf.set_rhs_chunk(128)                      # after the first assembly
+    S = apf.factor_schur()
+    f, G = apf.weighted_power(S, _dev(w, torch.float64))
+    g = apf.grad(G).cpu().numpy()
+    S_o, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
+    print(f"[gpu] 1200x92 in chunks of 64: rel err S {_rel(S.cpu().numpy(), S_o):.2e} grad {_rel(g, g_o):.2e}",
+          flush=True)
+    assert _rel(S.cpu().numpy(), S_o) < TOL
+    assert _rel(g, g_o) < TOL
+
+
 def test_repeat_is_bitwise_deterministic_and_reassembles():
     prob, eps, w = inputs.tiny_problem(nx=40, ny=60, seed=5)
     from paper_2306_09257_amd import binding
