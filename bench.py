@@ -41,6 +41,7 @@ WORKLOADS = {
     "metasurface_24000x160": dict(kind="wide", nx=24000, seed=1),
     "metasurface_240x92": dict(kind="small", seed=0),
     "batch64_uneven": dict(kind="batch", seed=3, count=64),
+    "multiangle_48000x160": dict(kind="multiangle", nx=48000, seed=2),
 }
 
 
@@ -49,6 +50,9 @@ def make_workload(name):
     spec = WORKLOADS[name]
     if spec["kind"] == "wide":
         return inputs.metasurface_wide(seed=spec["seed"], nx=spec["nx"])
+    if spec["kind"] == "multiangle":
+        # the grouped objective takes the place of the weights
+        return inputs.metasurface_multiangle(seed=spec["seed"], nx=spec["nx"])
     return inputs.metasurface_small(seed=spec["seed"])
 
 
@@ -230,7 +234,8 @@ def main():
     t_an = time.perf_counter() - t0
     dev = torch.device("cuda:0")
     eps_d = torch.as_tensor(eps, dtype=torch.float64, device=dev).contiguous()
-    w_d = torch.as_tensor(w, dtype=torch.float64, device=dev).contiguous()
+    grouped = WORKLOADS[args.workload]["kind"] == "multiangle"
+    w_d = None if grouped else torch.as_tensor(w, dtype=torch.float64, device=dev).contiguous()
     S = torch.empty((prob.n_out, prob.n_in), dtype=torch.complex128, device=dev)
     grad = torch.empty((prob.n_design_rows, prob.nx), dtype=torch.float64, device=dev)
 
@@ -239,7 +244,7 @@ def main():
     def step():
         apf.assemble(eps_d)
         apf.factor_schur(S, precision=prec)
-        f, G = apf.weighted_power(S, w_d)
+        f, G = apf.group_fom(S, w) if grouped else apf.weighted_power(S, w_d)
         apf.grad(G, out=grad)
         return f
 
@@ -300,7 +305,7 @@ def main():
         S_m, g_m = S.clone(), grad.clone()
         apf.assemble(eps_d)
         S64 = apf.factor_schur(precision=binding.APF_FP64)
-        f64, G64 = apf.weighted_power(S64, w_d)
+        f64, G64 = apf.group_fom(S64, w) if grouped else apf.weighted_power(S64, w_d)
         g64 = apf.grad(G64)
         torch.cuda.synchronize()
         out["mixed_rel_err_vs_fp64"] = {
