@@ -145,6 +145,27 @@ def test_grad_before_factor_is_a_state_error():
     assert ei.value.status == binding.APF_ESTATE
 
 
+def test_objective_helpers_check_their_arguments_and_state():
+    from paper_2306_09257_amd import binding
+    import oracle.objectives as oobj
+    prob, eps, w = inputs.tiny_problem(nx=64, ny=60, seed=12)
+    apf = binding.APF(prob).analyze()
+    S0 = torch.zeros((prob.n_out, prob.n_in), dtype=torch.complex128, device="cuda")
+    with pytest.raises(binding.APFError) as ei:
+        apf.group_fom(S0, 2)                       # before the first assembly
+    assert ei.value.status == binding.APF_ESTATE
+    apf.assemble(_dev(eps, torch.float64))
+    S = apf.factor_schur()
+    for bad in ((0, 2), (2, -1)):
+        with pytest.raises(binding.APFError) as ei:
+            apf.group_fom(S, *bad)
+        assert ei.value.status == binding.APF_EINVAL
+    # a small grouped objective against the oracle formula on the same S
+    f, G = apf.group_fom(S, 1, 1)
+    f_o, G_o = oobj.group_fom(S.cpu().numpy(), prob.in_orders, prob.out_orders, 1, 1)
+    assert abs(float(f) - f_o) < 1e-13 * max(1.0, abs(f_o)) and _rel(G.cpu().numpy(), G_o) < 1e-13
+
+
 def test_autograd_function_matches_oracle_gradient():
     from paper_2306_09257_amd import binding
     prob, eps, w = inputs.tiny_problem(nx=32, ny=60, seed=7)
