@@ -615,7 +615,8 @@ static void build_plan(apf_handle *H) {
       if (!F.sweep) continue;
       const double p = F.p(), b = F.b();
       double direct = 2.0 * p * b * M, dsub = b * b * p + p * b * (p + b);
-      bool ok = !F.hasB && !F.hasC && F.b() > 0;
+      // (a root forms Wt in one 64 x 64 tile: b <= 64)
+      bool ok = !F.hasB && !F.hasC && F.b() > 0 && F.b() <= 64;
       for (int c = 0; c < F.nchild; ++c) {
         const int ch = F.child[c];
         if (!S.fronts[ch].sweep) continue;
