@@ -1,12 +1,17 @@
 """Planted mistakes in the oracle (on the CPU, via monkeypatch) must each be
-caught by at least one of the pins in test_oracle_pins: a dropped term, a
-wrong sign, a wrong index or a missing normalisation."""
+caught by at least one of the pins in test_oracle_pins, test_oracle_splitter
+or test_oracle_objectives: a dropped term, a wrong sign, a wrong index, a
+missing normalisation or conjugation, a missing periodic image."""
 import numpy as np
 import pytest
 
 import oracle.apf as oapf
 import oracle.fdfd as ofd
+import oracle.objectives as oobj
+import oracle.splitter as osp
+import tests.test_oracle_objectives as opins
 import tests.test_oracle_pins as pins
+import tests.test_oracle_splitter as spins
 
 
 def _mut_eps_sign(monkeypatch):
@@ -51,7 +56,66 @@ def _mut_pml_alpha(monkeypatch):
     monkeypatch.setattr(ofd, "pml_alpha", lambda h, e, L, m, R0: 0.0)
 
 
+def _mut_mirror_sign(monkeypatch):
+    def bad(edges, nx, mirror, eps_ridge, eps_gap):
+        e = np.asarray(edges, dtype=np.float64)
+        full = osp.full_edges(e, nx, mirror)
+        J = np.zeros((e.size, nx))
+        de = eps_ridge - eps_gap
+        for k in range(e.size):
+            J[k, osp.cell_of(full[k], nx)] += (-1.0 if k % 2 == 0 else 1.0) * de
+            if mirror:
+                q = full.size - 1 - k
+                J[k, osp.cell_of(full[q], nx)] += (-1.0 if q % 2 == 0 else 1.0) * de   # image moves with +1
+        return J
+    monkeypatch.setattr(osp, "jacobian", bad)
+
+
+def _mut_coverage_no_wrap(monkeypatch):
+    def bad(edges, nx, mirror):
+        e = osp.full_edges(edges, nx, mirror)
+        lo = np.arange(nx, dtype=np.float64) - 0.5
+        frac = np.zeros(nx)
+        for r in range(e.size // 2):
+            frac += np.clip(np.minimum(lo + 1.0, e[2 * r + 1]) - np.maximum(lo, e[2 * r]), 0.0, None)
+        return frac
+    monkeypatch.setattr(osp, "coverage", bad)
+
+
+def _mut_fom_orders(monkeypatch):
+    def bad(in_orders, out_orders, t1=0.5):
+        d = np.asarray(out_orders)[:, None] - np.asarray(in_orders)[None, :]
+        return np.where(np.abs(d) == 2, t1, 0.0)       # the +-2 orders
+    monkeypatch.setattr(osp, "targets", bad)
+
+
+def _mut_fom_no_conj(monkeypatch):
+    orig = osp.fom
+
+    def bad(S, i, o, t1=0.5):
+        f, G = orig(S, i, o, t1)
+        return f, np.conj(G)
+    monkeypatch.setattr(osp, "fom", bad)
+
+
+def _mut_group_no_deviation(monkeypatch):
+    orig = oobj.group_fom
+
+    def bad(S, i, o, delta, gmax=2):
+        f, G = orig(S, i, o, delta, gmax)
+        T = oobj.targets(i, o, delta, gmax)
+        return f, np.where(T, -np.conj(S), 0.0)        # the penalty's derivative dropped
+    monkeypatch.setattr(oobj, "group_fom", bad)
+
+
 MUTATIONS = {
+    "mirror_sign": (_mut_mirror_sign, [spins.test_jacobian_matches_finite_differences,
+                                       spins.test_edge_gradient_matches_central_differences]),
+    "coverage_no_wrap": (_mut_coverage_no_wrap,
+                         [spins.test_coverage_conserves_width_is_binary_on_cell_edges_and_mirror_symmetric]),
+    "fom_orders": (_mut_fom_orders, [spins.test_table_s2_design_splits_into_the_pm1_orders]),
+    "fom_no_conj": (_mut_fom_no_conj, [spins.test_fom_wirtinger_derivative_matches_central_differences]),
+    "group_no_deviation": (_mut_group_no_deviation, [opins.test_group_fom_derivative_matches_central_differences]),
     "eps_sign": (_mut_eps_sign, [pins.test_uniform_slab_converges_to_airy_at_second_order]),
     "half_row_index": (_mut_half_row_index, [pins.test_uniform_slab_converges_to_airy_at_second_order,
                                              pins.test_flux_conservation_lossless]),
