@@ -199,7 +199,7 @@ struct Plan {
   int n_wfronts = 0, n_wroots = 0;   // fronts of low-rank sweep subtrees, their roots
   int64_t ndesign = 0;        // design pixels (contraction slots)
   int nblk = 0;               // 32-column contraction partials per pixel
-  double *gpart = nullptr;    // ndesign x nblk
+  double *gpart = nullptr;    // nblk x ndesign (block-major)
   template <class T>
   T *at(int64_t off) const { return off < 0 ? nullptr : reinterpret_cast<T *>(blob + off); }
 };
@@ -1495,7 +1495,7 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
       for (size_t t = 0; t < P.swl.size(); ++t) {
         if (P.nswl[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] {
-            return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, P.nblk, P.swl_deep[t] != 0);
+            return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, (int)P.ndesign, P.swl_deep[t] != 0);
           });
         if (P.nswtb[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] { return launch_lowrank_w(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s); });

@@ -15,10 +15,11 @@ hipError_t launch_fill_int(int *p, int v, hipStream_t s);
 constexpr int N_INV_VARIANTS = 8;
 int inverse_variant(int p);   // kernel variant of a pivot block of size p
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
-// part / nblk: output of the tasks flagged G_CONTRACT (unused otherwise);
+// part / pstride: output of the tasks flagged G_CONTRACT, partial of design
+// slot g and 32-column block b at part[b * pstride + g] (unused otherwise);
 // deep: MFMA-bound deep-K task list (three-product complex form on FP64)
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
-                       bool f32 = false, double *part = nullptr, int nblk = 0, bool deep = false);
+                       bool f32 = false, double *part = nullptr, int pstride = 0, bool deep = false);
 // Wt = Y_bnd Lam_bnd^T of the low-rank subtree roots: one task (b <= 64) per
 // root, one workgroup per task; nlim: the chunk's width (k extent)
 hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStream_t s);

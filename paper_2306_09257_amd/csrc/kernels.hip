@@ -525,7 +525,7 @@ struct GemmPrec<true> {
 // a third more accumulator registers.
 template <bool F32, bool TRI, bool K3 = false>
 __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, int nlimk, const cplx *ext,
-                                          double *part, int nblk, typename GemmPrec<F32>::lds_t (*As)[64],
+                                          double *part, int pstride, typename GemmPrec<F32>::lds_t (*As)[64],
                                           typename GemmPrec<F32>::lds_t (*Bs)[64]) {
   typedef GemmPrec<F32> GP;
   typedef typename GP::lds_t lds_t;
@@ -811,7 +811,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
         for (int off = 1; off < 16; off <<= 1) a += __shfl_xor(a, off, 64);
         if ((lane & 15) == 0 && rowok[r][q]) {
           const int g = T.auxmap[oi[r][q]];
-          if (g >= 0) part[(int64_t)g * nblk + (coff + T.tn + wc) / 32] = a;
+          if (g >= 0) part[(int64_t)((coff + T.tn + wc) / 32) * pstride + g] = a;
         }
       }
   }
@@ -819,7 +819,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
 
 template <bool F32>
 __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
-                                                 double *part, int nblk) {
+                                                 double *part, int pstride) {
   __shared__ typename GemmPrec<F32>::lds_t As[KT][64];
   __shared__ typename GemmPrec<F32>::lds_t Bs[KT][64];
   const GemmTask T = tasks[blockIdx.x];
@@ -827,9 +827,9 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
   const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
   if (T.tn >= N) return;
   if (T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U))
-    gemm_tile<F32, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+    gemm_tile<F32, true>(T, coff, N, nlim, ext, part, pstride, As, Bs);
   else
-    gemm_tile<F32, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+    gemm_tile<F32, false>(T, coff, N, nlim, ext, part, pstride, As, Bs);
 }
 
 // Launches that hold deep-K tasks (Schur partials, weighted adjoint source,
@@ -839,7 +839,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff
 // merged batch) keep the four-product form, so that every task rounds the
 // same way whichever launch runs it.
 __global__ __launch_bounds__(256, 3) void k_gemm_k3(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
-                                                   double *part, int nblk) {
+                                                   double *part, int pstride) {
   __shared__ double2 As[KT][64];
   __shared__ double2 Bs[KT][64];
   const GemmTask T = tasks[blockIdx.x];
@@ -848,14 +848,14 @@ __global__ __launch_bounds__(256, 3) void k_gemm_k3(const GemmTask *tasks, int c
   const bool tri = T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U);
   if (T.flags & G_K3) {
     if (tri)
-      gemm_tile<false, true, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, true, true>(T, coff, N, nlim, ext, part, pstride, As, Bs);
     else
-      gemm_tile<false, false, true>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, false, true>(T, coff, N, nlim, ext, part, pstride, As, Bs);
   } else {
     if (tri)
-      gemm_tile<false, true, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, true, false>(T, coff, N, nlim, ext, part, pstride, As, Bs);
     else
-      gemm_tile<false, false, false>(T, coff, N, nlim, ext, part, nblk, As, Bs);
+      gemm_tile<false, false, false>(T, coff, N, nlim, ext, part, pstride, As, Bs);
   }
 }
 
@@ -990,13 +990,14 @@ __global__ __launch_bounds__(256) void k_wprop(const WFront *fr, double scale, d
   }
 }
 
-// grad[g] = scale * (sum of the nblk contraction partials of slot g)
+// grad[g] = scale * (sum of the nblk contraction partials of slot g); the
+// partials are block-major, part[b * n + g], so that the threads of a wave
+// read consecutive slots
 __global__ void k_reduce_partials(const double *part, int nblk, int64_t n, double scale, double *grad) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= n) return;
-  const double *p = part + g * nblk;
   double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += p[b];
+  for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * n + g];
   grad[g] = scale * acc;
 }
 
@@ -1247,14 +1248,14 @@ hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipS
   return hipGetLastError();
 }
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
-                       double *part, int nblk, bool deep) {
+                       double *part, int pstride, bool deep) {
   if (n == 0) return hipSuccess;
   if (deep && !f32)
-    hipLaunchKernelGGL(k_gemm_k3, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
+    hipLaunchKernelGGL(k_gemm_k3, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
   else if (f32)
-    hipLaunchKernelGGL(k_gemm<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
+    hipLaunchKernelGGL(k_gemm<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
   else
-    hipLaunchKernelGGL(k_gemm<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, nblk);
+    hipLaunchKernelGGL(k_gemm<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
   return hipGetLastError();
 }
 
