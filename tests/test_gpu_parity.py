@@ -47,13 +47,19 @@ CASES = [
     dict(nx=40, ny=140, leaf=128, seed=8),     # pivot blocks up to 140 (register-blocked inverse)
     dict(nx=48, ny=160, leaf=96, seed=9),      # pivot blocks of 160, the largest register variant
     dict(nx=12, ny=200, leaf=0, seed=10, layout=(20, 60, 40, 60, 20)),   # 200-row separators: fallback inverse
+    dict(nx=40, ny=60, leaf=0, seed=11, n_orders=1),                     # one channel each way: 1-wide panels
+    dict(nx=50, ny=60, leaf=0, seed=12, layout=(16, 10, 1, 17, 16)),     # a one-row design region
+    dict(nx=45, ny=60, leaf=16, seed=13, in_orders=[0, 1], out_orders=[-2, -1, 0, 1, 2]),  # M_in != M_out
 ]
+
+_PROBLEM_KEYS = ("layout", "n_orders", "in_orders", "out_orders")
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c['nx']}x{c['ny']}-leaf{c['leaf']}")
 def test_S_and_grad_match_oracle_small(case):
-    prob, eps, w = inputs.tiny_problem(nx=case["nx"], ny=case["ny"], seed=case["seed"],
-                                       layout=case.get("layout"))
+    kw = {k: (np.asarray(v, np.int32) if isinstance(v, list) else v)
+          for k, v in case.items() if k in _PROBLEM_KEYS}
+    prob, eps, w = inputs.tiny_problem(nx=case["nx"], ny=case["ny"], seed=case["seed"], **kw)
     _, S, f, G, g = _run_gpu(prob, eps, w, case["leaf"])
     S_o, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
     assert _rel(S, S_o) < TOL
@@ -178,5 +184,5 @@ def test_autograd_function_matches_oracle_gradient():
     loss = (_dev(w, torch.float64) * S.abs() ** 2).sum()
     loss.backward()
     _, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
-    assert abs(float(loss) - f_o) < TOL * abs(f_o)
+    assert abs(float(loss.detach()) - f_o) < TOL * abs(f_o)
     assert _rel(x.grad.cpu().numpy(), g_o) < TOL
