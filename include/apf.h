@@ -220,9 +220,12 @@ apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev,
  * APF_ESTATE); APF_EINVAL unless max_chunk is 0 or a positive multiple of 64. */
 apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk);
 
-/* Enable (on != 0) or disable per-class HIP-event timing of every launch
- * the handle makes (counters reset).  When on, each call waits for its own
- * events at its end, so calls become synchronous. */
+/* Per-class HIP-event timing of the handle's launches (counters reset):
+ * on = 0 off, 1 every launch, 2 only the GEMM-family launches (classes
+ * gemm_factor, gemm_schur, gemm_sweep; half the events of mode 1, for timed
+ * runs that need only the GEMM figures).  When on, each call waits for its
+ * own events at its end, so calls become synchronous.  APF_EINVAL for any
+ * other value. */
 apf_status apf_set_profiling(apf_handle *h, int32_t on);
 
 /* Free the handle, its symbolic data, factors and device buffers.  Waits for

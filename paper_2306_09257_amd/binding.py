@@ -141,8 +141,10 @@ class APF:
         _check(self._lib.apf_set_rhs_chunk(self._h, int(max_chunk)))
         return self
 
-    def set_profiling(self, on: bool):
-        _check(self._lib.apf_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on, gemm_only: bool = False):
+        """Event timing of every launch (on), of the GEMM launches only
+        (on and gemm_only), or none."""
+        _check(self._lib.apf_set_profiling(self._h, (2 if gemm_only else 1) if on else 0))
 
     def profile(self):
         """{class: (ms, launches)} summed since profiling was enabled."""

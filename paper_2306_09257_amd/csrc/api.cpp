@@ -114,6 +114,8 @@ const char *const kProfNames[P_NCLASS] = {"stencil", "zero", "assemble", "invers
 
 struct Profiler {
   bool on = false;
+  bool gemm_only = false;    // time only the GEMM-family launches
+  static bool gemm_class(int cls) { return cls == P_GEMM_FACTOR || cls == P_GEMM_SCHUR || cls == P_GEMM_SWEEP; }
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, int>> marks;  // (class, index of the start event)
   double ms[P_NCLASS] = {0};
@@ -121,15 +123,17 @@ struct Profiler {
   size_t used = 0;
   hipEvent_t next() {
     if (used == pool.size()) {
+      // timing only: no system-scope fence at each record (nothing on the
+      // host reads device memory through these events)
       hipEvent_t e;
-      HIPCHK(hipEventCreate(&e));
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       pool.push_back(e);
     }
     return pool[used++];
   }
   template <class Fn>
   void run(int cls, hipStream_t s, Fn &&fn) {
-    if (!on) {
+    if (!on || (gemm_only && !gemm_class(cls))) {
       HIPCHK(fn());
       return;
     }
@@ -1535,8 +1539,10 @@ extern "C" apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk) {
 extern "C" apf_status apf_set_profiling(apf_handle *h, int32_t on) {
   if (!h) return fail(APF_EINVAL, "null handle");
   return guarded([&]() -> apf_status {
+    if (on < 0 || on > 2) return fail(APF_EINVAL, "profiling mode must be 0, 1 or 2");
     h->prof.reset();
     h->prof.on = on != 0;
+    h->prof.gemm_only = on == 2;
     return APF_OK;
   });
 }

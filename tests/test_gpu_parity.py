@@ -140,6 +140,35 @@ def test_repeat_is_bitwise_deterministic_and_reassembles():
     assert _rel(S2, oapf.scattering_matrix(prob, eps2)) < TOL
 
 
+def test_profiling_modes_time_the_launch_classes_they_name():
+    from paper_2306_09257_amd import binding
+    prob, eps, w = inputs.tiny_problem(nx=64, ny=92, seed=7)
+    apf = binding.APF(prob).analyze()
+    eps_d, w_d = _dev(eps, torch.float64), _dev(w, torch.float64)
+
+    def solve():
+        apf.assemble(eps_d)
+        S = apf.factor_schur()
+        f, G = apf.weighted_power(S, w_d)
+        return apf.grad(G)
+
+    g0 = solve()
+    gemm = ("gemm_factor", "gemm_schur", "gemm_sweep")
+    apf.set_profiling(True, gemm_only=True)
+    g1 = solve()
+    p_gemm = apf.profile()
+    apf.set_profiling(True)
+    g2 = solve()
+    p_all = apf.profile()
+    apf.set_profiling(False)
+    assert all(p_gemm[c][1] > 0 for c in gemm)
+    assert all(p_gemm[c][1] == 0 for c in p_gemm if c not in gemm)
+    assert all(p_all[c][1] > 0 for c in p_all)
+    assert all(p_all[c][1] == p_gemm[c][1] for c in gemm)
+    # timing changes nothing in the results
+    assert torch.equal(g0, g1) and torch.equal(g0, g2)
+
+
 def test_grad_before_factor_is_a_state_error():
     from paper_2306_09257_amd import binding
     prob, eps, w = inputs.tiny_problem(nx=24, ny=60, seed=6)

@@ -158,3 +158,11 @@ def test_work_counts_match_a_brute_force_symbolic_elimination(lib):
     assert algo >= count
     # and the channel-free part is tight for leaves and separators of a strip
     assert algo <= 1.6 * count
+
+
+def test_profiling_modes_are_checked(lib):
+    apf = binding.APF(_problem(24, 60)).analyze()
+    for mode in (0, 1, 2, 0):
+        assert lib.apf_set_profiling(apf._h, mode) == binding.APF_OK
+    for bad in (-1, 3):
+        assert lib.apf_set_profiling(apf._h, bad) == binding.APF_EINVAL
