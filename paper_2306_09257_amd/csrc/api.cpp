@@ -104,7 +104,7 @@ struct LevelTasks {
 };
 
 constexpr int64_t ZERO_CHUNK = 8192;   // complex elements per zeroing block
-constexpr int64_t SPLIT_K = 4096;      // k rows per FP32 partial of the mixed Schur product
+constexpr int64_t SPLIT_K = 4096;      // k rows per partial block of the split Schur product
 
 // Per-class HIP-event timing of the launches (off unless enabled).
 enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
@@ -176,14 +176,14 @@ struct Plan {
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
   int rhs_chunk = 0;
   std::vector<LevelTasks> lv;
-  int64_t gS = -1, vinit = -1, gidx = -1, fronts = -1, gSsplit = -1, vmap_base = -1, vmap_pidx = -1;
+  int64_t vinit = -1, gidx = -1, fronts = -1, gSsplit = -1, vmap_base = -1, vmap_pidx = -1;
   int64_t xc_rows = 0;        // rows of the weighted-adjoint operand store (sweep fronts with C rows)
   cplx *xc = nullptr;         // L^-T U^-T FC1^T of those fronts, stacked: xc_rows x n_out
   int32_t *vmap = nullptr;    // V row of every xc row (rebuilt from the pivot permutations per call)
   int nfronts = 0, ngSsplit = 0, nseg = 0;
-  cplx *spart = nullptr;      // FP64 partial Schur blocks of the mixed path (nseg x n_out x n_in)
+  cplx *spart = nullptr;      // FP64 partial Schur blocks (nseg x n_out x n_in)
   char *chan = nullptr;       // ChanParams of the source and projection rows, then their orders
-  int ngS = 0, nvinit = 0;
+  int nvinit = 0;
   // gradient sweeps: launch t holds the Y tiles of level H - t and the
   // adjoint tiles (with the contraction) of level H - t + 1
   std::vector<int64_t> swl;
@@ -785,7 +785,7 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), swY(H_ + 1), swL(H_ + 1), swW(H_ + 1);
   std::vector<std::vector<GemmTask>> wuL(H_ + 1), wqL(H_ + 1);
   std::vector<std::vector<WFront>> wpL(H_ + 1);
-  std::vector<GemmTask> gS, vinit;
+  std::vector<GemmTask> vinit;
   std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
   double cm_factor = 0, cm_sweep = 0, cm_wprop = 0;
@@ -978,21 +978,21 @@ static void build_plan(apf_handle *H) {
   P.gemm_cmacs_factor = cm_factor;
   P.gemm_cmacs_sweep = cm_sweep + cm_wprop;
   // S = sum over fronts holding both channel blocks of FC1 F11^-1 F1B
-  //   = (U^-T FC1^T)^T (L^-1 P^T F1B) = SC^T SB
-  g_cmacs_acc = 0;
-  add_tiles_xcd(gS, gemm(P.sc, Mo, P.sb, Mi, nullptr, Mi, Mo, Mi, (int)ktot, G_TRANS_A | G_C_EXT));
-  P.gemm_cmacs_schur = g_cmacs_acc;
-  // mixed precision: the same product split over k segments of SPLIT_K rows,
-  // each accumulated in FP32 on MFMA and written to an FP64 partial block
+  //   = (U^-T FC1^T)^T (L^-1 P^T F1B) = SC^T SB,
+  // split over k segments of SPLIT_K rows, each accumulated on MFMA (FP64,
+  // or FP32 on the mixed path) into an FP64 partial block; one kernel sums
+  // the blocks
   std::vector<GemmTask> gSsplit;
   P.nseg = (int)std::max<int64_t>(1, (ktot + SPLIT_K - 1) / SPLIT_K);
   HIPCHK(hipMalloc(&P.spart, (int64_t)P.nseg * Mo * Mi * sizeof(cplx)));
+  g_cmacs_acc = 0;
   for (int g = 0; g < P.nseg; ++g) {
     const int64_t k0 = (int64_t)g * SPLIT_K;
     const int kk = (int)std::min<int64_t>(SPLIT_K, ktot - k0);
     add_tiles_xcd(gSsplit, gemm(P.sc + k0 * Mo, Mo, P.sb + k0 * Mi, Mi, P.spart + (int64_t)g * Mo * Mi, Mi, Mo, Mi,
                                 std::max(kk, 0), G_TRANS_A));
   }
+  P.gemm_cmacs_schur = g_cmacs_acc;
 
   // ---- assemble the blob ------------------------------------------------------
   Blob &bl = ib;  // continue after the integer arrays
@@ -1035,7 +1035,6 @@ static void build_plan(apf_handle *H) {
     P.wq[l] = bl.add(wqL[l]); P.nwq[l] = (int)wqL[l].size();
     P.wp[l] = bl.add(wpL[l]); P.nwp[l] = (int)wpL[l].size();
   }
-  P.gS = bl.add(gS); P.ngS = (int)gS.size();
   // the Schur partials and the weighted adjoint source are K_total / M_out
   // deep: always the three-product form
   for (GemmTask &T : gSsplit) T.flags |= G_K3;

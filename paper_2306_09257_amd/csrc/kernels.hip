@@ -578,7 +578,6 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) blk_ok[r][c] = T.tm + wr + 16 * r < M && T.tn + wc + 16 * c < N;
-  const bool blk_all = blk_ok[0][0] && blk_ok[0][1] && blk_ok[1][0] && blk_ok[1][1];
   for (int k0 = kbeg; k0 < kend; k0 += KT) {
     double2 ra[4], rb[4];
     if (slab_raw(k0)) {
