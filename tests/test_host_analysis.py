@@ -166,3 +166,50 @@ def test_profiling_modes_are_checked(lib):
         assert lib.apf_set_profiling(apf._h, mode) == binding.APF_OK
     for bad in (-1, 3):
         assert lib.apf_set_profiling(apf._h, bad) == binding.APF_EINVAL
+
+
+def test_host_side_argument_and_state_checks(lib):
+    """Every entry point rejects null arguments, bad values and calls out of
+    order on the host, before any device work (the buffers below are host
+    placeholders that none of these calls reaches)."""
+    import ctypes
+    E, S = binding.APF_EINVAL, binding.APF_ESTATE
+    buf = np.zeros(64)
+    p = buf.ctypes.data_as(ctypes.c_void_p)
+    v = ctypes.c_double()
+
+    prob = _problem(24, 60)
+    fresh = binding.APF(prob)                        # created, not analysed
+    assert lib.apf_query(fresh._h, b"n_fronts", ctypes.byref(v)) == S
+    assert lib.apf_assemble(fresh._h, p, None) == S
+    info = (ctypes.c_int32 * 8)()
+    assert lib.apf_front(fresh._h, 0, info, None, None) == S
+
+    apf = binding.APF(prob).analyze()
+    h = apf._h
+    assert lib.apf_query(h, b"no_such_key", ctypes.byref(v)) == E
+    assert lib.apf_query(h, b"rhs_chunk", ctypes.byref(v)) == binding.APF_OK and v.value == -1.0
+    nf = int(apf.query("n_fronts"))
+    for f in (-1, nf):
+        assert lib.apf_front(h, f, info, None, None) == E
+    for cap in (-64, 100, 63):
+        assert lib.apf_set_rhs_chunk(h, cap) == E
+    for cap in (0, 64, 4096):
+        assert lib.apf_set_rhs_chunk(h, cap) == binding.APF_OK
+    # numeric calls before the first assembly
+    assert lib.apf_factor_schur(h, binding.APF_FP64, p, None) == S
+    assert lib.apf_factor_schur(h, 7, p, None) == E          # unknown precision first
+    assert lib.apf_grad(h, p, p, None) == S
+    assert lib.apf_weighted_power(h, p, p, p, p, None) == S
+    assert lib.apf_splitter_fom(h, p, 0.5, p, p, None) == S
+    assert lib.apf_group_fom(h, p, 2, 2, p, p, None) == S
+    assert lib.apf_group_fom(h, p, 0, 2, p, p, None) == E
+    # null arguments
+    assert lib.apf_assemble(h, None, None) == E
+    assert lib.apf_factor_schur(h, binding.APF_FP64, None, None) == E
+    assert lib.apf_grad(h, None, p, None) == E
+    assert lib.apf_weighted_power(h, p, None, p, p, None) == E
+    assert lib.apf_set_profiling(None, 1) == E
+    assert lib.apf_query(None, b"n_fronts", ctypes.byref(v)) == E
+    assert lib.apf_destroy(None) == binding.APF_OK
+    assert b"null" in lib.apf_last_error()
