@@ -59,11 +59,12 @@ typedef enum {
 typedef enum {
   APF_FP64 = 0,        /* every front operation in complex FP64            */
   APF_MIXED = 1        /* front GEMMs and sweeps on FP32 MFMA (operands
-                          rounded to FP32, FP32 accumulation), pivot blocks,
-                          storage and the S / gradient reductions in FP64;
-                          no iterative refinement: the result carries the
-                          FP32 rounding amplified by ill-conditioned pivot
-                          blocks (measured 1e-4 .. 1e-2 relative)          */
+                          rounded to FP32, FP32 accumulation); pivot blocks,
+                          storage, the S / gradient reductions and the
+                          low-rank subtree products in FP64; no iterative
+                          refinement: the result carries the FP32 rounding
+                          amplified by ill-conditioned pivot blocks
+                          (measured 1e-6 .. 4e-4 relative)                 */
 } apf_precision;
 
 typedef struct apf_handle apf_handle;

@@ -1508,16 +1508,19 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
       return launch_reduce_partials(P.gpart, P.nblk, P.ndesign, two_h2, grad_dev, s);
     });
     // low-rank sweep subtrees, from the top: U1t, Qt, then the gradient of
-    // the level's fronts and their children's Wt
+    // the level's fronts and their children's Wt.  These products stay FP64
+    // on the mixed path too: a front's gradient is the diagonal of Qt, far
+    // smaller than the entries of Wt that form it, so FP32 rounding of U1t
+    // and Qt would swamp it.
     for (int l = (int)P.wp.size() - 1; l >= 0; --l) {
       if (P.nwp[l] == 0) continue;
       if (P.nwu[l] > 0)
         pr.run(P_GEMM_SWEEP, s, [&] {
-          return launch_gemm(P.at<GemmTask>(P.wu[l]), P.nwu[l], 0, INT_MAX, nullptr, s, f32, nullptr, 0, P.wu_deep[l] != 0);
+          return launch_gemm(P.at<GemmTask>(P.wu[l]), P.nwu[l], 0, INT_MAX, nullptr, s, false, nullptr, 0, P.wu_deep[l] != 0);
         });
       if (P.nwq[l] > 0)
         pr.run(P_GEMM_SWEEP, s, [&] {
-          return launch_gemm(P.at<GemmTask>(P.wq[l]), P.nwq[l], 0, INT_MAX, nullptr, s, f32, nullptr, 0, P.wq_deep[l] != 0);
+          return launch_gemm(P.at<GemmTask>(P.wq[l]), P.nwq[l], 0, INT_MAX, nullptr, s, false, nullptr, 0, P.wq_deep[l] != 0);
         });
       pr.run(P_CONTRACT, s, [&] { return launch_wprop(P.at<WFront>(P.wp[l]), P.nwp[l], two_h2, grad_dev, s); });
     }

@@ -1,10 +1,13 @@
 """The APF_MIXED precision option (front GEMMs and sweeps on FP32 MFMA, FP64
-storage, pivot blocks and reductions, no refinement): it must run through
-the single and the batched entry points with identical results, and stay
-within the accuracy measured for it.  Measured relative errors against the
-FP64 oracle: ~1e-3 (S) and ~1e-2 (gradient) on the 240 x 92 random-eps
-problem, where nearly singular pivot blocks amplify FP32 rounding; ~1e-4
-against the FP64 path at 24000 x 160."""
+storage, pivot blocks, reductions and low-rank subtree products, no
+refinement): it must run through the single and the batched entry points
+with identical results, and stay within the accuracy measured for it.
+Measured relative errors against the FP64 oracle: ~1e-6 (S) and ~1e-5
+(gradient) on the 240 x 92 problem; against the FP64 path, 1e-5 / 5e-5 at
+1200 x 92 and 3e-5 / 2e-4 at 24000 x 160, where the gradient of the
+low-rank sweep subtrees is the diagonal of products whose entries are far
+larger than it (those products run in FP64 on both paths: in FP32 they gave
+6e-2 and 0.28)."""
 import numpy as np
 import pytest
 
@@ -40,3 +43,26 @@ def test_mixed_single_and_batched_agree_and_are_near_the_oracle():
         print(f"[gpu] mixed {prob.nx}x{prob.ny}: rel err S {eS:.2e} grad {eg:.2e}", flush=True)
         assert np.isfinite(S).all() and np.isfinite(g).all()
         assert eS < 5e-3 and eg < 5e-2
+
+
+def test_mixed_gradient_of_the_low_rank_subtrees_stays_near_fp64():
+    """1200 x 92 (832 fronts in low-rank sweep subtrees): the mixed gradient
+    within 1e-3 of the FP64 path's in every 75-column block of the grid (a
+    single near-resonant block in FP32 subtree products exceeded 0.2)."""
+    from paper_2306_09257_amd import binding
+    prob, eps, w = inputs.tiny_problem(nx=1200, ny=92, seed=3)
+    apf = binding.APF(prob).analyze()
+    eps_d = torch.as_tensor(eps, dtype=torch.float64, device="cuda")
+    w_d = torch.as_tensor(w, dtype=torch.float64, device="cuda")
+    out = {}
+    for prec in (binding.APF_FP64, binding.APF_MIXED):
+        apf.assemble(eps_d)
+        S = apf.factor_schur(precision=prec)
+        f, G = apf.weighted_power(S, w_d)
+        out[prec] = (S.cpu().numpy(), apf.grad(G).cpu().numpy())
+    assert apf.query("lowrank_fronts") > 0
+    (S64, g64), (Sm, gm) = out[binding.APF_FP64], out[binding.APF_MIXED]
+    blocks = [_rel(gm[:, x], g64[:, x]) for x in np.array_split(np.arange(prob.nx), 16)]
+    print(f"[gpu] mixed 1200x92 vs FP64: S {_rel(Sm, S64):.2e}, grad {_rel(gm, g64):.2e}, "
+          f"worst block {max(blocks):.2e}", flush=True)
+    assert _rel(Sm, S64) < 1e-4 and _rel(gm, g64) < 1e-3 and max(blocks) < 1e-3
