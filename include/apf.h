@@ -221,6 +221,16 @@ apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev,
  * APF_ESTATE); APF_EINVAL unless max_chunk is 0 or a positive multiple of 64. */
 apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk);
 
+/* Allow (on = 1, the default) or forbid (on = 0) the low-rank sweep
+ * subtrees: channel-free sweep subtrees of up to two levels whose gradient
+ * comes from the b x b product Wt = Y_bnd Lam_bnd^T of their root instead of
+ * the Y and Lam sweeps (the same quantity, Eqs. (1)-(3), in another order of
+ * operations; cheaper where b^2 < 2 p b summed over the subtree).  With 0
+ * every sweep front runs the sweeps: for checking one route against the
+ * other.  Call before the first apf_assemble (else APF_ESTATE); APF_EINVAL
+ * for other values. */
+apf_status apf_set_lowrank(apf_handle *h, int32_t on);
+
 /* Per-class HIP-event timing of the handle's launches (counters reset):
  * on = 0 off, 1 every launch, 2 only the GEMM-family launches (classes
  * gemm_factor, gemm_schur, gemm_sweep; half the events of mode 1, for timed

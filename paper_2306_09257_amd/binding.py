@@ -27,7 +27,8 @@ APF_MIXED = 1
 
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
                 "apf_weighted_power", "apf_splitter_fom", "apf_group_fom", "apf_ridges_eps", "apf_ridges_grad",
-                "apf_grad", "apf_set_rhs_chunk", "apf_set_profiling", "apf_destroy", "apf_last_error", "apf_query", "apf_front")
+                "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
+                "apf_last_error", "apf_query", "apf_front")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow")
 
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_grad.argtypes = [vp, vp, vp, vp]
     lib.apf_set_profiling.argtypes = [vp, i32]
     lib.apf_set_rhs_chunk.argtypes = [vp, i32]
+    lib.apf_set_lowrank.argtypes = [vp, i32]
     lib.apf_destroy.argtypes = [vp]
     lib.apf_last_error.argtypes = []
     lib.apf_last_error.restype = ctypes.c_char_p
@@ -139,6 +141,11 @@ class APF:
     def set_rhs_chunk(self, max_chunk: int):
         """Cap the sweeps' right-hand-side chunk (before the first assemble)."""
         _check(self._lib.apf_set_rhs_chunk(self._h, int(max_chunk)))
+        return self
+
+    def set_lowrank(self, on: bool):
+        """Allow or forbid the low-rank sweep subtrees (before the first assemble)."""
+        _check(self._lib.apf_set_lowrank(self._h, 1 if on else 0))
         return self
 
     def set_profiling(self, on, gemm_only: bool = False):

@@ -342,6 +342,7 @@ struct apf_handle {
   int state = 0;        // 0 analysed, 1 assembled, 2 factored
   bool mixed = false;   // precision of the factors held (APF_MIXED)
   int max_chunk = 0;    // cap on the right-hand-side chunk of the sweeps (0: memory decides)
+  bool lowrank = true;  // low-rank sweep subtrees allowed
 };
 
 // ---------------------------------------------------------------------------
@@ -506,7 +507,7 @@ static double mean_tile_k(const std::vector<GemmTask> &v) {
 // run faster on the three-product kernel (fewer MFMAs) despite its lower
 // occupancy; shallower lists are bound by their loads and epilogues.
 constexpr double kDeepMeanK = 96.0;
-constexpr int kWMaxLevels = 3;   // levels of a low-rank sweep subtree
+constexpr int kWMaxLevels = 2;   // levels of a low-rank sweep subtree
 // Flags every task of a deep list for the three-product form.  The flag is
 // per task, so a task rounds the same way in any launch that holds it
 // (single problems and merged batches alike).
@@ -604,9 +605,9 @@ static void build_plan(apf_handle *H) {
   // no chosen ancestor is a subtree root.  Subtrees span at most
   // kWMaxLevels levels: the rounding error of the dense propagation grows by
   // the cancellation factor of both field reconstructions at every level,
-  // where the sweeps add it once per level (24000 x 160, sampled gradient
-  // against the oracle: 5.6e-13 for 1 or 2 levels, 1.7e-11 for 3, 2.3e-10
-  // for 5, 1.4e-10 unlimited).
+  // where the sweeps add it once per level (24000 x 160, gradient over all
+  // pixels against the plain sweeps: 1.6e-15 for one level, 8e-14 for two,
+  // 4.3e-9 for three, with 1.5e-8 in the worst sixteenth of the grid).
   std::vector<char> wcov(nf, 0), wroot(nf, 0);
   std::vector<int64_t> bf_off(nf, -1), qt_off(nf, -1);
   {
@@ -620,7 +621,7 @@ static void build_plan(apf_handle *H) {
       const double p = F.p(), b = F.b();
       double direct = 2.0 * p * b * M, dsub = b * b * p + p * b * (p + b);
       // (a root forms Wt in one 64 x 64 tile: b <= 64)
-      bool ok = !F.hasB && !F.hasC && F.b() > 0 && F.b() <= 64;
+      bool ok = H->lowrank && !F.hasB && !F.hasC && F.b() > 0 && F.b() <= 64;
       for (int c = 0; c < F.nchild; ++c) {
         const int ch = F.child[c];
         if (!S.fronts[ch].sweep) continue;
@@ -1535,6 +1536,14 @@ extern "C" apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk) {
     return fail(APF_EINVAL, "the chunk cap must be 0 or a positive multiple of 64");
   if (h->planned) return fail(APF_ESTATE, "the sweep arrays are already sized (apf_assemble has run)");
   h->max_chunk = max_chunk;
+  return APF_OK;
+}
+
+extern "C" apf_status apf_set_lowrank(apf_handle *h, int32_t on) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  if (on != 0 && on != 1) return fail(APF_EINVAL, "low-rank switch must be 0 or 1");
+  if (h->planned) return fail(APF_ESTATE, "the sweep plan is already built (apf_assemble has run)");
+  h->lowrank = on != 0;
   return APF_OK;
 }
 
