@@ -51,7 +51,7 @@ typedef enum {
   APF_EINVAL = -1,     /* bad argument or descriptor                       */
   APF_ENOMEM = -2,     /* device or host allocation failed                 */
   APF_EHIP = -3,       /* a HIP runtime call failed                        */
-  APF_ESINGULAR = -4,  /* a zero pivot appeared in a pivot block           */
+  APF_ESINGULAR = -4,  /* a zero or non-finite pivot appeared in a pivot block */
   APF_ENOTCONV = -5,   /* iterative refinement did not reach its tolerance */
   APF_ESTATE = -6      /* call out of order (see apf_grad / apf_factor_schur) */
 } apf_status;
@@ -105,9 +105,10 @@ apf_status apf_analyze(apf_handle *h);
  * the GPU: its five stencil values per node, which the factorization scatters
  * into the frontal workspaces level by level (the rows of B and C are
  * generated there from the channel definitions).
- *   eps_dev: float64 [ny][nx] relative permittivity (real; must be nonzero
- *   and finite -- checked on the host-visible copy is not possible, so the
- *   factorization reports APF_ESINGULAR if it produces a zero pivot).
+ *   eps_dev: float64 [ny][nx] relative permittivity (real, nonzero and
+ *   finite).  The values are checked on the GPU as they are read; since this
+ *   call only enqueues work, a zero, NaN or infinite value is reported by the
+ *   next apf_factor_schur (or apf_factor_schur_batched) as APF_EINVAL.
  * The first call allocates the device plan (workspaces, factor storage, task
  * lists) and synchronises `stream` once; later calls only enqueue work.
  * Requires apf_analyze. */
@@ -119,8 +120,11 @@ apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *stream);
  * prec: APF_FP64 or APF_MIXED (see apf_precision); apf_grad then runs its
  * sweeps in the same precision.
  * The factors are kept on the handle for apf_grad.  Synchronises `stream` at
- * the end to read the pivot status word (returns APF_ESINGULAR on a zero
- * pivot).  Requires apf_assemble since the last factorization. */
+ * the end to read the device status words: APF_EINVAL if the last assembled
+ * permittivity had a zero or non-finite value, APF_ESINGULAR if a pivot block
+ * met a zero or non-finite pivot (the pivot search always picks an unused row,
+ * so the factorization itself stays in bounds; S is then meaningless and
+ * apf_grad refuses to run).  Requires apf_assemble. */
 apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev,
                             void *stream);
 
@@ -135,8 +139,10 @@ apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev,
  * profiling is on for hs[0]).
  *   hs: n handle pointers (host array); S_devs: n device pointers, complex128
  *   [n_out_i][n_in_i] each.  The factors stay on each handle for apf_grad.
- *   Synchronises `stream` at the end; APF_ESINGULAR if any pivot block of the
- *   batch had a zero pivot (then no handle may be used by apf_grad). */
+ *   Synchronises `stream` at the end; APF_EINVAL if a problem's permittivity
+ *   had a zero or non-finite value, APF_ESINGULAR if any pivot block of the
+ *   batch had a zero or non-finite pivot (either way no handle of the batch
+ *   may then be used by apf_grad). */
 apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n, apf_precision prec,
                                     double *const *S_devs, void *stream);
 
@@ -247,7 +253,10 @@ apf_status apf_destroy(apf_handle *h);
 const char *apf_last_error(void);
 
 /* Read a named statistic of an analysed handle (host only):
- *   "n_fronts", "n_levels", "max_front" (largest p+b), "factor_cmacs" and
+ *   "n_fronts", "n_levels", "max_front" (largest p+b), "n_factorizations"
+ *   (factorizations run on the handle so far, failed ones included: a caller
+ *   that keeps the factors for a later apf_grad can tell whether they were
+ *   replaced meanwhile), "factor_cmacs" and
  *   "grad_cmacs" (complex multiply-adds the factorization and the gradient
  *   perform), "algo_factor_cmacs" (sum over fronts of the rank-p updates of
  *   the rectangular front, channel block included), "ws_bytes" (workspace

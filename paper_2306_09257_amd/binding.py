@@ -268,12 +268,29 @@ def solve(apf: APF, eps, precision: int = APF_FP64):
     return apf.factor_schur(precision=precision)
 
 
+class StaleFactorsError(RuntimeError):
+    """The handle was factorized again between an autograd forward and its
+    backward, so its factors belong to another permittivity."""
+
+
+def check_factor_epoch(apf, saved: int) -> None:
+    """Raise StaleFactorsError unless `apf` has run exactly the factorizations
+    counted in `saved` (its "n_factorizations" statistic at forward time)."""
+    now = int(apf.query("n_factorizations"))
+    if now != saved:
+        raise StaleFactorsError(
+            f"the APF handle was factorized {now - saved} more time(s) after this forward pass; its factors "
+            f"no longer belong to the forward permittivity (use one handle per pending backward)")
+
+
 def make_autograd_function():
     """torch.autograd.Function around the library: forward S(eps), backward
     grad_eps from the weighted adjoint of apf_grad.  torch hands backward
     grad_S = 2 conj(dF/dS) for a real loss (its convention for complex
     inputs), so the Wirtinger derivative passed to the library is
-    conj(grad_S)/2."""
+    conj(grad_S)/2.  apf_grad uses the factors the handle holds, so backward
+    checks that no other factorization ran on the handle since this forward
+    (StaleFactorsError otherwise)."""
     import torch
 
     class APFFunction(torch.autograd.Function):
@@ -285,10 +302,12 @@ def make_autograd_function():
             apf.assemble(eps.contiguous())
             S = apf.factor_schur(precision=precision)
             ctx.apf = apf
+            ctx.epoch = int(apf.query("n_factorizations"))
             return S
 
         @staticmethod
         def backward(ctx, grad_S):
+            check_factor_epoch(ctx.apf, ctx.epoch)
             dfdS = (grad_S.conj() * 0.5).contiguous()
             g = ctx.apf.grad(dfdS)
             return g, None, None, None

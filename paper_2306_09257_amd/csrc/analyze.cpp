@@ -18,7 +18,6 @@ namespace apf {
 
 namespace {
 
-constexpr int kMaxPivots = 128;   // largest pivot block of one front
 // Default leaf size (nodes).  24000 x 160: 169.3 ms/solve at 48 against
 // 179.4 at 40, 172.2 at 56 and 172.1 at 64.
 constexpr int kLeafNodes = 48;
@@ -70,11 +69,11 @@ struct Builder {
   int node(int x, int y) const { return y * d.nx + x; }
 
   // Emit a front over `piv` with children c0, c1; separators longer than
-  // kMaxPivots become a chain of fronts (each the parent of the previous), so
+  // MAX_PIVOTS become a chain of fronts (each the parent of the previous), so
   // that no pivot block exceeds what one workgroup factors in registers.
   int emit(std::vector<int> &&piv, int c0, int c1, int x0, int x1, int y0, int y1) {
     const int p = (int)piv.size();
-    const int nchunk = (p + kMaxPivots - 1) / kMaxPivots;
+    const int nchunk = (p + MAX_PIVOTS - 1) / MAX_PIVOTS;
     const int chunk = (p + nchunk - 1) / nchunk;
     int prev = -1;
     for (int j = 0; j < nchunk; ++j) {

@@ -188,4 +188,13 @@ struct WFront {
 
 constexpr int GEMM_TILE = 64;
 
+// Largest pivot block of one front.  The nested dissection splits longer
+// separators into chains of fronts; the pivot-block kernels, the low-rank
+// subtree gather and the plan builder are all sized by this one constant.
+constexpr int MAX_PIVOTS = 128;
+
+// Bits of the device status word a factorization reports through.
+constexpr int ST_SINGULAR = 1;   // a pivot block met a zero or non-finite pivot
+constexpr int ST_BAD_EPS = 2;    // the assembled permittivity had a zero or non-finite value
+
 }  // namespace apf

@@ -171,7 +171,7 @@ struct Plan {
   cplx *ws = nullptr, *fs = nullptr, *sb = nullptr, *sc = nullptr, *X = nullptr, *V = nullptr, *aval = nullptr;
   int32_t *perms = nullptr;   // pivot permutation of every front, at its first elimination index
   char *blob = nullptr;
-  int *status = nullptr;
+  int *status = nullptr;      // [0]: pivot status of the last factorization; [1]: permittivity check of the last assembly
   double *part = nullptr;
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
   int rhs_chunk = 0;
@@ -343,6 +343,7 @@ struct apf_handle {
   bool mixed = false;   // precision of the factors held (APF_MIXED)
   int max_chunk = 0;    // cap on the right-hand-side chunk of the sweeps (0: memory decides)
   bool lowrank = true;  // low-rank sweep subtrees allowed
+  int64_t n_factor = 0; // factorizations run on this handle (a caller can tell whether the factors changed)
 };
 
 // ---------------------------------------------------------------------------
@@ -542,9 +543,9 @@ static void build_plan(apf_handle *H) {
   HIPCHK(hipMalloc(&P.perms, (int64_t)d.nx * d.ny * sizeof(int32_t)));
   HIPCHK(hipMalloc(&P.xc, std::max<int64_t>(P.xc_rows * Mo, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.vmap, std::max<int64_t>(P.xc_rows, 1) * sizeof(int32_t)));
-  HIPCHK(hipMalloc(&P.status, sizeof(int)));
+  HIPCHK(hipMalloc(&P.status, 2 * sizeof(int)));
   HIPCHK(hipMalloc(&P.part, 1024 * sizeof(double)));
-  HIPCHK(hipMemset(P.status, 0, sizeof(int)));
+  HIPCHK(hipMemset(P.status, 0, 2 * sizeof(int)));
 
   // sweep arrays: pick the right-hand-side chunk from the free memory
   {
@@ -650,7 +651,7 @@ static void build_plan(apf_handle *H) {
       if (!wcov[f]) continue;
       ++P.n_wfronts;
       const Front &F = S.fronts[f];
-      if (F.p() > 128) throw std::runtime_error("pivot block larger than 128 in a low-rank sweep subtree");
+      if (F.p() > MAX_PIVOTS) throw std::runtime_error("pivot block larger than MAX_PIVOTS in a low-rank sweep subtree");
       const int64_t n = F.p() + F.b();
       bf_off[f] = wtot;
       wtot += (int64_t)F.b() * n;
@@ -725,7 +726,11 @@ static void build_plan(apf_handle *H) {
     std::vector<int32_t> inv[N_INV_VARIANTS];
     for (int f : S.levels[lvl]) {
       const Front &F = S.fronts[f];
-      if (F.p() > 0) inv[inverse_variant(F.p())].push_back(f);
+      if (F.p() > 0) {
+        const int v = inverse_variant(F.p());
+        if (v < 0) throw std::runtime_error("pivot block larger than MAX_PIVOTS");
+        inv[v].push_back(f);
+      }
     }
     LevelTasks &L = P.lv[lvl];
     for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = ib.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
@@ -1132,7 +1137,8 @@ extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *s
       }
     }
     Profiler &pr = h->prof;
-    pr.run(P_STENCIL, s, [&] { return launch_stencil(h->phys, eps_dev, h->plan.aval, s); });
+    HIPCHK(launch_fill_int(h->plan.status + 1, 0, s));
+    pr.run(P_STENCIL, s, [&] { return launch_stencil(h->phys, eps_dev, h->plan.aval, h->plan.status + 1, s); });
     if (pr.on) pr.collect();
     h->state = 1;
     return APF_OK;
@@ -1197,13 +1203,18 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
     HIPCHK(launch_fill_int(P.status, 0, s));
     run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32);
     enqueue_schur(P, f32, S_dev, pr, s, h->d.n_out, h->d.n_in);
-    int st = 0;
-    HIPCHK(hipMemcpyAsync(&st, P.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    int st[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(st, P.status, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (pr.on) pr.collect();
-    if (st) {
+    ++h->n_factor;
+    if (st[1] & ST_BAD_EPS) {
       h->state = 0;
-      return fail(APF_ESINGULAR, "zero pivot in a pivot block");
+      return fail(APF_EINVAL, "the permittivity has a zero or non-finite value");
+    }
+    if (st[0]) {
+      h->state = 0;
+      return fail(APF_ESINGULAR, "zero or non-finite pivot in a pivot block");
     }
     h->state = 2;
     h->mixed = f32;
@@ -1381,11 +1392,21 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
     HIPCHK(hipMemcpyAsync(&st, B->status, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (pr.on) pr.collect();
-    for (int i = 0; i < n; ++i) {
-      hs[i]->state = st ? 0 : 2;
-      hs[i]->mixed = f32;
+    int bad_eps = -1;
+    for (int i = 0; i < n && bad_eps < 0; ++i) {
+      int e = 0;
+      HIPCHK(hipMemcpy(&e, hs[i]->plan.status + 1, sizeof(int), hipMemcpyDeviceToHost));
+      if (e & ST_BAD_EPS) bad_eps = i;
     }
-    if (st) return fail(APF_ESINGULAR, "zero pivot in a pivot block of the batch");
+    for (int i = 0; i < n; ++i) {
+      hs[i]->state = (st || bad_eps >= 0) ? 0 : 2;
+      hs[i]->mixed = f32;
+      ++hs[i]->n_factor;
+    }
+    if (bad_eps >= 0)
+      return fail(APF_EINVAL, "the permittivity of problem " + std::to_string(bad_eps) +
+                                  " of the batch has a zero or non-finite value");
+    if (st) return fail(APF_ESINGULAR, "zero or non-finite pivot in a pivot block of the batch");
     return APF_OK;
   });
 }
@@ -1590,6 +1611,7 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
   else if (k == "factor_bytes") *value = (double)h->plan.fs_elems * sizeof(cplx);
   else if (k == "schur_store_bytes") *value = (double)S.k_total * (h->d.n_in + h->d.n_out) * sizeof(cplx);
   else if (k == "rhs_chunk") *value = h->planned ? (double)h->plan.rhs_chunk : -1.0;
+  else if (k == "n_factorizations") *value = (double)h->n_factor;
   else if (k == "lowrank_fronts") *value = h->planned ? (double)h->plan.n_wfronts : -1.0;
   else if (k == "lowrank_roots") *value = h->planned ? (double)h->plan.n_wroots : -1.0;
   else if (k == "gemm_cmacs_factor") *value = h->planned ? h->plan.gemm_cmacs_factor : -1.0;

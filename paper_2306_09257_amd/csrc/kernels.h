@@ -8,12 +8,14 @@
 namespace apf {
 
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s);
-hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStream_t s);
+// status: ST_BAD_EPS is or-ed in for a zero or non-finite permittivity
+hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, int *status, hipStream_t s);
 hipError_t launch_scatter_A(const AsmEntry *e, int n, hipStream_t s);
 hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, hipStream_t s);
-constexpr int N_INV_VARIANTS = 8;
-int inverse_variant(int p);   // kernel variant of a pivot block of size p
+constexpr int N_INV_VARIANTS = 6;
+// kernel variant of a pivot block of size p (1 <= p <= MAX_PIVOTS), -1 beyond
+int inverse_variant(int p);
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s);
 // part / pstride: output of the tasks flagged G_CONTRACT, partial of design
 // slot g and 32-column block b at part[b * pstride + g] (unused otherwise);

@@ -75,14 +75,16 @@ __device__ double2 stretch(const Phys &P, double y) {
 
 // Stencil values of A for every node (a1): Aval[node][dir], dir 0 centre,
 // 1 x-1, 2 x+1, 3 y-1, 4 y+1 (x periodic; entries beyond the first and last
-// rows are never scattered).
-__global__ void k_stencil(Phys P, const double *eps, cplx *Aval) {
+// rows are never scattered).  A zero or non-finite permittivity sets
+// ST_BAD_EPS in *status (the factorization reports it).
+__global__ void k_stencil(Phys P, const double *eps, cplx *Aval, int *status) {
   const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (n >= (int64_t)P.nx * P.ny) return;
   const int j = (int)(n / P.nx);
   const double2 sj = stretch(P, (double)j);
   const double2 up = cinv(stretch(P, j - 0.5)), dn = cinv(stretch(P, j + 0.5));
   const double ep = eps[n];
+  if (!(fabs(ep) > 0.0) || !(fabs(ep) < INFINITY)) atomicOr(status, ST_BAD_EPS);
   double2 c = cadd(make_double2(2.0 * sj.x, 2.0 * sj.y), cadd(up, dn));
   c = csub(c, make_double2(P.h2 * ep * sj.x, P.h2 * ep * sj.y));
   cplx *o = Aval + n * 5;
@@ -153,8 +155,7 @@ __global__ void k_assemble_panel(const PanelEntry *e, int n) {
 // and row k of L, and the U triangle (i < k, j > k) with column k of U and
 // row k of U scaled by 1/u_kk; the two touch disjoint entries.
 // ---------------------------------------------------------------------------
-constexpr int INV_THREADS = 256;
-constexpr int INV_MAXP = 1024;
+constexpr int INV_MAXP = 1024;   // "no step" marker of a register row past p
 
 // Register-blocked variant for p <= TR*RR = TC*RC: thread (ti, tj) of a
 // TR x TC grid keeps entries (ti + TR*ra, tj + TC*ca) in registers.  Steps
@@ -165,6 +166,7 @@ template <int TR, int TC, int RR, int RC>
 __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const int32_t *ids, int *status) {
   constexpr int MAXP = TR * RR;
   static_assert(TR * RR == TC * RC, "square coverage");
+  static_assert(MAXP < INV_MAXP, "the no-step marker must exceed every step");
   static_assert(TR <= 64 && (64 % TR) == 0, "a pivot-column group must sit inside one wave");
   const FrontDev F = fr[ids[blockIdx.x]];
   const int p = F.p, n = F.p + F.b;
@@ -193,23 +195,26 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
       const int k = kq * TC + kc;
       if (k >= p) break;
       if (tj == kc) {
-        // largest unused row of column k (ties: lowest row)
+        // largest unused row of column k (ties: lowest row).  bi == p means
+        // "no unused row seen"; any unused row replaces it, so the search
+        // returns an unused row even when the column holds NaNs (which no
+        // comparison selects); a NaN or zero pivot is then flagged.
         double bv = -1.0;
         int bi = p;
 #pragma unroll
         for (int ra = 0; ra < RR; ++ra) {
           const double2 v = a[ra][kq];
           const double m = v.x * v.x + v.y * v.y;
-          if (un[ra] && m > bv) { bv = m; bi = ti + TR * ra; }
+          if (un[ra] && (bi == p || m > bv)) { bv = m; bi = ti + TR * ra; }
         }
 #pragma unroll
         for (int off = TR / 2; off > 0; off >>= 1) {
           const double ov = __shfl_xor(bv, off, TR);
           const int oi = __shfl_xor(bi, off, TR);
-          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+          if (oi != p && (bi == p || ov > bv || (ov == bv && oi < bi))) { bv = ov; bi = oi; }
         }
         if (ti == 0) {
-          if (!(bv > 0.0)) s_bad = 1;
+          if (!(bv > 0.0) || !(bv < INFINITY)) s_bad = 1;
           s_r = bi;
           piv_row[k] = bi;
           piv_step[bi] = k;
@@ -362,7 +367,7 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
       __syncthreads();
     }
   }
-  if (tid == 0 && s_bad) atomicOr(status, 1);
+  if (tid == 0 && s_bad) atomicOr(status, ST_SINGULAR);
   for (int k = tid; k < p; k += TR * TC) F.perm[k] = piv_row[k];
 #pragma unroll
   for (int ra = 0; ra < RR; ++ra)
@@ -371,100 +376,6 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
       const int x = ti + TR * ra, y = tj + TC * ca;
       if (x < p && y < p) st2(F.tri + (int64_t)st[ra] * p + y, a[ra][ca]);
     }
-}
-
-// Fallback for pivot blocks larger than the register variants cover: the same
-// two phases on a copy of the block in F.tri (global memory, L2 resident),
-// one workgroup, INV_THREADS threads striding over rows/entries.
-__global__ __launch_bounds__(INV_THREADS) void k_lu_inv_global(const FrontDev *fr, const int32_t *ids, int *status) {
-  const FrontDev F = fr[ids[blockIdx.x]];
-  const int p = F.p, n = F.p + F.b, tid = threadIdx.x;
-  __shared__ double2 rowbuf[INV_MAXP], colbuf[INV_MAXP];
-  __shared__ int used[INV_MAXP], piv_row[INV_MAXP], piv_step[INV_MAXP];
-  __shared__ double redv[INV_THREADS];
-  __shared__ int redi[INV_THREADS];
-  cplx *a = F.tri;   // working copy, rows in F11's (natural) order
-  for (int e = tid; e < p * p; e += INV_THREADS) {
-    const int i = e / p, j = e - i * p;
-    st2(a + e, ld2(F.core + (int64_t)i * n + j));
-  }
-  for (int t = tid; t < p; t += INV_THREADS) used[t] = 0;
-  __syncthreads();
-  bool bad = false;
-  for (int k = 0; k < p; ++k) {
-    double bv = -1.0;
-    int bi = p;
-    for (int i = tid; i < p; i += INV_THREADS) {
-      const double2 v = ld2(a + (int64_t)i * p + k);
-      const double m = v.x * v.x + v.y * v.y;
-      if (!used[i] && (m > bv || (m == bv && i < bi))) { bv = m; bi = i; }
-    }
-    redv[tid] = bv;
-    redi[tid] = bi;
-    __syncthreads();
-    for (int s = INV_THREADS / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double ov = redv[tid + s];
-        const int oi = redi[tid + s];
-        if (ov > redv[tid] || (ov == redv[tid] && oi < redi[tid])) { redv[tid] = ov; redi[tid] = oi; }
-      }
-      __syncthreads();
-    }
-    const int r = redi[0];
-    if (!(redv[0] > 0.0)) bad = true;
-    __syncthreads();
-    if (tid == 0) { used[r] = 1; piv_row[k] = r; piv_step[r] = k; }
-    for (int j = tid; j < p; j += INV_THREADS) rowbuf[j] = ld2(a + (int64_t)r * p + j);
-    for (int i = tid; i < p; i += INV_THREADS) colbuf[i] = ld2(a + (int64_t)i * p + k);
-    __syncthreads();
-    const double2 inv = cinv(rowbuf[k]);
-    for (int e = tid; e < p * p; e += INV_THREADS) {
-      const int i = e / p, j = e - i * p;
-      if (used[i]) continue;
-      const double2 l = cmul(colbuf[i], inv);
-      if (j == k) st2(a + e, l);
-      else if (j > k) st2(a + e, csub(ld2(a + e), cmul(l, rowbuf[j])));
-    }
-    __syncthreads();
-  }
-  // phase B on the natural-order copy, rows addressed through piv_row
-  for (int k = 0; k < p; ++k) {
-    const int r = piv_row[k];
-    for (int j = tid; j < p; j += INV_THREADS) rowbuf[j] = ld2(a + (int64_t)r * p + j);
-    for (int i = tid; i < p; i += INV_THREADS) colbuf[i] = ld2(a + (int64_t)i * p + k);
-    __syncthreads();
-    const double2 inv = cinv(rowbuf[k]);
-    for (int e = tid; e < p * p; e += INV_THREADS) {
-      const int x = e / p, j = e - x * p;
-      const int i = piv_step[x];
-      const double2 c = colbuf[x];
-      if (j == k) {
-        if (i > k) st2(a + e, make_double2(-c.x, -c.y));
-        else if (i < k) st2(a + e, make_double2(-(c.x * inv.x - c.y * inv.y), -(c.x * inv.y + c.y * inv.x)));
-        else st2(a + e, inv);
-      } else if (i == k) {
-        if (j > k) st2(a + e, cmul(rowbuf[j], inv));
-      } else if (i > k && j < k) {
-        st2(a + e, csub(ld2(a + e), cmul(c, rowbuf[j])));
-      } else if (i < k && j > k) {
-        st2(a + e, csub(ld2(a + e), cmul(c, cmul(rowbuf[j], inv))));
-      }
-    }
-    __syncthreads();
-  }
-  // reorder rows into step order: stage through the core's pivot block, which
-  // is no longer needed once the copy is factored
-  for (int e = tid; e < p * p; e += INV_THREADS) {
-    const int x = e / p, j = e - x * p;
-    st2(F.core + (int64_t)piv_step[x] * n + j, ld2(a + e));
-  }
-  __syncthreads();
-  for (int e = tid; e < p * p; e += INV_THREADS) {
-    const int i = e / p, j = e - i * p;
-    st2(a + e, ld2(F.core + (int64_t)i * n + j));
-  }
-  for (int k = tid; k < p; k += INV_THREADS) F.perm[k] = piv_row[k];
-  if (tid == 0 && bad) atomicOr(status, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -960,7 +871,7 @@ __global__ __launch_bounds__(256, 3) void k_lowrank_w(const GemmTask *tasks, int
 // maps (kinv(i): the step whose pivot row is i).
 __global__ __launch_bounds__(256) void k_wprop(const WFront *fr, double scale, double *grad) {
   const WFront F = fr[blockIdx.x];
-  __shared__ int kinv[128];
+  __shared__ int kinv[MAX_PIVOTS];   // the plan builder rejects larger pivot blocks here
   const int p = F.p, ld = F.p + F.b;
   for (int k = threadIdx.x; k < p; k += blockDim.x) kinv[F.perm[k]] = k;
   __syncthreads();
@@ -1189,9 +1100,9 @@ hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(n), dim3(256), 0, s, r, n);
   return hipGetLastError();
 }
-hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, hipStream_t s) {
+hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, int *status, hipStream_t s) {
   int64_t N = (int64_t)P.nx * P.ny;
-  hipLaunchKernelGGL(k_stencil, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, eps, Aval);
+  hipLaunchKernelGGL(k_stencil, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, eps, Aval, status);
   return hipGetLastError();
 }
 hipError_t launch_scatter_A(const AsmEntry *e, int n, hipStream_t s) {
@@ -1208,15 +1119,13 @@ hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n);
   return hipGetLastError();
 }
+// Largest pivot block of each variant of launch_inverse.
+constexpr int kInvCover[N_INV_VARIANTS] = {8 * 2, 8 * 4, 8 * 6, 16 * 4, 32 * 3, 32 * 4};
+static_assert(kInvCover[N_INV_VARIANTS - 1] == MAX_PIVOTS, "the largest variant covers exactly MAX_PIVOTS");
 int inverse_variant(int p) {
-  if (p <= 16) return 0;
-  if (p <= 32) return 1;
-  if (p <= 48) return 2;
-  if (p <= 64) return 3;
-  if (p <= 96) return 4;
-  if (p <= 128) return 5;
-  if (p <= 160) return 6;
-  return 7;
+  for (int v = 0; v < N_INV_VARIANTS; ++v)
+    if (p >= 1 && p <= kInvCover[v]) return v;
+  return -1;
 }
 
 // Small blocks (p <= 48, the leaves and short separators) run on one wave:
@@ -1230,8 +1139,7 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
     case 3: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
     case 4: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
     case 5: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
-    case 6: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 5, 10>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
-    default: hipLaunchKernelGGL(k_lu_inv_global, dim3(n), dim3(INV_THREADS), 0, s, fr, ids, status); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -42,7 +42,8 @@ def test_mixed_single_and_batched_agree_and_are_near_the_oracle():
         eS, eg = _rel(S, S_o), _rel(g, g_o)
         print(f"[gpu] mixed {prob.nx}x{prob.ny}: rel err S {eS:.2e} grad {eg:.2e}", flush=True)
         assert np.isfinite(S).all() and np.isfinite(g).all()
-        assert eS < 5e-3 and eg < 5e-2
+        # measured (unrefined FP32 fronts): S 1.2e-6 / 1.8e-6, gradient 8.4e-6 / 3.1e-5 on the two grids
+        assert eS < 1e-5 and eg < 1e-4
 
 
 def test_mixed_gradient_of_the_low_rank_subtrees_stays_near_fp64():

@@ -19,6 +19,7 @@ import pytest
 
 from paper_2306_09257_amd import inputs
 import oracle.objectives as oobj
+from tests.parity import worst_block, worst_block_sampled
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -54,12 +55,16 @@ def test_multiangle_48000x160_against_oracle_samples():
     eG = _rel(G_h[:, cols], gold["G_cols"])
     eg = _rel(g_h.ravel()[gold["pixels"]], gold["grad"])
     en = abs(np.linalg.norm(g_h) - float(gold["grad_norm"])) / float(gold["grad_norm"])
+    eS_blk = worst_block(S_h[:, cols], gold["S_cols"], axis=0)
+    eg_blk = worst_block_sampled(g_h.ravel()[gold["pixels"]], gold["grad"], gold["pixels"] % prob.nx, prob.nx)
     f_o, G_o = oobj.group_fom(S_h, prob.in_orders, prob.out_orders, delta)
     print(f"[gpu] rhs chunk {apf.query('rhs_chunk'):.0f}; rel err S columns {eS:.2e}, dF/dS columns {eG:.2e}, "
           f"sampled grad {eg:.2e}, grad norm {en:.2e}; objective kernel f {abs(float(f) - f_o) / abs(f_o):.2e}, "
-          f"dF/dS {_rel(G_h, G_o):.2e}; gradient call {t_grad:.2f} s", flush=True)
+          f"dF/dS {_rel(G_h, G_o):.2e}; worst blocks S {eS_blk:.2e}, grad {eg_blk:.2e}; gradient call "
+          f"{t_grad:.2f} s", flush=True)
     assert apf.query("rhs_chunk") < prob.n_in      # the chunked sweeps take part
     assert eS < TOL and eG < TOL and eg < TOL and en < TOL
+    assert eS_blk < TOL and eg_blk < TOL
     assert abs(float(f) - f_o) < 1e-12 * abs(f_o) and _rel(G_h, G_o) < 1e-12
     flux = np.sum(np.abs(S_h) ** 2, axis=0)
     assert np.all(np.isfinite(S_h)) and flux.max() <= 1.0 + 1e-9

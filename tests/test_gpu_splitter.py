@@ -8,7 +8,7 @@ one 24-um period (25 inputs, 51 outputs):
   symmetric), step by step at 1e-10 (the permittivity to 1e-13);
 * a seeded random design: the edge gradient against central differences of
   f evaluated on the GPU path;
-* a period without mirror symmetry (Supplement Sec. 6): permittivity and edge
+* a period without mirror symmetry (Supplement Sec. 7, optimization without mirror symmetry): permittivity and edge
   gradient against the oracle;
 * gradient descent on the edges with the backtracking line search of
   Supplement Sec. 4 lowers f at every accepted step.

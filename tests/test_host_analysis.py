@@ -218,3 +218,33 @@ def test_host_side_argument_and_state_checks(lib):
     assert lib.apf_query(None, b"n_fronts", ctypes.byref(v)) == E
     assert lib.apf_destroy(None) == binding.APF_OK
     assert b"null" in lib.apf_last_error()
+
+
+def test_factorization_counter_and_stale_factor_guard(lib):
+    """The handle counts its factorizations ("n_factorizations"); the autograd
+    backward refuses to run when the count moved since its forward (the
+    factors then belong to another permittivity)."""
+    apf = binding.APF(_problem(24, 60)).analyze()
+    assert apf.query("n_factorizations") == 0.0
+
+    class Fake:
+        def __init__(self, n):
+            self.n = n
+
+        def query(self, key):
+            assert key == "n_factorizations"
+            return float(self.n)
+
+    binding.check_factor_epoch(Fake(3), 3)
+    with pytest.raises(binding.StaleFactorsError):
+        binding.check_factor_epoch(Fake(4), 3)
+
+
+def test_pivot_limit_is_shared_by_the_analysis_and_the_kernels(lib):
+    """No front exceeds the pivot limit the kernels are sized for (a 200-row
+    separator is chained into two fronts of 100)."""
+    prob = _problem(12, 200, layout=(20, 60, 40, 60, 20))
+    apf = binding.APF(prob).analyze()
+    ps = [apf.front(f)[0][2] for f in range(int(apf.query("n_fronts")))]
+    assert max(ps) <= 128
+    assert 100 in ps

@@ -108,7 +108,24 @@ def _mut_group_no_deviation(monkeypatch):
     monkeypatch.setattr(oobj, "group_fom", bad)
 
 
+def _mut_sampled_adjoint_columns(monkeypatch):
+    def bad(prob, eps, G, solver=None):
+        if solver is None:
+            solver = oapf.make_solver(prob, eps)
+        cols = np.nonzero(np.any(G != 0, axis=0))[0]
+        Y = oapf.forward_fields(prob, solver, cols)
+        src = ofd.projection_row(prob).T @ G[:, :cols.size]         # adjoint from the wrong input columns
+        Lam = solver.solve(oapf._rhs_on_row(prob, prob.prj_row, src))
+        return oapf.gradient_from_fields(prob, Y, Lam), cols, Y
+    monkeypatch.setattr(oapf, "grad_sampled_inputs", bad)
+
+
+def _sampled_pin():
+    pins.test_sampled_input_gradient_equals_the_full_gradient(16, 60, 0.15, "row")
+
+
 MUTATIONS = {
+    "sampled_adjoint_columns": (_mut_sampled_adjoint_columns, [_sampled_pin]),
     "mirror_sign": (_mut_mirror_sign, [spins.test_jacobian_matches_finite_differences,
                                        spins.test_edge_gradient_matches_central_differences]),
     "coverage_no_wrap": (_mut_coverage_no_wrap,

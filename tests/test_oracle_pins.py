@@ -15,7 +15,7 @@ mathematics, independent of the oracle's own formulas:
   two-sided S for lossless eps (within the PML's residual reflection);
 * the gradient: Eq. (1)+(3) with the weighted adjoint, Supplement Eq. (S1)
   and the augmented Eq. (4) agree; central finite differences; the Taylor
-  remainder of Supplement Sec. 4 scales as |dp|^3;
+  remainder of Supplement Sec. 3 (gradient validation) scales as |dp|^3;
 * channel counts the paper prints (tests/golden/channel_counts.json).
 """
 import json
@@ -231,6 +231,32 @@ def test_gradient_routes_agree():
     assert np.abs(S - S_aug).max() < 1e-12 * np.abs(S).max()
 
 
+@pytest.mark.parametrize("nx,ny,dx,kind", [(16, 60, 0.15, "row"), (16, 60, 0.15, "column"),
+                                           (64, 92, 0.05, "row"), (64, 92, 0.05, "column")])
+def test_sampled_input_gradient_equals_the_full_gradient(nx, ny, dx, kind):
+    """The gradient for a dF/dS supported on a few input columns, computed from
+    those inputs' fields only (the route that writes the stored full-size
+    expected values), equals the all-input weighted-adjoint gradient (pinned
+    above against Supplement Eq. (S1), the augmented Eq. (4) and finite
+    differences) and, on the smaller grid, the dense Eq. (S1) route itself."""
+    prob, eps, w = _tiny(nx=nx, ny=ny, seed=17, dx_over_lambda=dx)
+    assert prob.n_in >= 5
+    rng = np.random.default_rng(5)
+    cols = np.sort(rng.choice(prob.n_in, size=min(3, prob.n_in), replace=False))
+    G = np.zeros((prob.n_out, prob.n_in), dtype=np.complex128)
+    G[:, cols] = rng.standard_normal((prob.n_out, cols.size)) + 1j * rng.standard_normal((prob.n_out, cols.size))
+    solver = oapf.make_solver(prob, eps, kind)
+    g_s, got_cols, Y = oapf.grad_sampled_inputs(prob, eps, G, solver=solver)
+    _, g_full, _ = oapf.solve_S_and_grad(prob, eps, G=G, solver=oapf.make_solver(prob, eps, kind))
+    assert list(got_cols) == list(cols)
+    assert Y.shape == (prob.ny, prob.nx, cols.size)
+    scale = np.abs(g_full).max()
+    assert np.abs(g_s - g_full).max() < 1e-12 * scale
+    if nx == 16:
+        g_conv = oapf.grad_conventional(prob, eps, G)
+        assert np.abs(g_s - g_conv).max() < 1e-12 * scale
+
+
 def test_gradient_central_differences():
     prob, eps, w = _tiny(nx=12, ny=60, seed=6)
     _, g, _ = oapf.solve_S_and_grad(prob, eps, w=w)
@@ -241,7 +267,7 @@ def test_gradient_central_differences():
 
 
 def test_taylor_remainder_is_third_order():
-    """Supplement Sec. 4: |df - grad f(p0 + dp/2) . dp| = O(|dp|^3)."""
+    """Supplement Sec. 3 (gradient validation): |df - grad f(p0 + dp/2) . dp| = O(|dp|^3)."""
     prob, eps0, w = _tiny(nx=10, ny=60, seed=8)
     rng = np.random.default_rng(99)
     r0, r1 = prob.design_row0, prob.design_row1
