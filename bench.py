@@ -7,10 +7,14 @@ derivative + the gradient over every design pixel (weighted-adjoint sweeps
 and contraction).  The symbolic analysis depends only on the grid and is done
 once, outside the timed region.  Inputs (eps, w) are resident in HBM.
 
-Workload (default): 1,200-wavelength metasurface, 24,000 x 160 grid
-(3.84M unknowns, dx = lambda/20), 2,399 input x 2,399 output channels,
-960,000 design pixels of binary {1, 4} permittivity smoothed by a 3-px-FWHM
-Gaussian, f = sum w |S|^2 with w ~ U[0, 1].  Synthetic, seeded.
+Workload (default, the largest single-GPU configuration): 2,400-wavelength
+multi-angle metasurface, 48,000 x 160 grid (7.68M unknowns, dx = lambda/20),
+4,559 input x 4,559 output channels (all orders within sin(theta) < 0.95),
+1.92M design pixels of binary {1, 4} permittivity smoothed by a 3-px-FWHM
+Gaussian, grouped objective (five target orders per input, 100 orders apart,
+with a uniformity penalty).  --workload metasurface_24000x160 runs the
+1,200-wavelength metasurface (2,399 x 2,399 channels, f = sum w |S|^2).
+Synthetic, seeded.
 
 Prints one JSON line.  The roofline block is for the batched complex FP64
 MFMA GEMM kernels (k_gemm, its three-product variant k_gemm_k3 and the
@@ -18,10 +22,13 @@ low-rank k_lowrank_w): their algorithmic flops (8 per complex MAC of the
 M x N x K products the tasks specify, a triangular factor counting only its
 stored triangle) over their HIP-event time in the timed region; traffic is
 their HBM bytes per launch from the committed counter summary under
-profiles/, or null when that summary was taken on other sources.  The
-cpu_baseline block times the CPU FP64 oracle on a bounded narrow-strip
-sample of the same workload and scales it by the oracle's cost model to the
-full workload.
+profiles/, or null when that summary was taken on other sources.  The same
+block reports the flops the MFMA units execute (6 per complex MAC where the
+three-product form runs) over the same time.  The cpu_baseline block times
+the CPU FP64 oracle on three narrow strips of the same layout and
+permittivity recipe, fits the two coefficients of the oracle's cost model
+(grid term, channel term) on two of them, checks the fit on the third and
+scales it to the full workload.
 """
 import argparse
 import hashlib
@@ -93,37 +100,90 @@ def profiled_traffic(workload, precision):
     return float(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
 
 
-def oracle_cost_model(nx, ny, m):
-    """Complex MACs of the oracle's cyclic column-block solve for S and the
-    gradient: two solves (forward, weighted adjoint), each eliminating nx
-    column blocks of size ny against 2 ny + m right-hand sides, with a dense
-    border update per column."""
-    return 2.0 * nx * ny * ny * (4.3 * ny + 4.0 * m)
+def oracle_cost_terms(nx, ny, m):
+    """The two terms of the oracle's cyclic column-block solve for S and the
+    gradient, in complex MACs: two solves (forward, weighted adjoint), each
+    eliminating nx column blocks of size ny (a grid term ~ nx ny^3: the block
+    LU and the border updates) against m right-hand sides (a channel term
+    ~ nx ny^2 m: triangular solves and back substitution)."""
+    return 2.0 * nx * ny ** 3, 2.0 * nx * ny ** 2 * m
 
 
-def cpu_baseline(prob_full):
-    """Oracle on a 960-column strip of the same layout and eps recipe."""
-    import numpy as np  # noqa: F401
+def cpu_model_name():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_strip_seconds(workload, nx, dx_over_lambda):
+    """Oracle S + gradient (forward solve, objective, weighted adjoint solve,
+    contraction) on an nx-wide strip of the workload's layout and eps recipe;
+    the channel set follows the workload (all orders, or sin < 0.95) at the
+    given grid step, which sets the channel count."""
+    import numpy as np
     from paper_2306_09257_amd import inputs
     import oracle.apf as oapf
+    import oracle.fdfd as ofd
+    import oracle.objectives as oobj
+    multi = WORKLOADS[workload]["kind"] == "multiangle"
+    orders = inputs.channel_orders(nx, dx_over_lambda, sin_max=0.95 if multi else 1.0)
+    prob = inputs.make_problem(nx, 160, dx_over_lambda=dx_over_lambda, in_orders=orders)
+    rng = np.random.default_rng(WORKLOADS[workload]["seed"])
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    w = inputs.weights_uniform(prob, rng)
+    t0 = time.perf_counter()
+    solver = oapf.make_solver(prob, eps, "column")
+    Y = oapf.forward_fields(prob, solver)
+    S = ofd.projection_row(prob) @ Y[prob.prj_row]
+    if multi:
+        _, G = oobj.group_fom(S, prob.in_orders, prob.out_orders, max(1, round(nx * dx_over_lambda / 24)))
+    else:
+        _, G = oapf.weighted_power(S, w)
+    Lam = oapf.adjoint_fields(prob, solver, G)
+    oapf.gradient_from_fields(prob, Y, Lam)
+    return time.perf_counter() - t0, prob
+
+
+def cpu_baseline(prob_full, workload):
+    """The oracle timed on three strips of the workload (same layout, eps
+    recipe and objective): a 480-wide strip at the workload's grid step, the
+    same strip at dx = lambda/5 (four times the channels, so that the channel
+    term dominates) -- these two fix the coefficients of the grid and the
+    channel term -- and a 960-wide strip at the workload's step, on which the
+    fitted model is checked.  The fitted model then gives the full
+    workload's time."""
+    import numpy as np
     try:
         from threadpoolctl import threadpool_info
         cores = max(i["num_threads"] for i in threadpool_info()) if threadpool_info() else os.cpu_count()
     except Exception:
         cores = os.cpu_count()
-    nx_s = 960
-    prob, eps, w = inputs.metasurface_wide(seed=1, nx=nx_s)
-    t0 = time.perf_counter()
-    oapf.solve_S_and_grad(prob, eps, w=w, solver=oapf.make_solver(prob, eps, "column"))
-    dt = time.perf_counter() - t0
-    scale = oracle_cost_model(prob_full.nx, prob_full.ny, prob_full.n_in) / \
-        oracle_cost_model(prob.nx, prob.ny, prob.n_in)
+    dx = 0.05
+    pts = []
+    for nx, d in ((480, dx), (480, 0.2), (960, dx)):
+        t, p = _oracle_strip_seconds(workload, nx, d)
+        pts.append((nx, p.n_in, t, oracle_cost_terms(nx, p.ny, p.n_in)))
+    M = np.array([pts[0][3], pts[1][3]])
+    a, b = np.linalg.solve(M, np.array([pts[0][2], pts[1][2]]))
+    pred = a * pts[2][3][0] + b * pts[2][3][1]
+    check_err = (pred - pts[2][2]) / pts[2][2]
+    ga, gb = oracle_cost_terms(prob_full.nx, prob_full.ny, prob_full.n_in)
+    t_full = a * ga + b * gb
     return {
-        "value": 1.0 / (dt * scale), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-        "sample": f"oracle S+grad on a {nx_s}x{prob.ny} strip ({prob.n_in} channels) of the same "
-                  f"layout and eps recipe: {dt:.2f} s; scaled by the oracle's cost model "
-                  f"2*nx*ny^2*(4.3*ny+4*M) (x{scale:.0f}) to the full workload",
-        "sample_seconds": dt,
+        "value": 1.0 / t_full, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+        "cpu_model": cpu_model_name(),
+        "sample": "oracle S+grad on strips of the same layout, eps recipe and objective: "
+                  + "; ".join(f"{nx}x160 with {m} channels {t:.2f} s" for nx, m, t, _ in pts)
+                  + f"; model t = a*2*nx*ny^3 + b*2*nx*ny^2*M fitted on the first two "
+                  f"(a = {a:.3e} s, b = {b:.3e} s per complex MAC), off by {100 * check_err:+.1f}% on the "
+                  f"third; full workload {t_full:.0f} s ({ga:.2e} + {gb:.2e} MAC)",
+        "sample_seconds": sum(t for _, _, t, _ in pts),
+        "model_check_rel_err": check_err,
     }
 
 
@@ -196,7 +256,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="metasurface_24000x160", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="multiangle_48000x160", choices=sorted(WORKLOADS))
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -276,11 +336,16 @@ def main():
     ms_step = 1e3 * dt / args.steps
     value = args.steps / dt
 
-    cm = {k: apf.query("gemm_cmacs_" + k) for k in ("factor", "schur", "sweep")}
+    cm = {k: apf.query("gemm_cmacs_" + k) for k in ("factor", "schur", "sweep", "k3", "lowrank_w")}
     gemm_ms = (prof["gemm_factor"][0] + prof["gemm_schur"][0] + prof["gemm_sweep"][0]) / args.steps
     gemm_launches = (prof["gemm_factor"][1] + prof["gemm_schur"][1] + prof["gemm_sweep"][1]) / args.steps
-    gemm_flop = 8.0 * (cm["factor"] + cm["schur"] + cm["sweep"])
+    gemm_cm = cm["factor"] + cm["schur"] + cm["sweep"]
+    gemm_flop = 8.0 * gemm_cm
     achieved = gemm_flop / (gemm_ms * 1e-3) / 1e12
+    # flops the MFMA units execute: 6 per complex MAC of the three-product
+    # form (FP64 deep lists and the low-rank W kernel), 8 elsewhere
+    k3 = cm["k3"] if args.precision == "fp64" else cm["lowrank_w"]
+    executed = (8.0 * (gemm_cm - k3) + 6.0 * k3) / (gemm_ms * 1e-3) / 1e12
     peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "mixed" else FP64_MFMA_PEAK_TFLOPS
     traffic, traffic_note = profiled_traffic(args.workload, args.precision)
     roofline = {
@@ -291,6 +356,8 @@ def main():
         "traffic_source": traffic_note,
         "flop_per_step": gemm_flop, "launches_per_step": gemm_launches,
         "avg_launch_ms": gemm_ms / max(gemm_launches, 1),
+        "executed": executed, "executed_frac": executed / peak,
+        "executed_note": "MFMA flops issued: 6 per complex MAC in the three-product form, 8 otherwise",
     }
     phases = {c: round(prof_all[c][0], 3) for c in prof_all}
 
@@ -319,7 +386,7 @@ def main():
             "S": float(torch.linalg.norm(S_m - S64) / torch.linalg.norm(S64)),
             "grad": float(torch.linalg.norm(g_m - g64) / torch.linalg.norm(g64))}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(prob, args.workload)
     print(json.dumps(out), flush=True)
 
 

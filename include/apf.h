@@ -266,6 +266,10 @@ const char *apf_last_error(void);
  *   "gemm_cmacs_schur", "gemm_cmacs_sweep" (complex multiply-adds of the
  *   GEMM tasks of one call whose operands are structurally nonzero: the
  *   stored triangle of a triangular factor, no tile padding),
+ *   "gemm_cmacs_k3" (the part of those three that the FP64 path runs in the
+ *   three-product complex form, 6 real flops per complex multiply-add
+ *   instead of 8), "gemm_cmacs_lowrank_w" (the part run by the low-rank W
+ *   kernel, three-product on both paths),
  *   "lowrank_fronts" and "lowrank_roots" (sweep fronts served by the
  *   low-rank subtree products, and the subtrees' roots);
  *   with profiling on: "ms_<class>" and "launches_<class>", the summed

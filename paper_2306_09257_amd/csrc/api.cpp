@@ -168,6 +168,10 @@ struct Profiler {
 struct Plan {
   int device = -1;
   double gemm_cmacs_factor = 0, gemm_cmacs_schur = 0, gemm_cmacs_sweep = 0;
+  // of those, the complex MACs the FP64 path runs in the three-product form
+  // (6 real flops each instead of 8), and those of the low-rank W kernel
+  // (always three-product, also on the mixed path)
+  double gemm_cmacs_k3 = 0, gemm_cmacs_w = 0;
   cplx *ws = nullptr, *fs = nullptr, *sb = nullptr, *sc = nullptr, *X = nullptr, *V = nullptr, *aval = nullptr;
   int32_t *perms = nullptr;   // pivot permutation of every front, at its first elimination index
   char *blob = nullptr;
@@ -794,7 +798,7 @@ static void build_plan(apf_handle *H) {
   std::vector<GemmTask> vinit;
   std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
-  double cm_factor = 0, cm_sweep = 0, cm_wprop = 0;
+  double cm_factor = 0, cm_sweep = 0, cm_wprop = 0, cm_w = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
     const FrontDev &D = fd[f];
@@ -932,6 +936,7 @@ static void build_plan(apf_handle *H) {
         tw.arowmap = bm;
         tw.browmap = bm;
         g_cmacs_acc += (double)b * b * ch;
+        cm_w += (double)b * b * Mi;
         swW[lvl].push_back(tw);
       }
       if (wcov[f]) {
@@ -974,12 +979,14 @@ static void build_plan(apf_handle *H) {
   }
   // weighted adjoint source of every sweep front with C rows in one GEMM:
   // V[vmap[r]] = XC[r] G, rows scattered through the permutation map
+  double cm_vinit = 0;
   if (P.xc_rows) {
     g_cmacs_acc = 0;
     GemmTask ti = gemm(P.xc, Mo, nullptr, Mi, P.V, P.rhs_chunk, (int)P.xc_rows, P.rhs_chunk, Mo, G_B_EXT | G_B_COFF);
     ti.crowmap = P.vmap;
     add_tiles_xcd(vinit, ti);
-    cm_sweep += g_cmacs_acc * ((double)Mi / P.rhs_chunk);
+    cm_vinit = g_cmacs_acc * ((double)Mi / P.rhs_chunk);
+    cm_sweep += cm_vinit;
   }
   P.gemm_cmacs_factor = cm_factor;
   P.gemm_cmacs_sweep = cm_sweep + cm_wprop;
@@ -1002,6 +1009,12 @@ static void build_plan(apf_handle *H) {
 
   // ---- assemble the blob ------------------------------------------------------
   Blob &bl = ib;  // continue after the integer arrays
+  auto list_cmacs = [](const std::vector<GemmTask> &v) {
+    double c = 0.0;
+    for (const GemmTask &T : v) c += tile_cmacs(T, T.tm, T.tn);
+    return c;
+  };
+  double cm_k3 = P.gemm_cmacs_schur + cm_vinit;   // always three-product
   for (int lvl = 0; lvl <= H_; ++lvl) {
     LevelTasks &L = P.lv[lvl];
     L.zero = bl.add(zr[lvl]); L.nzero = (int)zr[lvl].size();
@@ -1010,6 +1023,9 @@ static void build_plan(apf_handle *H) {
     L.deep1 = mark_deep(g1[lvl]);
     L.deep2 = mark_deep(g2[lvl]);
     L.deep2b = mark_deep(g2b[lvl]);
+    if (L.deep1) cm_k3 += list_cmacs(g1[lvl]);
+    if (L.deep2) cm_k3 += list_cmacs(g2[lvl]);
+    if (L.deep2b) cm_k3 += list_cmacs(g2b[lvl]);
     L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
     L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
     L.g2b = bl.add(g2b[lvl]); L.ng2b = (int)g2b[lvl].size();
@@ -1022,6 +1038,7 @@ static void build_plan(apf_handle *H) {
     if (H_ - t >= 0) m.insert(m.end(), swY[H_ - t].begin(), swY[H_ - t].end());
     if (H_ - t + 1 <= H_) m.insert(m.end(), swL[H_ - t + 1].begin(), swL[H_ - t + 1].end());
     P.swl_deep[t] = mark_deep(m);
+    if (P.swl_deep[t]) cm_k3 += list_cmacs(m) * ((double)Mi / P.rhs_chunk);
     P.swl[t] = bl.add(m);
     P.nswl[t] = (int)m.size();
   }
@@ -1037,6 +1054,8 @@ static void build_plan(apf_handle *H) {
   for (int l = 0; l <= H_; ++l) {
     P.wu_deep[l] = mark_deep(wuL[l]);
     P.wq_deep[l] = mark_deep(wqL[l]);
+    if (P.wu_deep[l]) cm_k3 += list_cmacs(wuL[l]);
+    if (P.wq_deep[l]) cm_k3 += list_cmacs(wqL[l]);
     P.wu[l] = bl.add(wuL[l]); P.nwu[l] = (int)wuL[l].size();
     P.wq[l] = bl.add(wqL[l]); P.nwq[l] = (int)wqL[l].size();
     P.wp[l] = bl.add(wpL[l]); P.nwp[l] = (int)wpL[l].size();
@@ -1045,6 +1064,8 @@ static void build_plan(apf_handle *H) {
   // deep: always the three-product form
   for (GemmTask &T : gSsplit) T.flags |= G_K3;
   for (GemmTask &T : vinit) T.flags |= G_K3;
+  P.gemm_cmacs_k3 = cm_k3 + cm_w;
+  P.gemm_cmacs_w = cm_w;
   P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
   P.vmap_base = bl.add(vmap_base);
@@ -1617,6 +1638,8 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
   else if (k == "gemm_cmacs_factor") *value = h->planned ? h->plan.gemm_cmacs_factor : -1.0;
   else if (k == "gemm_cmacs_schur") *value = h->planned ? h->plan.gemm_cmacs_schur : -1.0;
   else if (k == "gemm_cmacs_sweep") *value = h->planned ? h->plan.gemm_cmacs_sweep : -1.0;
+  else if (k == "gemm_cmacs_k3") *value = h->planned ? h->plan.gemm_cmacs_k3 : -1.0;
+  else if (k == "gemm_cmacs_lowrank_w") *value = h->planned ? h->plan.gemm_cmacs_w : -1.0;
   else if (k.rfind("ms_", 0) == 0 || k.rfind("launches_", 0) == 0) {
     bool ms = k[0] == 'm';
     std::string cls = k.substr(ms ? 3 : 9);
