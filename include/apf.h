@@ -154,6 +154,22 @@ apf_status apf_weighted_power(apf_handle *h, const double *S_dev,
                               const double *w_dev, double *f_dev,
                               double *dfdS_dev, void *stream);
 
+/* The same objective as apf_weighted_power, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): no handle, no library allocation, no allocating library
+ * call.  The reduction's block partials (at most 1024 doubles) live in a
+ * static device array of the library, one per GPU, looked up on the first
+ * call on each device (with that device current).
+ *   S_dev, dfdS_dev: complex128 [n]; w_dev: float64 [n]; f_dev: one float64.
+ *   Writes f = sum w |S|^2 and dF/dS = w conj(S), summed in the same order as
+ *   apf_weighted_power for the same n.
+ * APF_EINVAL for a null pointer or n outside [1, 2^40]; APF_EHIP if the
+ * launch fails.  Every call on one GPU uses that GPU's single scratch array:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be serialised by the caller. */
+apf_status apf_weighted_power_noalloc(const double *S_dev, const double *w_dev, int64_t n,
+                                      double *f_dev, double *dfdS_dev, void *stream);
+
 /* Objective helper for the beam-splitter figure of merit (Sec. 3, Eq. (5)):
  *   f = sum_nm (|S_nm|^2 - t_nm)^2,  t_nm = t1 where the output order minus
  *   the input order is +-1 (the +-1 diffraction orders; the paper's t1 is

@@ -28,7 +28,7 @@ APF_MIXED = 1
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
                 "apf_weighted_power", "apf_splitter_fom", "apf_group_fom", "apf_ridges_eps", "apf_ridges_grad",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
-                "apf_last_error", "apf_query", "apf_front")
+                "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow")
 
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_factor_schur.argtypes = [vp, i32, vp, vp]
     lib.apf_factor_schur_batched.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp), vp]
     lib.apf_weighted_power.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.apf_weighted_power_noalloc.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
     lib.apf_splitter_fom.argtypes = [vp, vp, dbl, vp, vp, vp]
     lib.apf_group_fom.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     lib.apf_ridges_eps.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
@@ -247,6 +248,22 @@ class APF:
             self.close()
         except Exception:
             pass
+
+
+def weighted_power_noalloc(S, w, f=None, G=None):
+    """f = sum w |S|^2 and dF/dS = w conj(S) through the allocation-free entry
+    point (no handle; the outputs are the caller's: pass f and G to keep the
+    call free of allocations)."""
+    import torch
+    lib = load_library()
+    assert S.dtype == torch.complex128 and S.is_contiguous() and w.dtype == torch.float64 and w.is_contiguous()
+    assert S.numel() == w.numel()
+    if f is None:
+        f = torch.empty((), dtype=torch.float64, device=S.device)
+    if G is None:
+        G = torch.empty_like(S)
+    _check(lib.apf_weighted_power_noalloc(_ptr(S), _ptr(w), S.numel(), _ptr(f), _ptr(G), _stream()))
+    return f, G
 
 
 def factor_schur_batched(apfs, S_list=None, precision: int = APF_FP64):

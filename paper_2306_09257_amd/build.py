@@ -12,7 +12,7 @@ ARCH = "gfx950"
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST_FLAGS = ["-x", "c++", "-O2", "-std=c++17", "-fPIC", "-I/opt/rocm/include"]
-SOURCES = [("kernels.hip", True), ("api.cpp", False), ("analyze.cpp", False)]
+SOURCES = [("kernels.hip", True), ("noalloc.hip", True), ("api.cpp", False), ("analyze.cpp", False)]
 
 
 def build(verbose=False):

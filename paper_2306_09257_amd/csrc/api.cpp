@@ -27,6 +27,13 @@ apf_status fail(apf_status s, const std::string &msg) {
   return s;
 }
 
+}  // namespace
+
+// the thread-local message, for entry points defined in other sources
+void apf_set_error(const std::string &msg) { g_err = msg; }
+
+namespace {
+
 struct HipError : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
@@ -1438,7 +1445,7 @@ extern "C" apf_status apf_weighted_power(apf_handle *h, const double *S_dev, con
   if (!h->planned) return fail(APF_ESTATE, "apf_assemble has not run");
   return guarded([&]() -> apf_status {
     int64_t n = (int64_t)h->d.n_in * h->d.n_out;
-    int npart = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    int npart = weighted_power_parts(n);
     hipStream_t s = (hipStream_t)stream;
     Profiler &pr = h->prof;
     pr.run(P_WPOW, s, [&] {

@@ -34,6 +34,8 @@ hipError_t launch_reduce_partials(const double *part, int nblk, int64_t n, doubl
                                   hipStream_t s);
 hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx *G, int64_t n, double *part,
                                  int npart, hipStream_t s);
+// block partials of the weighted-power reduction for n entries (<= 1024)
+int weighted_power_parts(int64_t n);
 
 // beam-splitter workload: Eq. (5) figure of merit, ridge permittivity and
 // the chain rule to the edge positions (see include/apf.h)
