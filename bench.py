@@ -262,8 +262,11 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
-                    help="mixed: front GEMMs and sweeps on FP32 MFMA (FP64 storage, pivots, reductions)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "refined"],
+                    help="mixed: front GEMMs and sweeps on FP32 MFMA (FP64 storage, pivots, reductions); "
+                         "refined: the mixed factorization plus FP64 iterative refinement of the forward and "
+                         "adjoint fields")
+    ap.add_argument("--refine-iters", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the APF path here is a "
@@ -291,6 +294,8 @@ def main():
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     apf = binding.APF(prob, leaf_size=args.leaf).analyze()
+    if args.precision == "refined":
+        apf.set_refinement(args.refine_iters, 1e-10)
     t_an = time.perf_counter() - t0
     dev = torch.device("cuda:0")
     eps_d = torch.as_tensor(eps, dtype=torch.float64, device=dev).contiguous()
@@ -299,7 +304,7 @@ def main():
     S = torch.empty((prob.n_out, prob.n_in), dtype=torch.complex128, device=dev)
     grad = torch.empty((prob.n_design_rows, prob.nx), dtype=torch.float64, device=dev)
 
-    prec = binding.APF_MIXED if args.precision == "mixed" else binding.APF_FP64
+    prec = {"fp64": binding.APF_FP64, "mixed": binding.APF_MIXED, "refined": binding.APF_MIXED_REFINED}[args.precision]
 
     def step():
         apf.assemble(eps_d)
@@ -337,8 +342,14 @@ def main():
     value = args.steps / dt
 
     cm = {k: apf.query("gemm_cmacs_" + k) for k in ("factor", "schur", "sweep", "k3", "lowrank_w")}
-    gemm_ms = (prof["gemm_factor"][0] + prof["gemm_schur"][0] + prof["gemm_sweep"][0]) / args.steps
-    gemm_launches = (prof["gemm_factor"][1] + prof["gemm_schur"][1] + prof["gemm_sweep"][1]) / args.steps
+    # the refined path runs neither the Schur product nor the sweeps of the
+    # plain paths (its S and gradient come from the refined fields): its
+    # roofline covers the factorization GEMMs only
+    classes = ("gemm_factor",) if args.precision == "refined" else ("gemm_factor", "gemm_schur", "gemm_sweep")
+    if args.precision == "refined":
+        cm["schur"] = cm["sweep"] = cm["lowrank_w"] = 0.0
+    gemm_ms = sum(prof[c][0] for c in classes) / args.steps
+    gemm_launches = sum(prof[c][1] for c in classes) / args.steps
     gemm_cm = cm["factor"] + cm["schur"] + cm["sweep"]
     gemm_flop = 8.0 * gemm_cm
     achieved = gemm_flop / (gemm_ms * 1e-3) / 1e12
@@ -346,11 +357,11 @@ def main():
     # form (FP64 deep lists and the low-rank W kernel), 8 elsewhere
     k3 = cm["k3"] if args.precision == "fp64" else cm["lowrank_w"]
     executed = (8.0 * (gemm_cm - k3) + 6.0 * k3) / (gemm_ms * 1e-3) / 1e12
-    peak = FP32_MFMA_PEAK_TFLOPS if args.precision == "mixed" else FP64_MFMA_PEAK_TFLOPS
+    peak = FP64_MFMA_PEAK_TFLOPS if args.precision == "fp64" else FP32_MFMA_PEAK_TFLOPS
     traffic, traffic_note = profiled_traffic(args.workload, args.precision)
     roofline = {
         "kernel": "k_gemm / k_gemm_k3 / k_lowrank_w (batched complex %s MFMA GEMMs, all launches of a step)"
-                  % ("FP32" if args.precision == "mixed" else "FP64"),
+                  % ("FP64" if args.precision == "fp64" else "FP32"),
         "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
         "frac": achieved / peak, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
         "traffic_source": traffic_note,
@@ -365,7 +376,8 @@ def main():
         "metric": "APF solves/sec (S+grad f) at N unknowns, M channels",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c128 (f64)", "data": "synthetic",
+        "dtype": {"fp64": "c128 (f64)", "mixed": "c64 (f32) front GEMMs, f64 storage",
+                  "refined": "c64 (f32) front GEMMs + f64 refinement"}[args.precision], "data": "synthetic",
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "unknowns": prob.nx * prob.ny,
                    "n_in": prob.n_in, "n_out": prob.n_out, "design_pixels": prob.n_design_rows * prob.nx,
                    "precision": args.precision, "leaf_size": args.leaf or 48},
@@ -374,8 +386,13 @@ def main():
         "analysis_s": t_an,
         "factor_cmacs_algorithmic": apf.query("algo_factor_cmacs"),
     }
-    if args.precision == "mixed":
-        # accuracy of the unrefined mixed result against the FP64 path
+    if args.precision == "refined":
+        out["refine"] = {"chunk": apf.query("refine_chunk"), "residual_first": apf.query("refine_residual_first"),
+                         "residual_final": apf.query("refine_residual"),
+                         "retained_factor_bytes": apf.query("retained_factor_bytes"),
+                         "ms_refine_per_step": prof_all["refine"][0]}
+    if args.precision in ("mixed", "refined"):
+        # accuracy of the mixed result against the FP64 path
         S_m, g_m = S.clone(), grad.clone()
         apf.assemble(eps_d)
         S64 = apf.factor_schur(precision=binding.APF_FP64)

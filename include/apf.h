@@ -58,13 +58,22 @@ typedef enum {
 
 typedef enum {
   APF_FP64 = 0,        /* every front operation in complex FP64            */
-  APF_MIXED = 1        /* front GEMMs and sweeps on FP32 MFMA (operands
+  APF_MIXED = 1,       /* front GEMMs and sweeps on FP32 MFMA (operands
                           rounded to FP32, FP32 accumulation); pivot blocks,
                           storage, the S / gradient reductions and the
                           low-rank subtree products in FP64; no iterative
                           refinement: the result carries the FP32 rounding
                           amplified by ill-conditioned pivot blocks
                           (measured 1e-6 .. 4e-4 relative)                 */
+  APF_MIXED_REFINED = 2 /* the APF_MIXED factorization, then FP64 iterative
+                          refinement of the M_in forward fields A^-1 B (in
+                          apf_factor_schur) and of the M_in weighted adjoint
+                          fields A^-1 (C^T dF/dS) (in apf_grad): residuals
+                          r - A x from the FP64 stencil, corrections by
+                          full solves with the FP32-computed factors of every
+                          front, S = C x and the gradient contraction in
+                          FP64.  Needs apf_set_refinement before the first
+                          apf_assemble; not for the batched factorization */
 } apf_precision;
 
 typedef struct apf_handle apf_handle;
@@ -117,8 +126,10 @@ apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *stream);
 /* Numeric multifrontal partial factorization of K = [A, B; C, 0] (Sec. 2):
  * eliminates every grid unknown and writes the Schur-complement block as
  *   S_dev: complex128 [n_out][n_in],  S = C A^-1 B.
- * prec: APF_FP64 or APF_MIXED (see apf_precision); apf_grad then runs its
- * sweeps in the same precision.
+ * prec: APF_FP64, APF_MIXED or APF_MIXED_REFINED (see apf_precision); apf_grad
+ * then runs in the same precision.  APF_MIXED_REFINED returns APF_ENOTCONV
+ * when the refinement misses its tolerance (S is then the last iterate's,
+ * and apf_grad may still run).
  * The factors are kept on the handle for apf_grad.  Synchronises `stream` at
  * the end to read the device status words: APF_EINVAL if the last assembled
  * permittivity had a zero or non-finite value, APF_ESINGULAR if a pivot block
@@ -223,7 +234,11 @@ apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, int32_t n_edg
                            const double *grad_eps_dev, double *grad_edges_dev,
                            void *stream);
 
-/* Gradient of a real objective f(S) with respect to the permittivity of every
+/* (APF_MIXED_REFINED: the adjoint fields are refined like the forward ones,
+ * the call synchronises `stream` at its end to check the residuals and
+ * returns APF_ENOTCONV when they miss the tolerance; grad_dev then holds the
+ * gradient of the last iterate.)
+ * Gradient of a real objective f(S) with respect to the permittivity of every
  * design pixel (Sec. 2, Eq. (1) with dS/deps_k of Eq. (3), U_k = e_k and
  * Sigma_k = dA_kk/deps_k = -h^2):
  *   df/deps_k = sum_nm 2 Re(dF/dS_nm dS_nm/deps_k)
@@ -242,6 +257,19 @@ apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev,
  * memory the handle takes.  Call before the first apf_assemble (else
  * APF_ESTATE); APF_EINVAL unless max_chunk is 0 or a positive multiple of 64. */
 apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk);
+
+/* Enable (max_iter >= 1) or disable (0, the default) APF_MIXED_REFINED on
+ * this handle: the plan then keeps the triangular inverses, L21 and
+ * X12 = U^-1 U12 of every front (not only of the fronts the gradient sweeps
+ * visit), two N x rc field arrays, the forward fields of the design pixels
+ * (design pixels x n_in) and the channel rows of B and C; rc, the
+ * refinement's right-hand-side chunk, comes from the free memory and the cap
+ * of apf_set_rhs_chunk.  A refined call runs the first solve and max_iter
+ * corrections per chunk and returns APF_ENOTCONV when the final residual
+ * |r - A x| / |r| of some chunk exceeds tol (0 < tol < 1); the fields are then
+ * the last iterate.  Call before the first apf_assemble (else APF_ESTATE);
+ * APF_EINVAL for max_iter outside [0, 16] or a bad tol. */
+apf_status apf_set_refinement(apf_handle *h, int32_t max_iter, double tol);
 
 /* Allow (on = 1, the default) or forbid (on = 0) the low-rank sweep
  * subtrees: channel-free sweep subtrees of up to two levels whose gradient
@@ -269,6 +297,10 @@ apf_status apf_destroy(apf_handle *h);
 const char *apf_last_error(void);
 
 /* Read a named statistic of an analysed handle (host only):
+ *   "refine_chunk" (right-hand-side chunk of the refined solves, -1 before
+ *   the plan), "refine_residual" and "refine_residual_first" (largest final
+ *   and first-solve relative residual over the chunks of the last refined
+ *   call), "retained_factor_bytes" (factors kept for the refinement),
  *   "n_fronts", "n_levels", "max_front" (largest p+b), "n_factorizations"
  *   (factorizations run on the handle so far, failed ones included: a caller
  *   that keeps the factors for a later apf_grad can tell whether they were

@@ -24,13 +24,14 @@ APF_ENOTCONV = -5
 APF_ESTATE = -6
 APF_FP64 = 0
 APF_MIXED = 1
+APF_MIXED_REFINED = 2
 
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
                 "apf_weighted_power", "apf_splitter_fom", "apf_group_fom", "apf_ridges_eps", "apf_ridges_grad",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
-                "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc")
+                "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
-                   "contract", "wpow")
+                   "contract", "wpow", "refine")
 
 
 class APFError(RuntimeError):
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_profiling.argtypes = [vp, i32]
     lib.apf_set_rhs_chunk.argtypes = [vp, i32]
     lib.apf_set_lowrank.argtypes = [vp, i32]
+    lib.apf_set_refinement.argtypes = [vp, i32, dbl]
     lib.apf_destroy.argtypes = [vp]
     lib.apf_last_error.argtypes = []
     lib.apf_last_error.restype = ctypes.c_char_p
@@ -147,6 +149,12 @@ class APF:
     def set_lowrank(self, on: bool):
         """Allow or forbid the low-rank sweep subtrees (before the first assemble)."""
         _check(self._lib.apf_set_lowrank(self._h, 1 if on else 0))
+        return self
+
+    def set_refinement(self, max_iter: int, tol: float = 1e-10):
+        """Enable APF_MIXED_REFINED (before the first assemble): max_iter
+        corrections after the first solve, APF_ENOTCONV above tol."""
+        _check(self._lib.apf_set_refinement(self._h, int(max_iter), float(tol)))
         return self
 
     def set_profiling(self, on, gemm_only: bool = False):

@@ -141,6 +141,7 @@ enum GemmFlags : int32_t {
   G_K_LIM = 65536,         // K is limited to the launch's column limit (a right-hand-side chunk)
   G_ACC_CHUNK = 131072,    // C's old value is added when the launch's column offset is > 0
   G_K3 = 262144,           // complex products in the three-product form (launched on the deep-K kernel)
+  G_C_COFF = 524288,       // add the launch's column offset to C
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B (a 32 x 32 quadrant for W tasks)
@@ -162,6 +163,7 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B (a 
 };
 
 struct ZeroRange { cplx *ptr; int64_t n; };
+struct CopyRange { const cplx *src; cplx *dst; int64_t n; };   // n contiguous complex entries
 
 // A front of a low-rank sweep subtree.  A sweep front whose subtree holds no
 // channel rows has Y_piv = -X12 Y_bnd and Lam_piv[perm[k]] = -(Z^T Lam_bnd)[k]

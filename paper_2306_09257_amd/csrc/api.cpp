@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -115,9 +116,9 @@ constexpr int64_t SPLIT_K = 4096;      // k rows per partial block of the split 
 
 // Per-class HIP-event timing of the launches (off unless enabled).
 enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
-                 P_CONTRACT, P_WPOW, P_NCLASS };
+                 P_CONTRACT, P_WPOW, P_REFINE, P_NCLASS };
 const char *const kProfNames[P_NCLASS] = {"stencil", "zero", "assemble", "inverse", "gemm_factor",
-                                          "gemm_schur", "gemm_sweep", "contract", "wpow"};
+                                          "gemm_schur", "gemm_sweep", "contract", "wpow", "refine"};
 
 struct Profiler {
   bool on = false;
@@ -172,8 +173,45 @@ struct Profiler {
   }
 };
 
+// Iterative refinement of the mixed path (APF_MIXED_REFINED): a full solve
+// with the factors of every front, level by level like the factorization's
+// channel panels (forward: y1 = L^-1 P^T r1 and the children's updates
+// r2 - L21 y1 written into the parent's front-local rows; backward:
+// x1 = U^-1 y1 - X12 x2 in place, root to leaves), on right-hand-side chunks
+// of rc columns held in elimination order.
+struct RefineLevel {
+  int64_t zero = -1, copy = -1, g1 = -1, g2 = -1, g2b = -1, bk = -1;
+  int nzero = 0, ncopy = 0, ng1 = 0, ng2 = 0, ng2b = 0, nbk = 0;
+};
+
+struct Refine {
+  int iters = 0;               // corrections after the first solve
+  double tol = 0.0;            // bound on the final relative residual
+  int rc = 0;                  // right-hand-side chunk (columns)
+  int nchunks = 0;
+  int64_t ss_elems = 0;
+  cplx *ss = nullptr;          // retained factors of every front: tri, L21 and (non-sweep fronts) X12
+  cplx *X = nullptr, *W = nullptr;      // N x rc: solution, residual / correction (elimination order)
+  cplx *arena = nullptr;       // front-local right-hand-side panels and y1 blocks
+  int64_t arena_elems = 0;
+  cplx *Bmat = nullptr;        // nx x n_in: the source row of B
+  cplx *Cmat = nullptr;        // n_out x nx: the projection row of C
+  cplx *rowbuf = nullptr;      // nx x rc: C^T dF/dS of one chunk (the adjoint right-hand side)
+  cplx *Ydes = nullptr;        // design pixels x n_in: refined forward fields, kept for the gradient
+  int32_t *elim = nullptr;     // node -> elimination index
+  double *norms = nullptr;     // per chunk: (iters + 2) squared residual norms
+  char *blob = nullptr;
+  std::vector<RefineLevel> lv;
+  int64_t sgemm = -1, agemm = -1, erow_des = -1;
+  int nsgemm = 0, nagemm = 0;
+  double last_res = 0.0, last_res1 = 0.0;   // last call: final and first-solve relative residuals (max over chunks)
+  template <class T>
+  T *at(int64_t off) const { return off < 0 ? nullptr : reinterpret_cast<T *>(blob + off); }
+};
+
 struct Plan {
   int device = -1;
+  Refine R;
   double gemm_cmacs_factor = 0, gemm_cmacs_schur = 0, gemm_cmacs_sweep = 0;
   // of those, the complex MACs the FP64 path runs in the three-product form
   // (6 real flops each instead of 8), and those of the low-rank W kernel
@@ -337,6 +375,8 @@ struct Off {
   int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, tri = -1, u12 = -1, l21 = -1, u1b = -1, lc1t = -1;
   int64_t fs_x12 = -1, fs_z = -1, fs_x1b = -1, xk = -1, sk = -1;
   int64_t wsz = 0;
+  // refinement: retained tri, L21 and (fronts outside the sweeps) X12
+  int64_t ss_tri = -1, ss_l21 = -1, ss_x12 = -1;
 };
 
 }  // namespace
@@ -355,6 +395,9 @@ struct apf_handle {
   int max_chunk = 0;    // cap on the right-hand-side chunk of the sweeps (0: memory decides)
   bool lowrank = true;  // low-rank sweep subtrees allowed
   int64_t n_factor = 0; // factorizations run on this handle (a caller can tell whether the factors changed)
+  int refine_iters = 0; // > 0: the plan keeps every front's factors for APF_MIXED_REFINED
+  double refine_tol = 0.0;
+  bool refined = false; // the factors held come from APF_MIXED_REFINED (apf_grad refines too)
 };
 
 // ---------------------------------------------------------------------------
@@ -449,7 +492,7 @@ static void size_plan(apf_handle *H) {
   o.assign(nf, Off());
   Arena ar;
   std::vector<std::vector<int>> release_at(H_ + 2);
-  int64_t fs = 0, ktot = 0, xck = 0;
+  int64_t fs = 0, ktot = 0, xck = 0, ss = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
     int64_t p = F.p(), b = F.b(), n = p + b, mB = F.hasB ? Mi : 0, mC = F.hasC ? Mo : 0;
@@ -471,6 +514,13 @@ static void size_plan(apf_handle *H) {
       if (mC) { q.xk = xck; xck += p; }
     }
     if (F.sfront) { q.sk = ktot; ktot += p; }
+    if (H->refine_iters > 0) {
+      q.ss_tri = ss; ss += up(p * p);
+      if (b) {
+        q.ss_l21 = ss; ss += up(b * p);
+        if (!F.sweep) { q.ss_x12 = ss; ss += up(p * b); }
+      }
+    }
   }
   // lifetime allocation, level by level: a front's workspace is taken at its
   // first child's level and given back after its own level
@@ -494,6 +544,7 @@ static void size_plan(apf_handle *H) {
   }
   P.ws_elems = std::max<int64_t>(ar.top, 1);
   P.fs_elems = std::max<int64_t>(fs, 1);
+  P.R.ss_elems = ss;
   P.xc_rows = xck;
   S.k_total = ktot;
 }
@@ -534,6 +585,225 @@ static bool any_k3(const std::vector<GemmTask> &v) {
   return false;
 }
 
+// Device plan of the refined solves (after the main plan, whose channel
+// parameters, permutations and retained factors it uses).  The chunk rc is
+// taken from the free memory (two N x rc field arrays, the front-local panel
+// arena, the adjoint row buffer), capped by apf_set_rhs_chunk's cap.
+static void build_refine(apf_handle *H) {
+  Symbolic &S = H->sym;
+  const Desc &d = H->d;
+  Plan &P = H->plan;
+  Refine &R = P.R;
+  const std::vector<Off> &o = H->off;
+  const int nf = (int)S.fronts.size();
+  const int H_ = (int)S.levels.size() - 1;
+  const int Mi = d.n_in, Mo = d.n_out, nx = d.nx;
+  const int64_t N = (int64_t)d.nx * d.ny;
+  R.iters = H->refine_iters;
+  R.tol = H->refine_tol;
+
+  // element maps, channel matrices, kept forward fields
+  {
+    std::vector<int32_t> el(N);
+    for (int64_t n = 0; n < N; ++n) el[n] = (int32_t)S.node_elim[n];
+    HIPCHK(hipMalloc(&R.elim, N * sizeof(int32_t)));
+    HIPCHK(hipMemcpy(R.elim, el.data(), N * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMalloc(&R.Bmat, (int64_t)nx * Mi * sizeof(cplx)));
+  HIPCHK(hipMalloc(&R.Cmat, (int64_t)Mo * nx * sizeof(cplx)));
+  {
+    const ChanParams *cp = reinterpret_cast<const ChanParams *>(P.chan);
+    HIPCHK(launch_channel_matrices(cp, cp + 1, R.Bmat, R.Cmat, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+  }
+  HIPCHK(hipMalloc(&R.Ydes, std::max<int64_t>(P.ndesign * Mi, 1) * sizeof(cplx)));
+
+  // panel level of every front: its first child's level (its own for leaves)
+  std::vector<int> lp(nf);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    lp[f] = F.height;
+    for (int c = 0; c < F.nchild; ++c) lp[f] = std::min(lp[f], S.fronts[F.child[c]].height);
+  }
+  // arena of the front-local panels ((p + b) x rc, from the panel level to the
+  // own level) and y1 blocks (p x rc, at the own level)
+  std::vector<int64_t> pan_off(nf), y1_off(nf);
+  auto size_arena = [&](int64_t rc) -> int64_t {
+    Arena ar;
+    std::vector<std::vector<int>> alloc_at(H_ + 1), release_at(H_ + 2);
+    for (int f = 0; f < nf; ++f) alloc_at[lp[f]].push_back(f);
+    for (int lvl = 0; lvl <= H_; ++lvl) {
+      for (int f : release_at[lvl]) {
+        ar.release(pan_off[f], (int64_t)(S.fronts[f].p() + S.fronts[f].b()) * rc);
+        ar.release(y1_off[f], (int64_t)S.fronts[f].p() * rc);
+      }
+      for (int f : alloc_at[lvl]) pan_off[f] = ar.alloc((int64_t)(S.fronts[f].p() + S.fronts[f].b()) * rc);
+      for (int f : S.levels[lvl]) {
+        y1_off[f] = ar.alloc((int64_t)S.fronts[f].p() * rc);
+        release_at[lvl + 1].push_back(f);
+      }
+    }
+    return std::max<int64_t>(ar.top, 1);
+  };
+  {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    const double per_col = 2.0 * N * sizeof(cplx) + (double)nx * sizeof(cplx) +
+                           (double)size_arena(64) / 64.0 * sizeof(cplx);
+    int64_t rc = (int64_t)(0.5 * (double)fr / per_col);
+    rc = std::min<int64_t>(rc, Mi);
+    if (H->max_chunk > 0) rc = std::min<int64_t>(rc, H->max_chunk);
+    if (rc < Mi) rc = std::max<int64_t>(64, rc / 64 * 64);
+    R.rc = (int)std::max<int64_t>(rc, 1);
+  }
+  const int rc = R.rc;
+  R.arena_elems = size_arena(rc);
+  R.nchunks = (Mi + rc - 1) / rc;
+  HIPCHK(hipMalloc(&R.X, N * rc * sizeof(cplx)));
+  HIPCHK(hipMalloc(&R.W, N * rc * sizeof(cplx)));
+  HIPCHK(hipMalloc(&R.arena, R.arena_elems * sizeof(cplx)));
+  HIPCHK(hipMalloc(&R.rowbuf, (int64_t)nx * rc * sizeof(cplx)));
+  HIPCHK(hipMalloc(&R.norms, (int64_t)R.nchunks * (R.iters + 2) * sizeof(double)));
+
+  Blob bl;
+  {
+    const char pad[16] = {0};
+    bl.add(pad, sizeof pad);
+  }
+  auto PAN = [&](int f) { return R.arena + pan_off[f]; };
+  auto Y1 = [&](int f) { return R.arena + y1_off[f]; };
+  // integer arrays: boundary elimination rows, flagged parent rows, design
+  // and projection rows (offsets; rebased once the blob is allocated)
+  std::vector<int64_t> bnde_off(nf, -1), rows_off(nf, -1);
+  // writers of each front's panel rows: its own pivot rows are copied from
+  // the global array at its panel level (first writer); boundary rows are
+  // written by the children (first writer stores, later ones add)
+  std::vector<std::vector<uint8_t>> wr(nf);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    wr[f].assign(F.p() + F.b(), 0);
+    for (int k = 0; k < F.p(); ++k) wr[f][k] = 1;
+  }
+  std::vector<int> slot_of(nf, 0);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    int order[2] = {0, 1};
+    if (F.nchild == 2 && S.fronts[F.child[1]].height < S.fronts[F.child[0]].height) std::swap(order[0], order[1]);
+    for (int oc = 0; oc < F.nchild; ++oc) {
+      const int c = order[oc], cf = F.child[c];
+      const Front &Ch = S.fronts[cf];
+      slot_of[cf] = c;
+      if (Ch.b() == 0) continue;
+      std::vector<int32_t> rr;
+      for (int r = 0; r < Ch.b(); ++r) {
+        const int pr = Ch.rmap[r];
+        rr.push_back(pr | (wr[f][pr] ? EXT_ADD : 0));
+        wr[f][pr] = 1;
+      }
+      rows_off[cf] = bl.add(rr);
+    }
+    if (F.b()) {
+      std::vector<int32_t> be(F.b());
+      for (int k = 0; k < F.b(); ++k) be[k] = (int32_t)S.node_elim[F.bnd[k]];
+      bnde_off[f] = bl.add(be);
+    }
+  }
+  int64_t erow_prj = -1;
+  {
+    std::vector<int32_t> ep(nx), ed(P.ndesign);
+    for (int i = 0; i < nx; ++i) ep[i] = (int32_t)S.node_elim[(int64_t)d.prj_row * nx + i];
+    for (int y = d.design_row0; y < d.design_row1; ++y)
+      for (int x = 0; x < nx; ++x)
+        ed[(int64_t)(y - d.design_row0) * nx + x] = (int32_t)S.node_elim[(int64_t)y * nx + x];
+    erow_prj = bl.add(ep);
+    R.erow_des = bl.add(ed);
+  }
+  auto IP = [](int64_t off) { return reinterpret_cast<const int32_t *>((intptr_t)off); };   // rebased below
+
+  std::vector<std::vector<ZeroRange>> zr(H_ + 1);
+  std::vector<std::vector<CopyRange>> cr(H_ + 1);
+  std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), bk(H_ + 1);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    const Off &q = o[f];
+    const int p = F.p(), b = F.b(), lvl = F.height;
+    cplx *pan = PAN(f), *y1 = Y1(f);
+    cplx *tri = P.R.ss + q.ss_tri;
+    cplx *Wf = R.W + F.elim0 * rc;
+    for (int64_t o0 = 0; o0 < (int64_t)p * rc; o0 += ZERO_CHUNK)
+      cr[lp[f]].push_back({Wf + o0, pan + o0, std::min(ZERO_CHUNK, (int64_t)p * rc - o0)});
+    bool bnd_read = false;
+    for (int k = p; k < p + b; ++k) bnd_read = bnd_read || wr[f][k];
+    if (bnd_read)
+      for (int k = p; k < p + b;) {
+        if (wr[f][k]) { ++k; continue; }
+        int e = k + 1;
+        while (e < p + b && !wr[f][e]) ++e;
+        for (int64_t o0 = 0; o0 < (int64_t)(e - k) * rc; o0 += ZERO_CHUNK)
+          zr[lp[f]].push_back({pan + (int64_t)k * rc + o0, std::min(ZERO_CHUNK, (int64_t)(e - k) * rc - o0)});
+        k = e;
+      }
+    const int32_t *perm = P.perms + F.elim0;
+    // forward: y1 = L^-1 P^T r1; T = U^-1 y1 into the global rows; the
+    // parent's rows take r2 - L21 y1
+    add_tiles(g1[lvl], gemm(tri, p, pan, rc, y1, rc, p, rc, p, G_A_TRI_L, nullptr, 0, perm));
+    add_tiles(g2[lvl], gemm(tri, p, y1, rc, Wf, rc, p, rc, p, G_A_TRI_U));
+    if (b) {
+      const int par = F.parent;
+      GemmTask t = gemm(P.R.ss + q.ss_l21, p, y1, rc, PAN(par), rc, b, rc, p,
+                        G_NEG | (bnd_read ? G_CIN | G_CIN_OWN : 0), bnd_read ? pan + (int64_t)p * rc : nullptr, rc);
+      t.crowmap = IP(rows_off[f]);
+      add_tiles(slot_of[f] ? g2b[lvl] : g2[lvl], t);
+      // backward: x1 = T - X12 x2, in place
+      const cplx *x12 = q.ss_x12 >= 0 ? P.R.ss + q.ss_x12 : P.fs + q.fs_x12;
+      add_tiles(bk[lvl], gemm(x12, b, R.W, rc, Wf, rc, p, rc, b, G_NEG | G_CIN, Wf, rc, IP(bnde_off[f])));
+    }
+  }
+  // S columns = Cmat X[projection rows]; the adjoint rows C^T dF/dS
+  std::vector<GemmTask> sg, ag;
+  {
+    GemmTask t = gemm(R.Cmat, nx, R.X, rc, nullptr, Mi, Mo, rc, nx, G_C_EXT | G_C_COFF | G_K3, nullptr, 0,
+                      IP(erow_prj));
+    add_tiles_xcd(sg, t);
+    add_tiles_xcd(ag, gemm(R.Cmat, nx, nullptr, Mi, R.rowbuf, rc, nx, rc, Mo,
+                           G_TRANS_A | G_B_EXT | G_B_COFF | G_K3));
+  }
+  R.lv.assign(H_ + 1, RefineLevel());
+  for (int lvl = 0; lvl <= H_; ++lvl) {
+    RefineLevel &L = R.lv[lvl];
+    L.zero = bl.add(zr[lvl]); L.nzero = (int)zr[lvl].size();
+    L.copy = bl.add(cr[lvl]); L.ncopy = (int)cr[lvl].size();
+    L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
+    L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
+    L.g2b = bl.add(g2b[lvl]); L.ng2b = (int)g2b[lvl].size();
+    L.bk = bl.add(bk[lvl]); L.nbk = (int)bk[lvl].size();
+  }
+  R.sgemm = bl.add(sg); R.nsgemm = (int)sg.size();
+  R.agemm = bl.add(ag); R.nagemm = (int)ag.size();
+  HIPCHK(hipMalloc(&R.blob, bl.h.size()));
+  char *base = R.blob;
+  auto rebase = [&](const int32_t *&ptr) {
+    if (ptr) ptr = reinterpret_cast<const int32_t *>(base + (intptr_t)ptr);
+  };
+  for (int lvl = 0; lvl <= H_; ++lvl) {
+    const RefineLevel &L = R.lv[lvl];
+    for (int which = 0; which < 3; ++which) {
+      const int64_t off = which == 0 ? L.g2 : (which == 1 ? L.g2b : L.bk);
+      const int n = which == 0 ? L.ng2 : (which == 1 ? L.ng2b : L.nbk);
+      GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + off);
+      for (int k = 0; k < n; ++k) {
+        rebase(t[k].crowmap);
+        rebase(t[k].browmap);
+      }
+    }
+  }
+  {
+    GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + R.sgemm);
+    for (int k = 0; k < R.nsgemm; ++k) rebase(t[k].browmap);
+  }
+  HIPCHK(hipMemcpy(R.blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
+}
+
 static void build_plan(apf_handle *H) {
   Symbolic &S = H->sym;
   const Desc &d = H->d;
@@ -548,6 +818,7 @@ static void build_plan(apf_handle *H) {
   const int64_t ktot = S.k_total;
   HIPCHK(hipMalloc(&P.ws, P.ws_elems * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.fs, P.fs_elems * sizeof(cplx)));
+  if (H->refine_iters > 0) HIPCHK(hipMalloc(&P.R.ss, std::max<int64_t>(P.R.ss_elems, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.sb, std::max<int64_t>(ktot * Mi, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.sc, std::max<int64_t>(ktot * Mo, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.aval, (int64_t)d.nx * d.ny * 5 * sizeof(cplx)));
@@ -779,7 +1050,7 @@ static void build_plan(apf_handle *H) {
     D.bp_bnd = D.mB ? WS(q.pws + q.bp) + p * D.mB : nullptr;
     D.cpt_piv = D.mC ? WS(q.pws + q.cpiv) : nullptr;
     D.cpt_bnd = D.mC ? WS(q.pws + q.cbnd) : nullptr;
-    D.tri = WS(q.ws + q.tri);
+    D.tri = q.ss_tri >= 0 ? P.R.ss + q.ss_tri : WS(q.ws + q.tri);
     D.perm = P.perms + F.elim0;
     D.rmap = reinterpret_cast<const int32_t *>((intptr_t)rmap_off[f]);  // offset; rebased below
     D.parent = F.parent;
@@ -870,7 +1141,8 @@ static void build_plan(apf_handle *H) {
     const Off &q = o[f];
     cplx *core = D.core, *tri = D.tri;
     cplx *F12 = core + p, *F21 = core + (int64_t)p * n, *F22 = core + (int64_t)p * n + p;
-    cplx *u12 = b ? WS(q.ws + q.u12) : nullptr, *l21 = b ? WS(q.ws + q.l21) : nullptr;
+    cplx *u12 = b ? WS(q.ws + q.u12) : nullptr;
+    cplx *l21 = b ? (q.ss_l21 >= 0 ? P.R.ss + q.ss_l21 : WS(q.ws + q.l21)) : nullptr;
     cplx *u1b = mB ? U1B(f) : nullptr, *lc1t = mC ? LC1T(f) : nullptr;
     const int32_t *perm = D.perm;
     g_cmacs_acc = 0;
@@ -905,6 +1177,7 @@ static void build_plan(apf_handle *H) {
         add_tiles(gp, t);
       }
     }
+    if (q.ss_x12 >= 0) add_tiles(g2[lvl], gemm(tri, p, u12, b, P.R.ss + q.ss_x12, b, p, b, p, G_A_TRI_U));
     if (F.sweep) {
       if (b) add_tiles(g2[lvl], gemm(tri, p, u12, b, FSx(q.fs_x12), b, p, b, p, G_A_TRI_U));
       if (mB) add_tiles(g2[lvl], gemm(tri, p, u1b, mB, FSx(q.fs_x1b), mB, p, mB, p, G_A_TRI_U));
@@ -1127,12 +1400,15 @@ static void build_plan(apf_handle *H) {
   }
   (void)ib_size;
   HIPCHK(hipMemcpy(P.blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
+  if (H->refine_iters > 0) build_refine(H);
   H->planned = true;
 }
 
 static void free_plan(Plan &P) {
+  const Refine &R = P.R;
   void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
-                  P.xc, P.vmap, P.gpart, P.lrW};
+                  P.xc, P.vmap, P.gpart, P.lrW, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
+                  R.elim, R.norms, R.blob};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   P = Plan();
@@ -1219,18 +1495,110 @@ static void enqueue_schur(const Plan &P, bool f32, double *S_dev, Profiler &pr, 
   });
 }
 
+// One refined solve of the chunk's right-hand sides, in place on R.W:
+// forward through the fronts' local panels (leaves to root), then back
+// substitution (root to leaves).  FP32 MFMA with the mixed factors.
+static void refine_solve(const Plan &P, int w, Profiler &pr, hipStream_t s) {
+  const Refine &R = P.R;
+  pr.run(P_REFINE, s, [&] {
+    hipError_t e = hipSuccess;
+    for (size_t lvl = 0; lvl < R.lv.size() && e == hipSuccess; ++lvl) {
+      const RefineLevel &L = R.lv[lvl];
+      e = launch_zero(R.at<ZeroRange>(L.zero), L.nzero, s);
+      if (e == hipSuccess) e = launch_copy(R.at<CopyRange>(L.copy), L.ncopy, s);
+      if (e == hipSuccess) e = launch_gemm(R.at<GemmTask>(L.g1), L.ng1, 0, w, nullptr, s, true);
+      if (e == hipSuccess) e = launch_gemm(R.at<GemmTask>(L.g2), L.ng2, 0, w, nullptr, s, true);
+      if (e == hipSuccess) e = launch_gemm(R.at<GemmTask>(L.g2b), L.ng2b, 0, w, nullptr, s, true);
+    }
+    for (int lvl = (int)R.lv.size() - 1; lvl >= 0 && e == hipSuccess; --lvl)
+      e = launch_gemm(R.at<GemmTask>(R.lv[lvl].bk), R.lv[lvl].nbk, 0, w, nullptr, s, true);
+    return e;
+  });
+}
+
+// Refined fields of one right-hand-side chunk (w columns), into R.X:
+//   X = solve(r); then `iters` times: W = r - A X (FP64), X += solve(W);
+// finally the residual once more for the convergence check.  r is zero
+// except on grid row rrow (entries rb[i * ldr + coff + j]).  Squared norms:
+// slot 0 |r|^2, slot k the residual after k solves.
+static void refine_fields(apf_handle *h, int rrow, const cplx *rb, int ldr, int coff, int w, int chunk,
+                          hipStream_t s) {
+  Plan &P = h->plan;
+  Refine &R = P.R;
+  Profiler &pr = h->prof;
+  const int nx = h->d.nx, ny = h->d.ny;
+  const int64_t N = (int64_t)nx * ny;
+  double *nrm = R.norms + (int64_t)chunk * (R.iters + 2);
+  auto residual = [&](bool first, int slot) {
+    pr.run(P_REFINE, s, [&] {
+      return launch_residual(nx, ny, R.elim, P.aval, R.X, R.W, R.rc, w, rrow, rb, ldr, coff, first, nrm + slot, s);
+    });
+  };
+  residual(true, 0);
+  refine_solve(P, w, pr, s);
+  pr.run(P_REFINE, s, [&] { return launch_add_fields(R.X, R.W, N, R.rc, w, true, s); });
+  for (int it = 1; it <= R.iters; ++it) {
+    residual(false, it);
+    refine_solve(P, w, pr, s);
+    pr.run(P_REFINE, s, [&] { return launch_add_fields(R.X, R.W, N, R.rc, w, false, s); });
+  }
+  residual(false, R.iters + 1);
+}
+
+static std::string sci(double v) {
+  char b[32];
+  std::snprintf(b, sizeof b, "%.3e", v);
+  return b;
+}
+
+// Largest final and first relative residual over the chunks of the last
+// refined call (after the stream was synchronised).
+static void refine_residuals(Refine &R) {
+  std::vector<double> v((size_t)R.nchunks * (R.iters + 2));
+  HIPCHK(hipMemcpy(v.data(), R.norms, v.size() * sizeof(double), hipMemcpyDeviceToHost));
+  R.last_res = R.last_res1 = 0.0;
+  for (int c = 0; c < R.nchunks; ++c) {
+    const double *n = v.data() + (size_t)c * (R.iters + 2);
+    if (!(n[0] > 0.0)) continue;
+    R.last_res = std::max(R.last_res, std::sqrt(n[R.iters + 1] / n[0]));
+    R.last_res1 = std::max(R.last_res1, std::sqrt(n[1] / n[0]));
+  }
+}
+
 extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double *S_dev, void *stream) {
   if (!h || !S_dev) return fail(APF_EINVAL, "null argument");
-  if (prec != APF_FP64 && prec != APF_MIXED) return fail(APF_EINVAL, "unknown precision");
+  if (prec != APF_FP64 && prec != APF_MIXED && prec != APF_MIXED_REFINED) return fail(APF_EINVAL, "unknown precision");
   if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
+  const bool refine = prec == APF_MIXED_REFINED;
+  if (refine && h->refine_iters <= 0)
+    return fail(APF_ESTATE, "APF_MIXED_REFINED needs apf_set_refinement before the first apf_assemble");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     Plan &P = h->plan;
     Profiler &pr = h->prof;
-    const bool f32 = prec == APF_MIXED;
+    const bool f32 = prec != APF_FP64;
+    const int Mi = h->d.n_in;
     HIPCHK(launch_fill_int(P.status, 0, s));
     run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32);
-    enqueue_schur(P, f32, S_dev, pr, s, h->d.n_out, h->d.n_in);
+    if (!refine) {
+      enqueue_schur(P, f32, S_dev, pr, s, h->d.n_out, Mi);
+    } else {
+      // S from refined forward fields, chunk by chunk; their design rows are
+      // kept for apf_grad
+      Refine &R = P.R;
+      HIPCHK(launch_fill_double(R.norms, R.nchunks * (R.iters + 2), 0.0, s));
+      for (int c = 0; c < R.nchunks; ++c) {
+        const int m0 = c * R.rc, w = std::min(R.rc, Mi - m0);
+        refine_fields(h, h->d.src_row, R.Bmat, Mi, m0, w, c, s);
+        pr.run(P_GEMM_SCHUR, s, [&] {
+          return launch_gemm(R.at<GemmTask>(R.sgemm), R.nsgemm, m0, w, reinterpret_cast<const cplx *>(S_dev), s,
+                             false, nullptr, 0, true);
+        });
+        pr.run(P_REFINE, s, [&] {
+          return launch_gather_rows(R.at<int32_t>(R.erow_des), P.ndesign, R.X, R.rc, w, R.Ydes, Mi, m0, s);
+        });
+      }
+    }
     int st[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(st, P.status, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1246,6 +1614,13 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
     }
     h->state = 2;
     h->mixed = f32;
+    h->refined = refine;
+    if (refine) {
+      refine_residuals(P.R);
+      if (!(P.R.last_res <= P.R.tol))
+        return fail(APF_ENOTCONV, "refinement of the forward fields ended at relative residual " +
+                                      sci(P.R.last_res) + " (first solve " + sci(P.R.last_res1) + ")");
+    }
     return APF_OK;
   });
 }
@@ -1368,6 +1743,7 @@ void forget_batches_of(apf_handle *h) {
 extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n, apf_precision prec,
                                                double *const *S_devs, void *stream) {
   if (!hs || !S_devs || n < 1) return fail(APF_EINVAL, "need at least one handle and output");
+  if (prec == APF_MIXED_REFINED) return fail(APF_EINVAL, "the batched factorization has no refined precision");
   if (prec != APF_FP64 && prec != APF_MIXED) return fail(APF_EINVAL, "unknown precision");
   const bool f32 = prec == APF_MIXED;
   std::vector<apf_handle *> v(hs, hs + n);
@@ -1429,6 +1805,7 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
     for (int i = 0; i < n; ++i) {
       hs[i]->state = (st || bad_eps >= 0) ? 0 : 2;
       hs[i]->mixed = f32;
+      hs[i]->refined = false;
       ++hs[i]->n_factor;
     }
     if (bad_eps >= 0)
@@ -1538,8 +1915,32 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     const int Mi = h->d.n_in, ch = P.rhs_chunk;
     const cplx *G = reinterpret_cast<const cplx *>(dfdS_dev);
     const double two_h2 = 2.0 * h->phys.h2;
-    HIPCHK(launch_row_map(P.vmap, P.at<int32_t>(P.vmap_base), P.at<int32_t>(P.vmap_pidx), P.perms, P.xc_rows, s));
     Profiler &pr = h->prof;
+    if (h->refined) {
+      // refined weighted adjoint fields, contracted with the refined forward
+      // fields the factorization kept
+      Refine &R = P.R;
+      HIPCHK(launch_fill_double(R.norms, R.nchunks * (R.iters + 2), 0.0, s));
+      for (int c = 0; c < R.nchunks; ++c) {
+        const int m0 = c * R.rc, w = std::min(R.rc, Mi - m0);
+        pr.run(P_REFINE, s, [&] {
+          return launch_gemm(R.at<GemmTask>(R.agemm), R.nagemm, m0, w, G, s, false, nullptr, 0, true);
+        });
+        refine_fields(h, h->d.prj_row, R.rowbuf, R.rc, 0, w, c, s);
+        pr.run(P_CONTRACT, s, [&] {
+          return launch_contract_rows(R.at<int32_t>(R.erow_des), P.ndesign, R.X, R.rc, w, R.Ydes, Mi, m0, two_h2,
+                                      c == 0, grad_dev, s);
+        });
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      if (pr.on) pr.collect();
+      refine_residuals(R);
+      if (!(R.last_res <= R.tol))
+        return fail(APF_ENOTCONV, "refinement of the adjoint fields ended at relative residual " +
+                                      sci(R.last_res) + " (first solve " + sci(R.last_res1) + ")");
+      return APF_OK;
+    }
+    HIPCHK(launch_row_map(P.vmap, P.at<int32_t>(P.vmap_base), P.at<int32_t>(P.vmap_pidx), P.perms, P.xc_rows, s));
     const bool f32 = h->mixed;
     for (int m0 = 0; m0 < Mi; m0 += ch) {
       const int w = std::min(ch, Mi - m0);
@@ -1596,6 +1997,17 @@ extern "C" apf_status apf_set_lowrank(apf_handle *h, int32_t on) {
   return APF_OK;
 }
 
+extern "C" apf_status apf_set_refinement(apf_handle *h, int32_t max_iter, double tol) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  if (max_iter < 0 || max_iter > 16) return fail(APF_EINVAL, "max_iter must be in [0, 16]");
+  if (max_iter > 0 && !(tol > 0.0 && tol < 1.0)) return fail(APF_EINVAL, "tol must be in (0, 1)");
+  if (h->planned) return fail(APF_ESTATE, "the plan is already built (apf_assemble has run)");
+  h->refine_iters = max_iter;
+  h->refine_tol = max_iter > 0 ? tol : 0.0;
+  if (h->analyzed) size_plan(h);   // the retained-factor offsets depend on it
+  return APF_OK;
+}
+
 extern "C" apf_status apf_set_profiling(apf_handle *h, int32_t on) {
   if (!h) return fail(APF_EINVAL, "null handle");
   return guarded([&]() -> apf_status {
@@ -1640,6 +2052,10 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
   else if (k == "schur_store_bytes") *value = (double)S.k_total * (h->d.n_in + h->d.n_out) * sizeof(cplx);
   else if (k == "rhs_chunk") *value = h->planned ? (double)h->plan.rhs_chunk : -1.0;
   else if (k == "n_factorizations") *value = (double)h->n_factor;
+  else if (k == "refine_chunk") *value = h->planned ? (double)h->plan.R.rc : -1.0;
+  else if (k == "refine_residual") *value = h->plan.R.last_res;
+  else if (k == "refine_residual_first") *value = h->plan.R.last_res1;
+  else if (k == "retained_factor_bytes") *value = (double)h->plan.R.ss_elems * sizeof(cplx);
   else if (k == "lowrank_fronts") *value = h->planned ? (double)h->plan.n_wfronts : -1.0;
   else if (k == "lowrank_roots") *value = h->planned ? (double)h->plan.n_wroots : -1.0;
   else if (k == "gemm_cmacs_factor") *value = h->planned ? h->plan.gemm_cmacs_factor : -1.0;

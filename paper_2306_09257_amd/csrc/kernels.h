@@ -37,6 +37,20 @@ hipError_t launch_weighted_power(const cplx *S, const double *w, double *f, cplx
 // block partials of the weighted-power reduction for n entries (<= 1024)
 int weighted_power_parts(int64_t n);
 
+// iterative refinement of the mixed path (see kernels.hip)
+hipError_t launch_channel_matrices(const ChanParams *cp_src, const ChanParams *cp_prj, cplx *Bmat, cplx *Cmat,
+                                   hipStream_t s);
+hipError_t launch_residual(int nx, int ny, const int32_t *elim, const cplx *Aval, const cplx *X, cplx *W, int ld,
+                           int w, int rrow, const cplx *rb, int ldr, int coff, bool first, double *norm2,
+                           hipStream_t s);
+hipError_t launch_add_fields(cplx *X, const cplx *W, int64_t rows, int ld, int w, bool first, hipStream_t s);
+hipError_t launch_gather_rows(const int32_t *erow, int64_t n, const cplx *X, int ld, int w, cplx *Y, int64_t ldy,
+                              int coff, hipStream_t s);
+hipError_t launch_contract_rows(const int32_t *erow, int64_t n, const cplx *Lam, int ld, int w, const cplx *Y,
+                                int64_t ldy, int coff, double scale, bool first, double *grad, hipStream_t s);
+hipError_t launch_copy(const CopyRange *r, int n, hipStream_t s);
+hipError_t launch_fill_double(double *p, int n, double v, hipStream_t s);
+
 // beam-splitter workload: Eq. (5) figure of merit, ridge permittivity and
 // the chain rule to the edge positions (see include/apf.h)
 hipError_t launch_splitter_fom(const cplx *S, const int32_t *in_ord, const int32_t *out_ord, int n_in, int n_out,

@@ -447,6 +447,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   const cplx *Bp = (T.flags & G_B_EXT) ? ext : T.B;
   if (T.flags & G_B_COFF) Bp += coff;
   cplx *Cp = (T.flags & G_C_EXT) ? const_cast<cplx *>(ext) : T.C;
+  if (T.flags & G_C_COFF) Cp += coff;
 
   static_assert(!(K3 && F32), "the three-product form is for the FP64 path");
   // four-product form: cre, cim; three-product form: k1 -> cre, k2 -> cim, k3
@@ -1093,6 +1094,125 @@ __global__ __launch_bounds__(64) void k_ridges_grad(const double *edges, int n, 
 }
 
 // ---------------------------------------------------------------------------
+// Iterative refinement of the mixed path (FP32 front GEMMs): full-grid
+// right-hand sides in elimination order (row e = elimination index of a node,
+// `ld` columns), FP64 residuals from the stencil values, and the FP64
+// products that turn the refined fields into S and the gradient.
+// ---------------------------------------------------------------------------
+
+// Channel matrices of the refined path: Bmat [nx][n_in] = the source row's
+// entries of B (-2i sqrt(sin q_a) phi_a(i)) and Cmat [n_out][nx] = the
+// projection row's entries of C (sqrt(sin q_b) conj(phi_b(i))).
+__global__ void k_channel_matrices(const ChanParams *cp_src, const ChanParams *cp_prj, cplx *Bmat, cplx *Cmat) {
+  const Phys &P = cp_src->P;
+  const int nx = P.nx, mi = cp_src->m, mo = cp_prj->m;
+  const int64_t nb = (int64_t)nx * mi, nc = (int64_t)mo * nx;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nb + nc; t += (int64_t)gridDim.x * blockDim.x) {
+    if (t < nb) {
+      const int i = (int)(t / mi), a = (int)(t - (int64_t)i * mi);
+      const double2 v = channel_value(P, cp_src->orders[a], i, P.eps_src, false);
+      st2(Bmat + t, make_double2(2.0 * v.y, -2.0 * v.x));   // times -2i
+    } else {
+      const int64_t u = t - nb;
+      const int b = (int)(u / nx), i = (int)(u - (int64_t)b * nx);
+      st2(Cmat + u, channel_value(P, cp_prj->orders[b], i, P.eps_prj, true));
+    }
+  }
+}
+
+// W = r - A X over the whole grid for the first w columns, one wave per node:
+// r is zero except on grid row rrow, where r(i, j) = rb[i * ldr + coff + j];
+// A X from the five stencil values of the node (A's row) and the fields of
+// its neighbours (x periodic; no neighbour past the first and last rows).
+// first: X is taken as zero (W = r).  The squared norm of the residual is
+// added to *norm2 (a convergence measure only: atomic, order-free).
+__global__ __launch_bounds__(256) void k_residual(int nx, int ny, const int32_t *elim, const cplx *Aval,
+                                                  const cplx *X, cplx *W, int ld, int w, int rrow, const cplx *rb,
+                                                  int ldr, int coff, int first, double *norm2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  double acc = 0.0;
+  if (n < (int64_t)nx * ny) {
+    const int y = (int)(n / nx), x = (int)(n - (int64_t)y * nx);
+    const int64_t e = elim[n];
+    int64_t nb[5];
+    nb[0] = e;
+    nb[1] = elim[(int64_t)y * nx + (x == 0 ? nx - 1 : x - 1)];
+    nb[2] = elim[(int64_t)y * nx + (x == nx - 1 ? 0 : x + 1)];
+    nb[3] = y > 0 ? elim[n - nx] : -1;
+    nb[4] = y < ny - 1 ? elim[n + nx] : -1;
+    double2 a[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) a[d] = ld2(Aval + n * 5 + d);
+    const cplx *rrowp = y == rrow ? rb + (int64_t)x * ldr + coff : nullptr;
+    for (int j = lane; j < w; j += 64) {
+      double2 v = rrowp ? ld2(rrowp + j) : make_double2(0.0, 0.0);
+      if (!first) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+          if (nb[d] >= 0) v = csub(v, cmul(a[d], ld2(X + nb[d] * ld + j)));
+      }
+      st2(W + e * ld + j, v);
+      acc += v.x * v.x + v.y * v.y;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0 && acc != 0.0) atomicAdd(norm2, acc);
+}
+
+// X += W (first: X = W) over the first w columns of every row.
+__global__ void k_add_fields(cplx *X, const cplx *W, int64_t rows, int ld, int w, int first) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t r = t / w;
+  if (r >= rows) return;
+  const int64_t o = r * ld + (t - r * w);
+  st2(X + o, first ? ld2(W + o) : cadd(ld2(X + o), ld2(W + o)));
+}
+
+// Ydes[k][coff + j] = X[erow[k]][j] for the design pixels k (one wave each).
+__global__ __launch_bounds__(256) void k_gather_rows(const int32_t *erow, int64_t n, const cplx *X, int ld, int w,
+                                                     cplx *Y, int64_t ldy, int coff) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (k >= n) return;
+  const cplx *src = X + (int64_t)erow[k] * ld;
+  cplx *dst = Y + k * ldy + coff;
+  for (int j = lane; j < w; j += 64) st2(dst + j, ld2(src + j));
+}
+
+// grad[k] (+)= scale * Re sum_j Lam[erow[k]][j] Ydes[k][coff + j] over the
+// chunk's w columns (one wave per design pixel; the first chunk stores).
+__global__ __launch_bounds__(256) void k_contract_rows(const int32_t *erow, int64_t n, const cplx *Lam, int ld, int w,
+                                                       const cplx *Y, int64_t ldy, int coff, double scale, int first,
+                                                       double *grad) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (k >= n) return;
+  const cplx *l = Lam + (int64_t)erow[k] * ld;
+  const cplx *yv = Y + k * ldy + coff;
+  double acc = 0.0;
+  for (int j = lane; j < w; j += 64) {
+    const double2 a = ld2(l + j), b = ld2(yv + j);
+    acc += a.x * b.x - a.y * b.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) grad[k] = first ? scale * acc : grad[k] + scale * acc;
+}
+
+// Contiguous copies (one block per range).
+__global__ void k_copy(const CopyRange *r, int n) {
+  const CopyRange c = r[blockIdx.x];
+  const double2 *s = reinterpret_cast<const double2 *>(c.src);
+  double2 *d = reinterpret_cast<double2 *>(c.dst);
+  for (int64_t i = threadIdx.x; i < c.n; i += blockDim.x) d[i] = s[i];
+}
+
+__global__ void k_fill_double(double *p, int n, double v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
@@ -1248,6 +1368,50 @@ hipError_t launch_ridges_grad(const double *edges, int n, int mirror, int nx, in
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ridges_grad, dim3(n), dim3(64), 0, s, edges, n, mirror, nx, nrows, eps_ridge, eps_gap,
                      grad_eps, grad_edges);
+  return hipGetLastError();
+}
+
+hipError_t launch_channel_matrices(const ChanParams *cp_src, const ChanParams *cp_prj, cplx *Bmat, cplx *Cmat,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_channel_matrices, dim3(2048), dim3(256), 0, s, cp_src, cp_prj, Bmat, Cmat);
+  return hipGetLastError();
+}
+hipError_t launch_residual(int nx, int ny, const int32_t *elim, const cplx *Aval, const cplx *X, cplx *W, int ld,
+                           int w, int rrow, const cplx *rb, int ldr, int coff, bool first, double *norm2,
+                           hipStream_t s) {
+  const int64_t N = (int64_t)nx * ny;
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, nx, ny, elim, Aval, X, W, ld, w,
+                     rrow, rb, ldr, coff, first ? 1 : 0, norm2);
+  return hipGetLastError();
+}
+hipError_t launch_add_fields(cplx *X, const cplx *W, int64_t rows, int ld, int w, bool first, hipStream_t s) {
+  const int64_t n = rows * w;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, W, rows, ld, w,
+                     first ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_gather_rows(const int32_t *erow, int64_t n, const cplx *X, int ld, int w, cplx *Y, int64_t ldy,
+                              int coff, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, erow, n, X, ld, w, Y, ldy, coff);
+  return hipGetLastError();
+}
+hipError_t launch_contract_rows(const int32_t *erow, int64_t n, const cplx *Lam, int ld, int w, const cplx *Y,
+                                int64_t ldy, int coff, double scale, bool first, double *grad, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_contract_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, erow, n, Lam, ld, w, Y, ldy,
+                     coff, scale, first ? 1 : 0, grad);
+  return hipGetLastError();
+}
+hipError_t launch_copy(const CopyRange *r, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(n), dim3(256), 0, s, r, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_double(double *p, int n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_double, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

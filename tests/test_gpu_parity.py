@@ -165,7 +165,8 @@ def test_profiling_modes_time_the_launch_classes_they_name():
     apf.set_profiling(False)
     assert all(p_gemm[c][1] > 0 for c in gemm)
     assert all(p_gemm[c][1] == 0 for c in p_gemm if c not in gemm)
-    assert all(p_all[c][1] > 0 for c in p_all)
+    assert all(p_all[c][1] > 0 for c in p_all if c != "refine")     # no refinement on this path
+    assert p_all["refine"][1] == 0
     assert all(p_all[c][1] == p_gemm[c][1] for c in gemm)
     # timing changes nothing in the results
     assert torch.equal(g0, g1) and torch.equal(g0, g2)

@@ -248,3 +248,17 @@ def test_pivot_limit_is_shared_by_the_analysis_and_the_kernels(lib):
     ps = [apf.front(f)[0][2] for f in range(int(apf.query("n_fronts")))]
     assert max(ps) <= 128
     assert 100 in ps
+
+
+def test_refinement_switch_is_checked(lib):
+    apf = binding.APF(_problem(24, 60)).analyze()
+    h = apf._h
+    E = binding.APF_EINVAL
+    for it, tol in ((-1, 1e-10), (17, 1e-10), (2, 0.0), (2, 1.0), (2, float("nan"))):
+        assert lib.apf_set_refinement(h, it, tol) == E
+    assert lib.apf_set_refinement(None, 2, 1e-10) == E
+    assert lib.apf_set_refinement(h, 2, 1e-10) == binding.APF_OK
+    assert apf.query("retained_factor_bytes") > 0
+    assert lib.apf_set_refinement(h, 0, 0.0) == binding.APF_OK
+    assert apf.query("retained_factor_bytes") == 0
+    assert apf.query("refine_chunk") == -1.0
