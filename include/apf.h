@@ -250,6 +250,55 @@ apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, int32_t n_edg
 apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev,
                     void *stream);
 
+/* Flags of the parameter-augmented gradient. */
+#define APF_AUG_SKIP_UU 1   /* do not form the U(n)^T A^-1 U(n) block of S~(n) */
+
+/* Gradient with respect to general design parameters p_k by the
+ * parameter-augmented partial factorization (Sec. 2, Eq. (4), with the matrix
+ * division into N_sub sub-factorizations of Fig. 1d): dA/dp_k = U_k Sigma_k
+ * U_k^T (Eq. (2)) with U_k the unit vectors of the design pixels p_k changes
+ * and Sigma_k the corresponding diagonal entries of dA/dp_k.  The columns of
+ * U = [U_1, ..., U_Np] are divided into n_sub groups of whole parameters;
+ * sub-factorization n eliminates the grid unknowns of
+ *   K~(n) = [A, [B, U(n)]; [C; U(n)^T], 0]
+ * and yields C A^-1 U(n), U(n)^T A^-1 B and (unless APF_AUG_SKIP_UU)
+ * U(n)^T A^-1 U(n); Eq. (3) is applied to each sub's blocks, unmerged:
+ *   df/dp_k = -2 Re sum_{c in k} Sigma_c sum_nm (C A^-1 U)_nc dF/dS_nm (U^T A^-1 B)_cm.
+ *   n_cols, col_pixel, col_sigma (host): the columns of U, each the design
+ *     pixel (row-major index over the design rows) and its Sigma entry;
+ *   n_params, param_begin (host, n_params + 1 entries, non-decreasing from 0
+ *     to n_cols): the columns of parameter k are [param_begin[k],
+ *     param_begin[k + 1]);
+ *   n_sub: the number of sub-factorizations (>= 1), or 0 for the smallest
+ *     one whose S~(n) has at most 5 nnz(A) entries (clamped to [1, n_params]);
+ *     *n_sub_used (may be NULL) receives the number run;
+ *   dfdS_dev: complex128 [n_out][n_in], dF/dS (from an earlier apf_factor_schur
+ *     with the same permittivity); S_dev: NULL, or complex128 [n_out][n_in]
+ *     receiving the first sub-factorization's C A^-1 B; dfdp_dev: float64
+ *     [n_params].
+ * FP64.  Requires apf_assemble; every sub-factorization refactors A, and the
+ * handle then holds FP64 factors of the assembled permittivity (apf_grad may
+ * follow).  Synchronises `stream`.  APF_EINVAL for bad arguments (a pixel
+ * outside the design rows, a decreasing param_begin), plus the errors of
+ * apf_factor_schur. */
+apf_status apf_grad_augmented(apf_handle *h, int32_t n_cols, const int32_t *col_pixel,
+                              const double *col_sigma, int32_t n_params, const int32_t *param_begin,
+                              int32_t n_sub, int32_t flags, const double *dfdS_dev, double *S_dev,
+                              double *dfdp_dev, int32_t *n_sub_used, void *stream);
+
+/* apf_grad_augmented for the ridge parameterization of apf_ridges_eps: the
+ * parameters are the n_edges free edge positions; U_k holds the pixels of
+ * the cell holding edge k on every design row (and, with mirror = 1, those of
+ * the cell holding its image), Sigma_k = -h^2 deps/dx_k with deps/dx_k =
+ * -/+(eps_ridge - eps_gap) for a left / right edge and the opposite sign for
+ * the image (which moves by -1); r_k = 2 x design rows with mirror symmetry.
+ * The edges are read back from the device (the call synchronises `stream`).
+ * Same arguments and errors as apf_ridges_grad and apf_grad_augmented. */
+apf_status apf_ridges_grad_augmented(apf_handle *h, const double *edges_dev, int32_t n_edges,
+                                     int32_t mirror, double eps_ridge, double eps_gap, int32_t n_sub,
+                                     int32_t flags, const double *dfdS_dev, double *S_dev,
+                                     double *dfdp_dev, int32_t *n_sub_used, void *stream);
+
 /* Cap the right-hand-side chunk of the gradient sweeps (0: the default, as
  * many columns as half of the free device memory holds).  The sweep arrays
  * X and V hold one row per sweep pivot and `chunk` columns each; apf_grad

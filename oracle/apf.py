@@ -212,3 +212,46 @@ def objective_fd(prob, eps, w, pixels, step):
         fm, _ = weighted_power(scattering_matrix(prob, em), w)
         out.append((fp - fm) / (2.0 * step))
     return np.array(out)
+
+
+def grad_augmented_params(prob, eps, G, col_pixel, col_sigma, param_begin, n_sub):
+    """Gradient with respect to general parameters p_k by the augmented matrix
+    of Eq. (4) with the matrix division of Sec. 2 (Fig. 1d), dense (tiny grids).
+
+    dA/dp_k = U_k Sigma_k U_k^T (Eq. (2)): the columns of U_k are the unit
+    vectors of the design pixels col_pixel[c] (row-major over the design
+    rows) for c in [param_begin[k], param_begin[k+1]), Sigma_k holds
+    col_sigma[c].  The parameters are split into n_sub consecutive groups;
+    group n gives S~(n) = [C; U(n)^T] A^-1 [B, U(n)] and Eq. (3) is applied to
+    its blocks C A^-1 U(n) and U(n)^T A^-1 B without merging:
+        df/dp_k = sum_nm 2 Re(G_nm dS_nm/dp_k),
+        dS/dp_k = -(C A^-1 U_k) Sigma_k (U_k^T A^-1 B).
+    Returns (dfdp, S) with S = C A^-1 B from the first group."""
+    A = fdfd.assemble_dense(prob, eps)
+    B = fdfd.source_dense(prob)
+    C = fdfd.projection_dense(prob)
+    N = A.shape[0]
+    mo, mi = prob.n_out, prob.n_in
+    pb = np.asarray(param_begin)
+    n_params = pb.size - 1
+    nodes = design_nodes(prob)[np.asarray(col_pixel)]
+    dfdp = np.zeros(n_params)
+    S_first = None
+    for group in np.array_split(np.arange(n_params), n_sub):
+        if group.size == 0:
+            continue
+        c0, c1 = pb[group[0]], pb[group[-1] + 1]
+        r = c1 - c0
+        U = np.zeros((N, r))
+        U[nodes[c0:c1], np.arange(r)] = 1.0
+        St = np.concatenate([C, U.T], axis=0) @ np.linalg.solve(A, np.concatenate([B, U], axis=1))
+        if S_first is None:
+            S_first = St[:mo, :mi]
+        CAU = St[:mo, mi:]
+        UAB = St[mo:, :mi]
+        for k in group:
+            for c in range(pb[k], pb[k + 1]):
+                j = c - c0
+                dS = -np.outer(CAU[:, j], UAB[j, :]) * col_sigma[c]
+                dfdp[k] += np.sum(2.0 * np.real(G * dS))
+    return dfdp, S_first

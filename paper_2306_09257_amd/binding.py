@@ -22,6 +22,7 @@ APF_EHIP = -3
 APF_ESINGULAR = -4
 APF_ENOTCONV = -5
 APF_ESTATE = -6
+APF_AUG_SKIP_UU = 1
 APF_FP64 = 0
 APF_MIXED = 1
 APF_MIXED_REFINED = 2
@@ -29,7 +30,8 @@ APF_MIXED_REFINED = 2
 ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur", "apf_factor_schur_batched",
                 "apf_weighted_power", "apf_splitter_fom", "apf_group_fom", "apf_ridges_eps", "apf_ridges_grad",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
-                "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement")
+                "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement",
+                "apf_grad_augmented", "apf_ridges_grad_augmented")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow", "refine")
 
@@ -82,6 +84,9 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_rhs_chunk.argtypes = [vp, i32]
     lib.apf_set_lowrank.argtypes = [vp, i32]
     lib.apf_set_refinement.argtypes = [vp, i32, dbl]
+    lib.apf_grad_augmented.argtypes = [vp, i32, vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), vp]
+    lib.apf_ridges_grad_augmented.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, i32, vp, vp, vp,
+                                              ctypes.POINTER(i32), vp]
     lib.apf_destroy.argtypes = [vp]
     lib.apf_last_error.argtypes = []
     lib.apf_last_error.restype = ctypes.c_char_p
@@ -245,6 +250,42 @@ class APF:
             out = torch.empty((self.prob.n_design_rows, self.prob.nx), dtype=torch.float64, device=dfdS.device)
         _check(self._lib.apf_grad(self._h, _ptr(dfdS), _ptr(out), _stream()))
         return out
+
+    def grad_augmented(self, dfdS, col_pixel, col_sigma, param_begin, n_sub: int = 0, skip_uu: bool = False,
+                       want_S: bool = False):
+        """df/dp for dA/dp_k = U_k Sigma_k U_k^T by the parameter-augmented
+        factorization with n_sub sub-factorizations (0: chosen from the sizes).
+        col_pixel / col_sigma / param_begin: host arrays (see apf.h).
+        Returns (dfdp, S or None, n_sub used)."""
+        import torch
+        assert dfdS.dtype == torch.complex128 and dfdS.is_contiguous()
+        pix = np.ascontiguousarray(col_pixel, dtype=np.int32)
+        sig = np.ascontiguousarray(col_sigma, dtype=np.float64)
+        pb = np.ascontiguousarray(param_begin, dtype=np.int32)
+        assert pix.size == sig.size and pb.size >= 2
+        out = torch.empty(pb.size - 1, dtype=torch.float64, device=dfdS.device)
+        S = torch.empty_like(dfdS) if want_S else None
+        used = ctypes.c_int32()
+        _check(self._lib.apf_grad_augmented(
+            self._h, pix.size, pix.ctypes.data_as(ctypes.c_void_p), sig.ctypes.data_as(ctypes.c_void_p),
+            pb.size - 1, pb.ctypes.data_as(ctypes.c_void_p), int(n_sub), APF_AUG_SKIP_UU if skip_uu else 0,
+            _ptr(dfdS), _ptr(S) if S is not None else None, _ptr(out), ctypes.byref(used), _stream()))
+        return out, S, used.value
+
+    def ridges_grad_augmented(self, edges, dfdS, mirror: bool, eps_ridge: float, eps_gap: float, n_sub: int = 0,
+                              skip_uu: bool = False):
+        """df/d(edges) by the parameter-augmented factorization (U_k: the
+        cells of edge k and of its mirror image on every design row).
+        Returns (dfdp, n_sub used)."""
+        import torch
+        assert edges.dtype == torch.float64 and edges.is_contiguous() and edges.is_cuda
+        assert dfdS.dtype == torch.complex128 and dfdS.is_contiguous()
+        out = torch.empty_like(edges)
+        used = ctypes.c_int32()
+        _check(self._lib.apf_ridges_grad_augmented(
+            self._h, _ptr(edges), edges.numel(), int(mirror), float(eps_ridge), float(eps_gap), int(n_sub),
+            APF_AUG_SKIP_UU if skip_uu else 0, _ptr(dfdS), None, _ptr(out), ctypes.byref(used), _stream()))
+        return out, used.value
 
     def close(self):
         if getattr(self, "_h", None):

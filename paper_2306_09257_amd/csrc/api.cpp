@@ -111,6 +111,15 @@ struct LevelTasks {
   }
 };
 
+// Extra per-level work of one parameter-augmented sub-factorization (Eq. (4)
+// with U divided into N_sub parts): zeroing and unit entries of the fronts'
+// U / U^T panels at their panel level, then the panels' phase-1 and phase-2
+// products (the latter with the blocks of S~ they add into).
+struct AugLevel {
+  int64_t zero = -1, one = -1, g1 = -1, g2 = -1;
+  int nzero = 0, none = 0, ng1 = 0, ng2 = 0;
+};
+
 constexpr int64_t ZERO_CHUNK = 8192;   // complex elements per zeroing block
 constexpr int64_t SPLIT_K = 4096;      // k rows per partial block of the split Schur product
 
@@ -1455,11 +1464,21 @@ extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *s
 // blocks, then the two GEMM phases.  `blob` holds the task arrays that `lv`
 // indexes; `fr` the front descriptors.
 static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const FrontDev *fr, int *status,
-                       Profiler &pr, hipStream_t s, bool f32) {
+                       Profiler &pr, hipStream_t s, bool f32, const std::vector<AugLevel> *aug = nullptr,
+                       char *ablob = nullptr) {
   auto at = [&](int64_t off) -> char * { return off < 0 ? nullptr : blob + off; };
+  auto aat = [&](int64_t off) -> char * { return off < 0 ? nullptr : ablob + off; };
   for (size_t lvl = 0; lvl < lv.size(); ++lvl) {
     const LevelTasks &L = lv[lvl];
+    const AugLevel *A = (aug && lvl < aug->size()) ? &(*aug)[lvl] : nullptr;
     pr.run(P_ZERO, s, [&] { return launch_zero((const ZeroRange *)at(L.zero), L.nzero, s); });
+    if (A) {
+      pr.run(P_ZERO, s, [&] {
+        hipError_t e = launch_zero((const ZeroRange *)aat(A->zero), A->nzero, s);
+        if (e == hipSuccess) e = launch_set_one((cplx *const *)aat(A->one), A->none, s);
+        return e;
+      });
+    }
     pr.run(P_ASSEMBLE, s, [&] {
       hipError_t e = launch_scatter_A((const AsmEntry *)at(L.scat), L.nscat, s);
       if (e == hipSuccess) e = launch_assemble_panel((const PanelEntry *)at(L.pan), L.npan, s);
@@ -1478,6 +1497,14 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
       const bool deep = g == 0 ? L.deep1 : (g == 1 ? L.deep2 : L.deep2b);
       if (n > 0)
         pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32, nullptr, 0, deep); });
+      // the augmented panels' products after the main phase 1 (their inputs)
+      // and phase 2 (no dependence either way)
+      if (A && g < 2) {
+        const int64_t ao = g == 0 ? A->g1 : A->g2;
+        const int an = g == 0 ? A->ng1 : A->ng2;
+        if (an > 0)
+          pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)aat(ao), an, 0, INT_MAX, nullptr, s, f32); });
+      }
     }
   }
 }
@@ -1980,6 +2007,413 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
   });
 }
 
+// ---------------------------------------------------------------------------
+// Parameter-augmented partial factorization (Sec. 2, Eq. (4) and the N_sub
+// division of U): every sub-factorization eliminates the grid unknowns of
+//   K~(n) = [A, [B, U(n)]; [C; U(n)^T], 0]
+// and reads the blocks C A^-1 U(n), U(n)^T A^-1 B (and, unless skipped,
+// U(n)^T A^-1 U(n)) of its Schur complement; Eq. (3) is applied to each
+// sub's blocks without merging them.  A column of U is the unit vector of one
+// design pixel (Eq. (2): dA/dp_k is diagonal on the pixels p_k modifies), so
+// a front carries the columns of the pixels in its subtree: with the columns
+// sorted by the pixels' elimination index these are one contiguous range per
+// front, nested in the parent's range.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct AugBuffers {                 // grow-only device buffers of the augmented route
+  cplx *arena = nullptr; int64_t arena_elems = 0;
+  cplx *blocks = nullptr; int64_t block_elems = 0;
+  double *misc = nullptr; int64_t misc_elems = 0;   // v, partials, sigma
+  char *blob = nullptr; int64_t blob_bytes = 0;
+};
+
+template <class T>
+void grow(T *&p, int64_t &have, int64_t need) {
+  if (need <= have) return;
+  if (p) HIPCHK(hipFree(p));
+  p = nullptr;
+  have = 0;
+  HIPCHK(hipMalloc(&p, need * sizeof(T)));
+  have = need;
+}
+
+std::mutex g_aug_mu;
+std::map<apf_handle *, AugBuffers> g_aug;
+
+void forget_aug_of(apf_handle *h) {
+  std::lock_guard<std::mutex> lk(g_aug_mu);
+  auto it = g_aug.find(h);
+  if (it == g_aug.end()) return;
+  AugBuffers &B = it->second;
+  if (B.arena) (void)hipFree(B.arena);
+  if (B.blocks) (void)hipFree(B.blocks);
+  if (B.misc) (void)hipFree(B.misc);
+  if (B.blob) (void)hipFree(B.blob);
+  g_aug.erase(it);
+}
+
+struct AugSubPlan {
+  std::vector<AugLevel> lv;
+  int64_t cg = -1;            // Eq. (3) contraction tasks
+  int ncg = 0;
+  int r = 0;                  // columns of U(n)
+};
+
+}  // namespace
+
+static apf_status augmented_grad(apf_handle *h, int32_t n_cols, const int32_t *col_pixel, const double *col_sigma,
+                                 int32_t n_params, const int32_t *param_begin, int32_t n_sub, int32_t flags,
+                                 const double *dfdS_dev, double *S_dev, double *dfdp_dev, hipStream_t s,
+                                 int32_t *n_sub_used) {
+  Symbolic &S = h->sym;
+  const Desc &d = h->d;
+  Plan &P = h->plan;
+  const std::vector<Off> &o = h->off;
+  const int nf = (int)S.fronts.size();
+  const int H_ = (int)S.levels.size() - 1;
+  const int Mi = d.n_in, Mo = d.n_out;
+  const bool uu = !(flags & APF_AUG_SKIP_UU);
+  const int64_t ndes = P.ndesign;
+  for (int c = 0; c < n_cols; ++c)
+    if (col_pixel[c] < 0 || col_pixel[c] >= ndes) return fail(APF_EINVAL, "column pixel outside the design rows");
+  if (param_begin[0] != 0 || param_begin[n_params] != n_cols)
+    return fail(APF_EINVAL, "param_begin must run from 0 to n_cols");
+  for (int k = 0; k < n_params; ++k)
+    if (param_begin[k + 1] < param_begin[k]) return fail(APF_EINVAL, "param_begin must not decrease");
+  // N_sub: given, or the smallest division whose S~(n) has at most five
+  // times as many entries as A has nonzeros
+  int nsub = n_sub;
+  if (nsub == 0) {
+    const double nnzA = 5.0 * d.nx * d.ny;
+    nsub = 1;
+    while (nsub < n_params) {
+      const double r = std::ceil((double)n_cols / nsub);
+      if ((Mi + r) * (Mo + r) <= 5.0 * nnzA) break;
+      ++nsub;
+    }
+  }
+  nsub = std::max(1, std::min(nsub, std::max(1, n_params)));
+  *n_sub_used = nsub;
+  // parameters split into nsub consecutive groups of about equal column counts
+  std::vector<int> pgrp(nsub + 1, n_params);
+  pgrp[0] = 0;
+  {
+    int k = 0;
+    for (int g = 1; g < nsub; ++g) {
+      const int64_t target = (int64_t)n_cols * g / nsub;
+      while (k < n_params && param_begin[k] < target) ++k;
+      pgrp[g] = std::max(pgrp[g - 1], k);
+    }
+  }
+  // subtree elimination ranges [lo, elim0 + p) (postorder: contiguous)
+  std::vector<int64_t> lo(nf);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    lo[f] = F.elim0;
+    for (int c = 0; c < F.nchild; ++c) lo[f] = std::min(lo[f], lo[F.child[c]]);
+  }
+  std::vector<int> lp(nf);
+  for (int f = 0; f < nf; ++f) {
+    const Front &F = S.fronts[f];
+    lp[f] = F.height;
+    for (int c = 0; c < F.nchild; ++c) lp[f] = std::min(lp[f], S.fronts[F.child[c]].height);
+  }
+  auto WS = [&](int64_t off) { return P.ws + off; };
+
+  // pass 1: each sub's columns (sorted by elimination index), per-front
+  // column ranges, arena layout and block sizes
+  struct SubLayout {
+    int r = 0;
+    std::vector<std::pair<int64_t, int>> col;   // (elimination index, input column)
+    std::vector<int> c0, c1;
+    std::vector<int64_t> pan, own;
+    int64_t scu = 0, sub = 0, suu = 0;
+  };
+  std::vector<SubLayout> lay(nsub);
+  int64_t arena_max = 1, block_max = 1;
+  for (int n = 0; n < nsub; ++n) {
+    SubLayout &Y = lay[n];
+    const int c_beg = param_begin[pgrp[n]], c_end = param_begin[pgrp[n + 1]];
+    const int r = c_end - c_beg;
+    Y.r = r;
+    if (r == 0) continue;
+    Y.col.resize(r);
+    for (int c = 0; c < r; ++c) {
+      const int64_t px = col_pixel[c_beg + c];
+      const int64_t node = (int64_t)(d.design_row0 + px / d.nx) * d.nx + px % d.nx;
+      Y.col[c] = {S.node_elim[node], c_beg + c};
+    }
+    std::stable_sort(Y.col.begin(), Y.col.end(),
+                     [](const std::pair<int64_t, int> &x, const std::pair<int64_t, int> &y) { return x.first < y.first; });
+    std::vector<int64_t> ce(r);
+    for (int c = 0; c < r; ++c) ce[c] = Y.col[c].first;
+    Y.c0.assign(nf, 0);
+    Y.c1.assign(nf, 0);
+    for (int f = 0; f < nf; ++f) {
+      const Front &F = S.fronts[f];
+      Y.c0[f] = (int)(std::lower_bound(ce.begin(), ce.end(), lo[f]) - ce.begin());
+      Y.c1[f] = (int)(std::lower_bound(ce.begin(), ce.end(), F.elim0 + F.p()) - ce.begin());
+    }
+    // blocks: S_CU (Mo x r), S_UB (r x Mi), S_UU (r x r)
+    Y.scu = 0;
+    Y.sub = up((int64_t)Mo * r);
+    Y.suu = Y.sub + up((int64_t)r * Mi);
+    block_max = std::max<int64_t>(block_max, Y.suu + (uu ? up((int64_t)r * r) : 0));
+    // arena: U and U^T panels ((p + b) x r_f each, panel level to own level),
+    // U1U and LCU (p x r_f each, own level)
+    Arena ar;
+    Y.pan.assign(nf, -1);
+    Y.own.assign(nf, -1);
+    std::vector<std::vector<int>> alloc_at(H_ + 1), rel_at(H_ + 2);
+    for (int f = 0; f < nf; ++f)
+      if (Y.c1[f] > Y.c0[f]) alloc_at[lp[f]].push_back(f);
+    for (int lvl = 0; lvl <= H_; ++lvl) {
+      for (int f : rel_at[lvl]) {
+        const int64_t rf = Y.c1[f] - Y.c0[f];
+        ar.release(Y.pan[f], 2 * (int64_t)(S.fronts[f].p() + S.fronts[f].b()) * rf);
+        ar.release(Y.own[f], 2 * (int64_t)S.fronts[f].p() * rf);
+      }
+      for (int f : alloc_at[lvl])
+        Y.pan[f] = ar.alloc(2 * (int64_t)(S.fronts[f].p() + S.fronts[f].b()) * (Y.c1[f] - Y.c0[f]));
+      for (int f : S.levels[lvl])
+        if (Y.c1[f] > Y.c0[f]) {
+          Y.own[f] = ar.alloc(2 * (int64_t)S.fronts[f].p() * (Y.c1[f] - Y.c0[f]));
+          rel_at[lvl + 1].push_back(f);
+        }
+    }
+    arena_max = std::max<int64_t>(arena_max, ar.top);
+  }
+  const int nblk = 2 * ((Mi + 63) / 64);
+  AugBuffers *B;
+  {
+    std::lock_guard<std::mutex> lk(g_aug_mu);
+    B = &g_aug[h];
+  }
+  grow(B->arena, B->arena_elems, arena_max);
+  grow(B->blocks, B->block_elems, block_max);
+  grow(B->misc, B->misc_elems, (int64_t)n_cols + (int64_t)nblk * n_cols + n_cols);
+  double *v = B->misc, *part = v + n_cols, *sig = part + (int64_t)nblk * n_cols;
+
+  // pass 2: task lists with device pointers; the integer arrays (row maps,
+  // contraction slots, parameter ranges) are blob offsets rebased below
+  Blob bl;
+  {
+    const char pad[16] = {0};
+    bl.add(pad, sizeof pad);
+  }
+  auto IP = [](int64_t off) { return reinterpret_cast<const int32_t *>((intptr_t)off); };
+  std::vector<AugSubPlan> subs(nsub);
+  for (int n = 0; n < nsub; ++n) {
+    AugSubPlan &SP = subs[n];
+    const SubLayout &Y = lay[n];
+    const int r = Y.r;
+    SP.r = r;
+    SP.lv.assign(H_ + 1, AugLevel());
+    if (r == 0) continue;
+    cplx *const AR = B->arena, *const BK = B->blocks;
+    std::vector<std::vector<ZeroRange>> zr(H_ + 1);
+    std::vector<std::vector<cplx *>> ones(H_ + 1);
+    std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1);
+    for (int f = 0; f < nf; ++f) {
+      const int c0 = Y.c0[f], rf = Y.c1[f] - c0;
+      if (rf == 0) continue;
+      const Front &F = S.fronts[f];
+      const Off &q = o[f];
+      const int p = F.p(), b = F.b(), lvl = F.height, nn = p + b;
+      cplx *UP = AR + Y.pan[f], *UCT = UP + (int64_t)nn * rf, *U1U = AR + Y.own[f], *LCU = U1U + (int64_t)p * rf;
+      for (int64_t o0 = 0; o0 < 2 * (int64_t)nn * rf; o0 += ZERO_CHUNK)
+        zr[lp[f]].push_back({UP + o0, std::min(ZERO_CHUNK, 2 * (int64_t)nn * rf - o0)});
+      for (int c = c0; c < c0 + rf; ++c) {
+        const int64_t e = Y.col[c].first;
+        if (e >= F.elim0 && e < F.elim0 + p) {
+          ones[lp[f]].push_back(UP + (e - F.elim0) * rf + (c - c0));
+          ones[lp[f]].push_back(UCT + (e - F.elim0) * rf + (c - c0));
+        }
+      }
+      cplx *tri = q.ss_tri >= 0 ? P.R.ss + q.ss_tri : WS(q.ws + q.tri);
+      const int32_t *perm = P.perms + F.elim0;
+      // phase 1: U1U = L^-1 P^T U_piv, LCU = U^-T (U^T)_piv^T
+      add_tiles(g1[lvl], gemm(tri, p, UP, rf, U1U, rf, p, rf, p, G_A_TRI_L, nullptr, 0, perm));
+      add_tiles(g1[lvl], gemm(tri, p, UCT, rf, LCU, rf, p, rf, p, G_TRANS_A | G_A_TRI_U));
+      // phase 2: the parent's panels (its column range holds this front's
+      // at offset c0 - c0_parent; siblings hold disjoint columns, so every
+      // write adds to the zeroed panel), then the blocks of S~
+      if (b) {
+        const int par = F.parent, rp = Y.c1[par] - Y.c0[par];
+        const Front &PF = S.fronts[par];
+        cplx *pUP = AR + Y.pan[par], *pUCT = pUP + (int64_t)(PF.p() + PF.b()) * rp;
+        const int32_t *rm = IP(bl.add(F.rmap));
+        cplx *l21 = q.ss_l21 >= 0 ? P.R.ss + q.ss_l21 : WS(q.ws + q.l21);
+        cplx *u12 = WS(q.ws + q.u12);
+        GemmTask t = gemm(l21, p, U1U, rf, pUP + (c0 - Y.c0[par]), rp, b, rf, p, G_NEG | G_CIN | G_CIN_OWN | G_C_ACC,
+                          UP + (int64_t)p * rf, rf);
+        t.crowmap = rm;
+        add_tiles(g2[lvl], t);
+        GemmTask t2 = gemm(u12, b, LCU, rf, pUCT + (c0 - Y.c0[par]), rp, b, rf, p,
+                           G_TRANS_A | G_NEG | G_CIN | G_CIN_OWN | G_C_ACC, UCT + (int64_t)p * rf, rf);
+        t2.crowmap = rm;
+        add_tiles(g2[lvl], t2);
+      }
+      if (F.hasC) {
+        const cplx *lc1t = F.sfront ? P.sc + q.sk * Mo : WS(q.ws + q.lc1t);
+        add_tiles(g2[lvl], gemm(lc1t, Mo, U1U, rf, BK + Y.scu + c0, r, Mo, rf, p, G_TRANS_A | G_C_ACC));
+      }
+      if (F.hasB) {
+        const cplx *u1b = F.sfront ? P.sb + q.sk * Mi : WS(q.ws + q.u1b);
+        add_tiles(g2[lvl], gemm(LCU, rf, u1b, Mi, BK + Y.sub + (int64_t)c0 * Mi, Mi, rf, Mi, p, G_TRANS_A | G_C_ACC));
+      }
+      if (uu)
+        add_tiles(g2[lvl], gemm(LCU, rf, U1U, rf, BK + Y.suu + (int64_t)c0 * r + c0, r, rf, rf, p,
+                                G_TRANS_A | G_C_ACC));
+    }
+    // Eq. (3) on this sub's blocks: v_c = sum_m ((C A^-1 U)^T dF/dS)_cm (U^T A^-1 B)_cm,
+    // the contraction partials of column c going to its input index
+    std::vector<int32_t> slot(r);
+    for (int c = 0; c < r; ++c) slot[c] = Y.col[c].second;
+    std::vector<GemmTask> cg;
+    {
+      GemmTask t = gemm(BK + Y.scu, r, nullptr, Mi, BK + Y.sub, Mi, r, Mi, Mo,
+                        G_TRANS_A | G_B_EXT | G_CONTRACT | G_NO_STORE);
+      t.aux = BK + Y.sub;
+      t.auxmap = IP(bl.add(slot));
+      add_tiles(cg, t);
+    }
+    for (int lvl = 0; lvl <= H_; ++lvl) {
+      AugLevel &L = SP.lv[lvl];
+      L.zero = bl.add(zr[lvl]); L.nzero = (int)zr[lvl].size();
+      L.one = bl.add(ones[lvl]); L.none = (int)ones[lvl].size();
+      L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
+      L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
+    }
+    SP.cg = bl.add(cg); SP.ncg = (int)cg.size();
+  }
+  const int64_t cbeg_off = bl.add(param_begin, (size_t)(n_params + 1) * sizeof(int32_t));
+  grow(B->blob, B->blob_bytes, (int64_t)bl.h.size());
+  char *base = B->blob;
+  auto rb_i = [&](const int32_t *&ptr) {
+    if (ptr) ptr = reinterpret_cast<const int32_t *>(base + (intptr_t)ptr);
+  };
+  for (int n = 0; n < nsub; ++n) {
+    AugSubPlan &SP = subs[n];
+    if (SP.r == 0) continue;
+    for (AugLevel &L : SP.lv) {
+      GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + L.g2);
+      for (int k = 0; k < L.ng2; ++k) rb_i(t[k].crowmap);
+    }
+    GemmTask *t = reinterpret_cast<GemmTask *>(bl.h.data() + SP.cg);
+    for (int k = 0; k < SP.ncg; ++k) rb_i(t[k].auxmap);
+  }
+  HIPCHK(hipMemcpy(B->blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(sig, col_sigma, (size_t)n_cols * sizeof(double), hipMemcpyHostToDevice));
+
+  Profiler &pr = h->prof;
+  const cplx *G = reinterpret_cast<const cplx *>(dfdS_dev);
+  HIPCHK(launch_fill_int(P.status, 0, s));
+  for (int n = 0; n < nsub; ++n) {
+    const AugSubPlan &SP = subs[n];
+    HIPCHK(launch_zero_flat(B->blocks, block_max, s));
+    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, false, &SP.lv, B->blob);
+    if (n == 0 && S_dev) enqueue_schur(P, false, S_dev, pr, s, Mo, Mi);
+    if (SP.ncg > 0)
+      pr.run(P_CONTRACT, s, [&] {
+        return launch_gemm(reinterpret_cast<const GemmTask *>(B->blob + SP.cg), SP.ncg, 0, INT_MAX, G, s, false, part,
+                           n_cols, false);
+      });
+  }
+  pr.run(P_CONTRACT, s, [&] {
+    hipError_t e = launch_reduce_partials(part, nblk, n_cols, 1.0, v, s);
+    if (e == hipSuccess)
+      e = launch_param_sum(reinterpret_cast<const int32_t *>(B->blob + cbeg_off), n_params, sig, v, dfdp_dev, s);
+    return e;
+  });
+  int st[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(st, P.status, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (pr.on) pr.collect();
+  h->n_factor += nsub;
+  if (st[1] & ST_BAD_EPS) {
+    h->state = 0;
+    return fail(APF_EINVAL, "the permittivity has a zero or non-finite value");
+  }
+  if (st[0]) {
+    h->state = 0;
+    return fail(APF_ESINGULAR, "zero or non-finite pivot in a pivot block");
+  }
+  h->state = 2;
+  h->mixed = false;
+  h->refined = false;
+  return APF_OK;
+}
+
+extern "C" apf_status apf_grad_augmented(apf_handle *h, int32_t n_cols, const int32_t *col_pixel,
+                                         const double *col_sigma, int32_t n_params, const int32_t *param_begin,
+                                         int32_t n_sub, int32_t flags, const double *dfdS_dev, double *S_dev,
+                                         double *dfdp_dev, int32_t *n_sub_used, void *stream) {
+  if (!h || !col_pixel || !col_sigma || !param_begin || !dfdS_dev || !dfdp_dev)
+    return fail(APF_EINVAL, "null argument");
+  if (n_cols < 1 || n_params < 1) return fail(APF_EINVAL, "need at least one column and one parameter");
+  if (n_sub < 0) return fail(APF_EINVAL, "n_sub must be >= 0");
+  if (flags & ~APF_AUG_SKIP_UU) return fail(APF_EINVAL, "unknown flags");
+  if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
+  int32_t used = 0;
+  apf_status st = guarded([&]() -> apf_status {
+    return augmented_grad(h, n_cols, col_pixel, col_sigma, n_params, param_begin, n_sub, flags, dfdS_dev, S_dev,
+                          dfdp_dev, (hipStream_t)stream, &used);
+  });
+  if (n_sub_used) *n_sub_used = used;
+  return st;
+}
+
+extern "C" apf_status apf_ridges_grad_augmented(apf_handle *h, const double *edges_dev, int32_t n_edges,
+                                                int32_t mirror, double eps_ridge, double eps_gap, int32_t n_sub,
+                                                int32_t flags, const double *dfdS_dev, double *S_dev,
+                                                double *dfdp_dev, int32_t *n_sub_used, void *stream) {
+  if (apf_status st = check_ridges(h, edges_dev, n_edges, mirror)) return st;
+  if (!dfdS_dev || !dfdp_dev) return fail(APF_EINVAL, "null argument");
+  if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
+  return guarded([&]() -> apf_status {
+    // U_k: the pixels of the cells holding edge k (and its mirror image) on
+    // every design row, with Sigma = dA/dp = -h^2 deps/dp: -/+(eps_ridge -
+    // eps_gap) for a left / right edge, the image moving by -1
+    std::vector<double> e(n_edges);
+    HIPCHK(hipMemcpyAsync(e.data(), edges_dev, n_edges * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    const int nx = h->d.nx, nrows = h->d.design_row1 - h->d.design_row0, nfull = mirror ? 2 * n_edges : n_edges;
+    const double de = eps_ridge - eps_gap, h2 = h->phys.h2;
+    auto cell = [&](double x) { int c = (int)std::floor(x + 0.5) % nx; return c < 0 ? c + nx : c; };
+    auto edge = [&](int q) { return (!mirror || q < n_edges) ? e[q] : (double)nx - e[2 * n_edges - 1 - q]; };
+    std::vector<int32_t> pix, pbeg(1, 0);
+    std::vector<double> sig;
+    for (int k = 0; k < n_edges; ++k) {
+      const int ck = cell(e[k]);
+      double sk = k % 2 == 0 ? -de : de;
+      int ci = -1;
+      double si = 0.0;
+      if (mirror) {
+        const int q = nfull - 1 - k;
+        ci = cell(edge(q));
+        si = -(q % 2 == 0 ? -de : de);
+        if (ci == ck) { sk += si; ci = -1; }
+      }
+      for (int rr = 0; rr < nrows; ++rr) {
+        pix.push_back(rr * nx + ck);
+        sig.push_back(-h2 * sk);
+        if (ci >= 0) {
+          pix.push_back(rr * nx + ci);
+          sig.push_back(-h2 * si);
+        }
+      }
+      pbeg.push_back((int32_t)pix.size());
+    }
+    int32_t used = 0;
+    apf_status st = augmented_grad(h, (int32_t)pix.size(), pix.data(), sig.data(), n_edges, pbeg.data(), n_sub, flags,
+                                   dfdS_dev, S_dev, dfdp_dev, (hipStream_t)stream, &used);
+    if (n_sub_used) *n_sub_used = used;
+    return st;
+  });
+}
+
 extern "C" apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk) {
   if (!h) return fail(APF_EINVAL, "null handle");
   if (max_chunk < 0 || (max_chunk > 0 && max_chunk % 64 != 0))
@@ -2022,6 +2456,7 @@ extern "C" apf_status apf_set_profiling(apf_handle *h, int32_t on) {
 extern "C" apf_status apf_destroy(apf_handle *h) {
   if (!h) return APF_OK;
   forget_batches_of(h);
+  forget_aug_of(h);
   free_plan(h->plan);
   delete h;
   return APF_OK;

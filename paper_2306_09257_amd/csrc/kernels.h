@@ -51,6 +51,13 @@ hipError_t launch_contract_rows(const int32_t *erow, int64_t n, const cplx *Lam,
 hipError_t launch_copy(const CopyRange *r, int n, hipStream_t s);
 hipError_t launch_fill_double(double *p, int n, double v, hipStream_t s);
 
+// parameter-augmented factorization (Eq. (4)): unit entries of U and U^T in
+// the augmented panels; Eq. (3) summed per parameter
+hipError_t launch_set_one(cplx *const *p, int n, hipStream_t s);
+hipError_t launch_zero_flat(cplx *p, int64_t n, hipStream_t s);   // n contiguous complex zeros
+hipError_t launch_param_sum(const int32_t *cbeg, int np, const double *sigma, const double *v, double *dfdp,
+                            hipStream_t s);
+
 // beam-splitter workload: Eq. (5) figure of merit, ridge permittivity and
 // the chain rule to the edge positions (see include/apf.h)
 hipError_t launch_splitter_fom(const cplx *S, const int32_t *in_ord, const int32_t *out_ord, int n_in, int n_out,

@@ -1213,6 +1213,27 @@ __global__ void k_fill_double(double *p, int n, double v) {
 }
 
 // ---------------------------------------------------------------------------
+// Parameter-augmented factorization (Eq. (4)): unit entries of the singular
+// vectors U (columns) and U^T (rows) in the fronts' augmented panels, and
+// Eq. (3) summed per parameter.
+// ---------------------------------------------------------------------------
+__global__ void k_set_one(cplx *const *p, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) st2(p[t], make_double2(1.0, 0.0));
+}
+
+// df/dp_k = -2 sum over the columns c of parameter k of sigma_c Re(v_c),
+// v_c = sum_m (C A^-1 U)^T dF/dS ... (U^T A^-1 B) of column c; a parameter's
+// columns are the range [cbeg[k], cbeg[k + 1]).
+__global__ void k_param_sum(const int32_t *cbeg, int np, const double *sigma, const double *v, double *dfdp) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  double acc = 0.0;
+  for (int c = cbeg[k]; c < cbeg[k + 1]; ++c) acc += sigma[c] * v[c];
+  dfdp[k] = -2.0 * acc;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
@@ -1412,6 +1433,25 @@ hipError_t launch_copy(const CopyRange *r, int n, hipStream_t s) {
 hipError_t launch_fill_double(double *p, int n, double v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_double, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_one(cplx *const *p, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_one, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_param_sum(const int32_t *cbeg, int np, const double *sigma, const double *v, double *dfdp,
+                            hipStream_t s) {
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_param_sum, dim3((np + 255) / 256), dim3(256), 0, s, cbeg, np, sigma, v, dfdp);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_flat(cplx *p, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_zero, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<double2 *>(p), n);
   return hipGetLastError();
 }
 

@@ -120,11 +120,21 @@ def _mut_sampled_adjoint_columns(monkeypatch):
     monkeypatch.setattr(oapf, "grad_sampled_inputs", bad)
 
 
+def _mut_augmented_blocks(monkeypatch):
+    orig = oapf.grad_augmented_params
+
+    def bad(prob, eps, G, col_pixel, col_sigma, param_begin, n_sub):
+        d, S = orig(prob, eps, np.conj(G), col_pixel, col_sigma, param_begin, n_sub)   # dF/dS conjugated
+        return d, S
+    monkeypatch.setattr(oapf, "grad_augmented_params", bad)
+
+
 def _sampled_pin():
     pins.test_sampled_input_gradient_equals_the_full_gradient(16, 60, 0.15, "row")
 
 
 MUTATIONS = {
+    "augmented_conj": (_mut_augmented_blocks, [pins.test_augmented_parameter_gradient_pins]),
     "sampled_adjoint_columns": (_mut_sampled_adjoint_columns, [_sampled_pin]),
     "mirror_sign": (_mut_mirror_sign, [spins.test_jacobian_matches_finite_differences,
                                        spins.test_edge_gradient_matches_central_differences]),

@@ -257,6 +257,49 @@ def test_sampled_input_gradient_equals_the_full_gradient(nx, ny, dx, kind):
         assert np.abs(g_s - g_conv).max() < 1e-12 * scale
 
 
+def _param_spec(prob, rng, n_params=7, per=(1, 4)):
+    """A random parameterization eps(p) = eps0 + sum_k p_k J_k: parameter k
+    moves a few design pixels with weights J (possibly shared pixels)."""
+    npix = prob.n_design_rows * prob.nx
+    pix, jac, pb = [], [], [0]
+    for _ in range(n_params):
+        m = int(rng.integers(per[0], per[1] + 1))
+        pix.extend(rng.choice(npix, size=m, replace=False).tolist())
+        jac.extend(rng.uniform(-1.0, 1.0, size=m).tolist())
+        pb.append(len(pix))
+    return np.array(pix, dtype=np.int64), np.array(jac), np.array(pb)
+
+
+def test_augmented_parameter_gradient_pins():
+    """Eq. (4) with the N_sub division: independent of how U is divided,
+    equal to the chain rule through the per-pixel weighted-adjoint gradient,
+    and to central differences of f along each parameter."""
+    prob, eps, w = _tiny(nx=16, ny=60, seed=23, dx_over_lambda=0.15)
+    rng = np.random.default_rng(8)
+    pix, jac, pb = _param_spec(prob, rng)
+    sigma = -prob.h ** 2 * jac                       # dA_jj/dp = -h^2 deps_j/dp outside the PML
+    S, g_eps, f0 = oapf.solve_S_and_grad(prob, eps, w=w)
+    _, G = oapf.weighted_power(S, w)
+    runs = [oapf.grad_augmented_params(prob, eps, G, pix, sigma, pb, n) for n in (1, 2, 3, 7)]
+    scale = np.abs(runs[0][0]).max()
+    for d, S_aug in runs:
+        assert np.abs(d - runs[0][0]).max() < 1e-12 * scale
+        assert np.abs(S_aug - S).max() < 1e-12 * np.abs(S).max()
+    chain = np.array([np.sum(jac[pb[k]:pb[k + 1]] * g_eps.ravel()[pix[pb[k]:pb[k + 1]]]) for k in range(pb.size - 1)])
+    assert np.abs(runs[0][0] - chain).max() < 1e-12 * scale
+    r0, r1 = prob.design_row0, prob.design_row1
+    step = 1e-4
+    for k in range(pb.size - 1):
+        fs = []
+        for sgn in (1.0, -1.0):
+            e = eps.copy()
+            d = e[r0:r1].reshape(-1)
+            np.add.at(d, pix[pb[k]:pb[k + 1]], sgn * step * jac[pb[k]:pb[k + 1]])
+            e[r0:r1] = d.reshape(r1 - r0, prob.nx)
+            fs.append(oapf.weighted_power(oapf.scattering_matrix(prob, e), w)[0])
+        assert abs((fs[0] - fs[1]) / (2 * step) - runs[0][0][k]) < 1e-7 * scale
+
+
 def test_gradient_central_differences():
     prob, eps, w = _tiny(nx=12, ny=60, seed=6)
     _, g, _ = oapf.solve_S_and_grad(prob, eps, w=w)
