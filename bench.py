@@ -187,11 +187,50 @@ def cpu_baseline(prob_full, workload):
     }
 
 
+def batch_cpu_baseline(items):
+    """The oracle's S (one forward solve with all inputs, then the projection)
+    timed on six problems of the batch spread over its cost range; the two
+    coefficients of the column-block solver's cost (grid term nx ny^3,
+    channel term nx ny^2 M) are fitted to them by least squares and give the
+    whole batch's time."""
+    import numpy as np
+    import oracle.apf as oapf
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(i["num_threads"] for i in threadpool_info()) if threadpool_info() else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    terms = [(p.nx * p.ny ** 3, p.nx * p.ny ** 2 * p.n_in) for p, _, _ in items]
+    order = np.argsort([t[0] + t[1] for t in terms])
+    pick = [int(order[int(round(q * (len(order) - 1) * 0.5))]) for q in np.linspace(0.0, 1.0, 6)]
+    rows, ts = [], []
+    for i in pick:
+        prob, eps, _ = items[i]
+        t0 = time.perf_counter()
+        oapf.scattering_matrix(prob, eps, solver=oapf.make_solver(prob, eps, "column"))
+        ts.append(time.perf_counter() - t0)
+        rows.append(terms[i])
+    coef, *_ = np.linalg.lstsq(np.array(rows, dtype=float), np.array(ts), rcond=None)
+    pred = np.array(rows, dtype=float) @ coef
+    total = float(np.array(terms, dtype=float).sum(axis=0) @ coef)
+    return {
+        "value": len(items) / total, "unit": "factorizations/s", "cores": int(cores), "kind": "oracle",
+        "cpu_model": cpu_model_name(),
+        "sample": "oracle S on problems " + ", ".join(f"{items[i][0].nx}x{items[i][0].ny} ({items[i][0].n_in} ch) "
+                                                      f"{t:.2f} s" for i, t in zip(pick, ts))
+                  + f"; least-squares fit of t = a nx ny^3 + b nx ny^2 M (a = {coef[0]:.3e}, b = {coef[1]:.3e}), "
+                  f"worst fit error {100 * float(np.max(np.abs(pred - ts) / ts)):.0f}%; whole batch {total:.0f} s",
+        "sample_seconds": float(sum(ts)),
+    }
+
+
 def bench_batch(args):
     """64 independent problems of uneven size (nx 120..4800, ny 60/92/140,
     lambda/lambda0 in [0.9, 1.1]) factorized by one batched call per step;
-    value = problems factorized per second (S of every problem).  The same
-    problems factorized one call each are timed beside it."""
+    value = problems factorized per second (S of every problem), after the
+    autotuner picked the GEMM kernel forms of the merged plan (outside the
+    timed region).  The same steps with the fixed rule, and the problems
+    factorized one call each, are timed beside it."""
     import torch
     from paper_2306_09257_amd import binding, inputs
     spec = WORKLOADS[args.workload]
@@ -208,21 +247,39 @@ def bench_batch(args):
         outs.append(torch.empty((prob.n_out, prob.n_in), dtype=torch.complex128, device=dev))
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
-    binding.factor_schur_batched(apfs, outs)      # merged plan + graph capture
-    for _ in range(args.warmup):
-        binding.factor_schur_batched(apfs, outs)
-    torch.cuda.synchronize()
 
     def step():
         for a, e in zip(apfs, epss):
             a.assemble(e)
         binding.factor_schur_batched(apfs, outs)
 
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    def timed():
+        binding.factor_schur_batched(apfs, outs)      # merged plan + graph capture
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def gemm_profile():
+        # one eager step with the GEMM launches timed (profiling disables the graph)
+        apfs[0].set_profiling(True, gemm_only=True)
         step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        p = apfs[0].profile()
+        apfs[0].set_profiling(False)
+        return p["gemm_factor"][0] + p["gemm_schur"][0], p["gemm_factor"][1] + p["gemm_schur"][1]
+
+    dt_fixed = timed()
+    gemm_ms_fixed, _ = gemm_profile()
+    t0 = time.perf_counter()
+    binding.autotune(apfs, reps=2)
+    t_tune = time.perf_counter() - t0
+    dt = timed()
+    gemm_ms, gemm_launches = gemm_profile()
     # the same problems, one factorization call each
     t1 = time.perf_counter()
     for _ in range(args.steps):
@@ -233,6 +290,7 @@ def bench_batch(args):
     dt_seq = time.perf_counter() - t1
     n = len(items)
     cm = sum(a.query("gemm_cmacs_factor") + a.query("gemm_cmacs_schur") for a in apfs)
+    achieved = 8.0 * cm / (gemm_ms * 1e-3) / 1e12
     out = {
         "metric": "APF factorizations/sec (S), batch of uneven problems",
         "value": n * args.steps / dt, "unit": "factorizations/s", "n_gpus": 1, "steps": args.steps,
@@ -243,11 +301,20 @@ def bench_batch(args):
                    "nx_range": [min(p.nx for p, _, _ in items), max(p.nx for p, _, _ in items)],
                    "channels_range": [min(p.n_in for p, _, _ in items), max(p.n_in for p, _, _ in items)],
                    "precision": "fp64"},
+        "roofline": {"kernel": "k_gemm / k_gemm_k3 (merged batched complex FP64 MFMA GEMMs of a step)",
+                     "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "flop_per_step": 8.0 * cm, "launches_per_step": gemm_launches,
+                     "avg_launch_ms": gemm_ms / max(gemm_launches, 1),
+                     "gemm_ms_per_step": gemm_ms, "gemm_ms_per_step_fixed_rule": gemm_ms_fixed},
+        "fixed_rule_ms_per_step": 1e3 * dt_fixed / args.steps,
+        "autotune_s": t_tune,
         "sequential_ms_per_step": 1e3 * dt_seq / args.steps,
         "batched_speedup": dt_seq / dt,
-        "gemm_tflops_executed": 8.0 * cm * args.steps / dt / 1e12,
         "setup_s": t_plan,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batch_cpu_baseline(items)
     print(json.dumps(out), flush=True)
 
 

@@ -299,6 +299,30 @@ apf_status apf_ridges_grad_augmented(apf_handle *h, const double *edges_dev, int
                                      int32_t flags, const double *dfdS_dev, double *S_dev,
                                      double *dfdp_dev, int32_t *n_sub_used, void *stream);
 
+/* Autotuner of the GEMM kernel form.  Every GEMM task list of a plan runs
+ * in one of three forms: 0 the four-product complex kernel at four
+ * workgroups per CU, 1 the three-product (Karatsuba) form on the deep-K
+ * kernel at three workgroups per CU, 2 the four-product form on the deep-K
+ * kernel (the occupancy variant).  The tile is fixed at 64 x 64 (2 x 2 MFMA
+ * blocks of 16 x 16 per wave, four waves).  apf_autotune times every list in
+ * every form with HIP events over `reps` runs of the work the plan does --
+ * for n = 1 apf_factor_schur (FP64) and apf_grad of hs[0], for n > 1 the
+ * batched factorization of hs[0..n) -- groups the lists into buckets (mean k
+ * extent of a tile, log2; number of tiles, log2), picks the fastest form per
+ * bucket, applies it and, if save_path is not NULL, writes the table as text.
+ * apf_tuning_apply reads such a table and applies it to the same kind of
+ * plan without timing (buckets missing from the table keep their form).
+ * Both synchronise `stream` and reset the handle's profiling counters; the
+ * timing runs overwrite the factors (assemble again before the next
+ * apf_factor_schur if the permittivity changed).  A form changes only
+ * rounding (the three-product form rounds differently from the others), so
+ * after a batched autotune the batched and single factorizations agree to
+ * rounding, not bit for bit.  Requires apf_assemble on every handle
+ * (APF_ESTATE); APF_EINVAL for reps outside [1, 100] or an unreadable
+ * table. */
+apf_status apf_autotune(apf_handle *const *hs, int32_t n, int32_t reps, const char *save_path, void *stream);
+apf_status apf_tuning_apply(apf_handle *const *hs, int32_t n, const char *path, void *stream);
+
 /* Cap the right-hand-side chunk of the gradient sweeps (0: the default, as
  * many columns as half of the free device memory holds).  The sweep arrays
  * X and V hold one row per sweep pivot and `chunk` columns each; apf_grad

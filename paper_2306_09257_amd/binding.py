@@ -31,7 +31,7 @@ ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur",
                 "apf_weighted_power", "apf_splitter_fom", "apf_group_fom", "apf_ridges_eps", "apf_ridges_grad",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
                 "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement",
-                "apf_grad_augmented", "apf_ridges_grad_augmented")
+                "apf_grad_augmented", "apf_ridges_grad_augmented", "apf_autotune", "apf_tuning_apply")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow", "refine")
 
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_rhs_chunk.argtypes = [vp, i32]
     lib.apf_set_lowrank.argtypes = [vp, i32]
     lib.apf_set_refinement.argtypes = [vp, i32, dbl]
+    lib.apf_autotune.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.c_char_p, vp]
+    lib.apf_tuning_apply.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_char_p, vp]
     lib.apf_grad_augmented.argtypes = [vp, i32, vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), vp]
     lib.apf_ridges_grad_augmented.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, i32, vp, vp, vp,
                                               ctypes.POINTER(i32), vp]
@@ -313,6 +315,22 @@ def weighted_power_noalloc(S, w, f=None, G=None):
         G = torch.empty_like(S)
     _check(lib.apf_weighted_power_noalloc(_ptr(S), _ptr(w), S.numel(), _ptr(f), _ptr(G), _stream()))
     return f, G
+
+
+def autotune(apfs, reps: int = 3, save_path: Optional[str] = None):
+    """Time the GEMM lists of the plan these handles run (one handle: its
+    factorization and gradient; several: their batched factorization) in each
+    kernel form, apply the fastest per bucket and optionally save the table."""
+    lib = load_library()
+    hs = (ctypes.c_void_p * len(apfs))(*[a._h.value for a in apfs])
+    _check(lib.apf_autotune(hs, len(apfs), int(reps), save_path.encode() if save_path else None, _stream()))
+
+
+def tuning_apply(apfs, path: str):
+    """Apply a saved autotune table to the plan these handles run."""
+    lib = load_library()
+    hs = (ctypes.c_void_p * len(apfs))(*[a._h.value for a in apfs])
+    _check(lib.apf_tuning_apply(hs, len(apfs), path.encode(), _stream()))
 
 
 def factor_schur_batched(apfs, S_list=None, precision: int = APF_FP64):

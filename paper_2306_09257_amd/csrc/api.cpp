@@ -103,7 +103,8 @@ struct LevelTasks {
   // into the same parent rows as the first children's (g2) and run after them
   int64_t zero = -1, scat = -1, pan = -1, g1 = -1, g2 = -1, g2b = -1;
   int nzero = 0, nscat = 0, npan = 0, ng1 = 0, ng2 = 0, ng2b = 0;
-  bool deep1 = false, deep2 = false, deep2b = false;   // lists run by the three-product kernel
+  char deep1 = 0, deep2 = 0, deep2b = 0;   // lists run by the deep-K kernel (k_gemm_k3)
+  int id1 = -1, id2 = -1, id2b = -1;       // the lists' entries in the plan's tunable-list table
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
   LevelTasks() {
@@ -129,8 +130,23 @@ enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_INVERSE, P_GEMM_FACTOR, P_GEMM
 const char *const kProfNames[P_NCLASS] = {"stencil", "zero", "assemble", "inverse", "gemm_factor",
                                           "gemm_schur", "gemm_sweep", "contract", "wpow", "refine"};
 
+// A GEMM task list of a plan that the autotuner may run in another kernel
+// form: 0 the four-product kernel at four workgroups per CU (k_gemm), 1 the
+// three-product form on the deep-K kernel (three per CU), 2 the four-product
+// form on the deep-K kernel.
+struct TunableList {
+  char *blob = nullptr;      // device blob holding the tasks
+  int64_t off = -1;
+  int n = 0;
+  char *deep = nullptr;      // launch flag: 1 = the deep-K kernel
+};
+
 struct Profiler {
   bool on = false;
+  int cur_tag = -1;          // tunable-list id of the launches that follow (-1: none)
+  bool record = false;       // keep (tag, ms) of every timed launch in `trace`
+  std::vector<std::pair<int, float>> trace;
+  std::vector<int> tags;     // per mark
   bool gemm_only = false;    // time only the GEMM-family launches
   static bool gemm_class(int cls) { return cls == P_GEMM_FACTOR || cls == P_GEMM_SCHUR || cls == P_GEMM_SWEEP; }
   std::vector<hipEvent_t> pool;
@@ -160,21 +176,27 @@ struct Profiler {
     HIPCHK(fn());
     HIPCHK(hipEventRecord(b, s));
     marks.push_back({cls, (int)i0});
+    tags.push_back(cur_tag);
   }
   void collect() {
-    for (auto &m : marks) {
+    for (size_t i = 0; i < marks.size(); ++i) {
+      const auto &m = marks[i];
       float t = 0.f;
       HIPCHK(hipEventSynchronize(pool[m.second + 1]));
       HIPCHK(hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]));
       ms[m.first] += t;
       count[m.first] += 1;
+      if (record) trace.push_back({tags[i], t});
     }
     marks.clear();
+    tags.clear();
     used = 0;
   }
   void reset() {
     for (int k = 0; k < P_NCLASS; ++k) { ms[k] = 0; count[k] = 0; }
     marks.clear();
+    tags.clear();
+    trace.clear();
     used = 0;
   }
   ~Profiler() {
@@ -252,6 +274,10 @@ struct Plan {
   // from the top, the U1t and Qt products (wu, wq) and the gather of the
   // children's Wt with the fronts' gradient (wp)
   std::vector<char> swl_deep;
+  std::vector<int> swl_id, wu_id, wq_id;
+  char vinit_deep = 1, schur_deep = 1;      // the weighted adjoint source and the Schur partials
+  int vinit_id = -1, schur_id = -1;
+  std::vector<TunableList> tl;               // every tunable GEMM list of the plan
   std::vector<int64_t> swtb;
   std::vector<int> nswtb;
   std::vector<int64_t> wu, wq, wp;
@@ -1363,6 +1389,28 @@ static void build_plan(apf_handle *H) {
   P.nfronts = nf;
   HIPCHK(hipMalloc(&P.blob, bl.h.size()));
   base = P.blob;
+  {
+    auto reg = [&](int64_t off, int n, char *deep) -> int {
+      if (n <= 0) return -1;
+      P.tl.push_back({P.blob, off, n, deep});
+      return (int)P.tl.size() - 1;
+    };
+    for (LevelTasks &L : P.lv) {
+      L.id1 = reg(L.g1, L.ng1, &L.deep1);
+      L.id2 = reg(L.g2, L.ng2, &L.deep2);
+      L.id2b = reg(L.g2b, L.ng2b, &L.deep2b);
+    }
+    P.swl_id.assign(P.swl.size(), -1);
+    for (size_t t = 0; t < P.swl.size(); ++t) P.swl_id[t] = reg(P.swl[t], P.nswl[t], &P.swl_deep[t]);
+    P.vinit_id = reg(P.vinit, P.nvinit, &P.vinit_deep);
+    P.schur_id = reg(P.gSsplit, P.ngSsplit, &P.schur_deep);
+    P.wu_id.assign(P.wu.size(), -1);
+    P.wq_id.assign(P.wq.size(), -1);
+    for (size_t l = 0; l < P.wu.size(); ++l) {
+      P.wu_id[l] = reg(P.wu[l], P.nwu[l], &P.wu_deep[l]);
+      P.wq_id[l] = reg(P.wq[l], P.nwq[l], &P.wq_deep[l]);
+    }
+  }
   // rebase the pointers into the integer section
   auto rebase = [&](const int32_t *&ptr) {
     if (ptr) ptr = reinterpret_cast<const int32_t *>(base + (intptr_t)ptr);
@@ -1494,9 +1542,11 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     for (int g = 0; g < 3; ++g) {
       const int64_t off = g == 0 ? L.g1 : (g == 1 ? L.g2 : L.g2b);
       const int n = g == 0 ? L.ng1 : (g == 1 ? L.ng2 : L.ng2b);
-      const bool deep = g == 0 ? L.deep1 : (g == 1 ? L.deep2 : L.deep2b);
+      const bool deep = (g == 0 ? L.deep1 : (g == 1 ? L.deep2 : L.deep2b)) != 0;
+      pr.cur_tag = g == 0 ? L.id1 : (g == 1 ? L.id2 : L.id2b);
       if (n > 0)
         pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32, nullptr, 0, deep); });
+      pr.cur_tag = -1;
       // the augmented panels' products after the main phase 1 (their inputs)
       // and phase 2 (no dependence either way)
       if (A && g < 2) {
@@ -1514,12 +1564,15 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
 static void enqueue_schur(const Plan &P, bool f32, double *S_dev, Profiler &pr, hipStream_t s, int Mo, int Mi) {
   // k split into segments of SPLIT_K rows: shorter, more numerous tasks than
   // one K_total-deep tile each, summed in FP64 afterwards
+  pr.cur_tag = P.schur_id;
   pr.run(P_GEMM_SCHUR, s, [&] {
-    hipError_t e = launch_gemm(P.at<GemmTask>(P.gSsplit), P.ngSsplit, 0, INT_MAX, nullptr, s, f32, nullptr, 0, true);
+    hipError_t e = launch_gemm(P.at<GemmTask>(P.gSsplit), P.ngSsplit, 0, INT_MAX, nullptr, s, f32, nullptr, 0,
+                               P.schur_deep != 0);
     if (e == hipSuccess)
       e = launch_sum_partials(P.spart, P.nseg, (int64_t)Mo * Mi, reinterpret_cast<cplx *>(S_dev), (int64_t)Mo * Mi, s);
     return e;
   });
+  pr.cur_tag = -1;
 }
 
 // One refined solve of the chunk's right-hand sides, in place on R.W:
@@ -1671,6 +1724,7 @@ struct BatchPlan {
   hipStream_t cap = nullptr;       // private stream the graph is captured on
   std::vector<double *> graph_S;   // outputs the graph was captured with
   bool graph_f32 = false;          // and its precision
+  std::vector<TunableList> tl;     // the merged factorization lists
   ~BatchPlan() {
     if (cap) (void)hipStreamDestroy(cap);
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -1744,6 +1798,16 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
   }
   B->fronts = bl.add(fd);
   HIPCHK(hipMalloc(&B->blob, bl.h.size()));
+  for (LevelTasks &L : B->lv) {
+    auto reg = [&](int64_t off, int n, char *deep) -> int {
+      if (n <= 0) return -1;
+      B->tl.push_back({B->blob, off, n, deep});
+      return (int)B->tl.size() - 1;
+    };
+    L.id1 = reg(L.g1, L.ng1, &L.deep1);
+    L.id2 = reg(L.g2, L.ng2, &L.deep2);
+    L.id2b = reg(L.g2b, L.ng2b, &L.deep2b);
+  }
   HIPCHK(hipMemcpy(B->blob, bl.h.data(), bl.h.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&B->status, sizeof(int)));
   return B;
@@ -1972,12 +2036,16 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     for (int m0 = 0; m0 < Mi; m0 += ch) {
       const int w = std::min(ch, Mi - m0);
       if (P.nvinit > 0)
-        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32, nullptr, 0, true); });
+        pr.cur_tag = P.vinit_id;
+        pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32, nullptr, 0, P.vinit_deep != 0); });
+        pr.cur_tag = -1;
       for (size_t t = 0; t < P.swl.size(); ++t) {
+        pr.cur_tag = P.swl_id[t];
         if (P.nswl[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] {
             return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, (int)P.ndesign, P.swl_deep[t] != 0);
           });
+        pr.cur_tag = -1;
         if (P.nswtb[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] { return launch_lowrank_w(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s); });
       }
@@ -1992,14 +2060,17 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     // and Qt would swamp it.
     for (int l = (int)P.wp.size() - 1; l >= 0; --l) {
       if (P.nwp[l] == 0) continue;
+      pr.cur_tag = P.wu_id[l];
       if (P.nwu[l] > 0)
         pr.run(P_GEMM_SWEEP, s, [&] {
           return launch_gemm(P.at<GemmTask>(P.wu[l]), P.nwu[l], 0, INT_MAX, nullptr, s, false, nullptr, 0, P.wu_deep[l] != 0);
         });
+      pr.cur_tag = P.wq_id[l];
       if (P.nwq[l] > 0)
         pr.run(P_GEMM_SWEEP, s, [&] {
           return launch_gemm(P.at<GemmTask>(P.wq[l]), P.nwq[l], 0, INT_MAX, nullptr, s, false, nullptr, 0, P.wq_deep[l] != 0);
         });
+      pr.cur_tag = -1;
       pr.run(P_CONTRACT, s, [&] { return launch_wprop(P.at<WFront>(P.wp[l]), P.nwp[l], two_h2, grad_dev, s); });
     }
     if (h->prof.on) h->prof.collect();
@@ -2412,6 +2483,193 @@ extern "C" apf_status apf_ridges_grad_augmented(apf_handle *h, const double *edg
     if (n_sub_used) *n_sub_used = used;
     return st;
   });
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: the kernel form of every tunable GEMM list (four-product at four
+// workgroups per CU, three-product or four-product on the deep-K kernel at
+// three), decided per bucket of lists (mean k extent of a tile, number of
+// tiles) from HIP-event times of the actual launches, saved as a text table.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kTuneForms = 3;
+
+// bucket of a list: (log2 of mean tile k over 16, rounded; log2 of the tile count)
+std::pair<int, int> tune_bucket(const TunableList &t) {
+  std::vector<GemmTask> v = fetch<GemmTask>(t.blob, t.off, t.n);
+  const double mk = std::max(1.0, mean_tile_k(v));
+  const int kb = std::max(0, std::min(9, (int)std::lround(std::log2(mk / 16.0))));
+  const int tb = std::max(0, std::min(20, (int)std::floor(std::log2((double)std::max(1, t.n)))));
+  return {kb, tb};
+}
+
+void set_form(TunableList &t, int form, hipStream_t s) {
+  *t.deep = form != 0;
+  HIPCHK(launch_set_k3(reinterpret_cast<GemmTask *>(t.blob + t.off), t.n, form == 1, s));
+}
+
+struct TuneRow { double ms[kTuneForms] = {0, 0, 0}; int lists = 0; int form = -1; };
+
+std::string table_text(const std::map<std::pair<int, int>, TuneRow> &tab) {
+  std::string out = "# APF GEMM autotune table: bucket (kb = round(log2(mean tile k / 16)), tb = floor(log2(tiles)))\n"
+                    "# -> form (0 four-product k_gemm, 1 three-product k_gemm_k3, 2 four-product k_gemm_k3)\n"
+                    "# kb tb form ms_form0 ms_form1 ms_form2 lists\n";
+  char b[256];
+  for (const auto &kv : tab) {
+    std::snprintf(b, sizeof b, "%d %d %d %.4f %.4f %.4f %d\n", kv.first.first, kv.first.second, kv.second.form,
+                  kv.second.ms[0], kv.second.ms[1], kv.second.ms[2], kv.second.lists);
+    out += b;
+  }
+  return out;
+}
+
+}  // namespace
+
+// The lists an autotune call works on, and the work that runs them: the
+// single plan (factorization, Schur product, gradient sweeps) for n = 1, the
+// merged batch plan (factorization levels) for n > 1.
+static apf_status autotune_impl(apf_handle *const *hs, int32_t n, int32_t reps, const char *load_path,
+                                const char *save_path, hipStream_t s) {
+  std::vector<TunableList> *tl = nullptr;
+  BatchPlan *B = nullptr;
+  if (n == 1) {
+    tl = &hs[0]->plan.tl;
+  } else {
+    std::vector<apf_handle *> v(hs, hs + n);
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto &b : g_batches)
+      if (b->hs == v) B = b.get();
+    if (!B) {
+      g_batches.push_back(build_batch(v));
+      B = g_batches.back().get();
+    }
+    tl = &B->tl;
+  }
+  std::vector<std::pair<int, int>> bucket(tl->size());
+  for (size_t i = 0; i < tl->size(); ++i) bucket[i] = tune_bucket((*tl)[i]);
+  std::map<std::pair<int, int>, TuneRow> tab;
+  if (load_path) {
+    FILE *f = std::fopen(load_path, "r");
+    if (!f) return fail(APF_EINVAL, std::string("cannot open ") + load_path);
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+      if (line[0] == '#') continue;
+      int kb, tb, form, lists;
+      double a, b, c;
+      if (std::sscanf(line, "%d %d %d %lf %lf %lf %d", &kb, &tb, &form, &a, &b, &c, &lists) == 7 && form >= 0 &&
+          form < kTuneForms) {
+        TuneRow r;
+        r.ms[0] = a; r.ms[1] = b; r.ms[2] = c; r.lists = lists; r.form = form;
+        tab[{kb, tb}] = r;
+      }
+    }
+    std::fclose(f);
+  } else {
+    // time every list in every form over `reps` runs of the work
+    Profiler &pr = hs[0]->prof;
+    const bool was_on = pr.on, was_gemm = pr.gemm_only;
+    std::vector<double *> Ss(n, nullptr);
+    double *G = nullptr, *grad = nullptr;
+    auto cleanup = [&] {
+      for (double *p : Ss) if (p) (void)hipFree(p);
+      if (G) (void)hipFree(G);
+      if (grad) (void)hipFree(grad);
+      pr.on = was_on; pr.gemm_only = was_gemm; pr.record = false; pr.reset();
+    };
+    try {
+      for (int i = 0; i < n; ++i)
+        HIPCHK(hipMalloc(&Ss[i], (int64_t)hs[i]->d.n_out * hs[i]->d.n_in * 2 * sizeof(double)));
+      if (n == 1) {
+        HIPCHK(hipMalloc(&G, (int64_t)hs[0]->d.n_out * hs[0]->d.n_in * 2 * sizeof(double)));
+        HIPCHK(hipMemset(G, 0, (int64_t)hs[0]->d.n_out * hs[0]->d.n_in * 2 * sizeof(double)));
+        HIPCHK(hipMalloc(&grad, std::max<int64_t>(hs[0]->plan.ndesign, 1) * sizeof(double)));
+      }
+      std::vector<std::vector<double>> t(kTuneForms, std::vector<double>(tl->size(), 0.0));
+      auto work = [&]() -> apf_status {
+        if (n == 1) {
+          apf_status st = apf_factor_schur(hs[0], APF_FP64, Ss[0], s);
+          if (st == APF_OK) st = apf_grad(hs[0], G, grad, s);
+          return st;
+        }
+        return apf_factor_schur_batched(hs, n, APF_FP64, Ss.data(), s);
+      };
+      for (int form = 0; form < kTuneForms; ++form) {
+        for (TunableList &l : *tl) set_form(l, form, s);
+        HIPCHK(hipStreamSynchronize(s));
+        pr.reset();
+        pr.on = true; pr.gemm_only = true; pr.record = false;   // eager launches (no graph replay)
+        apf_status st = work();                         // warm-up
+        if (st != APF_OK) { cleanup(); return st; }
+        pr.reset();
+        pr.on = true; pr.gemm_only = true; pr.record = true;
+        for (int r = 0; r < reps; ++r) {
+          st = work();
+          if (st != APF_OK) { cleanup(); return st; }
+        }
+        for (const auto &e : pr.trace)
+          if (e.first >= 0 && e.first < (int)tl->size()) t[form][e.first] += e.second / reps;
+        pr.record = false;
+        pr.reset();
+      }
+      for (size_t i = 0; i < tl->size(); ++i) {
+        TuneRow &r = tab[bucket[i]];
+        for (int form = 0; form < kTuneForms; ++form) r.ms[form] += t[form][i];
+        ++r.lists;
+      }
+      for (auto &kv : tab) {
+        int best = 0;
+        for (int form = 1; form < kTuneForms; ++form)
+          if (kv.second.ms[form] < kv.second.ms[best]) best = form;
+        kv.second.form = best;
+      }
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
+  }
+  // apply: lists in a bucket of the table take its form; others keep theirs
+  for (size_t i = 0; i < tl->size(); ++i) {
+    auto it = tab.find(bucket[i]);
+    if (it != tab.end() && it->second.form >= 0) set_form((*tl)[i], it->second.form, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (B) {
+    // the captured graph launches the kernels the old forms chose
+    if (B->exec) { HIPCHK(hipGraphExecDestroy(B->exec)); B->exec = nullptr; }
+    if (B->graph) { HIPCHK(hipGraphDestroy(B->graph)); B->graph = nullptr; }
+  } else {
+    forget_batches_of(hs[0]);   // merged plans copied the old task flags
+  }
+  if (save_path) {
+    FILE *f = std::fopen(save_path, "w");
+    if (!f) return fail(APF_EINVAL, std::string("cannot write ") + save_path);
+    const std::string txt = table_text(tab);
+    std::fputs(txt.c_str(), f);
+    std::fclose(f);
+  }
+  return APF_OK;
+}
+
+extern "C" apf_status apf_autotune(apf_handle *const *hs, int32_t n, int32_t reps, const char *save_path,
+                                   void *stream) {
+  if (!hs || n < 1) return fail(APF_EINVAL, "need at least one handle");
+  if (reps < 1 || reps > 100) return fail(APF_EINVAL, "reps must be in [1, 100]");
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i]) return fail(APF_EINVAL, "null handle");
+    if (hs[i]->state < 1) return fail(APF_ESTATE, "apf_assemble has not run on every handle");
+  }
+  return guarded([&]() { return autotune_impl(hs, n, reps, nullptr, save_path, (hipStream_t)stream); });
+}
+
+extern "C" apf_status apf_tuning_apply(apf_handle *const *hs, int32_t n, const char *path, void *stream) {
+  if (!hs || n < 1 || !path) return fail(APF_EINVAL, "need handles and a table path");
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i]) return fail(APF_EINVAL, "null handle");
+    if (!hs[i]->planned) return fail(APF_ESTATE, "apf_assemble has not run on every handle");
+  }
+  return guarded([&]() { return autotune_impl(hs, n, 1, path, nullptr, (hipStream_t)stream); });
 }
 
 extern "C" apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk) {

@@ -55,6 +55,8 @@ hipError_t launch_fill_double(double *p, int n, double v, hipStream_t s);
 // the augmented panels; Eq. (3) summed per parameter
 hipError_t launch_set_one(cplx *const *p, int n, hipStream_t s);
 hipError_t launch_zero_flat(cplx *p, int64_t n, hipStream_t s);   // n contiguous complex zeros
+// autotuner: set or clear G_K3 on n tasks
+hipError_t launch_set_k3(GemmTask *t, int n, bool on, hipStream_t s);
 hipError_t launch_param_sum(const int32_t *cbeg, int np, const double *sigma, const double *v, double *dfdp,
                             hipStream_t s);
 

@@ -1233,6 +1233,12 @@ __global__ void k_param_sum(const int32_t *cbeg, int np, const double *sigma, co
   dfdp[k] = -2.0 * acc;
 }
 
+// Set (on) or clear the three-product flag of n GEMM tasks (autotuner).
+__global__ void k_set_k3(GemmTask *t, int n, int on) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i].flags = on ? (t[i].flags | G_K3) : (t[i].flags & ~G_K3);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
@@ -1452,6 +1458,12 @@ hipError_t launch_zero_flat(cplx *p, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_group_zero, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<double2 *>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_k3(GemmTask *t, int n, bool on, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_k3, dim3((n + 255) / 256), dim3(256), 0, s, t, n, on ? 1 : 0);
   return hipGetLastError();
 }
 
