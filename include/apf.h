@@ -234,7 +234,13 @@ apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, int32_t n_edg
                            const double *grad_eps_dev, double *grad_edges_dev,
                            void *stream);
 
-/* (APF_MIXED_REFINED: the adjoint fields are refined like the forward ones,
+/* The weighted adjoint source C^T dF/dS of the sweep fronts is one dense
+ * product unless dF/dS has at most 32 nonzeros in every input column (and at
+ * most n_out / 8): then (an objective over a few target outputs per input)
+ * it is formed from compact per-column lists, the same sum without its zero
+ * terms.  Telling the two apart reads the column counts back, so apf_grad
+ * synchronises `stream` once before the sweeps.
+ * (APF_MIXED_REFINED: the adjoint fields are refined like the forward ones,
  * the call synchronises `stream` at its end to check the residuals and
  * returns APF_ENOTCONV when they miss the tolerance; grad_dev then holds the
  * gradient of the last iterate.)
@@ -344,15 +350,17 @@ apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk);
  * APF_EINVAL for max_iter outside [0, 16] or a bad tol. */
 apf_status apf_set_refinement(apf_handle *h, int32_t max_iter, double tol);
 
-/* Allow (on = 1, the default) or forbid (on = 0) the low-rank sweep
- * subtrees: channel-free sweep subtrees of up to two levels whose gradient
- * comes from the b x b product Wt = Y_bnd Lam_bnd^T of their root instead of
- * the Y and Lam sweeps (the same quantity, Eqs. (1)-(3), in another order of
- * operations; cheaper where b^2 < 2 p b summed over the subtree).  With 0
- * every sweep front runs the sweeps: for checking one route against the
- * other.  Call before the first apf_assemble (else APF_ESTATE); APF_EINVAL
- * for other values. */
-apf_status apf_set_lowrank(apf_handle *h, int32_t on);
+/* Depth of the low-rank sweep subtrees: channel-free sweep subtrees of up to
+ * `levels` levels (0, 1 or 2) whose gradient comes from the b x b product
+ * Wt = Y_bnd Lam_bnd^T of their root instead of the Y and Lam sweeps (the same
+ * quantity, Eqs. (1)-(3), in another order of operations; cheaper where
+ * b^2 < 2 p b summed over the subtree).  With 0 every sweep front runs the
+ * sweeps.  The dense propagation below a root multiplies the rounding error
+ * of its fields by the cancellation of both field reconstructions, which
+ * depends on dF/dS; the default depth is the library's default (see the
+ * design notes of the release).  Call before the first apf_assemble (else
+ * APF_ESTATE); APF_EINVAL for other values. */
+apf_status apf_set_lowrank(apf_handle *h, int32_t levels);
 
 /* Per-class HIP-event timing of the handle's launches (counters reset):
  * on = 0 off, 1 every launch, 2 only the GEMM-family launches (classes
@@ -391,13 +399,19 @@ const char *apf_last_error(void);
  *   three-product complex form, 6 real flops per complex multiply-add
  *   instead of 8), "gemm_cmacs_lowrank_w" (the part run by the low-rank W
  *   kernel, three-product on both paths),
+ *   "gemm_cmacs_vinit" (the dense weighted-adjoint-source product's part of
+ *   gemm_cmacs_sweep), "adjoint_source_sparse_k" (0 if the last apf_grad ran
+ *   that dense product, else the width of the compact column lists of a
+ *   dF/dS with at most 32 nonzeros per input column, at most n_out / 8),
  *   "lowrank_fronts" and "lowrank_roots" (sweep fronts served by the
  *   low-rank subtree products, and the subtrees' roots);
  *   with profiling on: "ms_<class>" and "launches_<class>", the summed
  *   HIP-event time and launch count since profiling was enabled, for the
  *   classes stencil, zero, assemble, inverse, gemm_factor, gemm_schur,
- *   gemm_sweep, contract, wpow (the children's contribution blocks are
- *   added into their parents by the gemm_factor launches). */
+ *   gemm_sweep, contract, wpow, refine (APF_MIXED_REFINED's solves and
+ *   residuals), adjoint_source (the sparse weighted adjoint source); the
+ *   children's contribution blocks are added into their parents by the
+ *   gemm_factor launches. */
 apf_status apf_query(apf_handle *h, const char *key, double *value);
 
 /* Structure export for host-side validation (host only, after apf_analyze).

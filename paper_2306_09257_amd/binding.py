@@ -33,7 +33,7 @@ ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur",
                 "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement",
                 "apf_grad_augmented", "apf_ridges_grad_augmented", "apf_autotune", "apf_tuning_apply")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
-                   "contract", "wpow", "refine")
+                   "contract", "wpow", "refine", "adjoint_source")
 
 
 class APFError(RuntimeError):
@@ -153,9 +153,11 @@ class APF:
         _check(self._lib.apf_set_rhs_chunk(self._h, int(max_chunk)))
         return self
 
-    def set_lowrank(self, on: bool):
-        """Allow or forbid the low-rank sweep subtrees (before the first assemble)."""
-        _check(self._lib.apf_set_lowrank(self._h, 1 if on else 0))
+    def set_lowrank(self, levels):
+        """Depth of the low-rank sweep subtrees (0 forbids them; False/True
+        mean 0 and 2), before the first assemble."""
+        lv = (2 if levels else 0) if isinstance(levels, bool) else int(levels)
+        _check(self._lib.apf_set_lowrank(self._h, lv))
         return self
 
     def set_refinement(self, max_iter: int, tol: float = 1e-10):

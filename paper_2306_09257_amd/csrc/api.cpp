@@ -126,9 +126,15 @@ constexpr int64_t SPLIT_K = 4096;      // k rows per partial block of the split 
 
 // Per-class HIP-event timing of the launches (off unless enabled).
 enum ProfClass { P_STENCIL, P_ZERO, P_ASSEMBLE, P_INVERSE, P_GEMM_FACTOR, P_GEMM_SCHUR, P_GEMM_SWEEP,
-                 P_CONTRACT, P_WPOW, P_REFINE, P_NCLASS };
+                 P_CONTRACT, P_WPOW, P_REFINE, P_VSRC, P_NCLASS };
 const char *const kProfNames[P_NCLASS] = {"stencil", "zero", "assemble", "inverse", "gemm_factor",
-                                          "gemm_schur", "gemm_sweep", "contract", "wpow", "refine"};
+                                          "gemm_schur", "gemm_sweep", "contract", "wpow", "refine",
+                                          "adjoint_source"};
+// A dF/dS with at most this many nonzeros in every input column (and at most
+// an eighth of the outputs) takes the sparse weighted-adjoint-source kernel.
+constexpr int kSparseG = 32;
+// Levels of the low-rank sweep subtrees unless apf_set_lowrank says otherwise.
+constexpr int kWMaxLevelsDefault = 1;
 
 // A GEMM task list of a plan that the autotuner may run in another kernel
 // form: 0 the four-product kernel at four workgroups per CU (k_gemm), 1 the
@@ -252,6 +258,12 @@ struct Plan {
   int32_t *perms = nullptr;   // pivot permutation of every front, at its first elimination index
   char *blob = nullptr;
   int *status = nullptr;      // [0]: pivot status of the last factorization; [1]: permittivity check of the last assembly
+  int32_t *g_nnz = nullptr;   // column-sparse dF/dS: nonzeros per input, their max, compact (row, value) lists
+  int *g_max = nullptr;
+  int32_t *g_idx = nullptr;
+  cplx *g_val = nullptr;
+  int last_sparse_k = 0;      // the last apf_grad's compact width (0: dense product)
+  double vinit_cmacs = 0;     // complex MACs of the dense weighted-adjoint-source product
   double *part = nullptr;
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
   int rhs_chunk = 0;
@@ -428,7 +440,7 @@ struct apf_handle {
   int state = 0;        // 0 analysed, 1 assembled, 2 factored
   bool mixed = false;   // precision of the factors held (APF_MIXED)
   int max_chunk = 0;    // cap on the right-hand-side chunk of the sweeps (0: memory decides)
-  bool lowrank = true;  // low-rank sweep subtrees allowed
+  int lowrank = kWMaxLevelsDefault;  // levels of a low-rank sweep subtree (0: none)
   int64_t n_factor = 0; // factorizations run on this handle (a caller can tell whether the factors changed)
   int refine_iters = 0; // > 0: the plan keeps every front's factors for APF_MIXED_REFINED
   double refine_tol = 0.0;
@@ -605,7 +617,7 @@ static double mean_tile_k(const std::vector<GemmTask> &v) {
 // run faster on the three-product kernel (fewer MFMAs) despite its lower
 // occupancy; shallower lists are bound by their loads and epilogues.
 constexpr double kDeepMeanK = 96.0;
-constexpr int kWMaxLevels = 2;   // levels of a low-rank sweep subtree
+constexpr int kWMaxLevels = 2;   // most levels of a low-rank sweep subtree
 // Flags every task of a deep list for the three-product form.  The flag is
 // per task, so a task rounds the same way in any launch that holds it
 // (single problems and merged batches alike).
@@ -861,6 +873,10 @@ static void build_plan(apf_handle *H) {
   HIPCHK(hipMalloc(&P.xc, std::max<int64_t>(P.xc_rows * Mo, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.vmap, std::max<int64_t>(P.xc_rows, 1) * sizeof(int32_t)));
   HIPCHK(hipMalloc(&P.status, 2 * sizeof(int)));
+  HIPCHK(hipMalloc(&P.g_nnz, (int64_t)Mi * sizeof(int32_t)));
+  HIPCHK(hipMalloc(&P.g_max, sizeof(int)));
+  HIPCHK(hipMalloc(&P.g_idx, (int64_t)Mi * kSparseG * sizeof(int32_t)));
+  HIPCHK(hipMalloc(&P.g_val, (int64_t)Mi * kSparseG * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.part, 1024 * sizeof(double)));
   HIPCHK(hipMemset(P.status, 0, 2 * sizeof(int)));
 
@@ -939,7 +955,7 @@ static void build_plan(apf_handle *H) {
       const double p = F.p(), b = F.b();
       double direct = 2.0 * p * b * M, dsub = b * b * p + p * b * (p + b);
       // (a root forms Wt in one 64 x 64 tile: b <= 64)
-      bool ok = H->lowrank && !F.hasB && !F.hasC && F.b() > 0 && F.b() <= 64;
+      bool ok = H->lowrank > 0 && !F.hasB && !F.hasC && F.b() > 0 && F.b() <= 64;
       for (int c = 0; c < F.nchild; ++c) {
         const int ch = F.child[c];
         if (!S.fronts[ch].sweep) continue;
@@ -947,7 +963,7 @@ static void build_plan(apf_handle *H) {
         dsub += dense[ch];
         sdepth[f] = std::max(sdepth[f], sdepth[ch] + 1);
       }
-      ok = ok && sdepth[f] < kWMaxLevels;
+      ok = ok && sdepth[f] < std::min(H->lowrank, kWMaxLevels);
       dense[f] = dsub;
       const double viaW = b * b * M + dsub;
       pick[f] = ok && viaW < direct;
@@ -1302,6 +1318,7 @@ static void build_plan(apf_handle *H) {
     add_tiles_xcd(vinit, ti);
     cm_vinit = g_cmacs_acc * ((double)Mi / P.rhs_chunk);
     cm_sweep += cm_vinit;
+    P.vinit_cmacs = cm_vinit;
   }
   P.gemm_cmacs_factor = cm_factor;
   P.gemm_cmacs_sweep = cm_sweep + cm_wprop;
@@ -1464,7 +1481,7 @@ static void build_plan(apf_handle *H) {
 static void free_plan(Plan &P) {
   const Refine &R = P.R;
   void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
-                  P.xc, P.vmap, P.gpart, P.lrW, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
+                  P.xc, P.vmap, P.gpart, P.lrW, P.g_nnz, P.g_max, P.g_idx, P.g_val, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
                   R.elim, R.norms, R.blob};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -2033,12 +2050,33 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     }
     HIPCHK(launch_row_map(P.vmap, P.at<int32_t>(P.vmap_base), P.at<int32_t>(P.vmap_pidx), P.perms, P.xc_rows, s));
     const bool f32 = h->mixed;
+    // a dF/dS with few nonzeros per input column (a few target orders per
+    // input) forms the weighted adjoint source from compact column lists
+    int K = 0;
+    if (P.nvinit > 0) {
+      const int Mo = h->d.n_out;
+      int mx = 0;
+      HIPCHK(launch_fill_int(P.g_max, 0, s));
+      HIPCHK(launch_col_nnz(G, Mo, Mi, P.g_nnz, P.g_max, s));
+      HIPCHK(hipMemcpyAsync(&mx, P.g_max, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (mx <= kSparseG && 8 * mx <= Mo) {
+        K = std::max(mx, 1);
+        HIPCHK(launch_col_compact(G, Mo, Mi, K, P.g_idx, P.g_val, s));
+      }
+    }
+    P.last_sparse_k = K;
     for (int m0 = 0; m0 < Mi; m0 += ch) {
       const int w = std::min(ch, Mi - m0);
-      if (P.nvinit > 0)
+      if (P.nvinit > 0 && K > 0) {
+        pr.run(P_VSRC, s, [&] {
+          return launch_sparse_vinit(P.xc, h->d.n_out, P.xc_rows, P.vmap, P.g_idx, P.g_val, K, m0, w, P.V, ch, s);
+        });
+      } else if (P.nvinit > 0) {
         pr.cur_tag = P.vinit_id;
         pr.run(P_GEMM_SWEEP, s, [&] { return launch_gemm(P.at<GemmTask>(P.vinit), P.nvinit, m0, w, G, s, f32, nullptr, 0, P.vinit_deep != 0); });
         pr.cur_tag = -1;
+      }
       for (size_t t = 0; t < P.swl.size(); ++t) {
         pr.cur_tag = P.swl_id[t];
         if (P.nswl[t] > 0)
@@ -2681,11 +2719,11 @@ extern "C" apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk) {
   return APF_OK;
 }
 
-extern "C" apf_status apf_set_lowrank(apf_handle *h, int32_t on) {
+extern "C" apf_status apf_set_lowrank(apf_handle *h, int32_t levels) {
   if (!h) return fail(APF_EINVAL, "null handle");
-  if (on != 0 && on != 1) return fail(APF_EINVAL, "low-rank switch must be 0 or 1");
+  if (levels < 0 || levels > kWMaxLevels) return fail(APF_EINVAL, "low-rank subtree levels must be 0, 1 or 2");
   if (h->planned) return fail(APF_ESTATE, "the sweep plan is already built (apf_assemble has run)");
-  h->lowrank = on != 0;
+  h->lowrank = levels;
   return APF_OK;
 }
 
@@ -2755,6 +2793,8 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
   else if (k == "gemm_cmacs_schur") *value = h->planned ? h->plan.gemm_cmacs_schur : -1.0;
   else if (k == "gemm_cmacs_sweep") *value = h->planned ? h->plan.gemm_cmacs_sweep : -1.0;
   else if (k == "gemm_cmacs_k3") *value = h->planned ? h->plan.gemm_cmacs_k3 : -1.0;
+  else if (k == "gemm_cmacs_vinit") *value = h->planned ? h->plan.vinit_cmacs : -1.0;
+  else if (k == "adjoint_source_sparse_k") *value = h->planned ? (double)h->plan.last_sparse_k : -1.0;
   else if (k == "gemm_cmacs_lowrank_w") *value = h->planned ? h->plan.gemm_cmacs_w : -1.0;
   else if (k.rfind("ms_", 0) == 0 || k.rfind("launches_", 0) == 0) {
     bool ms = k[0] == 'm';

@@ -55,6 +55,11 @@ hipError_t launch_fill_double(double *p, int n, double v, hipStream_t s);
 // the augmented panels; Eq. (3) summed per parameter
 hipError_t launch_set_one(cplx *const *p, int n, hipStream_t s);
 hipError_t launch_zero_flat(cplx *p, int64_t n, hipStream_t s);   // n contiguous complex zeros
+// weighted adjoint source from a column-sparse dF/dS
+hipError_t launch_col_nnz(const cplx *G, int n_out, int n_in, int *nnz, int *maxnnz, hipStream_t s);
+hipError_t launch_col_compact(const cplx *G, int n_out, int n_in, int K, int32_t *idx, cplx *val, hipStream_t s);
+hipError_t launch_sparse_vinit(const cplx *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
+                               const cplx *val, int K, int coff, int w, cplx *V, int ldv, hipStream_t s);
 // autotuner: set or clear G_K3 on n tasks
 hipError_t launch_set_k3(GemmTask *t, int n, bool on, hipStream_t s);
 hipError_t launch_param_sum(const int32_t *cbeg, int np, const double *sigma, const double *v, double *dfdp,

@@ -1240,6 +1240,68 @@ __global__ void k_set_k3(GemmTask *t, int n, int on) {
 }
 
 // ---------------------------------------------------------------------------
+// Weighted adjoint source for a dF/dS with few nonzeros per input column
+// (such as an objective over a few target orders per input): the columns are
+// compacted to (output index, value) lists and V = XC G is formed from them,
+// reading each row of XC where the column's nonzeros sit; the same values as
+// the dense product (whose other terms are exact zeros).
+// ---------------------------------------------------------------------------
+
+// Nonzero count of every column of G (n_out x n_in, row-major); the largest
+// goes to *maxnnz.
+__global__ void k_col_nnz(const double2 *G, int n_out, int n_in, int *nnz, int *maxnnz) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_in) return;
+  int c = 0;
+  for (int b = 0; b < n_out; ++b) {
+    const double2 v = G[(int64_t)b * n_in + m];
+    c += (v.x != 0.0 || v.y != 0.0);
+  }
+  nnz[m] = c;
+  atomicMax(maxnnz, c);
+}
+
+// The first K nonzeros of every column as (row, value), in row order; unused
+// slots hold row 0 and value 0.
+__global__ void k_col_compact(const double2 *G, int n_out, int n_in, int K, int32_t *idx, double2 *val) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_in) return;
+  int c = 0;
+  for (int b = 0; b < n_out && c < K; ++b) {
+    const double2 v = G[(int64_t)b * n_in + m];
+    if (v.x != 0.0 || v.y != 0.0) {
+      idx[(int64_t)m * K + c] = b;
+      val[(int64_t)m * K + c] = v;
+      ++c;
+    }
+  }
+  for (; c < K; ++c) {
+    idx[(int64_t)m * K + c] = 0;
+    val[(int64_t)m * K + c] = make_double2(0.0, 0.0);
+  }
+}
+
+// V[vmap[r]][j] = sum_k XC[r][idx[m][k]] val[m][k], m = coff + j, for the
+// chunk's w columns; one thread per (row, column), columns fastest so that a
+// wave reads consecutive entries of an XC row.
+__global__ void k_sparse_vinit(const double2 *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
+                               const double2 *val, int K, int coff, int w, double2 *V, int ldv) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t r = t / w;
+  if (r >= rows) return;
+  const int j = (int)(t - r * w), m = coff + j;
+  const double2 *x = XC + r * n_out;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < K; ++k) {
+    const double2 g = val[(int64_t)m * K + k];
+    const double2 a = x[idx[(int64_t)m * K + k]];
+    acc.x = fma(a.x, g.x, fma(-a.y, g.y, acc.x));
+    acc.y = fma(a.x, g.y, fma(a.y, g.x, acc.y));
+  }
+  V[(int64_t)vmap[r] * ldv + j] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
@@ -1464,6 +1526,26 @@ hipError_t launch_zero_flat(cplx *p, int64_t n, hipStream_t s) {
 hipError_t launch_set_k3(GemmTask *t, int n, bool on, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_set_k3, dim3((n + 255) / 256), dim3(256), 0, s, t, n, on ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_nnz(const cplx *G, int n_out, int n_in, int *nnz, int *maxnnz, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_nnz, dim3((n_in + 255) / 256), dim3(256), 0, s, reinterpret_cast<const double2 *>(G),
+                     n_out, n_in, nnz, maxnnz);
+  return hipGetLastError();
+}
+hipError_t launch_col_compact(const cplx *G, int n_out, int n_in, int K, int32_t *idx, cplx *val, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_compact, dim3((n_in + 255) / 256), dim3(256), 0, s,
+                     reinterpret_cast<const double2 *>(G), n_out, n_in, K, idx, reinterpret_cast<double2 *>(val));
+  return hipGetLastError();
+}
+hipError_t launch_sparse_vinit(const cplx *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
+                               const cplx *val, int K, int coff, int w, cplx *V, int ldv, hipStream_t s) {
+  const int64_t n = rows * w;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sparse_vinit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double2 *>(XC), n_out, rows, vmap, idx,
+                     reinterpret_cast<const double2 *>(val), K, coff, w, reinterpret_cast<double2 *>(V), ldv);
   return hipGetLastError();
 }
 

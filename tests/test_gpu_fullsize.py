@@ -50,7 +50,7 @@ def test_metasurface_24000x160_against_oracle_samples():
     nlr, nroot = apf.query("lowrank_fronts"), apf.query("lowrank_roots")
     print(f"[gpu] rel err S columns {eS:.2e} (worst block {eS_blk:.2e}), sampled grad {eg:.2e} (worst x block "
           f"{eg_blk:.2e}), grad norm {en:.2e}; {nlr:.0f} fronts in {nroot:.0f} low-rank sweep subtrees", flush=True)
-    assert nroot > 0 and nlr > nroot      # the subtree products take part
+    assert nroot > 0 and nlr >= nroot     # the subtree products take part
     assert eS < TOL and eS_blk < TOL
     assert eg < TOL and eg_blk < TOL
     assert en < TOL
@@ -63,7 +63,8 @@ def test_low_rank_subtrees_and_plain_sweeps_agree_on_every_pixel():
     sweep front then runs the Y and Lam sweeps.  S does not depend on the
     route (bitwise equal), and the two FP64 gradients agree at 1e-10 in
     2-norm over all 960,000 pixels and in every 1,500-column block (a
-    check of the subtree products beyond the oracle's sampled pixels)."""
+    check of the subtree products beyond the oracle's sampled pixels), with
+    the default one-level subtrees."""
     from paper_2306_09257_amd import binding
     prob, eps, w = inputs.metasurface_wide(seed=1)
     dev = torch.device("cuda:0")

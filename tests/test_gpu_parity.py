@@ -98,8 +98,42 @@ def test_lowrank_subtrees_match_oracle_1200x92():
     nlr, nroot = apf.query("lowrank_fronts"), apf.query("lowrank_roots")
     S_o, g_o, f_o = oapf.solve_S_and_grad(prob, eps, w=w)
     print(f"[gpu] 1200x92 ({prob.n_in} channels): {nlr:.0f} fronts in {nroot:.0f} low-rank subtrees", flush=True)
-    assert nroot > 0 and nlr > nroot
+    assert nroot > 0 and nlr >= nroot
     _check(S, g, S_o, g_o, "1200x92 low-rank subtrees")
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_low_rank_subtree_depth_against_oracle_for_several_objectives(levels):
+    """1200 x 92 (seed 13): the gradient for four kinds of dF/dS (weighted
+    power, the grouped objective, random sparse and random dense) against the
+    oracle in 2-norm and in every sixteenth of the grid.  One-level subtrees
+    (the default) meet the 1e-10 bar; two-level ones lose up to 1e-9 here
+    (measured 9.7e-10, worst block 3.7e-9), the cancellation of both field
+    reconstructions in the dense propagation compounding over the second
+    level, and are checked only against a 1e-8 bound."""
+    from paper_2306_09257_amd import binding
+    import oracle.objectives as oobj
+    prob = inputs.make_problem(1200, 92)
+    rng = np.random.default_rng(13)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    w = rng.uniform(size=(prob.n_out, prob.n_in))
+    Gr = np.zeros((prob.n_out, prob.n_in), complex)
+    for m in range(prob.n_in):
+        rows = rng.choice(prob.n_out, 3, replace=False)
+        Gr[rows, m] = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    Gd = rng.standard_normal((prob.n_out, prob.n_in)) + 1j * rng.standard_normal((prob.n_out, prob.n_in))
+    S_o = oapf.scattering_matrix(prob, eps)
+    _, Gg = oobj.group_fom(S_o, prob.in_orders, prob.out_orders, 10, 2)
+    apf = binding.APF(prob).analyze().set_lowrank(levels)
+    apf.assemble(_dev(eps, torch.float64))
+    apf.factor_schur()
+    bound = TOL if levels == 1 else 1e-8
+    for name, G in (("weighted", w * np.conj(S_o)), ("grouped", Gg), ("sparse", Gr), ("dense", Gd)):
+        g = apf.grad(_dev(G, torch.complex128)).cpu().numpy()
+        g_o = oapf.solve_S_and_grad(prob, eps, G=G)[1]
+        e, eb = _rel(g, g_o), worst_block(g, g_o, axis=1)
+        print(f"[gpu] low-rank levels {levels}, {name} dF/dS: grad {e:.2e}, worst block {eb:.2e}", flush=True)
+        assert e < bound and eb < bound, (name, e, eb)
 
 
 def test_chunked_sweeps_match_oracle_1200x92():
@@ -165,8 +199,9 @@ def test_profiling_modes_time_the_launch_classes_they_name():
     apf.set_profiling(False)
     assert all(p_gemm[c][1] > 0 for c in gemm)
     assert all(p_gemm[c][1] == 0 for c in p_gemm if c not in gemm)
-    assert all(p_all[c][1] > 0 for c in p_all if c != "refine")     # no refinement on this path
-    assert p_all["refine"][1] == 0
+    # no refinement on this path, and w > 0 makes dF/dS dense (no sparse adjoint source)
+    assert all(p_all[c][1] > 0 for c in p_all if c not in ("refine", "adjoint_source"))
+    assert p_all["refine"][1] == 0 and p_all["adjoint_source"][1] == 0
     assert all(p_all[c][1] == p_gemm[c][1] for c in gemm)
     # timing changes nothing in the results
     assert torch.equal(g0, g1) and torch.equal(g0, g2)
@@ -251,3 +286,32 @@ def test_non_finite_or_zero_permittivity_is_rejected(bad):
     apf.assemble(_dev(eps, torch.float64))
     S = apf.factor_schur().cpu().numpy()
     assert _rel(S, oapf.scattering_matrix(prob, eps)) < TOL
+
+
+def test_sparse_adjoint_source_matches_the_dense_product_and_the_oracle():
+    """A dF/dS with a few nonzeros per input column (the grouped objective's
+    targets) takes the sparse weighted-adjoint-source kernel; the gradient
+    equals the oracle's and, to rounding, the dense product's (forced by a
+    dF/dS whose zeros are replaced with tiny values)."""
+    from paper_2306_09257_amd import binding
+    import oracle.objectives as oobj
+    prob = inputs.make_problem(1200, 92)
+    rng = np.random.default_rng(13)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    apf = binding.APF(prob).analyze()
+    apf.assemble(_dev(eps, torch.float64))
+    S = apf.factor_schur()
+    f, G = apf.group_fom(S, 10, 2)
+    g_sparse = apf.grad(G).cpu().numpy()
+    k = apf.query("adjoint_source_sparse_k")
+    Gd = G.clone()
+    Gd[Gd == 0] = 1e-300                       # structurally dense, numerically the same
+    g_dense = apf.grad(Gd).cpu().numpy()
+    assert apf.query("adjoint_source_sparse_k") == 0
+    _, G_o = oobj.group_fom(oapf.scattering_matrix(prob, eps), prob.in_orders, prob.out_orders, 10, 2)
+    _, g_o, _ = oapf.solve_S_and_grad(prob, eps, G=G_o)
+    print(f"[gpu] sparse adjoint source (width {k:.0f}): vs oracle {_rel(g_sparse, g_o):.2e}, "
+          f"vs dense {_rel(g_sparse, g_dense):.2e}, worst block {worst_block(g_sparse, g_o, axis=1):.2e}", flush=True)
+    assert 1 <= k <= 5
+    assert _rel(g_sparse, g_o) < TOL and worst_block(g_sparse, g_o, axis=1) < TOL
+    assert _rel(g_sparse, g_dense) < 1e-12

@@ -196,9 +196,9 @@ def test_host_side_argument_and_state_checks(lib):
         assert lib.apf_set_rhs_chunk(h, cap) == E
     for cap in (0, 64, 4096):
         assert lib.apf_set_rhs_chunk(h, cap) == binding.APF_OK
-    for on in (-1, 2):
+    for on in (-1, 3):
         assert lib.apf_set_lowrank(h, on) == E
-    for on in (0, 1):
+    for on in (0, 1, 2):
         assert lib.apf_set_lowrank(h, on) == binding.APF_OK
     assert lib.apf_set_lowrank(None, 1) == E
     # numeric calls before the first assembly
