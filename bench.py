@@ -334,6 +334,11 @@ def main():
                          "refined: the mixed factorization plus FP64 iterative refinement of the forward and "
                          "adjoint fields")
     ap.add_argument("--refine-iters", type=int, default=2)
+    ap.add_argument("--factor-only", action="store_true",
+                    help="time assemble + factorization (S) per step, no gradient (metric: factorizations/s)")
+    ap.add_argument("--compress", default="",
+                    help="PAD,WINDOW: B/C compression with PAD extra orders and a WINDOW-wavelength truncation "
+                         "(implies --factor-only)")
     ap.add_argument("--lowrank", type=int, default=-1,
                     help="levels of the low-rank sweep subtrees (0-2; default: the library's)")
     args = ap.parse_args()
@@ -367,6 +372,10 @@ def main():
         apf.set_refinement(args.refine_iters, 1e-10)
     if args.lowrank >= 0:
         apf.set_lowrank(args.lowrank)
+    if args.compress:
+        pad, window = args.compress.split(",")
+        apf.set_compression(int(pad), float(window))
+        args.factor_only = True
     t_an = time.perf_counter() - t0
     dev = torch.device("cuda:0")
     eps_d = torch.as_tensor(eps, dtype=torch.float64, device=dev).contiguous()
@@ -380,6 +389,8 @@ def main():
     def step():
         apf.assemble(eps_d)
         apf.factor_schur(S, precision=prec)
+        if args.factor_only:
+            return None
         f, G = apf.group_fom(S, w) if grouped else apf.weighted_power(S, w_d)
         apf.grad(G, out=grad)
         return f
@@ -417,8 +428,11 @@ def main():
     # plain paths (its S and gradient come from the refined fields): its
     # roofline covers the factorization GEMMs only
     classes = ("gemm_factor",) if args.precision == "refined" else ("gemm_factor", "gemm_schur", "gemm_sweep")
-    if args.precision == "refined":
-        cm["schur"] = cm["sweep"] = cm["lowrank_w"] = 0.0
+    if args.precision == "refined" or args.compress:
+        cm["schur"] = 0.0                         # (compressed: S~ blocks and decompression not counted)
+    if args.precision == "refined" or args.factor_only:
+        cm["sweep"] = cm["lowrank_w"] = 0.0
+        cm["k3"] = 0.0 if args.compress else cm["k3"]
     sparse_k = apf.query("adjoint_source_sparse_k")
     if sparse_k > 0:
         # the weighted adjoint source ran as the sparse kernel (not a GEMM):
@@ -451,14 +465,16 @@ def main():
     phases = {c: round(prof_all[c][0], 3) for c in prof_all}
 
     out = {
-        "metric": "APF solves/sec (S+grad f) at N unknowns, M channels",
-        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": ("APF factorizations/sec (S) at N unknowns, M channels" if args.factor_only
+                   else "APF solves/sec (S+grad f) at N unknowns, M channels"),
+        "value": value, "unit": "factorizations/s" if args.factor_only else "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "c128 (f64)", "mixed": "c64 (f32) front GEMMs, f64 storage",
                   "refined": "c64 (f32) front GEMMs + f64 refinement"}[args.precision], "data": "synthetic",
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "unknowns": prob.nx * prob.ny,
                    "n_in": prob.n_in, "n_out": prob.n_out, "design_pixels": prob.n_design_rows * prob.nx,
-                   "precision": args.precision, "leaf_size": args.leaf or 48},
+                   "precision": args.precision, "leaf_size": args.leaf or 48,
+                   "compression": args.compress or None},
         "roofline": roofline,
         "phase_ms_per_step": phases,
         "analysis_s": t_an,
@@ -471,7 +487,7 @@ def main():
                          "residual_final": apf.query("refine_residual"),
                          "retained_factor_bytes": apf.query("retained_factor_bytes"),
                          "ms_refine_per_step": prof_all["refine"][0]}
-    if args.precision in ("mixed", "refined"):
+    if args.precision in ("mixed", "refined") and not args.compress:
         # accuracy of the mixed result against the FP64 path
         S_m, g_m = S.clone(), grad.clone()
         apf.assemble(eps_d)
@@ -482,7 +498,7 @@ def main():
         out["mixed_rel_err_vs_fp64"] = {
             "S": float(torch.linalg.norm(S_m - S64) / torch.linalg.norm(S64)),
             "grad": float(torch.linalg.norm(g_m - g64) / torch.linalg.norm(g64))}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.factor_only:
         out["cpu_baseline"] = cpu_baseline(prob, args.workload)
     print(json.dumps(out), flush=True)
 

@@ -337,6 +337,27 @@ apf_status apf_tuning_apply(apf_handle *const *hs, int32_t n, const char *path, 
  * APF_ESTATE); APF_EINVAL unless max_chunk is 0 or a positive multiple of 64. */
 apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk);
 
+/* B/C compression (Supplement Sec. 1; this library's reading of its
+ * one-sentence recipe).  The input orders a_lo..a_hi and the output orders
+ * (each set consecutive) are extended by `pad` orders (pad / 2 below),
+ * M' = M + pad, with window weights w_t = sin^2(pi (t + 1/2) / M'); the
+ * compressed source column j on the source row is
+ *   b_j(x) = sum_t w_t phi_{a'_t}(x) exp(-2 pi i t j / M'),
+ * localized around x_j = j nx / M' and truncated to the nodes within half of
+ * `window_wavelengths` (periodic distance), and the compressed projection rows
+ * c_j are the conjugate construction on the projection row.  The
+ * factorization then carries, per front, only the compressed columns whose
+ * window meets its region, forms S~ = C~ A^-1 B~ (M'_C x M'_B) block by block
+ * and returns S = D_C S~ D_B, the exact S of the original channels when
+ * nothing is truncated and an approximation otherwise (about 1e-3 .. 1e-2 at
+ * a 3-wavelength window and pad = M / 5, less for wider windows; see the
+ * design notes).  apf_grad and the augmented and batched entry points refuse
+ * compressed handles (APF_EINVAL).  pad = -1 switches compression off again.
+ * Call after apf_analyze and before the first apf_assemble (else
+ * APF_ESTATE); APF_EINVAL for non-consecutive orders, pad < -1, a window that
+ * is not positive or narrower than the spacing nx / M' of the columns. */
+apf_status apf_set_compression(apf_handle *h, int32_t pad, double window_wavelengths);
+
 /* Enable (max_iter >= 1) or disable (0, the default) APF_MIXED_REFINED on
  * this handle: the plan then keeps the triangular inverses, L21 and
  * X12 = U^-1 U12 of every front (not only of the fronts the gradient sweeps

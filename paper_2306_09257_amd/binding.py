@@ -31,7 +31,8 @@ ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur",
                 "apf_weighted_power", "apf_splitter_fom", "apf_group_fom", "apf_ridges_eps", "apf_ridges_grad",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
                 "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement",
-                "apf_grad_augmented", "apf_ridges_grad_augmented", "apf_autotune", "apf_tuning_apply")
+                "apf_grad_augmented", "apf_ridges_grad_augmented", "apf_autotune", "apf_tuning_apply",
+                "apf_set_compression")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow", "refine", "adjoint_source")
 
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_rhs_chunk.argtypes = [vp, i32]
     lib.apf_set_lowrank.argtypes = [vp, i32]
     lib.apf_set_refinement.argtypes = [vp, i32, dbl]
+    lib.apf_set_compression.argtypes = [vp, i32, dbl]
     lib.apf_autotune.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.c_char_p, vp]
     lib.apf_tuning_apply.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_char_p, vp]
     lib.apf_grad_augmented.argtypes = [vp, i32, vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), vp]
@@ -158,6 +160,13 @@ class APF:
         mean 0 and 2), before the first assemble."""
         lv = (2 if levels else 0) if isinstance(levels, bool) else int(levels)
         _check(self._lib.apf_set_lowrank(self._h, lv))
+        return self
+
+    def set_compression(self, pad: int, window_wavelengths: float = 3.0):
+        """B/C compression (after analyze, before the first assemble): pad the
+        channel sets by `pad` orders, Hann-weight, transform to localized
+        columns truncated to the window; pad = -1 switches it off."""
+        _check(self._lib.apf_set_compression(self._h, int(pad), float(window_wavelengths)))
         return self
 
     def set_refinement(self, max_iter: int, tol: float = 1e-10):

@@ -104,6 +104,14 @@ struct LevelTasks {
   int64_t zero = -1, scat = -1, pan = -1, g1 = -1, g2 = -1, g2b = -1;
   int nzero = 0, nscat = 0, npan = 0, ng1 = 0, ng2 = 0, ng2b = 0;
   char deep1 = 0, deep2 = 0, deep2b = 0;   // lists run by the deep-K kernel (k_gemm_k3)
+  // compressed channels: panel rows copied from the compressed basis, and
+  // the blocks of S~ of the level's fronts, in launches whose blocks do not
+  // overlap
+  int64_t cpy = -1;
+  int ncpy = 0;
+  static constexpr int kSchurColors = 4;
+  int64_t sch[kSchurColors] = {-1, -1, -1, -1};
+  int nsch[kSchurColors] = {0, 0, 0, 0};
   int id1 = -1, id2 = -1, id2b = -1;       // the lists' entries in the plan's tunable-list table
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
@@ -263,6 +271,12 @@ struct Plan {
   int32_t *g_idx = nullptr;
   cplx *g_val = nullptr;
   int last_sparse_k = 0;      // the last apf_grad's compact width (0: dense product)
+  // compressed channels: the bases on the channel rows (nx x M'_B, nx x M'_C),
+  // S~ (M'_C x M'_B), the decompression matrices D_B (M'_B x n_in) and D_C
+  // (n_out x M'_C), the product S~ D_B, and the two decompression task lists
+  cplx *czBt = nullptr, *czCt = nullptr, *czS = nullptr, *czDB = nullptr, *czDC = nullptr, *czT = nullptr;
+  int64_t czD1 = -1, czD2 = -1;
+  int nczD1 = 0, nczD2 = 0;
   double vinit_cmacs = 0;     // complex MACs of the dense weighted-adjoint-source product
   double *part = nullptr;
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
@@ -428,8 +442,22 @@ struct Off {
 
 }  // namespace
 
+// B/C compression (Supplement Sec. 1, reading of this library): the channel
+// sets are extended by `pad` orders, weighted by a Hann window, transformed
+// to spatially localized columns on the channel rows and truncated to
+// +-half_px; the factorization carries, per front, only the columns whose
+// window meets its region, and S is recovered from S~ = C~ A^-1 B~ by two
+// dense products.
+struct Compress {
+  int pad = -1;                          // < 0: off
+  double half_px = 0.0;
+  int MxB = 0, MxC = 0, a0B = 0, a0C = 0;
+  std::vector<int> cB0, cB1, cC0, cC1;   // per front: column ranges of its B / C panels
+};
+
 struct apf_handle {
   Desc d;
+  Compress cz;
   bool analyzed = false;
   Symbolic sym;
   Phys phys{};
@@ -542,13 +570,16 @@ static void size_plan(apf_handle *H) {
   int64_t fs = 0, ktot = 0, xck = 0, ss = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
-    int64_t p = F.p(), b = F.b(), n = p + b, mB = F.hasB ? Mi : 0, mC = F.hasC ? Mo : 0;
+    const bool cz = H->cz.pad >= 0;
+    int64_t p = F.p(), b = F.b(), n = p + b;
+    int64_t mB = F.hasB ? (cz ? H->cz.cB1[f] - H->cz.cB0[f] : Mi) : 0;
+    int64_t mC = F.hasC ? (cz ? H->cz.cC1[f] - H->cz.cC0[f] : Mo) : 0;
     Off &q = o[f];
     int64_t w = 0;
     q.tri = w; w += up(p * p);
     if (b) { q.u12 = w; w += up(p * b); q.l21 = w; w += up(b * p); }
-    if (mB && !F.sfront) { q.u1b = w; w += up(p * mB); }
-    if (mC && !F.sfront) { q.lc1t = w; w += up(p * mC); }
+    if (mB && (!F.sfront || cz)) { q.u1b = w; w += up(p * mB); }
+    if (mC && (!F.sfront || cz)) { q.lc1t = w; w += up(p * mC); }
     q.wsz = w;
     int64_t pw = 0;
     q.core = pw; pw += up(n * n);
@@ -560,7 +591,7 @@ static void size_plan(apf_handle *H) {
       if (mB) { q.fs_x1b = fs; fs += up(p * mB); }
       if (mC) { q.xk = xck; xck += p; }
     }
-    if (F.sfront) { q.sk = ktot; ktot += p; }
+    if (F.sfront && !cz) { q.sk = ktot; ktot += p; }
     if (H->refine_iters > 0) {
       q.ss_tri = ss; ss += up(p * p);
       if (b) {
@@ -865,6 +896,51 @@ static void build_plan(apf_handle *H) {
   const int64_t ktot = S.k_total;
   HIPCHK(hipMalloc(&P.ws, P.ws_elems * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.fs, P.fs_elems * sizeof(cplx)));
+  const bool cz = H->cz.pad >= 0;
+  if (cz) {
+    const Compress &Z = H->cz;
+    const int nx = d.nx;
+    HIPCHK(hipMalloc(&P.czBt, (int64_t)nx * Z.MxB * sizeof(cplx)));
+    HIPCHK(hipMalloc(&P.czCt, (int64_t)nx * Z.MxC * sizeof(cplx)));
+    HIPCHK(hipMalloc(&P.czS, (int64_t)Z.MxC * Z.MxB * sizeof(cplx)));
+    HIPCHK(hipMalloc(&P.czT, (int64_t)Z.MxC * Mi * sizeof(cplx)));
+    HIPCHK(hipMalloc(&P.czDB, (int64_t)Z.MxB * Mi * sizeof(cplx)));
+    HIPCHK(hipMalloc(&P.czDC, (int64_t)Mo * Z.MxC * sizeof(cplx)));
+    HIPCHK(hipMemset(P.czBt, 0, (int64_t)nx * Z.MxB * sizeof(cplx)));
+    HIPCHK(hipMemset(P.czCt, 0, (int64_t)nx * Z.MxC * sizeof(cplx)));
+    HIPCHK(launch_compress_basis(nx, Z.MxB, Z.a0B, Z.half_px, false, P.czBt, nullptr));
+    HIPCHK(launch_compress_basis(nx, Z.MxC, Z.a0C, Z.half_px, true, P.czCt, nullptr));
+    // D_C[b][j] = gamma_b exp(-2 pi i t_b j / M'_C) / (M'_C w_tb),
+    // D_B[j][a] = exp(+2 pi i t_a j / M'_B) beta_a / (M'_B w_ta), with the
+    // channel normalisations beta_a = -2i sqrt(sin q_a), gamma_b = sqrt(sin q_b)
+    const double h = 2.0 * M_PI * d.dx_over_lambda;
+    auto sinq = [&](int a, double eps) {
+      const double sa = std::sin(M_PI * a / nx), rhs = h * h * eps / 4.0 - sa * sa;
+      return std::sin(2.0 * std::asin(std::sqrt(rhs)));
+    };
+    auto wt = [](int t, int M) { const double v = std::sin(M_PI * (t + 0.5) / M); return v * v; };
+    std::vector<cplx> DB((size_t)Z.MxB * Mi), DC((size_t)Mo * Z.MxC);
+    for (int a = 0; a < Mi; ++a) {
+      const int t = d.in_orders[a] - Z.a0B;
+      const double bmag = 2.0 * std::sqrt(sinq(d.in_orders[a], d.eps_top)) / (Z.MxB * wt(t, Z.MxB));
+      for (int j = 0; j < Z.MxB; ++j) {
+        const double ang = 2.0 * M_PI * (double)(((int64_t)t * j) % Z.MxB) / Z.MxB;
+        // beta_a = -2i sqrt(sin q):  (cos + i sin) * (-i) * bmag
+        DB[(size_t)j * Mi + a] = {bmag * std::sin(ang), -bmag * std::cos(ang)};
+      }
+    }
+    for (int b = 0; b < Mo; ++b) {
+      const int t = d.out_orders[b] - Z.a0C;
+      const double g = std::sqrt(sinq(d.out_orders[b], d.eps_bot)) / (Z.MxC * wt(t, Z.MxC));
+      for (int j = 0; j < Z.MxC; ++j) {
+        const double ang = 2.0 * M_PI * (double)(((int64_t)t * j) % Z.MxC) / Z.MxC;
+        DC[(size_t)b * Z.MxC + j] = {g * std::cos(ang), -g * std::sin(ang)};
+      }
+    }
+    HIPCHK(hipMemcpy(P.czDB, DB.data(), DB.size() * sizeof(cplx), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(P.czDC, DC.data(), DC.size() * sizeof(cplx), hipMemcpyHostToDevice));
+    HIPCHK(hipDeviceSynchronize());
+  }
   if (H->refine_iters > 0) HIPCHK(hipMalloc(&P.R.ss, std::max<int64_t>(P.R.ss_elems, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.sb, std::max<int64_t>(ktot * Mi, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.sc, std::max<int64_t>(ktot * Mo, 1) * sizeof(cplx)));
@@ -922,7 +998,8 @@ static void build_plan(apf_handle *H) {
     std::vector<int32_t> gi(std::max<int64_t>(S.n_sweep_rows, 1), -1);
     for (int y = d.design_row0; y < d.design_row1; ++y)
       for (int x = 0; x < d.nx; ++x)
-        gi[S.node_sweep_row[(int64_t)y * d.nx + x]] = (int32_t)((int64_t)(y - d.design_row0) * d.nx + x);
+        if (S.node_sweep_row[(int64_t)y * d.nx + x] >= 0)
+          gi[S.node_sweep_row[(int64_t)y * d.nx + x]] = (int32_t)((int64_t)(y - d.design_row0) * d.nx + x);
     P.gidx = ib.add(gi);
     P.ndesign = (int64_t)(d.design_row1 - d.design_row0) * d.nx;
     P.nblk = 2 * ((Mi + 63) / 64);
@@ -1042,11 +1119,11 @@ static void build_plan(apf_handle *H) {
       for (int r = 0; r < Ch.b(); ++r) {
         const int pr = Ch.rmap[r];
         if (Ch.hasB) {
-          rb.push_back(pr | (wb[pr] ? EXT_ADD : 0));
+          rb.push_back(pr | ((wb[pr] || cz) ? EXT_ADD : 0));
           wb[pr] = 1;
         }
         if (Ch.hasC) {
-          rc.push_back(pr | (wc[pr] ? EXT_ADD : 0));
+          rc.push_back(pr | ((wc[pr] || cz) ? EXT_ADD : 0));
           wc[pr] = 1;
         }
       }
@@ -1093,8 +1170,8 @@ static void build_plan(apf_handle *H) {
     FrontDev &D = fd[f];
     int64_t p = F.p(), b = F.b(), n = p + b;
     D.p = (int)p; D.b = (int)b;
-    D.mB = F.hasB ? Mi : 0;
-    D.mC = F.hasC ? Mo : 0;
+    D.mB = F.hasB ? (cz ? H->cz.cB1[f] - H->cz.cB0[f] : Mi) : 0;
+    D.mC = F.hasC ? (cz ? H->cz.cC1[f] - H->cz.cC0[f] : Mo) : 0;
     D.sweep_row0 = F.sweep ? (int32_t)S.node_sweep_row[F.piv[0]] : -1;
     D.core = WS(q.pws + q.core);
     D.bp_piv = D.mB ? WS(q.pws + q.bp) : nullptr;
@@ -1111,16 +1188,19 @@ static void build_plan(apf_handle *H) {
   // the Schur operand stores
   auto U1B = [&](int f) -> cplx * {
     const Off &q = o[f];
-    return S.fronts[f].sfront ? P.sb + q.sk * Mi : WS(q.ws + q.u1b);
+    return (S.fronts[f].sfront && !cz) ? P.sb + q.sk * Mi : WS(q.ws + q.u1b);
   };
   auto LC1T = [&](int f) -> cplx * {
     const Off &q = o[f];
-    return S.fronts[f].sfront ? P.sc + q.sk * Mo : WS(q.ws + q.lc1t);
+    return (S.fronts[f].sfront && !cz) ? P.sc + q.sk * Mo : WS(q.ws + q.lc1t);
   };
 
   std::vector<std::vector<ZeroRange>> zr(H_ + 1);
   std::vector<std::vector<AsmEntry>> ae(H_ + 1);
   std::vector<std::vector<PanelEntry>> pe(H_ + 1);
+  std::vector<std::vector<CopyRange>> cpyL(H_ + 1);
+  std::vector<std::vector<std::vector<GemmTask>>> schL(H_ + 1);   // compressed: S~ blocks, per colour
+  std::vector<std::vector<std::vector<GemmTask>>> schTiles(H_ + 1, std::vector<std::vector<GemmTask>>(LevelTasks::kSchurColors));
   std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), swY(H_ + 1), swL(H_ + 1), swW(H_ + 1);
   std::vector<std::vector<GemmTask>> wuL(H_ + 1), wqL(H_ + 1);
   std::vector<std::vector<WFront>> wpL(H_ + 1);
@@ -1156,8 +1236,18 @@ static void build_plan(apf_handle *H) {
       }
       return bnd_read;
     };
-    const bool cinB = mB ? zero_rows(D.bp_piv, D.bp_bnd, mB, wrB[f]) : false;
-    const bool cinC = mC ? zero_rows(D.cpt_piv, D.cpt_bnd, mC, wrC[f]) : false;
+    bool cinB = false, cinC = false;
+    if (!cz) {
+      cinB = mB ? zero_rows(D.bp_piv, D.bp_bnd, mB, wrB[f]) : false;
+      cinC = mC ? zero_rows(D.cpt_piv, D.cpt_bnd, mC, wrC[f]) : false;
+    } else {
+      // compressed panels: zeroed whole, every writer adds (the sibling
+      // panels' column ranges overlap)
+      if (mB) zero(D.bp_piv, (int64_t)n * mB);
+      if (mC) zero(D.cpt_piv, (int64_t)n * mC);
+      cinB = mB > 0;
+      cinC = mC > 0;
+    }
     // stencil entries owned by this front (the earlier-eliminated end of each edge)
     for (int k = 0; k < p; ++k) loc[F.piv[k]] = k;
     for (int k = 0; k < b; ++k) loc[F.bnd[k]] = p + k;
@@ -1177,8 +1267,16 @@ static void build_plan(apf_handle *H) {
         ae[lp].push_back({src, D.core + (int64_t)lu * n + lv});
         if (dir > 0) ae[lp].push_back({src, D.core + (int64_t)lv * n + lu});   // A = A^T
       }
-      if (mB && y == d.src_row) pe[lp].push_back({u, 0, D.bp_piv + (int64_t)k * mB, cp_src});
-      if (mC && y == d.prj_row) pe[lp].push_back({u, 0, D.cpt_piv + (int64_t)k * mC, cp_prj});
+      if (!cz) {
+        if (mB && y == d.src_row) pe[lp].push_back({u, 0, D.bp_piv + (int64_t)k * mB, cp_src});
+        if (mC && y == d.prj_row) pe[lp].push_back({u, 0, D.cpt_piv + (int64_t)k * mC, cp_prj});
+      } else {
+        const int64_t i = u % d.nx;
+        if (mB && y == d.src_row)
+          cpyL[lp].push_back({P.czBt + i * H->cz.MxB + H->cz.cB0[f], D.bp_piv + (int64_t)k * mB, (int64_t)mB});
+        if (mC && y == d.prj_row)
+          cpyL[lp].push_back({P.czCt + i * H->cz.MxC + H->cz.cC0[f], D.cpt_piv + (int64_t)k * mC, (int64_t)mC});
+      }
     }
     for (int k = 0; k < p; ++k) loc[F.piv[k]] = -1;
     for (int k = 0; k < b; ++k) loc[F.bnd[k]] = -1;
@@ -1216,17 +1314,46 @@ static void build_plan(apf_handle *H) {
         add_tiles(gp, t);
       }
       if (mB) {
-        GemmTask t = gemm(l21, p, u1b, mB, PD.bp_piv, mB, b, mB, p, G_NEG | (cinB ? G_CIN | G_CIN_OWN : 0),
+        cplx *dst = PD.bp_piv + (cz ? H->cz.cB0[f] - H->cz.cB0[F.parent] : 0);
+        GemmTask t = gemm(l21, p, u1b, mB, dst, PD.mB, b, mB, p, G_NEG | (cinB ? G_CIN | G_CIN_OWN : 0),
                           cinB ? D.bp_bnd : nullptr, mB);
         t.crowmap = reinterpret_cast<const int32_t *>((intptr_t)rowsB_off[f]);  // rebased below
         add_tiles(gp, t);
       }
       if (mC) {
-        GemmTask t = gemm(u12, b, lc1t, mC, PD.cpt_piv, mC, b, mC, p,
+        cplx *dst = PD.cpt_piv + (cz ? H->cz.cC0[f] - H->cz.cC0[F.parent] : 0);
+        GemmTask t = gemm(u12, b, lc1t, mC, dst, PD.mC, b, mC, p,
                           G_TRANS_A | G_NEG | (cinC ? G_CIN | G_CIN_OWN : 0), cinC ? D.cpt_bnd : nullptr, mC);
         t.crowmap = reinterpret_cast<const int32_t *>((intptr_t)rowsC_off[f]);  // rebased below
         add_tiles(gp, t);
       }
+    }
+    if (cz && F.sfront) {
+      // S~[C range, B range] += LC1T^T U1B, in the first colour whose blocks
+      // of this level it does not overlap
+      const int r0 = H->cz.cC0[f], r1 = H->cz.cC1[f], k0 = H->cz.cB0[f], k1 = H->cz.cB1[f];
+      GemmTask t = gemm(lc1t, mC, u1b, mB, P.czS + (int64_t)r0 * H->cz.MxB + k0, H->cz.MxB, mC, mB, p,
+                        G_TRANS_A | G_C_ACC);
+      std::vector<std::vector<GemmTask>> &cols = schL[lvl];
+      int colour = -1;
+      for (size_t c = 0; c < cols.size() && colour < 0; ++c) {
+        bool clash = false;
+        for (const GemmTask &o2 : cols[c]) {
+          const int64_t off2 = o2.C - P.czS, rr0 = off2 / H->cz.MxB, kk0 = off2 % H->cz.MxB;
+          if (rr0 < r1 && r0 < rr0 + o2.M && kk0 < k1 && k0 < kk0 + o2.N) { clash = true; break; }
+        }
+        if (!clash) colour = (int)c;
+      }
+      if (colour < 0) {
+        cols.emplace_back();
+        colour = (int)cols.size() - 1;
+      }
+      if (colour >= LevelTasks::kSchurColors) throw std::runtime_error("too many overlapping S~ blocks on one level");
+      std::vector<GemmTask> tiles;
+      add_tiles(tiles, t);
+      // remember the block (one whole-block task) for the overlap test, and its tiles
+      cols[colour].push_back(t);
+      schTiles[lvl][colour].insert(schTiles[lvl][colour].end(), tiles.begin(), tiles.end());
     }
     if (q.ss_x12 >= 0) add_tiles(g2[lvl], gemm(tri, p, u12, b, P.R.ss + q.ss_x12, b, p, b, p, G_A_TRI_U));
     if (F.sweep) {
@@ -1327,10 +1454,15 @@ static void build_plan(apf_handle *H) {
   // split over k segments of SPLIT_K rows, each accumulated on MFMA (FP64,
   // or FP32 on the mixed path) into an FP64 partial block; one kernel sums
   // the blocks
-  std::vector<GemmTask> gSsplit;
-  P.nseg = (int)std::max<int64_t>(1, (ktot + SPLIT_K - 1) / SPLIT_K);
-  HIPCHK(hipMalloc(&P.spart, (int64_t)P.nseg * Mo * Mi * sizeof(cplx)));
+  std::vector<GemmTask> gSsplit, czD1, czD2;
+  P.nseg = cz ? 0 : (int)std::max<int64_t>(1, (ktot + SPLIT_K - 1) / SPLIT_K);
+  if (!cz) HIPCHK(hipMalloc(&P.spart, (int64_t)P.nseg * Mo * Mi * sizeof(cplx)));
   g_cmacs_acc = 0;
+  if (cz) {
+    // S = D_C (S~ D_B)
+    add_tiles_xcd(czD1, gemm(P.czS, H->cz.MxB, P.czDB, Mi, P.czT, Mi, H->cz.MxC, Mi, H->cz.MxB, G_K3));
+    add_tiles_xcd(czD2, gemm(P.czDC, H->cz.MxC, P.czT, Mi, nullptr, Mi, Mo, Mi, H->cz.MxC, G_C_EXT | G_K3));
+  }
   for (int g = 0; g < P.nseg; ++g) {
     const int64_t k0 = (int64_t)g * SPLIT_K;
     const int kk = (int)std::min<int64_t>(SPLIT_K, ktot - k0);
@@ -1352,6 +1484,11 @@ static void build_plan(apf_handle *H) {
     L.zero = bl.add(zr[lvl]); L.nzero = (int)zr[lvl].size();
     L.scat = bl.add(ae[lvl]); L.nscat = (int)ae[lvl].size();
     L.pan = bl.add(pe[lvl]); L.npan = (int)pe[lvl].size();
+    L.cpy = bl.add(cpyL[lvl]); L.ncpy = (int)cpyL[lvl].size();
+    for (int c = 0; c < LevelTasks::kSchurColors; ++c) {
+      L.sch[c] = bl.add(schTiles[lvl][c]);
+      L.nsch[c] = (int)schTiles[lvl][c].size();
+    }
     L.deep1 = mark_deep(g1[lvl]);
     L.deep2 = mark_deep(g2[lvl]);
     L.deep2b = mark_deep(g2b[lvl]);
@@ -1399,6 +1536,8 @@ static void build_plan(apf_handle *H) {
   P.gemm_cmacs_k3 = cm_k3 + cm_w;
   P.gemm_cmacs_w = cm_w;
   P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
+  P.czD1 = bl.add(czD1); P.nczD1 = (int)czD1.size();
+  P.czD2 = bl.add(czD2); P.nczD2 = (int)czD2.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
   P.vmap_base = bl.add(vmap_base);
   P.vmap_pidx = bl.add(vmap_pidx);
@@ -1481,7 +1620,8 @@ static void build_plan(apf_handle *H) {
 static void free_plan(Plan &P) {
   const Refine &R = P.R;
   void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
-                  P.xc, P.vmap, P.gpart, P.lrW, P.g_nnz, P.g_max, P.g_idx, P.g_val, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
+                  P.xc, P.vmap, P.gpart, P.lrW, P.g_nnz, P.g_max, P.g_idx, P.g_val, P.czBt, P.czCt, P.czS,
+                  P.czDB, P.czDC, P.czT, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
                   R.elim, R.norms, R.blob};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -1547,6 +1687,7 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     pr.run(P_ASSEMBLE, s, [&] {
       hipError_t e = launch_scatter_A((const AsmEntry *)at(L.scat), L.nscat, s);
       if (e == hipSuccess) e = launch_assemble_panel((const PanelEntry *)at(L.pan), L.npan, s);
+      if (e == hipSuccess) e = launch_copy((const CopyRange *)at(L.cpy), L.ncpy, s);
       return e;
     });
     pr.run(P_INVERSE, s, [&] {
@@ -1573,6 +1714,10 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
           pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)aat(ao), an, 0, INT_MAX, nullptr, s, f32); });
       }
     }
+    // compressed channels: the level's blocks of S~, one launch per colour
+    for (int c = 0; c < LevelTasks::kSchurColors; ++c)
+      if (L.nsch[c] > 0)
+        pr.run(P_GEMM_SCHUR, s, [&] { return launch_gemm((const GemmTask *)at(L.sch[c]), L.nsch[c], 0, INT_MAX, nullptr, s, f32); });
   }
 }
 
@@ -1669,6 +1814,7 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
   const bool refine = prec == APF_MIXED_REFINED;
   if (refine && h->refine_iters <= 0)
     return fail(APF_ESTATE, "APF_MIXED_REFINED needs apf_set_refinement before the first apf_assemble");
+  if (refine && h->cz.pad >= 0) return fail(APF_EINVAL, "APF_MIXED_REFINED does not combine with compressed channels");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     Plan &P = h->plan;
@@ -1676,8 +1822,19 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
     const bool f32 = prec != APF_FP64;
     const int Mi = h->d.n_in;
     HIPCHK(launch_fill_int(P.status, 0, s));
+    const bool cz = h->cz.pad >= 0;
+    if (cz) HIPCHK(launch_zero_flat(P.czS, (int64_t)h->cz.MxC * h->cz.MxB, s));
     run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32);
-    if (!refine) {
+    if (cz) {
+      // decompression: S = D_C (S~ D_B), FP64
+      pr.run(P_GEMM_SCHUR, s, [&] {
+        hipError_t e = launch_gemm(P.at<GemmTask>(P.czD1), P.nczD1, 0, INT_MAX, nullptr, s, false, nullptr, 0, true);
+        if (e == hipSuccess)
+          e = launch_gemm(P.at<GemmTask>(P.czD2), P.nczD2, 0, INT_MAX, reinterpret_cast<const cplx *>(S_dev), s,
+                          false, nullptr, 0, true);
+        return e;
+      });
+    } else if (!refine) {
       enqueue_schur(P, f32, S_dev, pr, s, h->d.n_out, Mi);
     } else {
       // S from refined forward fields, chunk by chunk; their design rows are
@@ -1858,6 +2015,7 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
   for (int i = 0; i < n; ++i) {
     if (!hs[i] || !S_devs[i]) return fail(APF_EINVAL, "null handle or output");
     if (hs[i]->state < 1) return fail(APF_ESTATE, "apf_assemble has not run on every handle");
+    if (hs[i]->cz.pad >= 0) return fail(APF_EINVAL, "compressed channels are not batched");
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(APF_EINVAL, "a handle appears twice in the batch");
   }
@@ -2017,6 +2175,8 @@ extern "C" apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, in
 extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev, void *stream) {
   if (!h || !dfdS_dev || !grad_dev) return fail(APF_EINVAL, "null argument");
   if (h->state != 2) return fail(APF_ESTATE, "apf_factor_schur has not run since the last assembly");
+  if (h->cz.pad >= 0)
+    return fail(APF_EINVAL, "the per-pixel gradient needs the uncompressed channel panels (apf_set_compression)");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     Plan &P = h->plan;
@@ -2465,6 +2625,7 @@ extern "C" apf_status apf_grad_augmented(apf_handle *h, int32_t n_cols, const in
   if (n_sub < 0) return fail(APF_EINVAL, "n_sub must be >= 0");
   if (flags & ~APF_AUG_SKIP_UU) return fail(APF_EINVAL, "unknown flags");
   if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
+  if (h->cz.pad >= 0) return fail(APF_EINVAL, "the augmented route runs on uncompressed channel panels");
   int32_t used = 0;
   apf_status st = guarded([&]() -> apf_status {
     return augmented_grad(h, n_cols, col_pixel, col_sigma, n_params, param_begin, n_sub, flags, dfdS_dev, S_dev,
@@ -2481,6 +2642,7 @@ extern "C" apf_status apf_ridges_grad_augmented(apf_handle *h, const double *edg
   if (apf_status st = check_ridges(h, edges_dev, n_edges, mirror)) return st;
   if (!dfdS_dev || !dfdp_dev) return fail(APF_EINVAL, "null argument");
   if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
+  if (h->cz.pad >= 0) return fail(APF_EINVAL, "the augmented route runs on uncompressed channel panels");
   return guarded([&]() -> apf_status {
     // U_k: the pixels of the cells holding edge k (and its mirror image) on
     // every design row, with Sigma = dA/dp = -h^2 deps/dp: -/+(eps_ridge -
@@ -2725,6 +2887,72 @@ extern "C" apf_status apf_set_lowrank(apf_handle *h, int32_t levels) {
   if (h->planned) return fail(APF_ESTATE, "the sweep plan is already built (apf_assemble has run)");
   h->lowrank = levels;
   return APF_OK;
+}
+
+extern "C" apf_status apf_set_compression(apf_handle *h, int32_t pad, double window_wavelengths) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  if (!h->analyzed) return fail(APF_ESTATE, "apf_analyze has not run");
+  if (h->planned) return fail(APF_ESTATE, "the plan is already built (apf_assemble has run)");
+  if (pad < -1) return fail(APF_EINVAL, "pad must be >= 0 (or -1 to switch compression off)");
+  const Desc &d = h->d;
+  return guarded([&]() -> apf_status {
+    if (pad < 0) {
+      // back to full channel panels and the gradient sweeps
+      h->cz = Compress();
+      analyze(h->d, h->sym);
+      size_plan(h);
+      return APF_OK;
+    }
+    if (!(window_wavelengths > 0.0) || !std::isfinite(window_wavelengths))
+      return fail(APF_EINVAL, "the window must be a positive number of wavelengths");
+    for (int k = 1; k < d.n_in; ++k)
+      if (d.in_orders[k] != d.in_orders[k - 1] + 1) return fail(APF_EINVAL, "input orders must be consecutive");
+    for (int k = 1; k < d.n_out; ++k)
+      if (d.out_orders[k] != d.out_orders[k - 1] + 1) return fail(APF_EINVAL, "output orders must be consecutive");
+    Compress Z;
+    Z.pad = pad;
+    Z.half_px = 0.5 * window_wavelengths / d.dx_over_lambda;
+    Z.MxB = d.n_in + pad;
+    Z.MxC = d.n_out + pad;
+    Z.a0B = d.in_orders[0] - pad / 2;
+    Z.a0C = d.out_orders[0] - pad / 2;
+    // every node must lie in some column's window
+    if ((double)d.nx / std::min(Z.MxB, Z.MxC) > 2.0 * Z.half_px)
+      return fail(APF_EINVAL, "the window is narrower than the spacing of the compressed columns");
+    // the compressed panels make the gradient sweeps unavailable: no front
+    // keeps sweep data
+    Symbolic &S = h->sym;
+    for (Front &F : S.fronts) F.sweep = false;
+    S.n_sweep_rows = 0;
+    std::fill(S.node_sweep_row.begin(), S.node_sweep_row.end(), -1);
+    // per front: the columns whose window meets the front's region (x0..x1,
+    // periodic), one margin column each side; a range that would wrap is the
+    // whole set.  A parent's region holds its children's, so its range does.
+    const int nf = (int)S.fronts.size();
+    auto range = [&](const Front &F, int Mx, int &c0, int &c1) {
+      const double lo = (F.x0 - Z.half_px) * Mx / (double)d.nx, hi = (F.x1 - 1 + Z.half_px) * Mx / (double)d.nx;
+      c0 = (int)std::ceil(lo) - 1;
+      c1 = (int)std::floor(hi) + 2;   // exclusive
+      if (c0 < 0 || c1 > Mx || F.x1 - F.x0 >= d.nx - 1) { c0 = 0; c1 = Mx; }
+    };
+    Z.cB0.assign(nf, 0); Z.cB1.assign(nf, 0); Z.cC0.assign(nf, 0); Z.cC1.assign(nf, 0);
+    for (int f = 0; f < nf; ++f) {
+      const Front &F = S.fronts[f];
+      if (F.hasB) range(F, Z.MxB, Z.cB0[f], Z.cB1[f]);
+      if (F.hasC) range(F, Z.MxC, Z.cC0[f], Z.cC1[f]);
+    }
+    for (int f = 0; f < nf; ++f) {   // nesting (guaranteed by the regions; checked)
+      const Front &F = S.fronts[f];
+      if (F.parent < 0) continue;
+      if (F.hasB && (Z.cB0[f] < Z.cB0[F.parent] || Z.cB1[f] > Z.cB1[F.parent]))
+        throw std::runtime_error("compressed column ranges do not nest");
+      if (F.hasC && (Z.cC0[f] < Z.cC0[F.parent] || Z.cC1[f] > Z.cC1[F.parent]))
+        throw std::runtime_error("compressed column ranges do not nest");
+    }
+    h->cz = std::move(Z);
+    size_plan(h);
+    return APF_OK;
+  });
 }
 
 extern "C" apf_status apf_set_refinement(apf_handle *h, int32_t max_iter, double tol) {

@@ -60,6 +60,8 @@ hipError_t launch_col_nnz(const cplx *G, int n_out, int n_in, int *nnz, int *max
 hipError_t launch_col_compact(const cplx *G, int n_out, int n_in, int K, int32_t *idx, cplx *val, hipStream_t s);
 hipError_t launch_sparse_vinit(const cplx *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
                                const cplx *val, int K, int coff, int w, cplx *V, int ldv, hipStream_t s);
+// compressed channel basis on one channel row (nx x Mx, zeroed beforehand)
+hipError_t launch_compress_basis(int nx, int Mx, int a0, double half_px, bool conj_all, cplx *out, hipStream_t s);
 // autotuner: set or clear G_K3 on n tasks
 hipError_t launch_set_k3(GemmTask *t, int n, bool on, hipStream_t s);
 hipError_t launch_param_sum(const int32_t *cbeg, int np, const double *sigma, const double *v, double *dfdp,

@@ -1302,6 +1302,42 @@ __global__ void k_sparse_vinit(const double2 *XC, int n_out, int64_t rows, const
 }
 
 // ---------------------------------------------------------------------------
+// Compressed channels (Supplement Sec. 1, this library's reading): the Mx
+// extended orders a'_t = a0 + t carry window weights w_t = sin^2(pi (t + 1/2) / Mx);
+// column j of the compressed basis on a channel row is
+//   sum_t w_t exp(2 pi i a'_t x / nx) exp(-2 pi i t j / Mx) / sqrt(nx),
+// localized around x_j = j nx / Mx and truncated to the nodes within
+// half_px of x_j (periodic distance).  out (nx x Mx, zeroed beforehand)
+// receives the window's entries; conj_all conjugates them (projection rows).
+// One thread per (column, node of its window).
+// ---------------------------------------------------------------------------
+__global__ void k_compress_basis(int nx, int Mx, int a0, double half_px, int lo, int hi, int conj_all, cplx *out) {
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t j = t0 / (hi - lo + 1);
+  if (j >= Mx) return;
+  const int off = (int)(t0 - j * (hi - lo + 1)) + lo;   // distinct nodes: hi - lo + 1 <= nx
+  const double xj = (double)j * nx / Mx;
+  int i = (int)floor(xj + 0.5) + off;
+  i = ((i % nx) + nx) % nx;
+  double d = fabs((double)i - xj);
+  d = fmin(d, (double)nx - d);
+  if (d > half_px) return;
+  double re = 0.0, im = 0.0;
+  for (int t = 0; t < Mx; ++t) {
+    const double wt = sin(M_PI * (t + 0.5) / Mx);
+    const int64_t ai = (((int64_t)(a0 + t) * i) % nx + nx) % nx;
+    const int64_t tj = ((int64_t)t * j) % Mx;
+    const double ang = 2.0 * M_PI * ((double)ai / nx - (double)tj / Mx);
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    re += wt * wt * cs;
+    im += wt * wt * sn;
+  }
+  const double sc = 1.0 / sqrt((double)nx);
+  st2(out + (int64_t)i * Mx + j, make_double2(re * sc, conj_all ? -im * sc : im * sc));
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
@@ -1546,6 +1582,15 @@ hipError_t launch_sparse_vinit(const cplx *XC, int n_out, int64_t rows, const in
   hipLaunchKernelGGL(k_sparse_vinit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<const double2 *>(XC), n_out, rows, vmap, idx,
                      reinterpret_cast<const double2 *>(val), K, coff, w, reinterpret_cast<double2 *>(V), ldv);
+  return hipGetLastError();
+}
+
+hipError_t launch_compress_basis(int nx, int Mx, int a0, double half_px, bool conj_all, cplx *out, hipStream_t s) {
+  const double reach = std::ceil(half_px) + 1.0;
+  const int lo = -(int)std::min<double>(reach, (double)((nx - 1) / 2)), hi = (int)std::min<double>(reach, nx / 2);
+  const int64_t n = (int64_t)Mx * (hi - lo + 1);
+  hipLaunchKernelGGL(k_compress_basis, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nx, Mx, a0, half_px, lo, hi,
+                     conj_all ? 1 : 0, out);
   return hipGetLastError();
 }
 

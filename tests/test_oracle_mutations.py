@@ -129,11 +129,27 @@ def _mut_augmented_blocks(monkeypatch):
     monkeypatch.setattr(oapf, "grad_augmented_params", bad)
 
 
+def _mut_compress_phase(monkeypatch):
+    import oracle.compress as oc
+    orig = oc.decompression
+
+    def bad(prob, pad):
+        DC, DB = orig(prob, pad)
+        return DC, np.conj(DB)                        # wrong sign of the inverse transform's phase
+    monkeypatch.setattr(oc, "decompression", bad)
+
+
+def _compress_pin():
+    import tests.test_oracle_compress as cpins
+    cpins.test_untruncated_compression_reproduces_S(6)
+
+
 def _sampled_pin():
     pins.test_sampled_input_gradient_equals_the_full_gradient(16, 60, 0.15, "row")
 
 
 MUTATIONS = {
+    "compress_phase": (_mut_compress_phase, [_compress_pin]),
     "augmented_conj": (_mut_augmented_blocks, [pins.test_augmented_parameter_gradient_pins]),
     "sampled_adjoint_columns": (_mut_sampled_adjoint_columns, [_sampled_pin]),
     "mirror_sign": (_mut_mirror_sign, [spins.test_jacobian_matches_finite_differences,
