@@ -351,12 +351,24 @@ apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk);
  * and returns S = D_C S~ D_B, the exact S of the original channels when
  * nothing is truncated and an approximation otherwise (about 1e-3 .. 1e-2 at
  * a 3-wavelength window and pad = M / 5, less for wider windows; see the
- * design notes).  apf_grad and the augmented and batched entry points refuse
- * compressed handles (APF_EINVAL).  pad = -1 switches compression off again.
+ * design notes).  apf_grad then runs Eq. (3) over the compressed channels:
+ * dF/dS~ = D_C^T dF/dS D_B^T, forward fields A^-1 B~ and weighted adjoint
+ * fields A^-1 C~^T dF/dS~ over the M'_B compressed columns (the exact
+ * gradient of the decompressed S).  The augmented and batched entry points
+ * refuse compressed handles (APF_EINVAL).  pad = -1 switches compression off
+ * again.
  * Call after apf_analyze and before the first apf_assemble (else
  * APF_ESTATE); APF_EINVAL for non-consecutive orders, pad < -1, a window that
  * is not positive or narrower than the spacing nx / M' of the columns. */
 apf_status apf_set_compression(apf_handle *h, int32_t pad, double window_wavelengths);
+
+/* Whether the plan prepares the gradient sweeps (on = 1, the default) or
+ * only S (on = 0): without them the factorization skips the products that
+ * only the sweeps read (X12 = U^-1 U12, Z = L21 L^-1, X1B and XC1 of the
+ * fronts the sweeps visit) and the handle allocates no sweep arrays;
+ * apf_grad then returns APF_ESTATE.  Call after apf_analyze and before the
+ * first apf_assemble (else APF_ESTATE); APF_EINVAL unless on is 0 or 1. */
+apf_status apf_set_gradient(apf_handle *h, int32_t on);
 
 /* Enable (max_iter >= 1) or disable (0, the default) APF_MIXED_REFINED on
  * this handle: the plan then keeps the triangular inverses, L21 and

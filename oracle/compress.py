@@ -100,3 +100,22 @@ def scattering_matrix_compressed(prob, eps, pad, half_px, solver=None):
     Sp = compressed_schur(prob, eps, pad, half_px, solver)
     DC, DB = decompression(prob, pad)
     return DC @ Sp @ DB
+
+
+def grad_compressed(prob, eps, G, pad, half_px, solver=None):
+    """Eq. (3) over the compressed channels: the exact gradient of f(S) with
+    S = D_C S' D_B and S' = C~ A^-1 B~.  Since dS/dp = D_C (dS'/dp) D_B, the
+    derivative with respect to S' is G' = D_C^T G D_B^T, and the gradient is
+    the one of the plain route with (B~, C~, G') in place of (B, C, G):
+    forward fields A^-1 B~, weighted adjoint fields A^-1 C~^T G'.
+    Returns (S, grad)."""
+    if solver is None:
+        solver = apf.make_solver(prob, eps)
+    Bt = source_basis(prob, pad, half_px)
+    Ct = projection_basis(prob, pad, half_px)
+    DC, DB = decompression(prob, pad)
+    Y = solver.solve(apf._rhs_on_row(prob, prob.src_row, Bt))
+    S = DC @ (Ct @ Y[prob.prj_row]) @ DB
+    Gp = DC.T @ G @ DB.T
+    Lam = solver.solve(apf._rhs_on_row(prob, prob.prj_row, Ct.T @ Gp))
+    return S, apf.gradient_from_fields(prob, Y, Lam)

@@ -32,7 +32,7 @@ ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
                 "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement",
                 "apf_grad_augmented", "apf_ridges_grad_augmented", "apf_autotune", "apf_tuning_apply",
-                "apf_set_compression")
+                "apf_set_compression", "apf_set_gradient")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow", "refine", "adjoint_source")
 
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_lowrank.argtypes = [vp, i32]
     lib.apf_set_refinement.argtypes = [vp, i32, dbl]
     lib.apf_set_compression.argtypes = [vp, i32, dbl]
+    lib.apf_set_gradient.argtypes = [vp, i32]
     lib.apf_autotune.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.c_char_p, vp]
     lib.apf_tuning_apply.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_char_p, vp]
     lib.apf_grad_augmented.argtypes = [vp, i32, vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), vp]
@@ -167,6 +168,12 @@ class APF:
         channel sets by `pad` orders, Hann-weight, transform to localized
         columns truncated to the window; pad = -1 switches it off."""
         _check(self._lib.apf_set_compression(self._h, int(pad), float(window_wavelengths)))
+        return self
+
+    def set_gradient(self, on: bool):
+        """Prepare the gradient sweeps (default) or only S (after analyze,
+        before the first assemble)."""
+        _check(self._lib.apf_set_gradient(self._h, 1 if on else 0))
         return self
 
     def set_refinement(self, max_iter: int, tol: float = 1e-10):

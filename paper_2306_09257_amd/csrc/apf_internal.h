@@ -121,7 +121,8 @@ enum GemmFlags : int32_t {
   G_CIN = 4,               // Cin present (else treated as zero)
   G_B_COFF = 8,            // add the launch's column offset to B
   G_CIN_COFF = 16,         // add the launch's column offset to Cin
-  G_B_EXT = 32,            // B is the launch's external pointer (caller buffer)
+  G_B_EXT = 32,            // B is the launch's external pointer (caller buffer) plus the element
+                           // offset held in the B field (a plain number, not an address)
   G_C_EXT = 64,            // C is the launch's external pointer (caller buffer)
   // triangular operands stored packed in one square array (masks apply to the
   // stored indices (r, c); zero blocks of K are skipped):
@@ -142,6 +143,10 @@ enum GemmFlags : int32_t {
   G_ACC_CHUNK = 131072,    // C's old value is added when the launch's column offset is > 0
   G_K3 = 262144,           // complex products in the three-product form (launched on the deep-K kernel)
   G_C_COFF = 524288,       // add the launch's column offset to C
+  // Cin covers only the global columns [cin_c0, cin_c0 + cin_w) of the
+  // launch (column coff + j of the launch is Cin column coff + j - cin_c0;
+  // zero outside): a compressed channel panel of one front
+  G_CIN_RANGE = 1048576,
 };
 
 struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B (a 32 x 32 quadrant for W tasks)
@@ -160,6 +165,7 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B (a 
   const int32_t *auxmap;   // G_CONTRACT: row -> contraction slot, or -1
   const int32_t *ccolmap;  // if set, column j of C is column ccolmap[j]
   const int32_t *arowmap;  // W tasks: row i of A is A + arowmap[i]*lda
+  int32_t cin_c0, cin_w;   // G_CIN_RANGE: the global columns Cin holds
 };
 
 struct ZeroRange { cplx *ptr; int64_t n; };

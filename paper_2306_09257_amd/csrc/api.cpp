@@ -277,6 +277,11 @@ struct Plan {
   cplx *czBt = nullptr, *czCt = nullptr, *czS = nullptr, *czDB = nullptr, *czDC = nullptr, *czT = nullptr;
   int64_t czD1 = -1, czD2 = -1;
   int nczD1 = 0, nczD2 = 0;
+  // compressed gradient: dF/dS~ = D_C^T dF/dS D_B^T (M'_C x M'_B) through
+  // T2 = D_C^T dF/dS (M'_C x n_in), with D_B^T stored (n_in x M'_B)
+  cplx *czG = nullptr, *czT2 = nullptr, *czDBt = nullptr;
+  int64_t czG1 = -1, czG2 = -1;
+  int nczG1 = 0, nczG2 = 0;
   double vinit_cmacs = 0;     // complex MACs of the dense weighted-adjoint-source product
   double *part = nullptr;
   int64_t ws_elems = 0, fs_elems = 0, x_elems = 0;
@@ -284,7 +289,9 @@ struct Plan {
   std::vector<LevelTasks> lv;
   int64_t vinit = -1, gidx = -1, fronts = -1, gSsplit = -1, vmap_base = -1, vmap_pidx = -1;
   int64_t xc_rows = 0;        // rows of the weighted-adjoint operand store (sweep fronts with C rows)
-  cplx *xc = nullptr;         // L^-T U^-T FC1^T of those fronts, stacked: xc_rows x n_out
+  int64_t xc_elems = 0;       // its size: xc_rows x n_out, or the sum of p x mC of compressed panels
+  cplx *xc = nullptr;         // L^-T U^-T FC1^T of those fronts, stacked front by front (ld mC)
+  int ncol = 0;               // right-hand-side columns of the sweeps: n_in, or M'_B when compressed
   int32_t *vmap = nullptr;    // V row of every xc row (rebuilt from the pivot permutations per call)
   int nfronts = 0, ngSsplit = 0, nseg = 0;
   cplx *spart = nullptr;      // FP64 partial Schur blocks (nseg x n_out x n_in)
@@ -420,9 +427,6 @@ GemmTask gemm(const cplx *A, int lda, const cplx *B, int ldb, cplx *C, int ldc, 
   return t;
 }
 
-// Offsets of one front's blocks: workspace (transient) sub-blocks relative
-// to its workspace block `ws`; factor-store offsets encoded as -2 - offset
-// for blocks that live in the persistent store.
 // Offsets of one front's blocks.  Workspace (transient) sub-blocks are
 // relative to the front's workspace block `ws`; fs_* are offsets in the
 // persistent factor store (-1 if absent); sk is the front's first row in the
@@ -435,6 +439,7 @@ struct Off {
   int64_t pws = -1, pwsz = 0;
   int64_t ws = -1, core = -1, bp = -1, cpiv = -1, cbnd = -1, tri = -1, u12 = -1, l21 = -1, u1b = -1, lc1t = -1;
   int64_t fs_x12 = -1, fs_z = -1, fs_x1b = -1, xk = -1, sk = -1;
+  int64_t xoff = -1;   // first element of the front's XC1 block (p x mC) in the xc store
   int64_t wsz = 0;
   // refinement: retained tri, L21 and (fronts outside the sweeps) X12
   int64_t ss_tri = -1, ss_l21 = -1, ss_x12 = -1;
@@ -473,7 +478,19 @@ struct apf_handle {
   int refine_iters = 0; // > 0: the plan keeps every front's factors for APF_MIXED_REFINED
   double refine_tol = 0.0;
   bool refined = false; // the factors held come from APF_MIXED_REFINED (apf_grad refines too)
+  bool sweeps = true;   // the plan prepares the gradient sweeps (apf_set_gradient)
 };
+
+// The gradient sweeps' data (X12, Z, X1B, XC1 of the sweep fronts, the X/V
+// arrays) is built only when the handle wants gradients: without it, no
+// front is a sweep front.
+static void drop_sweeps_unless_wanted(apf_handle *H) {
+  if (H->sweeps) return;
+  Symbolic &S = H->sym;
+  for (Front &F : S.fronts) F.sweep = false;
+  S.n_sweep_rows = 0;
+  std::fill(S.node_sweep_row.begin(), S.node_sweep_row.end(), -1);
+}
 
 // ---------------------------------------------------------------------------
 // validation and creation
@@ -541,6 +558,7 @@ extern "C" apf_status apf_analyze(apf_handle *h) {
   if (h->analyzed) return APF_OK;
   try {
     analyze(h->d, h->sym);
+    drop_sweeps_unless_wanted(h);
     size_plan(h);
   } catch (const std::bad_alloc &) {
     return fail(APF_ENOMEM, "host allocation failed in analysis");
@@ -567,7 +585,7 @@ static void size_plan(apf_handle *H) {
   o.assign(nf, Off());
   Arena ar;
   std::vector<std::vector<int>> release_at(H_ + 2);
-  int64_t fs = 0, ktot = 0, xck = 0, ss = 0;
+  int64_t fs = 0, ktot = 0, xck = 0, xce = 0, ss = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
     const bool cz = H->cz.pad >= 0;
@@ -589,7 +607,7 @@ static void size_plan(apf_handle *H) {
     if (F.sweep) {
       if (b) { q.fs_x12 = fs; fs += up(p * b); q.fs_z = fs; fs += up(b * p); }
       if (mB) { q.fs_x1b = fs; fs += up(p * mB); }
-      if (mC) { q.xk = xck; xck += p; }
+      if (mC) { q.xk = xck; xck += p; q.xoff = xce; xce += p * mC; }
     }
     if (F.sfront && !cz) { q.sk = ktot; ktot += p; }
     if (H->refine_iters > 0) {
@@ -624,6 +642,7 @@ static void size_plan(apf_handle *H) {
   P.fs_elems = std::max<int64_t>(fs, 1);
   P.R.ss_elems = ss;
   P.xc_rows = xck;
+  P.xc_elems = xce;
   S.k_total = ktot;
 }
 
@@ -894,6 +913,7 @@ static void build_plan(apf_handle *H) {
 
   const std::vector<Off> &o = H->off;
   const int64_t ktot = S.k_total;
+  P.ncol = H->cz.pad >= 0 ? H->cz.MxB : Mi;
   HIPCHK(hipMalloc(&P.ws, P.ws_elems * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.fs, P.fs_elems * sizeof(cplx)));
   const bool cz = H->cz.pad >= 0;
@@ -939,6 +959,15 @@ static void build_plan(apf_handle *H) {
     }
     HIPCHK(hipMemcpy(P.czDB, DB.data(), DB.size() * sizeof(cplx), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(P.czDC, DC.data(), DC.size() * sizeof(cplx), hipMemcpyHostToDevice));
+    if (S.n_sweep_rows > 0) {
+      std::vector<cplx> DBt((size_t)Mi * Z.MxB);
+      for (int j = 0; j < Z.MxB; ++j)
+        for (int a = 0; a < Mi; ++a) DBt[(size_t)a * Z.MxB + j] = DB[(size_t)j * Mi + a];
+      HIPCHK(hipMalloc(&P.czDBt, DBt.size() * sizeof(cplx)));
+      HIPCHK(hipMalloc(&P.czT2, (int64_t)Z.MxC * Mi * sizeof(cplx)));
+      HIPCHK(hipMalloc(&P.czG, (int64_t)Z.MxC * Z.MxB * sizeof(cplx)));
+      HIPCHK(hipMemcpy(P.czDBt, DBt.data(), DBt.size() * sizeof(cplx), hipMemcpyHostToDevice));
+    }
     HIPCHK(hipDeviceSynchronize());
   }
   if (H->refine_iters > 0) HIPCHK(hipMalloc(&P.R.ss, std::max<int64_t>(P.R.ss_elems, 1) * sizeof(cplx)));
@@ -946,7 +975,7 @@ static void build_plan(apf_handle *H) {
   HIPCHK(hipMalloc(&P.sc, std::max<int64_t>(ktot * Mo, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.aval, (int64_t)d.nx * d.ny * 5 * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.perms, (int64_t)d.nx * d.ny * sizeof(int32_t)));
-  HIPCHK(hipMalloc(&P.xc, std::max<int64_t>(P.xc_rows * Mo, 1) * sizeof(cplx)));
+  HIPCHK(hipMalloc(&P.xc, std::max<int64_t>(P.xc_elems, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.vmap, std::max<int64_t>(P.xc_rows, 1) * sizeof(int32_t)));
   HIPCHK(hipMalloc(&P.status, 2 * sizeof(int)));
   HIPCHK(hipMalloc(&P.g_nnz, (int64_t)Mi * sizeof(int32_t)));
@@ -963,9 +992,9 @@ static void build_plan(apf_handle *H) {
     int64_t rows = std::max<int64_t>(S.n_sweep_rows, 1);
     double budget = 0.5 * (double)fr;
     int64_t chunk = (int64_t)(budget / (2.0 * rows * sizeof(cplx)));
-    chunk = std::min<int64_t>(chunk, Mi);
+    chunk = std::min<int64_t>(chunk, P.ncol);
     if (H->max_chunk > 0) chunk = std::min<int64_t>(chunk, H->max_chunk);
-    if (chunk < Mi) chunk = std::max<int64_t>(64, chunk / 64 * 64);
+    if (chunk < P.ncol) chunk = std::max<int64_t>(64, chunk / 64 * 64);
     P.rhs_chunk = (int)std::max<int64_t>(chunk, 1);
     P.x_elems = rows * P.rhs_chunk;
     HIPCHK(hipMalloc(&P.X, P.x_elems * sizeof(cplx)));
@@ -1002,7 +1031,7 @@ static void build_plan(apf_handle *H) {
           gi[S.node_sweep_row[(int64_t)y * d.nx + x]] = (int32_t)((int64_t)(y - d.design_row0) * d.nx + x);
     P.gidx = ib.add(gi);
     P.ndesign = (int64_t)(d.design_row1 - d.design_row0) * d.nx;
-    P.nblk = 2 * ((Mi + 63) / 64);
+    P.nblk = 2 * ((P.ncol + 63) / 64);
     HIPCHK(hipMalloc(&P.gpart, std::max<int64_t>(P.ndesign * P.nblk, 1) * sizeof(double)));
     // slots of low-rank fronts' pixels are never written: keep them zero
     HIPCHK(hipMemset(P.gpart, 0, std::max<int64_t>(P.ndesign * P.nblk, 1) * sizeof(double)));
@@ -1207,7 +1236,7 @@ static void build_plan(apf_handle *H) {
   std::vector<GemmTask> vinit;
   std::vector<int32_t> vmap_base(P.xc_rows), vmap_pidx(P.xc_rows);
   std::vector<int> loc((int64_t)d.nx * d.ny, -1);
-  double cm_factor = 0, cm_sweep = 0, cm_wprop = 0, cm_w = 0;
+  double cm_factor = 0, cm_sweep = 0, cm_wprop = 0, cm_w = 0, vinit_acc = 0;
   for (int f = 0; f < nf; ++f) {
     const Front &F = S.fronts[f];
     const FrontDev &D = fd[f];
@@ -1360,7 +1389,7 @@ static void build_plan(apf_handle *H) {
       if (b) add_tiles(g2[lvl], gemm(tri, p, u12, b, FSx(q.fs_x12), b, p, b, p, G_A_TRI_U));
       if (mB) add_tiles(g2[lvl], gemm(tri, p, u1b, mB, FSx(q.fs_x1b), mB, p, mB, p, G_A_TRI_U));
       if (b) add_tiles(g2[lvl], gemm(l21, p, tri, p, FSx(q.fs_z), p, b, p, p, G_B_TRI_L));
-      if (mC) add_tiles(g2[lvl], gemm(tri, p, lc1t, mC, P.xc + q.xk * Mo, mC, p, mC, p, G_TRANS_A | G_A_TRI_L));
+      if (mC) add_tiles(g2[lvl], gemm(tri, p, lc1t, mC, P.xc + q.xoff, mC, p, mC, p, G_TRANS_A | G_A_TRI_L));
     }
     cm_factor += g_cmacs_acc;
     g_cmacs_acc = 0;
@@ -1375,7 +1404,12 @@ static void build_plan(apf_handle *H) {
       cplx *Xf = P.X + (int64_t)D.sweep_row0 * ch, *Vf = P.V + (int64_t)D.sweep_row0 * ch;
       const int32_t *bm = reinterpret_cast<const int32_t *>((intptr_t)bndrow_off[f]);  // rebased below
       GemmTask ty = gemm(b ? FSx(q.fs_x12) : nullptr, b, P.X, ch, Xf, ch, p, ch, b,
-                         G_NEG | (mB ? G_CIN | G_CIN_COFF : 0), mB ? FSx(q.fs_x1b) : nullptr, mB, b ? bm : nullptr);
+                         G_NEG | (mB ? G_CIN | (cz ? G_CIN_RANGE : G_CIN_COFF) : 0), mB ? FSx(q.fs_x1b) : nullptr, mB,
+                         b ? bm : nullptr);
+      if (cz && mB) {   // X1B holds the compressed columns [cB0, cB1) of the front
+        ty.cin_c0 = H->cz.cB0[f];
+        ty.cin_w = mB;
+      }
       bool lam_read = false;
       for (int c = 0; c < F.nchild; ++c) lam_read = lam_read || S.fronts[F.child[c]].sweep;
       GemmTask tv = gemm(b ? FSx(q.fs_z) : nullptr, p, P.V, ch, Vf, ch, p, ch, b,
@@ -1394,7 +1428,7 @@ static void build_plan(apf_handle *H) {
         tw.arowmap = bm;
         tw.browmap = bm;
         g_cmacs_acc += (double)b * b * ch;
-        cm_w += (double)b * b * Mi;
+        cm_w += (double)b * b * P.ncol;
         swW[lvl].push_back(tw);
       }
       if (wcov[f]) {
@@ -1432,13 +1466,30 @@ static void build_plan(apf_handle *H) {
           vmap_base[q.xk + k] = D.sweep_row0;
           vmap_pidx[q.xk + k] = (int32_t)(F.elim0 + k);
         }
+      if (mC && cz) {
+        // compressed: the front's own weighted adjoint source, V rows of its
+        // pivots = XC1 (p x mC) times rows [cC0, cC1) of dF/dS~ (the launch's
+        // external operand, at element offset cC0 M'_B)
+        GemmTask ti = gemm(P.xc + q.xoff, mC,
+                           reinterpret_cast<const cplx *>((intptr_t)((int64_t)H->cz.cC0[f] * H->cz.MxB)),
+                           H->cz.MxB, P.V, ch, p, ch, mC, G_B_EXT | G_B_COFF);
+        ti.crowmap = P.vmap + q.xk;
+        const double acc0 = g_cmacs_acc;
+        add_tiles_xcd(vinit, ti);
+        vinit_acc += g_cmacs_acc - acc0;
+        g_cmacs_acc = acc0;
+      }
     }
-    cm_sweep += g_cmacs_acc * ((double)Mi / P.rhs_chunk);
+    cm_sweep += g_cmacs_acc * ((double)P.ncol / P.rhs_chunk);
   }
   // weighted adjoint source of every sweep front with C rows in one GEMM:
   // V[vmap[r]] = XC[r] G, rows scattered through the permutation map
   double cm_vinit = 0;
-  if (P.xc_rows) {
+  if (cz) {
+    cm_vinit = vinit_acc * ((double)P.ncol / P.rhs_chunk);
+    cm_sweep += cm_vinit;
+    P.vinit_cmacs = cm_vinit;
+  } else if (P.xc_rows) {
     g_cmacs_acc = 0;
     GemmTask ti = gemm(P.xc, Mo, nullptr, Mi, P.V, P.rhs_chunk, (int)P.xc_rows, P.rhs_chunk, Mo, G_B_EXT | G_B_COFF);
     ti.crowmap = P.vmap;
@@ -1454,7 +1505,7 @@ static void build_plan(apf_handle *H) {
   // split over k segments of SPLIT_K rows, each accumulated on MFMA (FP64,
   // or FP32 on the mixed path) into an FP64 partial block; one kernel sums
   // the blocks
-  std::vector<GemmTask> gSsplit, czD1, czD2;
+  std::vector<GemmTask> gSsplit, czD1, czD2, czG1, czG2;
   P.nseg = cz ? 0 : (int)std::max<int64_t>(1, (ktot + SPLIT_K - 1) / SPLIT_K);
   if (!cz) HIPCHK(hipMalloc(&P.spart, (int64_t)P.nseg * Mo * Mi * sizeof(cplx)));
   g_cmacs_acc = 0;
@@ -1462,6 +1513,12 @@ static void build_plan(apf_handle *H) {
     // S = D_C (S~ D_B)
     add_tiles_xcd(czD1, gemm(P.czS, H->cz.MxB, P.czDB, Mi, P.czT, Mi, H->cz.MxC, Mi, H->cz.MxB, G_K3));
     add_tiles_xcd(czD2, gemm(P.czDC, H->cz.MxC, P.czT, Mi, nullptr, Mi, Mo, Mi, H->cz.MxC, G_C_EXT | G_K3));
+    if (P.czG) {
+      // dF/dS~ = (D_C^T dF/dS) D_B^T
+      add_tiles_xcd(czG1, gemm(P.czDC, H->cz.MxC, nullptr, Mi, P.czT2, Mi, H->cz.MxC, Mi, Mo,
+                               G_TRANS_A | G_B_EXT | G_K3));
+      add_tiles_xcd(czG2, gemm(P.czT2, Mi, P.czDBt, H->cz.MxB, P.czG, H->cz.MxB, H->cz.MxC, H->cz.MxB, Mi, G_K3));
+    }
   }
   for (int g = 0; g < P.nseg; ++g) {
     const int64_t k0 = (int64_t)g * SPLIT_K;
@@ -1538,6 +1595,8 @@ static void build_plan(apf_handle *H) {
   P.gSsplit = bl.add(gSsplit); P.ngSsplit = (int)gSsplit.size();
   P.czD1 = bl.add(czD1); P.nczD1 = (int)czD1.size();
   P.czD2 = bl.add(czD2); P.nczD2 = (int)czD2.size();
+  P.czG1 = bl.add(czG1); P.nczG1 = (int)czG1.size();
+  P.czG2 = bl.add(czG2); P.nczG2 = (int)czG2.size();
   P.vinit = bl.add(vinit); P.nvinit = (int)vinit.size();
   P.vmap_base = bl.add(vmap_base);
   P.vmap_pidx = bl.add(vmap_pidx);
@@ -1621,7 +1680,7 @@ static void free_plan(Plan &P) {
   const Refine &R = P.R;
   void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
                   P.xc, P.vmap, P.gpart, P.lrW, P.g_nnz, P.g_max, P.g_idx, P.g_val, P.czBt, P.czCt, P.czS,
-                  P.czDB, P.czDC, P.czT, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
+                  P.czDB, P.czDC, P.czT, P.czG, P.czT2, P.czDBt, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
                   R.elim, R.norms, R.blob};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -2175,12 +2234,12 @@ extern "C" apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, in
 extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev, void *stream) {
   if (!h || !dfdS_dev || !grad_dev) return fail(APF_EINVAL, "null argument");
   if (h->state != 2) return fail(APF_ESTATE, "apf_factor_schur has not run since the last assembly");
-  if (h->cz.pad >= 0)
-    return fail(APF_EINVAL, "the per-pixel gradient needs the uncompressed channel panels (apf_set_compression)");
+  if (!h->sweeps) return fail(APF_ESTATE, "the handle prepares no gradient sweeps (apf_set_gradient)");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     Plan &P = h->plan;
-    const int Mi = h->d.n_in, ch = P.rhs_chunk;
+    const int Mi = h->d.n_in, ch = P.rhs_chunk, ncol = P.ncol;
+    const bool cz = h->cz.pad >= 0;
     const cplx *G = reinterpret_cast<const cplx *>(dfdS_dev);
     const double two_h2 = 2.0 * h->phys.h2;
     Profiler &pr = h->prof;
@@ -2210,10 +2269,21 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
     }
     HIPCHK(launch_row_map(P.vmap, P.at<int32_t>(P.vmap_base), P.at<int32_t>(P.vmap_pidx), P.perms, P.xc_rows, s));
     const bool f32 = h->mixed;
+    if (cz) {
+      // Eq. (3) over the compressed channels: S = D_C S~ D_B, so the
+      // derivative with respect to S~ is D_C^T dF/dS D_B^T (FP64)
+      pr.run(P_VSRC, s, [&] {
+        hipError_t e = launch_gemm(P.at<GemmTask>(P.czG1), P.nczG1, 0, INT_MAX, G, s, false, nullptr, 0, true);
+        if (e == hipSuccess)
+          e = launch_gemm(P.at<GemmTask>(P.czG2), P.nczG2, 0, INT_MAX, nullptr, s, false, nullptr, 0, true);
+        return e;
+      });
+      G = P.czG;
+    }
     // a dF/dS with few nonzeros per input column (a few target orders per
     // input) forms the weighted adjoint source from compact column lists
     int K = 0;
-    if (P.nvinit > 0) {
+    if (P.nvinit > 0 && !cz) {
       const int Mo = h->d.n_out;
       int mx = 0;
       HIPCHK(launch_fill_int(P.g_max, 0, s));
@@ -2226,8 +2296,8 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
       }
     }
     P.last_sparse_k = K;
-    for (int m0 = 0; m0 < Mi; m0 += ch) {
-      const int w = std::min(ch, Mi - m0);
+    for (int m0 = 0; m0 < ncol; m0 += ch) {
+      const int w = std::min(ch, ncol - m0);
       if (P.nvinit > 0 && K > 0) {
         pr.run(P_VSRC, s, [&] {
           return launch_sparse_vinit(P.xc, h->d.n_out, P.xc_rows, P.vmap, P.g_idx, P.g_val, K, m0, w, P.V, ch, s);
@@ -2899,7 +2969,6 @@ extern "C" apf_status apf_set_compression(apf_handle *h, int32_t pad, double win
     if (pad < 0) {
       // back to full channel panels and the gradient sweeps
       h->cz = Compress();
-      analyze(h->d, h->sym);
       size_plan(h);
       return APF_OK;
     }
@@ -2919,12 +2988,7 @@ extern "C" apf_status apf_set_compression(apf_handle *h, int32_t pad, double win
     // every node must lie in some column's window
     if ((double)d.nx / std::min(Z.MxB, Z.MxC) > 2.0 * Z.half_px)
       return fail(APF_EINVAL, "the window is narrower than the spacing of the compressed columns");
-    // the compressed panels make the gradient sweeps unavailable: no front
-    // keeps sweep data
     Symbolic &S = h->sym;
-    for (Front &F : S.fronts) F.sweep = false;
-    S.n_sweep_rows = 0;
-    std::fill(S.node_sweep_row.begin(), S.node_sweep_row.end(), -1);
     // per front: the columns whose window meets the front's region (x0..x1,
     // periodic), one margin column each side; a range that would wrap is the
     // whole set.  A parent's region holds its children's, so its range does.
@@ -2950,6 +3014,23 @@ extern "C" apf_status apf_set_compression(apf_handle *h, int32_t pad, double win
         throw std::runtime_error("compressed column ranges do not nest");
     }
     h->cz = std::move(Z);
+    size_plan(h);
+    return APF_OK;
+  });
+}
+
+extern "C" apf_status apf_set_gradient(apf_handle *h, int32_t on) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  if (on != 0 && on != 1) return fail(APF_EINVAL, "on must be 0 or 1");
+  if (!h->analyzed) return fail(APF_ESTATE, "apf_analyze has not run");
+  if (h->planned) return fail(APF_ESTATE, "the plan is already built (apf_assemble has run)");
+  if (h->sweeps == (on != 0)) return APF_OK;
+  return guarded([&]() -> apf_status {
+    h->sweeps = on != 0;
+    // the analysis marks the sweep fronts; the tree (and any compressed
+    // column ranges over it) is the same on every run
+    analyze(h->d, h->sym);
+    drop_sweeps_unless_wanted(h);
     size_plan(h);
     return APF_OK;
   });

@@ -444,7 +444,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   const int M = T.M, K = ((T.flags & G_K_LIM) && nlimk < T.K) ? nlimk : T.K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool transA = T.flags & G_TRANS_A;
-  const cplx *Bp = (T.flags & G_B_EXT) ? ext : T.B;
+  const cplx *Bp = (T.flags & G_B_EXT) ? ext + reinterpret_cast<intptr_t>(T.B) : T.B;
   if (T.flags & G_B_COFF) Bp += coff;
   cplx *Cp = (T.flags & G_C_EXT) ? const_cast<cplx *>(ext) : T.C;
   if (T.flags & G_C_COFF) Cp += coff;
@@ -646,6 +646,9 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   const bool store = !(T.flags & G_NO_STORE), contract = T.flags & G_CONTRACT;
   const cplx *Cin = (T.flags & G_CIN) ? T.Cin : nullptr;
   if (Cin && (T.flags & G_CIN_COFF)) Cin += coff;
+  // G_CIN_RANGE: Cin column of output column j, or -1 where Cin is zero
+  const bool crange = T.flags & G_CIN_RANGE;
+  const int cshift = coff - T.cin_c0;
   // Epilogue in three passes (results, stores, contraction), so that the
   // loads of each pass are all in flight together.  Lane l holds rows
   // row(l, q) of the 16-row blocks r and columns l % 16 of the blocks c.
@@ -685,8 +688,13 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
         else
           v[r][c][q] = make_double2((double)cre[r][c][q], (double)cim[r][c][q]);
         if (neg) v[r][c][q] = make_double2(-v[r][c][q].x, -v[r][c][q].y);
-        if (Cin && rowok[r][q] && colok[c])
+        if (crange) {
+          const int cj = gj + cshift;
+          if (Cin && rowok[r][q] && colok[c] && cj >= 0 && cj < T.cin_w)
+            v[r][c][q] = cadd(v[r][c][q], ld2(Cin + ci[r][q] * T.ldcin + cj));
+        } else if (Cin && rowok[r][q] && colok[c]) {
           v[r][c][q] = cadd(v[r][c][q], ld2(Cin + ci[r][q] * T.ldcin + (own ? gj : oj[c])));
+        }
         if ((addold[r][q] || cacc) && rowok[r][q] && colok[c])
           v[r][c][q] = cadd(v[r][c][q], ld2(Cp + oi[r][q] * T.ldc + oj[c]));
       }

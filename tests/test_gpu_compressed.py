@@ -2,7 +2,10 @@
 reading): the compressed factorization's S against the oracle's compressed
 route (same padding, window and truncation) at 1e-10, and, with nothing
 truncated, against the plain oracle S at 1e-10; its distance from the
-uncompressed S at the paper's window; the state and argument checks."""
+uncompressed S at the paper's window; the gradient over the compressed
+channels (Eq. (3) with dF/dS~ = D_C^T dF/dS D_B^T) against the oracle's
+compressed route at 1e-10, with chunked sweeps and both low-rank depths; the
+state and argument checks."""
 import numpy as np
 import pytest
 
@@ -77,10 +80,16 @@ def test_compression_state_and_argument_checks():
         apf.set_compression(-1, 0.0)                   # after the first assembly
     assert ei.value.status == binding.APF_ESTATE
     S = apf.factor_schur()
-    f, G = apf.weighted_power(S, _dev(w))
+    # without the gradient sweeps: the same S, and apf_grad is refused
+    nog = binding.APF(prob).analyze().set_compression(4, 3.0).set_gradient(False)
+    nog.assemble(_dev(eps))
+    S_n = nog.factor_schur()
+    assert nog.query("n_sweep_rows") == 0 and nog.query("n_sweep_rows") < apf.query("n_sweep_rows")
+    assert torch.equal(S_n, S)
+    f, G = nog.weighted_power(S_n, _dev(w))
     with pytest.raises(binding.APFError) as ei:
-        apf.grad(G)
-    assert ei.value.status == binding.APF_EINVAL
+        nog.grad(G)
+    assert ei.value.status == binding.APF_ESTATE
     # switched off again before the plan: the plain path, gradient included
     plain = binding.APF(prob).analyze().set_compression(4, 3.0).set_compression(-1, 0.0)
     plain.assemble(_dev(eps))
@@ -88,3 +97,32 @@ def test_compression_state_and_argument_checks():
     f2, G2 = plain.weighted_power(S2, _dev(w))
     S_o, g_o, _ = oapf.solve_S_and_grad(prob, eps, w=w)
     assert rel(S2.cpu().numpy(), S_o) < TOL and rel(plain.grad(G2).cpu().numpy(), g_o) < TOL
+
+
+@pytest.mark.parametrize("nx,ny,pad,window,chunk,lowrank", [(64, 60, 6, 3.0, 0, 1), (240, 92, 24, 3.0, 0, 1),
+                                                           (130, 60, 7, 2.0, 0, 0), (480, 92, 20, 8.0, 64, 2),
+                                                           (960, 92, 40, 3.0, 64, 1)])
+def test_compressed_gradient_matches_the_oracle_route(nx, ny, pad, window, chunk, lowrank):
+    from paper_2306_09257_amd import binding
+    prob = inputs.make_problem(nx, ny)
+    rng = np.random.default_rng(nx + 1)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    w = rng.uniform(0.0, 1.0, size=(prob.n_out, prob.n_in))
+    half_px = 0.5 * window / prob.dx_over_lambda
+    S_oc = oc.scattering_matrix_compressed(prob, eps, pad, half_px)
+    G = w * np.conj(S_oc)
+    print(f"[gpu] compressed gradient {nx}x{ny}, {prob.n_in} channels, pad {pad}, window {window}, chunk {chunk}, "
+          f"low-rank {lowrank}", flush=True)
+    apf = binding.APF(prob).analyze().set_compression(pad, window).set_rhs_chunk(chunk).set_lowrank(lowrank)
+    apf.assemble(_dev(eps))
+    S = apf.factor_schur()
+    g = apf.grad(torch.as_tensor(G, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    S_o2, g_oc = oc.grad_compressed(prob, eps, G, pad, half_px)
+    _, g_plain, _ = oapf.solve_S_and_grad(prob, eps, G=G)
+    print(f"[gpu]   S {rel(S.cpu().numpy(), S_oc):.2e}; gradient vs oracle compressed {rel(g, g_oc):.2e} "
+          f"(worst column block {worst_block(g, g_oc, axis=1):.2e}), compressed vs plain oracle gradient "
+          f"{rel(g_oc, g_plain):.2e}; rhs chunk {apf.query('rhs_chunk'):.0f}", flush=True)
+    assert rel(S_o2, S_oc) < 1e-13
+    if chunk:
+        assert apf.query("rhs_chunk") < pad + prob.n_in
+    assert rel(g, g_oc) < TOL and worst_block(g, g_oc, axis=1) < TOL

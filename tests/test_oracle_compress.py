@@ -61,3 +61,38 @@ def test_compressed_columns_are_localized_and_truncation_error_falls_with_the_wi
     S = oapf.scattering_matrix(prob, eps, solver=solver)
     errs = [_rel(oc.scattering_matrix_compressed(prob, eps, pad, half_px=hw, solver=solver), S) for hw in (30, 60, 90)]
     assert errs[0] > errs[1] > errs[2] and errs[2] < 3e-4, errs
+
+
+def _small_case():
+    return inputs.tiny_problem(nx=64, ny=60, seed=3, in_orders=np.arange(-3, 4, dtype=np.int32),
+                               out_orders=np.arange(-2, 2, dtype=np.int32))
+
+
+@pytest.mark.parametrize("pad", [0, 6])
+def test_untruncated_compressed_gradient_is_the_plain_gradient(pad):
+    prob, eps, w = _small_case()
+    S, g, _ = oapf.solve_S_and_grad(prob, eps, w=w)
+    _, G = oapf.weighted_power(S, w)
+    Sc, gc = oc.grad_compressed(prob, eps, G, pad, half_px=prob.nx)
+    assert _rel(Sc, S) < 1e-12 and _rel(gc, g) < 1e-11
+
+
+def test_truncated_compressed_gradient_matches_central_differences():
+    """The gradient of the compressed route is the exact derivative of the
+    decompressed S it returns (truncated to a narrow window, so that S differs
+    from the plain one), whatever G' = D_C^T G D_B^T makes of dF/dS."""
+    prob, eps, w = _small_case()
+    pad, hw = 6, 9.0
+    Sc, _ = oc.grad_compressed(prob, eps, np.zeros((prob.n_out, prob.n_in), complex), pad, hw)
+    assert _rel(Sc, oapf.scattering_matrix(prob, eps)) > 1e-4      # the truncation matters here
+    _, G = oapf.weighted_power(Sc, w)
+    _, g = oc.grad_compressed(prob, eps, G, pad, hw)
+    step = 1e-4
+    for (r, i) in [(0, 0), (5, 17), (13, 40), (19, 63)]:
+        fs = []
+        for sgn in (1.0, -1.0):
+            e = eps.copy()
+            e[prob.design_row0 + r, i] += sgn * step
+            fs.append(oapf.weighted_power(oc.scattering_matrix_compressed(prob, e, pad, hw), w)[0])
+        fd = (fs[0] - fs[1]) / (2 * step)
+        assert abs(fd - g[r, i]) < 1e-7 * np.abs(g).max(), (r, i, fd, g[r, i])

@@ -139,6 +139,29 @@ def _mut_compress_phase(monkeypatch):
     monkeypatch.setattr(oc, "decompression", bad)
 
 
+def _mut_compress_grad_conj(monkeypatch):
+    import oracle.compress as oc
+    orig = oc.decompression
+
+    def grad_bad(prob, eps, G, pad, half_px, solver=None):
+        DC, DB = orig(prob, pad)
+        if solver is None:
+            solver = oapf.make_solver(prob, eps)
+        Bt = oc.source_basis(prob, pad, half_px)
+        Ct = oc.projection_basis(prob, pad, half_px)
+        Y = solver.solve(oapf._rhs_on_row(prob, prob.src_row, Bt))
+        S = DC @ (Ct @ Y[prob.prj_row]) @ DB
+        Gp = DC.conj().T @ G @ DB.conj().T                 # adjoint instead of transpose
+        Lam = solver.solve(oapf._rhs_on_row(prob, prob.prj_row, Ct.T @ Gp))
+        return S, oapf.gradient_from_fields(prob, Y, Lam)
+    monkeypatch.setattr(oc, "grad_compressed", grad_bad)
+
+
+def _compress_grad_pin():
+    import tests.test_oracle_compress as cpins
+    cpins.test_truncated_compressed_gradient_matches_central_differences()
+
+
 def _compress_pin():
     import tests.test_oracle_compress as cpins
     cpins.test_untruncated_compression_reproduces_S(6)
@@ -150,6 +173,7 @@ def _sampled_pin():
 
 MUTATIONS = {
     "compress_phase": (_mut_compress_phase, [_compress_pin]),
+    "compress_grad_conj": (_mut_compress_grad_conj, [_compress_grad_pin]),
     "augmented_conj": (_mut_augmented_blocks, [pins.test_augmented_parameter_gradient_pins]),
     "sampled_adjoint_columns": (_mut_sampled_adjoint_columns, [_sampled_pin]),
     "mirror_sign": (_mut_mirror_sign, [spins.test_jacobian_matches_finite_differences,
