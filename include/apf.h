@@ -438,6 +438,11 @@ const char *apf_last_error(void);
  *   dF/dS with at most 32 nonzeros per input column, at most n_out / 8),
  *   "lowrank_fronts" and "lowrank_roots" (sweep fronts served by the
  *   low-rank subtree products, and the subtrees' roots);
+ *   after a successful apf_factor_schur (else APF_ESTATE; copies from the
+ *   device): "pivot_spread_min" (the smallest, over the fronts, of the pivot
+ *   block's min |u_kk| / max |u_kk|: a pivot block close to singular, e.g.
+ *   near a resonance of the subdomain it eliminates, shows as a small value)
+ *   and "pivot_spread_front" (the front it belongs to);
  *   with profiling on: "ms_<class>" and "launches_<class>", the summed
  *   HIP-event time and launch count since profiling was enabled, for the
  *   classes stencil, zero, assemble, inverse, gemm_factor, gemm_schur,

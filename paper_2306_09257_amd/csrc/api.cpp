@@ -266,6 +266,7 @@ struct Plan {
   int32_t *perms = nullptr;   // pivot permutation of every front, at its first elimination index
   char *blob = nullptr;
   int *status = nullptr;      // [0]: pivot status of the last factorization; [1]: permittivity check of the last assembly
+  double *pivq = nullptr;     // per front: pivot spread min |u_kk| / max |u_kk| of the last factorization
   int32_t *g_nnz = nullptr;   // column-sparse dF/dS: nonzeros per input, their max, compact (row, value) lists
   int *g_max = nullptr;
   int32_t *g_idx = nullptr;
@@ -978,6 +979,7 @@ static void build_plan(apf_handle *H) {
   HIPCHK(hipMalloc(&P.xc, std::max<int64_t>(P.xc_elems, 1) * sizeof(cplx)));
   HIPCHK(hipMalloc(&P.vmap, std::max<int64_t>(P.xc_rows, 1) * sizeof(int32_t)));
   HIPCHK(hipMalloc(&P.status, 2 * sizeof(int)));
+  HIPCHK(hipMalloc(&P.pivq, std::max<size_t>(S.fronts.size(), 1) * sizeof(double)));
   HIPCHK(hipMalloc(&P.g_nnz, (int64_t)Mi * sizeof(int32_t)));
   HIPCHK(hipMalloc(&P.g_max, sizeof(int)));
   HIPCHK(hipMalloc(&P.g_idx, (int64_t)Mi * kSparseG * sizeof(int32_t)));
@@ -1678,7 +1680,7 @@ static void build_plan(apf_handle *H) {
 
 static void free_plan(Plan &P) {
   const Refine &R = P.R;
-  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.part, P.perms, P.chan, P.spart,
+  void *ptrs[] = {P.ws, P.fs, P.sb, P.sc, P.X, P.V, P.aval, P.blob, P.status, P.pivq, P.part, P.perms, P.chan, P.spart,
                   P.xc, P.vmap, P.gpart, P.lrW, P.g_nnz, P.g_max, P.g_idx, P.g_val, P.czBt, P.czCt, P.czS,
                   P.czDB, P.czDC, P.czT, P.czG, P.czT2, P.czDBt, R.ss, R.X, R.W, R.arena, R.Bmat, R.Cmat, R.rowbuf, R.Ydes,
                   R.elim, R.norms, R.blob};
@@ -1729,7 +1731,7 @@ extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *s
 // indexes; `fr` the front descriptors.
 static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const FrontDev *fr, int *status,
                        Profiler &pr, hipStream_t s, bool f32, const std::vector<AugLevel> *aug = nullptr,
-                       char *ablob = nullptr) {
+                       char *ablob = nullptr, double *pivq = nullptr) {
   auto at = [&](int64_t off) -> char * { return off < 0 ? nullptr : blob + off; };
   auto aat = [&](int64_t off) -> char * { return off < 0 ? nullptr : ablob + off; };
   for (size_t lvl = 0; lvl < lv.size(); ++lvl) {
@@ -1752,7 +1754,7 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     pr.run(P_INVERSE, s, [&] {
       hipError_t e = hipSuccess;
       for (int v = 0; v < N_INV_VARIANTS && e == hipSuccess; ++v)
-        e = launch_inverse(v, fr, (const int32_t *)at(L.inv[v]), L.ninv[v], status, s);
+        e = launch_inverse(v, fr, (const int32_t *)at(L.inv[v]), L.ninv[v], status, pivq, s);
       return e;
     });
     // (empty task lists launch nothing and are not counted)
@@ -1883,7 +1885,7 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
     HIPCHK(launch_fill_int(P.status, 0, s));
     const bool cz = h->cz.pad >= 0;
     if (cz) HIPCHK(launch_zero_flat(P.czS, (int64_t)h->cz.MxC * h->cz.MxB, s));
-    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32);
+    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32, nullptr, nullptr, P.pivq);
     if (cz) {
       // decompression: S = D_C (S~ D_B), FP64
       pr.run(P_GEMM_SCHUR, s, [&] {
@@ -2652,7 +2654,7 @@ static apf_status augmented_grad(apf_handle *h, int32_t n_cols, const int32_t *c
   for (int n = 0; n < nsub; ++n) {
     const AugSubPlan &SP = subs[n];
     HIPCHK(launch_zero_flat(B->blocks, block_max, s));
-    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, false, &SP.lv, B->blob);
+    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, false, &SP.lv, B->blob, P.pivq);
     if (n == 0 && S_dev) enqueue_schur(P, false, S_dev, pr, s, Mo, Mi);
     if (SP.ncg > 0)
       pr.run(P_CONTRACT, s, [&] {
@@ -3087,6 +3089,17 @@ extern "C" apf_status apf_query(apf_handle *h, const char *key, double *value) {
     *value = c;
   } else if (k == "k_total") *value = (double)S.k_total;
   else if (k == "xc_rows") *value = (double)h->plan.xc_rows;
+  else if (k == "pivot_spread_min" || k == "pivot_spread_front") {
+    // smallest pivot spread over the fronts of the last factorization
+    if (h->state != 2 || !h->plan.pivq) return fail(APF_ESTATE, "no factorization has completed since the last assembly");
+    std::vector<double> q(S.fronts.size());
+    if (hipMemcpy(q.data(), h->plan.pivq, q.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(APF_EHIP, "copy of the pivot spreads failed");
+    size_t arg = 0;
+    for (size_t f = 1; f < q.size(); ++f)
+      if (q[f] < q[arg]) arg = f;
+    *value = k == "pivot_spread_min" ? q[arg] : (double)arg;
+  }
   else if (k == "ws_bytes") *value = (double)h->plan.ws_elems * sizeof(cplx);
   else if (k == "factor_bytes") *value = (double)h->plan.fs_elems * sizeof(cplx);
   else if (k == "schur_store_bytes") *value = (double)S.k_total * (h->d.n_in + h->d.n_out) * sizeof(cplx);

@@ -163,7 +163,8 @@ constexpr int INV_MAXP = 1024;   // "no step" marker of a register row past p
 // column kq (a compile-time index) in the threads with tj == kc; only the
 // pivot row, found at run time, needs a run-time register choice.
 template <int TR, int TC, int RR, int RC>
-__global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const int32_t *ids, int *status) {
+__global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const int32_t *ids, int *status,
+                                                       double *pivq) {
   constexpr int MAXP = TR * RR;
   static_assert(TR * RR == TC * RC, "square coverage");
   static_assert(MAXP < INV_MAXP, "the no-step marker must exceed every step");
@@ -174,7 +175,11 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
   __shared__ double2 rowbuf[MAXP], colbuf[MAXP];
   __shared__ int piv_row[MAXP], piv_step[MAXP];
   __shared__ int s_r, s_bad;
+  __shared__ double s_pmin[TC], s_pmax[TC];
   if (tid == 0) s_bad = 0;
+  // smallest and largest |pivot|^2 of the steps this thread selects (the
+  // threads with ti == 0 select the pivots of their column group)
+  double pmin = INFINITY, pmax = 0.0;
   double2 a[RR][RC];
   bool un[RR];   // this thread's rows not pivoted yet
 #pragma unroll
@@ -215,6 +220,8 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
         }
         if (ti == 0) {
           if (!(bv > 0.0) || !(bv < INFINITY)) s_bad = 1;
+          pmin = fmin(pmin, bv);
+          pmax = fmax(pmax, bv);
           s_r = bi;
           piv_row[k] = bi;
           piv_step[bi] = k;
@@ -271,7 +278,21 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
       }
     }
   }
+  if (ti == 0) {
+    s_pmin[tj] = pmin;
+    s_pmax[tj] = pmax;
+  }
   __syncthreads();
+  // pivot spread of the block, min |u_kk| / max |u_kk| (a near-singular block
+  // shows as a small value)
+  if (tid == 0 && pivq) {
+    double lo = INFINITY, hi = 0.0;
+    for (int c = 0; c < TC; ++c) {
+      lo = fmin(lo, s_pmin[c]);
+      hi = fmax(hi, s_pmax[c]);
+    }
+    pivq[ids[blockIdx.x]] = (hi > 0.0 && lo <= hi) ? sqrt(lo / hi) : 0.0;
+  }
   // ---- phase B: in-place inverses of L and U, in step order
   int st[RR];
 #pragma unroll
@@ -1383,15 +1404,16 @@ int inverse_variant(int p) {
 
 // Small blocks (p <= 48, the leaves and short separators) run on one wave:
 // the per-step barriers are then free and more fronts fit on a CU.
-hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, hipStream_t s) {
+hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, double *pivq,
+                          hipStream_t s) {
   if (n == 0) return hipSuccess;
   switch (variant) {
-    case 0: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 2, 2>), dim3(n), dim3(64), 0, s, fr, ids, status); break;
-    case 1: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 4, 4>), dim3(n), dim3(64), 0, s, fr, ids, status); break;
-    case 2: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 6, 6>), dim3(n), dim3(64), 0, s, fr, ids, status); break;
-    case 3: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status); break;
-    case 4: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
-    case 5: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status); break;
+    case 0: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 2, 2>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq); break;
+    case 1: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 4, 4>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq); break;
+    case 2: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 6, 6>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq); break;
+    case 3: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status, pivq); break;
+    case 4: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status, pivq); break;
+    case 5: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status, pivq); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -315,3 +315,55 @@ def test_sparse_adjoint_source_matches_the_dense_product_and_the_oracle():
     assert 1 <= k <= 5
     assert _rel(g_sparse, g_o) < TOL and worst_block(g_sparse, g_o, axis=1) < TOL
     assert _rel(g_sparse, g_dense) < 1e-12
+
+
+def _pivot_spreads_by_elimination(apf, prob, eps):
+    """Per front, min |u_kk| / max |u_kk| of LU with partial pivoting (largest
+    modulus, ties to the lowest row) of the front's pivot block, the Schur
+    complement of A after eliminating every earlier node: dense elimination
+    in the library's order on the CPU (tiny grids only)."""
+    import oracle.fdfd as ofd
+    A = ofd.assemble_dense(prob, eps)
+    nf = int(apf.query("n_fronts"))
+    fronts = [apf.front(f) for f in range(nf)]
+    order = sorted(range(nf), key=lambda f: fronts[f][0][7])
+    alive = np.ones(A.shape[0], bool)
+    spreads = np.zeros(nf)
+    for f in order:
+        piv = fronts[f][1]
+        F = A[np.ix_(piv, piv)].copy()
+        unused = np.ones(len(piv), bool)
+        u = []
+        for k in range(len(piv)):
+            m = np.where(unused, np.abs(F[:, k]) ** 2, -1.0)
+            r = int(np.argmax(m))
+            u.append(abs(F[r, k]))
+            unused[r] = False
+            rows = np.nonzero(unused)[0]
+            F[rows, k:] -= np.outer(F[rows, k] / F[r, k], F[r, k:])
+        spreads[f] = min(u) / max(u)
+        alive[piv] = False
+        rest = np.nonzero(alive)[0]
+        App = A[np.ix_(piv, piv)]
+        A[np.ix_(rest, rest)] -= A[np.ix_(rest, piv)] @ np.linalg.solve(App, A[np.ix_(piv, rest)])
+    return spreads
+
+
+def test_pivot_spread_diagnostic_matches_a_dense_elimination():
+    from paper_2306_09257_amd import binding
+    prob, eps, w = inputs.tiny_problem(nx=24, ny=60, seed=21)
+    apf = binding.APF(prob).analyze()
+    with pytest.raises(binding.APFError) as ei:
+        apf.query("pivot_spread_min")
+    assert ei.value.status == binding.APF_ESTATE
+    apf.assemble(_dev(eps, torch.float64))
+    apf.factor_schur()
+    q, f = apf.query("pivot_spread_min"), int(apf.query("pivot_spread_front"))
+    ref = _pivot_spreads_by_elimination(apf, prob, eps)
+    print(f"[gpu] pivot spread min {q:.6e} at front {f} (p = {apf.front(f)[0][2]}); dense elimination "
+          f"{ref.min():.6e} at front {int(np.argmin(ref))}", flush=True)
+    assert 0.0 < q <= 1.0
+    assert abs(q - ref.min()) < 1e-8 * ref.min() and abs(ref[f] - q) < 1e-8 * q
+    apf.assemble(_dev(eps, torch.float64))
+    apf.factor_schur()
+    assert apf.query("pivot_spread_min") == q
