@@ -43,6 +43,13 @@ __device__ __forceinline__ double2 ldg(gcplx *p) {
   return make_double2(v.x, v.y);
 }
 __device__ __forceinline__ void st2(cplx *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
+// 16 bytes per lane straight from global memory into LDS: lane l's entry
+// lands at dst + l (dst must be the same for the whole wave)
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+__device__ __forceinline__ void ld_lds16(const cplx *src, double2 *dst) {
+  __builtin_amdgcn_global_load_lds((glb_void *)src, (lds_void *)dst, 16, 0, 0);
+}
 
 // ---------------------------------------------------------------------------
 // Zero the frontal workspaces of one level.
@@ -511,7 +518,130 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) blk_ok[r][c] = T.tm + wr + 16 * r < M && T.tn + wc + 16 * c < N;
-  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+  // FP64 interior tiles without a triangular operand: k stages of 8 loaded
+  // straight into LDS (no register staging), two stages in flight, one
+  // barrier per stage.  Stage 0 lives in As, stage 1 in Bs (two distinct
+  // LDS objects, so that the compiler sees the MFMA operand reads of one
+  // stage as independent of the loads in flight into the other): entries
+  // [0, 512) hold the A slab, [512, 1024) the B slab.  B and a
+  // transposed-stored A are [k][64] rows; a row-major A is [i][8] with entry
+  // (i, k) at i*8 + (k ^ ((i >> 1) & 7)), so that both the coalesced loads (8
+  // lanes per row) and the MFMA operand reads (16 rows at one k) meet every
+  // LDS bank once.
+  constexpr int KD = 8;
+  bool dma = false;
+  if constexpr (!F32 && !TRI) {
+    if (interior && K >= 2 * KD) {
+      dma = true;
+      double2 *S0 = &As[0][0], *S1 = &Bs[0][0];
+      const int nfull = K / KD, tail = K - nfull * KD;
+      // the wave index as a scalar, and the row map read through the constant
+      // address space: the B row indices of a stage are then scalar loads,
+      // which do not wait for the stage loads in flight
+      const int wv = __builtin_amdgcn_readfirstlane(wave);
+      typedef __attribute__((address_space(4))) const int32_t cint;
+      cint *bmap = (cint *)T.browmap;
+      int ao[2][2], bo[2][2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int kx = 4 * ks + (lane >> 4), i = wr + 16 * r + (lane & 15);
+          ao[ks][r] = transA ? kx * 64 + i : i * 8 + (kx ^ ((i >> 1) & 7));
+          bo[ks][r] = 512 + kx * 64 + wc + 16 * r + (lane & 15);
+        }
+      auto issue = [&](int k0, double2 *buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int kr = 2 * wv + q, gk = k0 + kr;
+          ld_lds16(Bp + (int64_t)(bmap ? bmap[gk] : gk) * T.ldb + T.tn + lane, buf + 512 + kr * 64);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int blk = 2 * wv + q;
+          if (transA) {
+            ld_lds16(T.A + (int64_t)(k0 + blk) * T.lda + T.tm + lane, buf + blk * 64);
+          } else {
+            const int i = 8 * blk + (lane >> 3), k = (lane & 7) ^ ((i >> 1) & 7);
+            ld_lds16(T.A + (int64_t)(T.tm + i) * T.lda + k0 + k, buf + blk * 64);
+          }
+        }
+      };
+      // the last, partial stage: plain loads, zeros past K
+      auto fill_tail = [&](int k0, double2 *buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int e = tid + 256 * q;
+          {
+            const int kr = e >> 6, j = e & 63, gk = k0 + kr;
+            buf[512 + kr * 64 + j] = gk < K ? ld2(Bp + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j)
+                                            : make_double2(0.0, 0.0);
+          }
+          if (transA) {
+            const int kr = e >> 6, i = e & 63, gk = k0 + kr;
+            buf[kr * 64 + i] = gk < K ? ld2(T.A + (int64_t)gk * T.lda + T.tm + i) : make_double2(0.0, 0.0);
+          } else {
+            const int i = e >> 3, k = e & 7, gk = k0 + k;
+            buf[i * 8 + (k ^ ((i >> 1) & 7))] = gk < K ? ld2(T.A + (int64_t)(T.tm + i) * T.lda + gk)
+                                                       : make_double2(0.0, 0.0);
+          }
+        }
+      };
+      auto compute = [&](const double2 *buf) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          double2 a[2], b[2];
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            a[r] = buf[ao[ks][r]];
+            b[r] = buf[bo[ks][r]];
+          }
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              if constexpr (K3) {
+                cre[r][c] = GP::mfma(a[r].x + a[r].y, b[c].x, cre[r][c]);
+                cim[r][c] = GP::mfma(a[r].x, b[c].y - b[c].x, cim[r][c]);
+                ck3[r][c] = GP::mfma(a[r].y, b[c].x + b[c].y, ck3[r][c]);
+              } else {
+                cre[r][c] = GP::mfma(a[r].x, b[c].x, cre[r][c]);
+                cre[r][c] = GP::mfma(-a[r].y, b[c].y, cre[r][c]);
+                cim[r][c] = GP::mfma(a[r].x, b[c].y, cim[r][c]);
+                cim[r][c] = GP::mfma(a[r].y, b[c].x, cim[r][c]);
+              }
+            }
+        }
+      };
+      // stage s in S0 (s even) or S1 (s odd): this wave's loads of stage s,
+      // then every wave's (and every wave done with the buffer the next
+      // stage overwrites), then the next stage's loads, then the MFMAs
+      issue(0, S0);
+      for (int s = 0; s < nfull; s += 2) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        __syncthreads();
+        if (s + 1 < nfull)
+          issue((s + 1) * KD, S1);
+        else if (tail)
+          fill_tail(nfull * KD, S1);
+        compute(S0);
+        if (s + 1 < nfull) {
+          __builtin_amdgcn_s_waitcnt(0x0F70);
+          __syncthreads();
+          if (s + 2 < nfull)
+            issue((s + 2) * KD, S0);
+          else if (tail)
+            fill_tail(nfull * KD, S0);
+          compute(S1);
+        }
+      }
+      if (tail) {
+        __syncthreads();
+        compute((nfull & 1) ? S1 : S0);
+      }
+    }
+  }
+  for (int k0 = dma ? kend : kbeg; k0 < kend; k0 += KT) {
     double2 ra[4], rb[4];
     if (slab_raw(k0)) {
       if (!transA) {
