@@ -126,3 +126,29 @@ def test_compressed_gradient_matches_the_oracle_route(nx, ny, pad, window, chunk
     if chunk:
         assert apf.query("rhs_chunk") < pad + prob.n_in
     assert rel(g, g_oc) < TOL and worst_block(g, g_oc, axis=1) < TOL
+
+
+def test_mixed_precision_with_compression_stays_near_the_fp64_compressed_route():
+    """APF_MIXED on a compressed handle: the S~ blocks run on FP32 MFMA like
+    every front GEMM, the decompression stays FP64; S and the gradient stay
+    within the mixed path's accuracy of the FP64 compressed result (the
+    bound is that of the uncompressed mixed path at 24000 x 160, 3.4e-5 for S
+    and 1.7e-4 for the gradient against FP64, with a margin; measured here
+    9.5e-6 and 1.4e-4)."""
+    from paper_2306_09257_amd import binding
+    prob = inputs.make_problem(480, 92)
+    rng = np.random.default_rng(7)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    w = rng.uniform(0.0, 1.0, size=(prob.n_out, prob.n_in))
+    apf = binding.APF(prob).analyze().set_compression(20, 6.0)
+    apf.assemble(_dev(eps))
+    S64 = apf.factor_schur(precision=binding.APF_FP64)
+    f64, G64 = apf.weighted_power(S64, _dev(w))
+    g64 = apf.grad(G64).cpu().numpy()
+    apf.assemble(_dev(eps))
+    S32 = apf.factor_schur(precision=binding.APF_MIXED)
+    f32, G32 = apf.weighted_power(S32, _dev(w))
+    g32 = apf.grad(G32).cpu().numpy()
+    eS, eg = rel(S32.cpu().numpy(), S64.cpu().numpy()), rel(g32, g64)
+    print(f"[gpu] compressed 480x92, mixed against FP64: S {eS:.2e}, gradient {eg:.2e}", flush=True)
+    assert eS < 5e-5 and eg < 5e-4
