@@ -366,7 +366,8 @@ apf_status apf_set_compression(apf_handle *h, int32_t pad, double window_wavelen
  * only S (on = 0): without them the factorization skips the products that
  * only the sweeps read (X12 = U^-1 U12, Z = L21 L^-1, X1B and XC1 of the
  * fronts the sweeps visit) and the handle allocates no sweep arrays;
- * apf_grad then returns APF_ESTATE.  Call after apf_analyze and before the
+ * apf_grad then returns APF_ESTATE, except after an APF_MIXED_REFINED
+ * factorization (the refined gradient solves for the fields itself).  Call after apf_analyze and before the
  * first apf_assemble (else APF_ESTATE); APF_EINVAL unless on is 0 or 1. */
 apf_status apf_set_gradient(apf_handle *h, int32_t on);
 

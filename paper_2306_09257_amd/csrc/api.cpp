@@ -2236,7 +2236,9 @@ extern "C" apf_status apf_ridges_grad(apf_handle *h, const double *edges_dev, in
 extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *grad_dev, void *stream) {
   if (!h || !dfdS_dev || !grad_dev) return fail(APF_EINVAL, "null argument");
   if (h->state != 2) return fail(APF_ESTATE, "apf_factor_schur has not run since the last assembly");
-  if (!h->sweeps) return fail(APF_ESTATE, "the handle prepares no gradient sweeps (apf_set_gradient)");
+  // (the refined gradient runs its own full solves, not the sweeps)
+  if (!h->sweeps && !h->refined)
+    return fail(APF_ESTATE, "the handle prepares no gradient sweeps (apf_set_gradient)");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     Plan &P = h->plan;

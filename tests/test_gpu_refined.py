@@ -65,6 +65,28 @@ def test_refined_mixed_path_meets_the_oracle_bar(name, chunk):
         assert v < 1e-10, (k, v)
 
 
+def test_refined_gradient_needs_no_sweep_data():
+    """A handle built for S only (apf_set_gradient(h, 0)) still gives the
+    refined gradient, which solves for the fields itself, at the oracle bar;
+    the plain paths' apf_grad is refused on it."""
+    from paper_2306_09257_amd import binding
+    prob, eps, w = inputs.metasurface_small(seed=0)
+    apf = binding.APF(prob).analyze().set_gradient(False).set_refinement(2, 1e-10)
+    assert apf.query("n_sweep_rows") == 0
+    S_o, g_o, _ = oapf.solve_S_and_grad(prob, eps, w=w)
+    S_r, g_r = _solve(apf, eps, w, binding.APF_MIXED_REFINED)
+    e = _errors(S_r, g_r, S_o, g_o)
+    print(f"[gpu] refined without sweep data: {e}", flush=True)
+    for k, v in e.items():
+        assert v < TOL, (k, v)
+    apf.assemble(torch.as_tensor(eps, dtype=torch.float64, device="cuda"))
+    S = apf.factor_schur(precision=binding.APF_FP64)
+    f, G = apf.weighted_power(S, torch.as_tensor(w, dtype=torch.float64, device="cuda"))
+    with pytest.raises(binding.APFError) as ei:
+        apf.grad(G)
+    assert ei.value.status == binding.APF_ESTATE
+
+
 def test_refinement_reports_non_convergence_and_checks_its_state():
     from paper_2306_09257_amd import binding
     prob, eps, w = inputs.tiny_problem(nx=48, ny=60, seed=21)
