@@ -408,6 +408,27 @@ apf_status apf_set_profiling(apf_handle *h, int32_t on);
  * nothing: the caller must have synchronised the streams it used. */
 apf_status apf_destroy(apf_handle *h);
 
+/* Kernel test hook (for the kernel unit tests, not for applications): one
+ * complex GEMM C = Cin +/- op(A) op(B) in the library's internal task format,
+ * cut into 64 x 64 tiles and run on one kernel form (0 four-product FP64,
+ * 1 three-product FP64, 2 four-product FP64 on the deep-K kernel, 3 FP32
+ * MFMA), so that its operand layouts, triangular masks, row and column maps,
+ * Cin forms, edges and k stages can be checked against a plain reference.
+ * flags: the internal task flags of the tested set (transposed A, negation,
+ * Cin and its column offset / own indexing / column range, external B with
+ * element offset b_offset, triangular A or B, accumulation into C, k limited
+ * to nlim); other flags give APF_EINVAL.  All pointers are device pointers
+ * to complex128 (A, B, Cin, C) or int32 maps (browmap, crowmap, ccolmap,
+ * each may be NULL); coff and nlim are the launch's column offset and
+ * column (or k) limit; xcd = 1 orders the tiles for the eight XCDs.
+ * Allocates and synchronises `stream`. */
+apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int32_t N, int32_t K,
+                         const double *A, int32_t lda, const double *B, int32_t ldb, int64_t b_offset,
+                         const double *Cin, int32_t ldcin, double *C, int32_t ldc,
+                         const int32_t *browmap, const int32_t *crowmap, const int32_t *ccolmap,
+                         int32_t cin_c0, int32_t cin_w, int32_t coff, int32_t nlim, int32_t xcd,
+                         void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *apf_last_error(void);
 

@@ -32,7 +32,7 @@ ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
                 "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement",
                 "apf_grad_augmented", "apf_ridges_grad_augmented", "apf_autotune", "apf_tuning_apply",
-                "apf_set_compression", "apf_set_gradient")
+                "apf_set_compression", "apf_set_gradient", "apf_test_gemm")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow", "refine", "adjoint_source")
 
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_refinement.argtypes = [vp, i32, dbl]
     lib.apf_set_compression.argtypes = [vp, i32, dbl]
     lib.apf_set_gradient.argtypes = [vp, i32]
+    lib.apf_test_gemm.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, ctypes.c_int64, vp, i32, vp, i32,
+                                  vp, vp, vp, i32, i32, i32, i32, i32, vp]
     lib.apf_autotune.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.c_char_p, vp]
     lib.apf_tuning_apply.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_char_p, vp]
     lib.apf_grad_augmented.argtypes = [vp, i32, vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), vp]
@@ -342,6 +344,26 @@ def autotune(apfs, reps: int = 3, save_path: Optional[str] = None):
     lib = load_library()
     hs = (ctypes.c_void_p * len(apfs))(*[a._h.value for a in apfs])
     _check(lib.apf_autotune(hs, len(apfs), int(reps), save_path.encode() if save_path else None, _stream()))
+
+
+# internal GEMM task flags the kernel test hook accepts (values of the
+# library's task format)
+GEMM_FLAGS = dict(TRANS_A=1, NEG=2, CIN=4, B_COFF=8, CIN_COFF=16, B_EXT=32, A_TRI_L=128, A_TRI_U=256,
+                  B_TRI_L=512, B_TRI_U=1024, CIN_OWN=8192, C_ACC=16384, K_LIM=65536, ACC_CHUNK=131072,
+                  C_COFF=524288, CIN_RANGE=1048576)
+EXT_ADD = 1 << 30
+
+
+def gemm_hook(form, flags, M, N, K, A, lda, B, ldb, C, ldc, Cin=None, ldcin=0, b_offset=0, browmap=None,
+              crowmap=None, ccolmap=None, cin_c0=0, cin_w=0, coff=0, nlim=1 << 30, xcd=False):
+    """Kernel test hook: one GEMM of the internal task format on kernel form
+    `form` (see apf_test_gemm in include/apf.h); tensors on the GPU (complex128
+    operands, int32 maps)."""
+    lib = load_library()
+    p = lambda t: None if t is None else _ptr(t)
+    _check(lib.apf_test_gemm(int(form), int(flags), int(M), int(N), int(K), _ptr(A), int(lda), _ptr(B), int(ldb),
+                             int(b_offset), p(Cin), int(ldcin), _ptr(C), int(ldc), p(browmap), p(crowmap), p(ccolmap),
+                             int(cin_c0), int(cin_w), int(coff), int(nlim), 1 if xcd else 0, _stream()))
 
 
 def tuning_apply(apfs, path: str):

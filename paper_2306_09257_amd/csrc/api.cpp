@@ -3144,3 +3144,50 @@ extern "C" apf_status apf_front(apf_handle *h, int32_t f, int32_t info[8], int32
   if (boundary) std::copy(F.bnd.begin(), F.bnd.end(), boundary);
   return APF_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Kernel test hook: one GEMM of the factorization's task format, cut into
+// tiles and launched on the chosen kernel form, so that the kernel's
+// semantics (operand layouts, triangular masks, row and column maps, Cin
+// forms, edges, the LDS-direct stages) can be checked against a plain
+// reference.  Allocates (the tile list) and synchronises `stream`.
+// ---------------------------------------------------------------------------
+extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int32_t N, int32_t K,
+                                    const double *A, int32_t lda, const double *B, int32_t ldb, int64_t b_offset,
+                                    const double *Cin, int32_t ldcin, double *C, int32_t ldc,
+                                    const int32_t *browmap, const int32_t *crowmap, const int32_t *ccolmap,
+                                    int32_t cin_c0, int32_t cin_w, int32_t coff, int32_t nlim, int32_t xcd,
+                                    void *stream) {
+  const int32_t allowed = G_TRANS_A | G_NEG | G_CIN | G_B_COFF | G_CIN_COFF | G_B_EXT | G_A_TRI_L | G_A_TRI_U |
+                          G_B_TRI_L | G_B_TRI_U | G_CIN_OWN | G_C_ACC | G_K_LIM | G_ACC_CHUNK | G_C_COFF |
+                          G_CIN_RANGE;
+  if (form < 0 || form > 3) return fail(APF_EINVAL, "form must be 0 (four-product), 1 (three-product), "
+                                                    "2 (four-product on the deep-K kernel) or 3 (FP32)");
+  if (flags & ~allowed) return fail(APF_EINVAL, "flag outside the tested set");
+  if (M < 1 || N < 1 || K < 0 || !A || !B || !C || nlim < 1) return fail(APF_EINVAL, "bad shape or null operand");
+  if ((flags & G_CIN) && !Cin) return fail(APF_EINVAL, "G_CIN without Cin");
+  return guarded([&]() -> apf_status {
+    hipStream_t s = (hipStream_t)stream;
+    const cplx *Bt = (flags & G_B_EXT) ? reinterpret_cast<const cplx *>((intptr_t)b_offset)
+                                       : reinterpret_cast<const cplx *>(B);
+    GemmTask t = gemm(reinterpret_cast<const cplx *>(A), lda, Bt, ldb, reinterpret_cast<cplx *>(C), ldc, M, N, K,
+                      flags | (form == 1 ? G_K3 : 0), reinterpret_cast<const cplx *>(Cin), ldcin, browmap);
+    t.crowmap = crowmap;
+    t.ccolmap = ccolmap;
+    t.cin_c0 = cin_c0;
+    t.cin_w = cin_w;
+    std::vector<GemmTask> v;
+    if (xcd) add_tiles_xcd(v, t);
+    else add_tiles(v, t);
+    GemmTask *dv = nullptr;
+    HIPCHK(hipMalloc(&dv, std::max<size_t>(v.size(), 1) * sizeof(GemmTask)));
+    hipError_t e = hipMemcpyAsync(dv, v.data(), v.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_gemm(dv, (int)v.size(), coff, nlim, (flags & G_B_EXT) ? reinterpret_cast<const cplx *>(B) : nullptr,
+                      s, form == 3, nullptr, 0, form == 1 || form == 2);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dv);
+    HIPCHK(e);
+    return APF_OK;
+  });
+}
