@@ -429,6 +429,19 @@ apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int32_t N, int3
                          int32_t cin_c0, int32_t cin_w, int32_t coff, int32_t nlim, int32_t xcd,
                          void *stream);
 
+/* Kernel test hook (for the kernel unit tests, not for applications): the
+ * pivot-block kernel on one p x p block F (device, complex128 row-major,
+ * 1 <= p <= 128; read only): LU with partial pivoting inside the block
+ * (largest modulus, ties to the lowest row), then the in-place inverses.
+ * tri_dev (device, complex128 p x p) receives L^-1 below the diagonal (unit
+ * diagonal implied) and U^-1 on and above it, perm_dev (device, int32 p) the
+ * row of F taken at each step, so that U^-1 L^-1 F[perm] = I; *spread (host,
+ * may be NULL) the pivot spread min |u_kk| / max |u_kk|.  APF_ESINGULAR when
+ * a pivot was zero or non-finite (the outputs are then undefined); the
+ * kernel runs to its end either way.  Allocates and synchronises `stream`. */
+apf_status apf_test_pivot_block(int32_t p, const double *F_dev, double *tri_dev, int32_t *perm_dev,
+                                double *spread, void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *apf_last_error(void);
 

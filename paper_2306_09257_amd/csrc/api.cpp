@@ -3191,3 +3191,41 @@ extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int3
     return APF_OK;
   });
 }
+
+// Kernel test hook: the pivot-block kernel on one p x p block.
+extern "C" apf_status apf_test_pivot_block(int32_t p, const double *F_dev, double *tri_dev, int32_t *perm_dev,
+                                           double *spread, void *stream) {
+  if (p < 1 || p > MAX_PIVOTS) return fail(APF_EINVAL, "p must be in [1, " + std::to_string(MAX_PIVOTS) + "]");
+  if (!F_dev || !tri_dev || !perm_dev) return fail(APF_EINVAL, "null argument");
+  return guarded([&]() -> apf_status {
+    hipStream_t s = (hipStream_t)stream;
+    FrontDev fd{};
+    fd.p = p;
+    fd.sweep_row0 = -1;
+    fd.core = const_cast<cplx *>(reinterpret_cast<const cplx *>(F_dev));
+    fd.tri = reinterpret_cast<cplx *>(tri_dev);
+    fd.perm = perm_dev;
+    fd.parent = -1;
+    char *buf = nullptr;   // FrontDev, id, status, spread
+    HIPCHK(hipMalloc(&buf, 256 * 4));
+    FrontDev *dfd = reinterpret_cast<FrontDev *>(buf);
+    int32_t *did = reinterpret_cast<int32_t *>(buf + 256);
+    int *dst = reinterpret_cast<int *>(buf + 512);
+    double *dq = reinterpret_cast<double *>(buf + 768);
+    const int32_t zero = 0;
+    hipError_t e = hipMemcpyAsync(dfd, &fd, sizeof fd, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(did, &zero, sizeof zero, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(dst, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_inverse(inverse_variant(p), dfd, did, 1, dst, dq, s);
+    int st = 0;
+    double q = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&st, dst, sizeof st, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&q, dq, sizeof q, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    HIPCHK(e);
+    if (spread) *spread = q;
+    if (st & ST_SINGULAR) return fail(APF_ESINGULAR, "zero or non-finite pivot in the block");
+    return APF_OK;
+  });
+}
