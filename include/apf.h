@@ -412,8 +412,10 @@ apf_status apf_destroy(apf_handle *h);
  * complex GEMM C = Cin +/- op(A) op(B) in the library's internal task format,
  * cut into 64 x 64 tiles and run on one kernel form (0 four-product FP64,
  * 1 three-product FP64, 2 four-product FP64 on the deep-K kernel, 3 FP32
- * MFMA), so that its operand layouts, triangular masks, row and column maps,
- * Cin forms, edges and k stages can be checked against a plain reference.
+ * MFMA, 4 four-product FP64 with the tiles of at most 32 valid rows on the
+ * thin kernel, as the factorization and sweep lists run), so that its
+ * operand layouts, triangular masks, row and column maps, Cin forms, edges
+ * and k stages can be checked against a plain reference.
  * flags: the internal task flags of the tested set (transposed A, negation,
  * Cin and its column offset / own indexing / column range, external B with
  * element offset b_offset, triangular A or B, accumulation into C, k limited
@@ -421,12 +423,20 @@ apf_status apf_destroy(apf_handle *h);
  * to complex128 (A, B, Cin, C) or int32 maps (browmap, crowmap, ccolmap,
  * each may be NULL); coff and nlim are the launch's column offset and
  * column (or k) limit; xcd = 1 orders the tiles for the eight XCDs.
- * Allocates and synchronises `stream`. */
+ * The contraction flag (G_CONTRACT, 2048; with G_NO_STORE, 4096, C itself is
+ * not written) also forms the gradient partials of the sweeps: for output
+ * row i (C row oi through crowmap) and each 32-column group g of the tile
+ * columns, part[((coff + 32 g) / 32) * pstride + auxmap[oi]] =
+ * sum over the group's columns j of Re(C(i, j) aux[oi * ldc + j]), written
+ * where auxmap[oi] >= 0 (aux: device complex128 rows of stride ldc; auxmap:
+ * device int32; part: device float64; coff a multiple of 32); pass NULL and
+ * 0 otherwise.  Allocates and synchronises `stream`. */
 apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int32_t N, int32_t K,
                          const double *A, int32_t lda, const double *B, int32_t ldb, int64_t b_offset,
                          const double *Cin, int32_t ldcin, double *C, int32_t ldc,
                          const int32_t *browmap, const int32_t *crowmap, const int32_t *ccolmap,
                          int32_t cin_c0, int32_t cin_w, int32_t coff, int32_t nlim, int32_t xcd,
+                         const double *aux, const int32_t *auxmap, double *part, int32_t pstride,
                          void *stream);
 
 /* Kernel test hook (for the kernel unit tests, not for applications): the

@@ -89,7 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_gradient.argtypes = [vp, i32]
     lib.apf_test_pivot_block.argtypes = [i32, vp, vp, vp, ctypes.POINTER(dbl), vp]
     lib.apf_test_gemm.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, ctypes.c_int64, vp, i32, vp, i32,
-                                  vp, vp, vp, i32, i32, i32, i32, i32, vp]
+                                  vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, i32, vp]
     lib.apf_autotune.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.c_char_p, vp]
     lib.apf_tuning_apply.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_char_p, vp]
     lib.apf_grad_augmented.argtypes = [vp, i32, vp, vp, i32, vp, i32, i32, vp, vp, vp, ctypes.POINTER(i32), vp]
@@ -351,20 +351,22 @@ def autotune(apfs, reps: int = 3, save_path: Optional[str] = None):
 # library's task format)
 GEMM_FLAGS = dict(TRANS_A=1, NEG=2, CIN=4, B_COFF=8, CIN_COFF=16, B_EXT=32, A_TRI_L=128, A_TRI_U=256,
                   B_TRI_L=512, B_TRI_U=1024, CIN_OWN=8192, C_ACC=16384, K_LIM=65536, ACC_CHUNK=131072,
-                  C_COFF=524288, CIN_RANGE=1048576)
+                  C_COFF=524288, CIN_RANGE=1048576, CONTRACT=2048, NO_STORE=4096)
 EXT_ADD = 1 << 30
 
 
 def gemm_hook(form, flags, M, N, K, A, lda, B, ldb, C, ldc, Cin=None, ldcin=0, b_offset=0, browmap=None,
-              crowmap=None, ccolmap=None, cin_c0=0, cin_w=0, coff=0, nlim=1 << 30, xcd=False):
+              crowmap=None, ccolmap=None, cin_c0=0, cin_w=0, coff=0, nlim=1 << 30, xcd=False, aux=None,
+              auxmap=None, part=None, pstride=0):
     """Kernel test hook: one GEMM of the internal task format on kernel form
     `form` (see apf_test_gemm in include/apf.h); tensors on the GPU (complex128
-    operands, int32 maps)."""
+    operands, int32 maps, float64 partials)."""
     lib = load_library()
     p = lambda t: None if t is None else _ptr(t)
     _check(lib.apf_test_gemm(int(form), int(flags), int(M), int(N), int(K), _ptr(A), int(lda), _ptr(B), int(ldb),
                              int(b_offset), p(Cin), int(ldcin), _ptr(C), int(ldc), p(browmap), p(crowmap), p(ccolmap),
-                             int(cin_c0), int(cin_w), int(coff), int(nlim), 1 if xcd else 0, _stream()))
+                             int(cin_c0), int(cin_w), int(coff), int(nlim), 1 if xcd else 0, p(aux), p(auxmap),
+                             p(part), int(pstride), _stream()))
 
 
 def pivot_block_hook(F, tri, perm):

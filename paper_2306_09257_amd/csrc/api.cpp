@@ -104,6 +104,7 @@ struct LevelTasks {
   int64_t zero = -1, scat = -1, pan = -1, g1 = -1, g2 = -1, g2b = -1;
   int nzero = 0, nscat = 0, npan = 0, ng1 = 0, ng2 = 0, ng2b = 0;
   char deep1 = 0, deep2 = 0, deep2b = 0;   // lists run by the deep-K kernel (k_gemm_k3)
+  int nthin1 = 0, nthin2 = 0, nthin2b = 0; // thin tiles at the end of each list (thin kernel)
   // compressed channels: panel rows copied from the compressed basis, and
   // the blocks of S~ of the level's fronts, in launches whose blocks do not
   // overlap
@@ -161,6 +162,7 @@ struct Profiler {
   bool record = false;       // keep (tag, ms) of every timed launch in `trace`
   std::vector<std::pair<int, float>> trace;
   std::vector<int> tags;     // per mark
+  std::vector<int> nkern;    // kernel launches per mark
   bool gemm_only = false;    // time only the GEMM-family launches
   static bool gemm_class(int cls) { return cls == P_GEMM_FACTOR || cls == P_GEMM_SCHUR || cls == P_GEMM_SWEEP; }
   std::vector<hipEvent_t> pool;
@@ -178,8 +180,9 @@ struct Profiler {
     }
     return pool[used++];
   }
+  // nk: kernel launches that fn makes (a GEMM list with thin tiles makes two)
   template <class Fn>
-  void run(int cls, hipStream_t s, Fn &&fn) {
+  void run(int cls, hipStream_t s, Fn &&fn, int nk = 1) {
     if (!on || (gemm_only && !gemm_class(cls))) {
       HIPCHK(fn());
       return;
@@ -191,6 +194,7 @@ struct Profiler {
     HIPCHK(hipEventRecord(b, s));
     marks.push_back({cls, (int)i0});
     tags.push_back(cur_tag);
+    nkern.push_back(nk);
   }
   void collect() {
     for (size_t i = 0; i < marks.size(); ++i) {
@@ -199,17 +203,19 @@ struct Profiler {
       HIPCHK(hipEventSynchronize(pool[m.second + 1]));
       HIPCHK(hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]));
       ms[m.first] += t;
-      count[m.first] += 1;
+      count[m.first] += nkern[i];
       if (record) trace.push_back({tags[i], t});
     }
     marks.clear();
     tags.clear();
+    nkern.clear();
     used = 0;
   }
   void reset() {
     for (int k = 0; k < P_NCLASS; ++k) { ms[k] = 0; count[k] = 0; }
     marks.clear();
     tags.clear();
+    nkern.clear();
     trace.clear();
     used = 0;
   }
@@ -301,7 +307,7 @@ struct Plan {
   // gradient sweeps: launch t holds the Y tiles of level H - t and the
   // adjoint tiles (with the contraction) of level H - t + 1
   std::vector<int64_t> swl;
-  std::vector<int> nswl;
+  std::vector<int> nswl, nswl_thin;   // (thin tiles at the end of each list)
   // low-rank sweep subtrees (no channel rows): instead of Y and Lam tiles,
   // launch t is followed by the Wt = Y_bnd Lam_bnd^T quadrant tasks of the
   // subtree roots of level H - t + 1 (swtb); after the sweeps, level by level
@@ -681,6 +687,14 @@ static bool any_k3(const std::vector<GemmTask> &v) {
   for (const GemmTask &T : v)
     if (T.flags & G_K3) return true;
   return false;
+}
+// Moves the thin tiles of a list to its end (in their order) and returns
+// their count: launch_gemm runs them on the thin kernel.  Whether a tile is
+// thin depends on the tile alone, so it runs the same kernel (and rounds the
+// same way) in every list that holds it, merged batches included.
+static int split_thin(std::vector<GemmTask> &v) {
+  auto it = std::stable_partition(v.begin(), v.end(), [](const GemmTask &T) { return !thin_tile_task(T); });
+  return (int)(v.end() - it);
 }
 
 // Device plan of the refined solves (after the main plan, whose channel
@@ -1551,22 +1565,32 @@ static void build_plan(apf_handle *H) {
     L.deep1 = mark_deep(g1[lvl]);
     L.deep2 = mark_deep(g2[lvl]);
     L.deep2b = mark_deep(g2b[lvl]);
-    if (L.deep1) cm_k3 += list_cmacs(g1[lvl]);
-    if (L.deep2) cm_k3 += list_cmacs(g2[lvl]);
-    if (L.deep2b) cm_k3 += list_cmacs(g2b[lvl]);
+    L.nthin1 = split_thin(g1[lvl]);
+    L.nthin2 = split_thin(g2[lvl]);
+    L.nthin2b = split_thin(g2b[lvl]);
+    // (tiles of a deep list that run thin take the four-product form)
+    auto k3_cmacs = [&](const std::vector<GemmTask> &v, int nthin) {
+      return list_cmacs(std::vector<GemmTask>(v.begin(), v.end() - nthin));
+    };
+    if (L.deep1) cm_k3 += k3_cmacs(g1[lvl], L.nthin1);
+    if (L.deep2) cm_k3 += k3_cmacs(g2[lvl], L.nthin2);
+    if (L.deep2b) cm_k3 += k3_cmacs(g2b[lvl], L.nthin2b);
     L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
     L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
     L.g2b = bl.add(g2b[lvl]); L.ng2b = (int)g2b[lvl].size();
   }
   P.swl.assign(H_ + 2, -1);
   P.nswl.assign(H_ + 2, 0);
+  P.nswl_thin.assign(H_ + 2, 0);
   P.swl_deep.assign(H_ + 2, 0);
   for (int t = 0; t <= H_ + 1; ++t) {
     std::vector<GemmTask> m;
     if (H_ - t >= 0) m.insert(m.end(), swY[H_ - t].begin(), swY[H_ - t].end());
     if (H_ - t + 1 <= H_) m.insert(m.end(), swL[H_ - t + 1].begin(), swL[H_ - t + 1].end());
     P.swl_deep[t] = mark_deep(m);
-    if (P.swl_deep[t]) cm_k3 += list_cmacs(m) * ((double)Mi / P.rhs_chunk);
+    P.nswl_thin[t] = split_thin(m);
+    if (P.swl_deep[t])
+      cm_k3 += list_cmacs(std::vector<GemmTask>(m.begin(), m.end() - P.nswl_thin[t])) * ((double)Mi / P.rhs_chunk);
     P.swl[t] = bl.add(m);
     P.nswl[t] = (int)m.size();
   }
@@ -1762,9 +1786,12 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
       const int64_t off = g == 0 ? L.g1 : (g == 1 ? L.g2 : L.g2b);
       const int n = g == 0 ? L.ng1 : (g == 1 ? L.ng2 : L.ng2b);
       const bool deep = (g == 0 ? L.deep1 : (g == 1 ? L.deep2 : L.deep2b)) != 0;
+      const int nthin = g == 0 ? L.nthin1 : (g == 1 ? L.nthin2 : L.nthin2b);
       pr.cur_tag = g == 0 ? L.id1 : (g == 1 ? L.id2 : L.id2b);
       if (n > 0)
-        pr.run(P_GEMM_FACTOR, s, [&] { return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32, nullptr, 0, deep); });
+        pr.run(P_GEMM_FACTOR, s, [&] {
+          return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32, nullptr, 0, deep, nthin);
+        }, gemm_kernel_launches(n, nthin, f32));
       pr.cur_tag = -1;
       // the augmented panels' products after the main phase 1 (their inputs)
       // and phase 2 (no dependence either way)
@@ -2024,6 +2051,9 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     L.scat = bl.add(ae); L.nscat = (int)ae.size();
     L.pan = bl.add(pe); L.npan = (int)pe.size();
     for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = bl.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
+    L.nthin1 = split_thin(g1);
+    L.nthin2 = split_thin(g2);
+    L.nthin2b = split_thin(g2b);
     L.g1 = bl.add(g1); L.ng1 = (int)g1.size();
     L.g2 = bl.add(g2); L.ng2 = (int)g2.size();
     L.g2b = bl.add(g2b); L.ng2b = (int)g2b.size();
@@ -2315,8 +2345,9 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
         pr.cur_tag = P.swl_id[t];
         if (P.nswl[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] {
-            return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, (int)P.ndesign, P.swl_deep[t] != 0);
-          });
+            return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, (int)P.ndesign,
+                               P.swl_deep[t] != 0, P.nswl_thin[t]);
+          }, gemm_kernel_launches(P.nswl[t], P.nswl_thin[t], f32));
         pr.cur_tag = -1;
         if (P.nswtb[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] { return launch_lowrank_w(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s); });
@@ -3157,15 +3188,20 @@ extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int3
                                     const double *Cin, int32_t ldcin, double *C, int32_t ldc,
                                     const int32_t *browmap, const int32_t *crowmap, const int32_t *ccolmap,
                                     int32_t cin_c0, int32_t cin_w, int32_t coff, int32_t nlim, int32_t xcd,
+                                    const double *aux, const int32_t *auxmap, double *part, int32_t pstride,
                                     void *stream) {
   const int32_t allowed = G_TRANS_A | G_NEG | G_CIN | G_B_COFF | G_CIN_COFF | G_B_EXT | G_A_TRI_L | G_A_TRI_U |
                           G_B_TRI_L | G_B_TRI_U | G_CIN_OWN | G_C_ACC | G_K_LIM | G_ACC_CHUNK | G_C_COFF |
-                          G_CIN_RANGE;
-  if (form < 0 || form > 3) return fail(APF_EINVAL, "form must be 0 (four-product), 1 (three-product), "
-                                                    "2 (four-product on the deep-K kernel) or 3 (FP32)");
+                          G_CIN_RANGE | G_CONTRACT | G_NO_STORE;
+  if (form < 0 || form > 4) return fail(APF_EINVAL, "form must be 0 (four-product), 1 (three-product), "
+                                                    "2 (four-product on the deep-K kernel), 3 (FP32) or 4 "
+                                                    "(four-product with the thin tiles on the thin kernel)");
   if (flags & ~allowed) return fail(APF_EINVAL, "flag outside the tested set");
   if (M < 1 || N < 1 || K < 0 || !A || !B || !C || nlim < 1) return fail(APF_EINVAL, "bad shape or null operand");
   if ((flags & G_CIN) && !Cin) return fail(APF_EINVAL, "G_CIN without Cin");
+  if ((flags & G_CONTRACT) && (!aux || !auxmap || !part || pstride < 1))
+    return fail(APF_EINVAL, "G_CONTRACT without aux, auxmap, part or a positive pstride");
+  if ((flags & G_CONTRACT) && coff % 32) return fail(APF_EINVAL, "G_CONTRACT with coff not a multiple of 32");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
     const cplx *Bt = (flags & G_B_EXT) ? reinterpret_cast<const cplx *>((intptr_t)b_offset)
@@ -3176,15 +3212,21 @@ extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int3
     t.ccolmap = ccolmap;
     t.cin_c0 = cin_c0;
     t.cin_w = cin_w;
+    if (flags & G_CONTRACT) {
+      t.aux = reinterpret_cast<const cplx *>(aux);
+      t.auxmap = auxmap;
+    }
     std::vector<GemmTask> v;
     if (xcd) add_tiles_xcd(v, t);
     else add_tiles(v, t);
+    const int nthin = form == 4 ? split_thin(v) : 0;
     GemmTask *dv = nullptr;
     HIPCHK(hipMalloc(&dv, std::max<size_t>(v.size(), 1) * sizeof(GemmTask)));
     hipError_t e = hipMemcpyAsync(dv, v.data(), v.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = launch_gemm(dv, (int)v.size(), coff, nlim, (flags & G_B_EXT) ? reinterpret_cast<const cplx *>(B) : nullptr,
-                      s, form == 3, nullptr, 0, form == 1 || form == 2);
+                      s, form == 3, (flags & G_CONTRACT) ? part : nullptr, (flags & G_CONTRACT) ? pstride : 0,
+                      form == 1 || form == 2, nthin);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dv);
     HIPCHK(e);

@@ -887,6 +887,176 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   }
 }
 
+// FP64 tiles whose valid rows fit in RB (1 or 2) blocks of 16: the small
+// separator fronts near the leaves (p of 8 to 32 pivots) and ragged last row
+// tiles.  In the 2x2 wave layout of gemm_tile such a tile leaves half of its
+// waves without a block and stages every k slab through LDS behind two
+// barriers, so its time is a chain of load round trips.  Here wave w owns the
+// 16 columns [16w, 16w + 16) of the tile and all RB row blocks, and loads its
+// MFMA operands from global memory straight into registers, KS k-steps of 4
+// at a time, with no LDS and no barrier in the k loop (A, a few KB per front,
+// is read by every wave, from cache).  Same task semantics and epilogue as
+// gemm_tile; the contraction's 32-column partials combine the row sums of
+// waves 2g and 2g + 1 through LDS (red: 4 x 16 RB doubles).
+template <int RB, int KS>
+__device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, int nlimk, const cplx *ext,
+                                          double *part, int pstride, double *red) {
+  typedef GemmPrec<false> GP;
+  const int M = T.M, K = ((T.flags & G_K_LIM) && nlimk < T.K) ? nlimk : T.K;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool transA = T.flags & G_TRANS_A;
+  const cplx *Bp = (T.flags & G_B_EXT) ? ext + reinterpret_cast<intptr_t>(T.B) : T.B;
+  if (T.flags & G_B_COFF) Bp += coff;
+  cplx *Cp = (T.flags & G_C_EXT) ? const_cast<cplx *>(ext) : T.C;
+  if (T.flags & G_C_COFF) Cp += coff;
+  const int wc = 16 * wave;
+  // MFMA operands of lane l: A(row l % 16 of a block, k = l / 16 of a step),
+  // B(k = l / 16, column l % 16)
+  const int bj = T.tn + wc + li;
+  const bool bjok = bj < N;
+  int ai[RB];
+  bool aiok[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    ai[r] = T.tm + 16 * r + li;
+    aiok[r] = ai[r] < M;
+  }
+  d4 cre[RB], cim[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    cre[r] = d4{0, 0, 0, 0};
+    cim[r] = d4{0, 0, 0, 0};
+  }
+  const bool wave_cols = T.tn + wc < N;   // the wave holds any output column
+  if (wave_cols) {
+    for (int k0 = 0; k0 < K; k0 += 4 * KS) {
+      double2 a[KS][RB], b[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int gk = k0 + 4 * s + lk;
+        const bool kok = gk < K;
+        const int br = kok ? (T.browmap ? T.browmap[gk] : gk) : 0;
+        b[s] = (kok && bjok) ? ldg(as_global(Bp) + (int64_t)br * T.ldb + bj) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+          a[s][r] = (kok && aiok[r])
+                        ? ldg(as_global(T.A) + (transA ? (int64_t)gk * T.lda + ai[r] : (int64_t)ai[r] * T.lda + gk))
+                        : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        if (k0 + 4 * s >= K) break;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          cre[r] = GP::mfma(a[s][r].x, b[s].x, cre[r]);
+          cre[r] = GP::mfma(-a[s][r].y, b[s].y, cre[r]);
+          cim[r] = GP::mfma(a[s][r].x, b[s].y, cim[r]);
+          cim[r] = GP::mfma(a[s][r].y, b[s].x, cim[r]);
+        }
+      }
+    }
+  }
+
+  // epilogue: lane l holds rows (l / 16) + 4q of each row block, column l % 16
+  const bool neg = T.flags & G_NEG;
+  const bool store = !(T.flags & G_NO_STORE), contract = T.flags & G_CONTRACT;
+  const cplx *Cin = (T.flags & G_CIN) ? T.Cin : nullptr;
+  if (Cin && (T.flags & G_CIN_COFF)) Cin += coff;
+  const bool crange = T.flags & G_CIN_RANGE;
+  const int cshift = coff - T.cin_c0;
+  const bool own = T.flags & G_CIN_OWN;
+  const bool cacc = (T.flags & G_C_ACC) || ((T.flags & G_ACC_CHUNK) && coff > 0);
+  const int gj = bj;
+  const bool colok = bjok;
+  const int oj = (colok && T.ccolmap) ? T.ccolmap[gj] : gj;
+  double2 v[RB][4];
+  int64_t oi[RB][4];
+  bool rowok[RB][4];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gi = T.tm + 16 * r + GP::row(lane, q);
+      rowok[r][q] = gi < M;
+      const int32_t m = (rowok[r][q] && T.crowmap) ? T.crowmap[gi] : gi;
+      oi[r][q] = rowok[r][q] ? (m & EXT_ROW_MASK) : 0;
+      const bool addold = (m & EXT_ADD) != 0;
+      const int64_t ci = own ? gi : oi[r][q];
+      double2 x = make_double2(cre[r][q], cim[r][q]);
+      if (neg) x = make_double2(-x.x, -x.y);
+      if (crange) {
+        const int cj = gj + cshift;
+        if (Cin && rowok[r][q] && colok && cj >= 0 && cj < T.cin_w) x = cadd(x, ld2(Cin + ci * T.ldcin + cj));
+      } else if (Cin && rowok[r][q] && colok) {
+        x = cadd(x, ld2(Cin + ci * T.ldcin + (own ? gj : oj)));
+      }
+      if ((addold || cacc) && rowok[r][q] && colok) x = cadd(x, ld2(Cp + oi[r][q] * T.ldc + oj));
+      v[r][q] = x;
+    }
+  if (store) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (rowok[r][q] && colok) st2(Cp + oi[r][q] * T.ldc + oj, v[r][q]);
+  }
+  if (contract) {
+    // row sums of Re(C aux) over the wave's 16 columns, then over the pair of
+    // waves that shares a 32-column partial
+    double acc[RB][4];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double a = 0.0;
+        if (rowok[r][q] && colok) {
+          const double2 y = ld2(T.aux + oi[r][q] * T.ldc + gj);
+          a = v[r][q].x * y.x - v[r][q].y * y.y;
+        }
+        for (int off = 1; off < 16; off <<= 1) a += __shfl_xor(a, off, 64);
+        acc[r][q] = a;
+      }
+    if ((wave & 1) && li == 0) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[(wave >> 1) * 16 * RB + 16 * r + GP::row(lane, q)] = acc[r][q];
+    }
+    __syncthreads();
+    if (!(wave & 1) && li == 0) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (rowok[r][q]) {
+            const int g = T.auxmap[oi[r][q]];
+            if (g >= 0)
+              part[(int64_t)((coff + T.tn + 32 * (wave >> 1)) / 32) * pstride + g] =
+                  acc[r][q] + red[(wave >> 1) * 16 * RB + 16 * r + GP::row(lane, q)];
+          }
+    }
+  }
+}
+
+// The thin tiles of a list (thin_tile_task: at most THIN_ROWS valid rows, no
+// triangular operand), which the plan moves to the end of the list, in a
+// launch of their own: with neither LDS stages nor the 2x2 layout's
+// accumulators this kernel holds twice the workgroups per CU of k_gemm.  A
+// thin tile is a short chain of dependent loads (task, row map, operands,
+// epilogue), so the number of tiles in flight sets its throughput.
+__global__ __launch_bounds__(256, 8) void k_gemm_thin(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
+                                                      double *part, int pstride) {
+  __shared__ double red[2 * 16 * 2];
+  const GemmTask T = tasks[blockIdx.x];
+  const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
+  if (T.tn >= N) return;
+  if (T.M - T.tm <= 16)
+    thin_tile<1, 2>(T, coff, N, nlim, ext, part, pstride, red);
+  else
+    thin_tile<2, 1>(T, coff, N, nlim, ext, part, pstride, red);
+}
+
 template <bool F32>
 __global__ __launch_bounds__(256, 4) void k_gemm(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
                                                  double *part, int pstride) {
@@ -1560,15 +1730,30 @@ hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipS
   return hipGetLastError();
 }
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
-                       double *part, int pstride, bool deep) {
+                       double *part, int pstride, bool deep, int nthin) {
   if (n == 0) return hipSuccess;
-  if (deep && !f32)
-    hipLaunchKernelGGL(k_gemm_k3, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
-  else if (f32)
-    hipLaunchKernelGGL(k_gemm<true>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
-  else
-    hipLaunchKernelGGL(k_gemm<false>, dim3(n), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
+  // the FP32 kernel takes the thin tiles too (the thin kernel is FP64)
+  const int nreg = f32 ? n : n - nthin;
+  if (nreg > 0) {
+    if (deep && !f32)
+      hipLaunchKernelGGL(k_gemm_k3, dim3(nreg), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
+    else if (f32)
+      hipLaunchKernelGGL(k_gemm<true>, dim3(nreg), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
+    else
+      hipLaunchKernelGGL(k_gemm<false>, dim3(nreg), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
+  }
+  if (nreg < n) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemm_thin, dim3(n - nreg), dim3(256), 0, s, t + nreg, coff, nlim, ext, part, pstride);
+  }
   return hipGetLastError();
+}
+
+int gemm_kernel_launches(int n, int nthin, bool f32) {
+  if (n == 0) return 0;
+  if (f32) return 1;
+  return (n - nthin > 0) + (nthin > 0);
 }
 
 // map[r] = base[r] + perm[pidx[r]]: destination rows of a GEMM whose output

@@ -5,8 +5,10 @@ maps of B), triangular masks (stored-index rules of the packed pivot-block
 factors), Cin forms (mapped rows, own indexing, column offset, column
 range), accumulation into C (per-row EXT_ADD, G_C_ACC, G_ACC_CHUNK), the
 launch's column offset and N or K limit, edge tiles and k tails of the
-LDS-direct stages, the XCD tile order, and the four kernel forms (FP64
-four-product, three-product, four-product on the deep-K kernel, FP32)."""
+LDS-direct stages, the XCD tile order, and the five kernel forms (FP64
+four-product, three-product, four-product on the deep-K kernel, FP32, and
+four-product with the tiles of at most 32 valid rows on the thin kernel, as
+the factorization and sweep lists run them)."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 F = dict(TRANS_A=1, NEG=2, CIN=4, B_COFF=8, CIN_COFF=16, B_EXT=32, A_TRI_L=128, A_TRI_U=256,
          B_TRI_L=512, B_TRI_U=1024, CIN_OWN=8192, C_ACC=16384, K_LIM=65536, ACC_CHUNK=131072,
-         C_COFF=524288, CIN_RANGE=1048576)
+         C_COFF=524288, CIN_RANGE=1048576, CONTRACT=2048, NO_STORE=4096)
 EXT_ADD = 1 << 30
 MASK = EXT_ADD - 1
 
@@ -25,7 +27,10 @@ def _c(rng, n):
 
 
 def reference(flags, M, N, K, A, lda, B, ldb, C0, ldc, Cin=None, ldcin=0, b_offset=0, browmap=None,
-              crowmap=None, ccolmap=None, cin_c0=0, cin_w=0, coff=0, nlim=1 << 30):
+              crowmap=None, ccolmap=None, cin_c0=0, cin_w=0, coff=0, nlim=1 << 30, aux=None, auxmap=None,
+              part0=None, pstride=0):
+    """C after the task, and (G_CONTRACT) the gradient partials: per output
+    row and 32-column group, the sum of Re(C(i, j) aux(oi, j))."""
     has = lambda f: bool(flags & F[f])
     Ke = min(K, nlim) if has("K_LIM") else K
     Ne = N if (has("K_LIM") or N < nlim) else nlim
@@ -56,6 +61,7 @@ def reference(flags, M, N, K, A, lda, B, ldb, C0, ldc, Cin=None, ldcin=0, b_offs
     out = C0.copy()
     cbase = coff if has("C_COFF") else 0
     cacc = has("C_ACC") or (has("ACC_CHUNK") and coff > 0)
+    part = None if part0 is None else part0.copy()
     for i in range(M):
         m = int(crowmap[i]) if crowmap is not None else i
         oi, addold = m & MASK, bool(m & EXT_ADD)
@@ -73,8 +79,16 @@ def reference(flags, M, N, K, A, lda, B, ldb, C0, ldc, Cin=None, ldcin=0, b_offs
                     v += Cin[ib + ci * ldcin + (j if has("CIN_OWN") else oj)]
             if addold or cacc:
                 v += C0[cbase + oi * ldc + oj]
-            out[cbase + oi * ldc + oj] = v
-    return out
+            if has("CONTRACT"):
+                P[i, j] = v          # the contraction takes the final value
+            if not has("NO_STORE"):
+                out[cbase + oi * ldc + oj] = v
+        if has("CONTRACT") and auxmap[oi] >= 0:
+            for g in range((Ne + 31) // 32):
+                js = np.arange(32 * g, min(32 * g + 32, Ne))
+                part[((coff + 32 * g) // 32) * pstride + auxmap[oi]] = np.sum(
+                    (P[i, js] * aux[oi * ldc + js]).real)
+    return out if part is None else (out, part)
 
 
 def _dev(a, dtype=torch.complex128):
@@ -100,10 +114,26 @@ CASES = {
     "xcd_order": dict(M=300, N=520, K=64, xcd=True),
     "degenerate_1x1x1": dict(M=1, N=1, K=1),
     "no_k_cin_only": dict(M=20, N=30, K=0, flags=["CIN"]),
+    # tiles with at most 16 or 32 valid rows (per-wave column strips, operands
+    # loaded straight into registers)
+    "thin16_b_rows_mapped_k_tail": dict(M=11, N=200, K=39, browmap=True, flags=["NEG", "CIN"]),
+    "thin32_b_rows_mapped_trans": dict(M=27, N=150, K=62, browmap=True, flags=["TRANS_A", "NEG"]),
+    "thin32_long_k_mapped_out": dict(M=22, N=90, K=449, crowmap=True, ccolmap=True, flags=["CIN"]),
+    "thin_ext_coff_nlim": dict(M=10, N=192, K=50, nlim=100, coff=64, b_offset=7,
+                               flags=["B_EXT", "B_COFF", "C_COFF"]),
+    "thin_k_limited_chunk_acc": dict(M=16, N=64, K=300, nlim=150, coff=64, flags=["K_LIM", "ACC_CHUNK"]),
+    "thin_cin_range_coff": dict(M=30, N=70, K=5, coff=64, cin_c0=90, cin_w=30,
+                                flags=["CIN", "CIN_RANGE", "CIN_COFF"]),
+    # the sweeps' contraction (gradient partials per 32-column group)
+    "contract_thin16_no_store": dict(M=11, N=150, K=39, browmap=True, crowmap=True, coff=64,
+                                     flags=["TRANS_A", "NEG", "CIN", "CONTRACT", "NO_STORE"]),
+    "contract_thin32": dict(M=27, N=100, K=62, browmap=True, flags=["NEG", "CIN", "CONTRACT"]),
+    "contract_ragged": dict(M=100, N=130, K=37, crowmap=True, flags=["TRANS_A", "CONTRACT"]),
+    "contract_interior": dict(M=128, N=128, K=40, browmap=True, flags=["TRANS_A", "NEG", "CONTRACT"]),
 }
 
 
-@pytest.mark.parametrize("form", [0, 1, 2, 3], ids=["four", "three", "four_deep", "fp32"])
+@pytest.mark.parametrize("form", [0, 1, 2, 3, 4], ids=["four", "three", "four_deep", "fp32", "four_thin"])
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_gemm_kernel_matches_the_task_semantics(name, form):
     from paper_2306_09257_amd import binding
@@ -132,16 +162,45 @@ def test_gemm_kernel_matches_the_task_semantics(name, form):
     Cin = _c(rng, (out_rows + 1) * ldcin + c.get("coff", 0) + 64) if flags & F["CIN"] else None
     kw = dict(b_offset=b_offset, cin_c0=c.get("cin_c0", 0), cin_w=c.get("cin_w", 0), coff=c.get("coff", 0),
               nlim=c.get("nlim", 1 << 30))
+    contract = bool(flags & F["CONTRACT"])
+    ckw = {}
+    if contract:
+        # auxmap: a permutation of the slots with a quarter of the rows unmapped
+        aux = _c(rng, out_rows * ldc + 1)
+        slots = out_rows + 5
+        auxmap = rng.permutation(slots)[:out_rows].astype(np.int32)
+        auxmap[rng.random(out_rows) < 0.25] = -1
+        ngrp = (c.get("coff", 0) + ((N + 63) // 64) * 64) // 32
+        part0 = np.full(ngrp * slots, np.nan)
+        ckw = dict(aux=aux, auxmap=auxmap, part0=part0, pstride=slots)
     want = reference(flags, M, N, K, A, lda, B, ldb, C0, ldc, Cin=Cin, ldcin=ldcin, browmap=browmap,
-                     crowmap=crow, ccolmap=ccol, **kw)
+                     crowmap=crow, ccolmap=ccol, **kw, **ckw)
+    if contract:
+        want, want_part = want
+        partd = _dev(part0, torch.float64)
+        hk = dict(aux=_dev(aux), auxmap=_dev(auxmap, torch.int32), part=partd, pstride=slots)
+    else:
+        hk = {}
     Cd = _dev(C0)
     binding.gemm_hook(form, flags, M, N, K, _dev(A), lda, _dev(B), ldb, Cd, ldc,
                       Cin=None if Cin is None else _dev(Cin), ldcin=ldcin,
                       browmap=None if browmap is None else _dev(browmap, torch.int32),
                       crowmap=None if crow is None else _dev(crow, torch.int32),
-                      ccolmap=None if ccol is None else _dev(ccol, torch.int32), xcd=c.get("xcd", False), **kw)
+                      ccolmap=None if ccol is None else _dev(ccol, torch.int32), xcd=c.get("xcd", False), **kw,
+                      **hk)
     got = Cd.cpu().numpy()
     scale = max(np.linalg.norm(want), 1e-300)
     err = np.linalg.norm(got - want) / scale
+    tol = 1e-6 if form == 3 else 1e-13
     print(f"[gpu] gemm {name} form {form}: rel err {err:.2e}", flush=True)
-    assert err < (1e-6 if form == 3 else 1e-13), (name, form, err)
+    assert err < tol, (name, form, err)
+    if contract:
+        gotp = partd.cpu().numpy()
+        sel = ~np.isnan(want_part)
+        perr = np.linalg.norm(gotp[sel] - want_part[sel]) / max(np.linalg.norm(want_part[sel]), 1e-300)
+        # slots the reference leaves unset: untouched, or zero for column
+        # groups past N inside the last tile
+        other = gotp[~sel]
+        print(f"[gpu] gemm {name} form {form}: partials rel err {perr:.2e}", flush=True)
+        assert perr < (1e-5 if form == 3 else 1e-12), (name, form, perr)
+        assert np.all(np.isnan(other) | (other == 0.0)), (name, form)
