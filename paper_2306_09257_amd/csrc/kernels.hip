@@ -518,12 +518,15 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) blk_ok[r][c] = T.tm + wr + 16 * r < M && T.tn + wc + 16 * c < N;
-  // FP64 interior tiles without a triangular operand: k stages of 8 loaded
-  // straight into LDS (no register staging), two stages in flight, one
-  // barrier per stage.  Stage 0 lives in As, stage 1 in Bs (two distinct
-  // LDS objects, so that the compiler sees the MFMA operand reads of one
-  // stage as independent of the loads in flight into the other): entries
-  // [0, 512) hold the A slab, [512, 1024) the B slab.  B and a
+  // FP64 tiles without a triangular operand: k stages of 8 loaded straight
+  // into LDS (no register staging), two stages in flight, one barrier per
+  // stage.  At a tile's edge the rows and columns past M and N load copies
+  // of the last row and column (their results are computed and not stored),
+  // so that the MFMA loop is the interior tiles' own.  Stage 0 lives in As,
+  // stage 1 in Bs (two distinct LDS objects, so that the compiler sees the
+  // MFMA operand reads of one stage as independent of the loads in flight
+  // into the other): entries [0, 512) hold the A slab, [512, 1024) the B
+  // slab.  B and a
   // transposed-stored A are [k][64] rows; a row-major A is [i][8] with entry
   // (i, k) at i*8 + (k ^ ((i >> 1) & 7)), so that both the coalesced loads (8
   // lanes per row) and the MFMA operand reads (16 rows at one k) meet every
@@ -531,7 +534,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
   constexpr int KD = 8;
   bool dma = false;
   if constexpr (!F32 && !TRI) {
-    if (interior && K >= 2 * KD) {
+    if (K >= 2 * KD) {
       dma = true;
       double2 *S0 = &As[0][0], *S1 = &Bs[0][0];
       const int nfull = K / KD, tail = K - nfull * KD;
@@ -541,6 +544,12 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
       const int wv = __builtin_amdgcn_readfirstlane(wave);
       typedef __attribute__((address_space(4))) const int32_t cint;
       cint *bmap = (cint *)T.browmap;
+      // B column and transposed-A column of this lane, row-major A rows of
+      // its two blocks, clamped to the operands' last column / row
+      const int bj = min(T.tn + lane, N - 1), at = min(T.tm + lane, M - 1);
+      int ar[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ar[q] = min(T.tm + 8 * (2 * wv + q) + (lane >> 3), M - 1);
       int ao[2][2], bo[2][2];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks)
@@ -554,36 +563,38 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int kr = 2 * wv + q, gk = k0 + kr;
-          ld_lds16(Bp + (int64_t)(bmap ? bmap[gk] : gk) * T.ldb + T.tn + lane, buf + 512 + kr * 64);
+          ld_lds16(Bp + (int64_t)(bmap ? bmap[gk] : gk) * T.ldb + bj, buf + 512 + kr * 64);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int blk = 2 * wv + q;
           if (transA) {
-            ld_lds16(T.A + (int64_t)(k0 + blk) * T.lda + T.tm + lane, buf + blk * 64);
+            ld_lds16(T.A + (int64_t)(k0 + blk) * T.lda + at, buf + blk * 64);
           } else {
             const int i = 8 * blk + (lane >> 3), k = (lane & 7) ^ ((i >> 1) & 7);
-            ld_lds16(T.A + (int64_t)(T.tm + i) * T.lda + k0 + k, buf + blk * 64);
+            ld_lds16(T.A + (int64_t)ar[q] * T.lda + k0 + k, buf + blk * 64);
           }
         }
       };
-      // the last, partial stage: plain loads, zeros past K
+      // the last, partial stage: plain loads, zeros past K, M and N
       auto fill_tail = [&](int k0, double2 *buf) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int e = tid + 256 * q;
           {
             const int kr = e >> 6, j = e & 63, gk = k0 + kr;
-            buf[512 + kr * 64 + j] = gk < K ? ld2(Bp + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j)
-                                            : make_double2(0.0, 0.0);
+            buf[512 + kr * 64 + j] = (gk < K && T.tn + j < N)
+                                         ? ld2(Bp + (int64_t)(T.browmap ? T.browmap[gk] : gk) * T.ldb + T.tn + j)
+                                         : make_double2(0.0, 0.0);
           }
           if (transA) {
             const int kr = e >> 6, i = e & 63, gk = k0 + kr;
-            buf[kr * 64 + i] = gk < K ? ld2(T.A + (int64_t)gk * T.lda + T.tm + i) : make_double2(0.0, 0.0);
+            buf[kr * 64 + i] = (gk < K && T.tm + i < M) ? ld2(T.A + (int64_t)gk * T.lda + T.tm + i)
+                                                        : make_double2(0.0, 0.0);
           } else {
             const int i = e >> 3, k = e & 7, gk = k0 + k;
-            buf[i * 8 + (k ^ ((i >> 1) & 7))] = gk < K ? ld2(T.A + (int64_t)(T.tm + i) * T.lda + gk)
-                                                       : make_double2(0.0, 0.0);
+            buf[i * 8 + (k ^ ((i >> 1) & 7))] = (gk < K && T.tm + i < M) ? ld2(T.A + (int64_t)(T.tm + i) * T.lda + gk)
+                                                                         : make_double2(0.0, 0.0);
           }
         }
       };
