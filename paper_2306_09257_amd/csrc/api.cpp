@@ -670,10 +670,12 @@ static double mean_tile_k(const std::vector<GemmTask> &v) {
   }
   return sum / (double)v.size();
 }
-// Threshold measured at 24000x160: lists with a mean k extent of 96 or more
-// run faster on the three-product kernel (fewer MFMAs) despite its lower
-// occupancy; shallower lists are bound by their loads and epilogues.
-constexpr double kDeepMeanK = 96.0;
+// Threshold measured at 24000x160 and 48000x160 with the thin tiles on their
+// own kernel: lists with a mean k extent of 32 or more run faster on the
+// three-product kernel (fewer MFMAs) despite its lower occupancy (thresholds
+// from 0 to 64 within 3 ms of each other; 96 cost 3 and 6 ms); shallower
+// lists are bound by their loads and epilogues.
+constexpr double kDeepMeanK = 32.0;
 constexpr int kWMaxLevels = 2;   // most levels of a low-rank sweep subtree
 // Flags every task of a deep list for the three-product form.  The flag is
 // per task, so a task rounds the same way in any launch that holds it
