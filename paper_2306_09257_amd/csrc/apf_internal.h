@@ -169,14 +169,14 @@ struct GemmTask {          // one 64 x 64 output tile of C = Cin +/- op(A) B (a 
 };
 
 // Tiles that the thin GEMM kernel takes: at most THIN_ROWS valid rows (the
-// small separator fronts near the leaves, ragged last row tiles), no
-// triangular operand; the plan moves them to the end of the factorization
-// and sweep lists.
+// small separator fronts near the leaves, the leaves' products with at most
+// 32 output rows, ragged last row tiles); the plan moves them to the end of
+// the factorization and sweep lists.
 constexpr int THIN_ROWS = 32;
 inline bool thin_tile_task(const GemmTask &T) {
-  return T.M > 0 && T.N > 0 && T.M - T.tm <= THIN_ROWS &&
-         !(T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U | G_TRANS_B));
+  return T.M > 0 && T.N > 0 && T.M - T.tm <= THIN_ROWS && !(T.flags & G_TRANS_B);
 }
+inline bool tri_task(const GemmTask &T) { return T.flags & (G_A_TRI_L | G_A_TRI_U | G_B_TRI_L | G_B_TRI_U); }
 
 struct ZeroRange { cplx *ptr; int64_t n; };
 struct CopyRange { const cplx *src; cplx *dst; int64_t n; };   // n contiguous complex entries

@@ -104,7 +104,8 @@ struct LevelTasks {
   int64_t zero = -1, scat = -1, pan = -1, g1 = -1, g2 = -1, g2b = -1;
   int nzero = 0, nscat = 0, npan = 0, ng1 = 0, ng2 = 0, ng2b = 0;
   char deep1 = 0, deep2 = 0, deep2b = 0;   // lists run by the deep-K kernel (k_gemm_k3)
-  int nthin1 = 0, nthin2 = 0, nthin2b = 0; // thin tiles at the end of each list (thin kernel)
+  int nthin1 = 0, nthin2 = 0, nthin2b = 0; // thin tiles at the end of each list (thin kernels)
+  int ntri1 = 0, ntri2 = 0, ntri2b = 0;    // of which the last have a triangular operand
   // compressed channels: panel rows copied from the compressed basis, and
   // the blocks of S~ of the level's fronts, in launches whose blocks do not
   // overlap
@@ -690,12 +691,15 @@ static bool any_k3(const std::vector<GemmTask> &v) {
     if (T.flags & G_K3) return true;
   return false;
 }
-// Moves the thin tiles of a list to its end (in their order) and returns
-// their count: launch_gemm runs them on the thin kernel.  Whether a tile is
-// thin depends on the tile alone, so it runs the same kernel (and rounds the
-// same way) in every list that holds it, merged batches included.
-static int split_thin(std::vector<GemmTask> &v) {
+// Moves the thin tiles of a list to its end (in their order), those with a
+// triangular operand last, and returns their count (*ntri: the triangular
+// ones): launch_gemm runs them on the thin kernels.  Whether a tile is thin
+// depends on the tile alone, so it runs the same kernel (and rounds the same
+// way) in every list that holds it, merged batches included.
+static int split_thin(std::vector<GemmTask> &v, int *ntri) {
   auto it = std::stable_partition(v.begin(), v.end(), [](const GemmTask &T) { return !thin_tile_task(T); });
+  auto jt = std::stable_partition(it, v.end(), [](const GemmTask &T) { return !tri_task(T); });
+  *ntri = (int)(v.end() - jt);
   return (int)(v.end() - it);
 }
 
@@ -1567,9 +1571,9 @@ static void build_plan(apf_handle *H) {
     L.deep1 = mark_deep(g1[lvl]);
     L.deep2 = mark_deep(g2[lvl]);
     L.deep2b = mark_deep(g2b[lvl]);
-    L.nthin1 = split_thin(g1[lvl]);
-    L.nthin2 = split_thin(g2[lvl]);
-    L.nthin2b = split_thin(g2b[lvl]);
+    L.nthin1 = split_thin(g1[lvl], &L.ntri1);
+    L.nthin2 = split_thin(g2[lvl], &L.ntri2);
+    L.nthin2b = split_thin(g2b[lvl], &L.ntri2b);
     // (tiles of a deep list that run thin take the four-product form)
     auto k3_cmacs = [&](const std::vector<GemmTask> &v, int nthin) {
       return list_cmacs(std::vector<GemmTask>(v.begin(), v.end() - nthin));
@@ -1590,7 +1594,9 @@ static void build_plan(apf_handle *H) {
     if (H_ - t >= 0) m.insert(m.end(), swY[H_ - t].begin(), swY[H_ - t].end());
     if (H_ - t + 1 <= H_) m.insert(m.end(), swL[H_ - t + 1].begin(), swL[H_ - t + 1].end());
     P.swl_deep[t] = mark_deep(m);
-    P.nswl_thin[t] = split_thin(m);
+    int ntri_sw = 0;
+    P.nswl_thin[t] = split_thin(m, &ntri_sw);
+    if (ntri_sw) throw std::runtime_error("triangular operand in a sweep list");
     if (P.swl_deep[t])
       cm_k3 += list_cmacs(std::vector<GemmTask>(m.begin(), m.end() - P.nswl_thin[t])) * ((double)Mi / P.rhs_chunk);
     P.swl[t] = bl.add(m);
@@ -1789,11 +1795,13 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
       const int n = g == 0 ? L.ng1 : (g == 1 ? L.ng2 : L.ng2b);
       const bool deep = (g == 0 ? L.deep1 : (g == 1 ? L.deep2 : L.deep2b)) != 0;
       const int nthin = g == 0 ? L.nthin1 : (g == 1 ? L.nthin2 : L.nthin2b);
+      const int ntri = g == 0 ? L.ntri1 : (g == 1 ? L.ntri2 : L.ntri2b);
       pr.cur_tag = g == 0 ? L.id1 : (g == 1 ? L.id2 : L.id2b);
       if (n > 0)
         pr.run(P_GEMM_FACTOR, s, [&] {
-          return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32, nullptr, 0, deep, nthin);
-        }, gemm_kernel_launches(n, nthin, f32));
+          return launch_gemm((const GemmTask *)at(off), n, 0, INT_MAX, nullptr, s, f32, nullptr, 0, deep, nthin,
+                             ntri);
+        }, gemm_kernel_launches(n, nthin, ntri, f32));
       pr.cur_tag = -1;
       // the augmented panels' products after the main phase 1 (their inputs)
       // and phase 2 (no dependence either way)
@@ -2053,9 +2061,9 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<apf_handle *> &hs) {
     L.scat = bl.add(ae); L.nscat = (int)ae.size();
     L.pan = bl.add(pe); L.npan = (int)pe.size();
     for (int v = 0; v < N_INV_VARIANTS; ++v) { L.inv[v] = bl.add(inv[v]); L.ninv[v] = (int)inv[v].size(); }
-    L.nthin1 = split_thin(g1);
-    L.nthin2 = split_thin(g2);
-    L.nthin2b = split_thin(g2b);
+    L.nthin1 = split_thin(g1, &L.ntri1);
+    L.nthin2 = split_thin(g2, &L.ntri2);
+    L.nthin2b = split_thin(g2b, &L.ntri2b);
     L.g1 = bl.add(g1); L.ng1 = (int)g1.size();
     L.g2 = bl.add(g2); L.ng2 = (int)g2.size();
     L.g2b = bl.add(g2b); L.ng2b = (int)g2b.size();
@@ -2349,7 +2357,7 @@ extern "C" apf_status apf_grad(apf_handle *h, const double *dfdS_dev, double *gr
           pr.run(P_GEMM_SWEEP, s, [&] {
             return launch_gemm(P.at<GemmTask>(P.swl[t]), P.nswl[t], m0, w, nullptr, s, f32, P.gpart, (int)P.ndesign,
                                P.swl_deep[t] != 0, P.nswl_thin[t]);
-          }, gemm_kernel_launches(P.nswl[t], P.nswl_thin[t], f32));
+          }, gemm_kernel_launches(P.nswl[t], P.nswl_thin[t], 0, f32));
         pr.cur_tag = -1;
         if (P.nswtb[t] > 0)
           pr.run(P_GEMM_SWEEP, s, [&] { return launch_lowrank_w(P.at<GemmTask>(P.swtb[t]), P.nswtb[t], m0, w, s); });
@@ -3221,14 +3229,15 @@ extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int3
     std::vector<GemmTask> v;
     if (xcd) add_tiles_xcd(v, t);
     else add_tiles(v, t);
-    const int nthin = form == 4 ? split_thin(v) : 0;
+    int ntri = 0;
+    const int nthin = form == 4 ? split_thin(v, &ntri) : 0;
     GemmTask *dv = nullptr;
     HIPCHK(hipMalloc(&dv, std::max<size_t>(v.size(), 1) * sizeof(GemmTask)));
     hipError_t e = hipMemcpyAsync(dv, v.data(), v.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = launch_gemm(dv, (int)v.size(), coff, nlim, (flags & G_B_EXT) ? reinterpret_cast<const cplx *>(B) : nullptr,
                       s, form == 3, (flags & G_CONTRACT) ? part : nullptr, (flags & G_CONTRACT) ? pstride : 0,
-                      form == 1 || form == 2, nthin);
+                      form == 1 || form == 2, nthin, ntri);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dv);
     HIPCHK(e);

@@ -23,12 +23,13 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
 // slot g and 32-column block b at part[b * pstride + g] (unused otherwise);
 // deep: MFMA-bound deep-K task list (three-product complex form on FP64);
 // nthin: the last nthin tasks are thin tiles (thin_tile_task), run by the
-// thin kernel on the FP64 path (by the FP32 kernel with the rest otherwise)
+// thin kernels on the FP64 path (by the FP32 kernel with the rest
+// otherwise); the last nthin_tri of them have a triangular operand
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
                        bool f32 = false, double *part = nullptr, int pstride = 0, bool deep = false,
-                       int nthin = 0);
+                       int nthin = 0, int nthin_tri = 0);
 // kernel launches that launch_gemm makes for such a list
-int gemm_kernel_launches(int n, int nthin, bool f32);
+int gemm_kernel_launches(int n, int nthin, int nthin_tri, bool f32);
 // Wt = Y_bnd Lam_bnd^T of the low-rank subtree roots: one task (b <= 64) per
 // root, one workgroup per task; nlim: the chunk's width (k extent)
 hipError_t launch_lowrank_w(const GemmTask *t, int n, int coff, int nlim, hipStream_t s);

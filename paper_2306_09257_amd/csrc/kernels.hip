@@ -899,7 +899,8 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
 }
 
 // FP64 tiles whose valid rows fit in RB (1 or 2) blocks of 16: the small
-// separator fronts near the leaves (p of 8 to 32 pivots) and ragged last row
+// separator fronts near the leaves (p of 8 to 32 pivots), the leaves' L21 and
+// Z products (b up to 32 rows, a triangular operand) and ragged last row
 // tiles.  In the 2x2 wave layout of gemm_tile such a tile leaves half of its
 // waves without a block and stages every k slab through LDS behind two
 // barriers, so its time is a chain of load round trips.  Here wave w owns the
@@ -909,7 +910,7 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
 // is read by every wave, from cache).  Same task semantics and epilogue as
 // gemm_tile; the contraction's 32-column partials combine the row sums of
 // waves 2g and 2g + 1 through LDS (red: 4 x 16 RB doubles).
-template <int RB, int KS>
+template <int RB, int KS, bool TRI>
 __device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, int nlimk, const cplx *ext,
                                           double *part, int pstride, double *red) {
   typedef GemmPrec<false> GP;
@@ -939,25 +940,43 @@ __device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, in
     cre[r] = d4{0, 0, 0, 0};
     cim[r] = d4{0, 0, 0, 0};
   }
+  // a triangular operand: masked loads (the stored-triangle rules of
+  // tri_mask) and the k range that can hold nonzeros for this tile's rows and
+  // this wave's columns, from a k-step boundary
+  const int fl = T.flags;
+  const bool triA = TRI && (fl & (G_A_TRI_L | G_A_TRI_U)), triB = TRI && (fl & (G_B_TRI_L | G_B_TRI_U));
+  int kbeg = 0, kend = K;
+  if (TRI) {
+    if (fl & G_A_TRI_L) { if (transA) kbeg = T.tm; else kend = min(kend, T.tm + 16 * RB); }
+    if (fl & G_A_TRI_U) { if (transA) kend = min(kend, T.tm + 16 * RB); else kbeg = T.tm; }
+    if (fl & G_B_TRI_L) kbeg = max(kbeg, T.tn + wc);
+    if (fl & G_B_TRI_U) kend = min(kend, T.tn + wc + 16);
+    kbeg &= ~3;
+  }
   const bool wave_cols = T.tn + wc < N;   // the wave holds any output column
   if (wave_cols) {
-    for (int k0 = 0; k0 < K; k0 += 4 * KS) {
+    for (int k0 = kbeg; k0 < kend; k0 += 4 * KS) {
       double2 a[KS][RB], b[KS];
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int gk = k0 + 4 * s + lk;
-        const bool kok = gk < K;
+        const bool kok = gk < kend;
         const int br = kok ? (T.browmap ? T.browmap[gk] : gk) : 0;
         b[s] = (kok && bjok) ? ldg(as_global(Bp) + (int64_t)br * T.ldb + bj) : make_double2(0.0, 0.0);
+        if (triB) b[s] = tri_mask(fl & G_B_TRI_L, gk, bj, kok && bjok, b[s]);
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int r = 0; r < RB; ++r) {
           a[s][r] = (kok && aiok[r])
                         ? ldg(as_global(T.A) + (transA ? (int64_t)gk * T.lda + ai[r] : (int64_t)ai[r] * T.lda + gk))
                         : make_double2(0.0, 0.0);
+          if (triA)
+            a[s][r] = transA ? tri_mask(fl & G_A_TRI_L, gk, ai[r], kok && aiok[r], a[s][r])
+                             : tri_mask(fl & G_A_TRI_L, ai[r], gk, kok && aiok[r], a[s][r]);
+        }
       }
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        if (k0 + 4 * s >= K) break;
+        if (k0 + 4 * s >= kend) break;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           cre[r] = GP::mfma(a[s][r].x, b[s].x, cre[r]);
@@ -1063,9 +1082,24 @@ __global__ __launch_bounds__(256, 8) void k_gemm_thin(const GemmTask *tasks, int
   const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
   if (T.tn >= N) return;
   if (T.M - T.tm <= 16)
-    thin_tile<1, 2>(T, coff, N, nlim, ext, part, pstride, red);
+    thin_tile<1, 2, false>(T, coff, N, nlim, ext, part, pstride, red);
   else
-    thin_tile<2, 1>(T, coff, N, nlim, ext, part, pstride, red);
+    thin_tile<2, 1, false>(T, coff, N, nlim, ext, part, pstride, red);
+}
+
+// The thin tiles with a triangular operand (after the others in a list), in
+// a kernel of their own so that their masks and k ranges do not cost the
+// plain thin tiles registers.
+__global__ __launch_bounds__(256, 8) void k_gemm_thin_tri(const GemmTask *tasks, int coff, int nlim,
+                                                          const cplx *ext, double *part, int pstride) {
+  __shared__ double red[2 * 16 * 2];
+  const GemmTask T = tasks[blockIdx.x];
+  const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
+  if (T.tn >= N) return;
+  if (T.M - T.tm <= 16)
+    thin_tile<1, 2, true>(T, coff, N, nlim, ext, part, pstride, red);
+  else
+    thin_tile<2, 1, true>(T, coff, N, nlim, ext, part, pstride, red);
 }
 
 template <bool F32>
@@ -1741,7 +1775,7 @@ hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipS
   return hipGetLastError();
 }
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
-                       double *part, int pstride, bool deep, int nthin) {
+                       double *part, int pstride, bool deep, int nthin, int nthin_tri) {
   if (n == 0) return hipSuccess;
   // the FP32 kernel takes the thin tiles too (the thin kernel is FP64)
   const int nreg = f32 ? n : n - nthin;
@@ -1753,18 +1787,25 @@ hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx 
     else
       hipLaunchKernelGGL(k_gemm<false>, dim3(nreg), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
   }
-  if (nreg < n) {
+  const int nplain = nreg < n ? nthin - nthin_tri : 0, ntri = nreg < n ? nthin_tri : 0;
+  if (nplain > 0) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gemm_thin, dim3(n - nreg), dim3(256), 0, s, t + nreg, coff, nlim, ext, part, pstride);
+    hipLaunchKernelGGL(k_gemm_thin, dim3(nplain), dim3(256), 0, s, t + nreg, coff, nlim, ext, part, pstride);
+  }
+  if (ntri > 0) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemm_thin_tri, dim3(ntri), dim3(256), 0, s, t + nreg + nplain, coff, nlim, ext, part,
+                       pstride);
   }
   return hipGetLastError();
 }
 
-int gemm_kernel_launches(int n, int nthin, bool f32) {
+int gemm_kernel_launches(int n, int nthin, int nthin_tri, bool f32) {
   if (n == 0) return 0;
   if (f32) return 1;
-  return (n - nthin > 0) + (nthin > 0);
+  return (n - nthin > 0) + (nthin - nthin_tri > 0) + (nthin_tri > 0);
 }
 
 // map[r] = base[r] + perm[pidx[r]]: destination rows of a GEMM whose output

@@ -124,6 +124,13 @@ CASES = {
     "thin_k_limited_chunk_acc": dict(M=16, N=64, K=300, nlim=150, coff=64, flags=["K_LIM", "ACC_CHUNK"]),
     "thin_cin_range_coff": dict(M=30, N=70, K=5, coff=64, cin_c0=90, cin_w=30,
                                 flags=["CIN", "CIN_RANGE", "CIN_COFF"]),
+    # thin tiles with a triangular operand (the leaves' L21 = F21 U^-1 and
+    # Z = L21 L^-1, the small fronts' L^-1 P^T F12, X12 = U^-1 U12, LC1T)
+    "thin_tri_a_lower_perm": dict(M=20, N=130, K=20, browmap=True, flags=["A_TRI_L"]),
+    "thin_tri_a_upper": dict(M=9, N=36, K=9, flags=["A_TRI_U"]),
+    "thin_tri_a_upper_trans": dict(M=30, N=70, K=30, flags=["A_TRI_U", "TRANS_A"]),
+    "thin_tri_b_upper": dict(M=26, N=38, K=38, flags=["B_TRI_U"]),
+    "thin_tri_b_lower_neg_cin": dict(M=26, N=70, K=70, flags=["B_TRI_L", "NEG", "CIN"]),
     # the sweeps' contraction (gradient partials per 32-column group)
     "contract_thin16_no_store": dict(M=11, N=150, K=39, browmap=True, crowmap=True, coff=64,
                                      flags=["TRANS_A", "NEG", "CIN", "CONTRACT", "NO_STORE"]),
