@@ -322,7 +322,7 @@ def bench_batch(args):
                    "nx_range": [min(p.nx for p, _, _ in items), max(p.nx for p, _, _ in items)],
                    "channels_range": [min(p.n_in for p, _, _ in items), max(p.n_in for p, _, _ in items)],
                    "precision": "fp64"},
-        "roofline": {"kernel": "k_gemm / k_gemm_thin / k_gemm_k3 (merged batched complex FP64 MFMA GEMMs of a step)",
+        "roofline": {"kernel": "k_gemm / k_gemm_thin / k_gemm_thin_tri / k_gemm_k3 (merged batched complex FP64 MFMA GEMMs of a step)",
                      "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
                      "flop_per_step": 8.0 * cm, "launches_per_step": gemm_launches,
@@ -503,7 +503,7 @@ def main():
     else:
         traffic, traffic_note = profiled_traffic(args.workload, args.precision)
     roofline = {
-        "kernel": "k_gemm / k_gemm_thin / k_gemm_k3 / k_lowrank_w (batched complex %s MFMA GEMMs, all launches of a step)"
+        "kernel": "k_gemm / k_gemm_thin / k_gemm_thin_tri / k_gemm_k3 / k_lowrank_w (batched complex %s MFMA GEMMs, all launches of a step)"
                   % ("FP64" if args.precision == "fp64" else "FP32"),
         "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
         "frac": achieved / peak, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
