@@ -413,7 +413,8 @@ apf_status apf_destroy(apf_handle *h);
  * cut into 64 x 64 tiles and run on one kernel form (0 four-product FP64,
  * 1 three-product FP64, 2 four-product FP64 on the deep-K kernel, 3 FP32
  * MFMA, 4 four-product FP64 with the tiles of at most 32 valid rows on the
- * thin kernel, as the factorization and sweep lists run), so that its
+ * thin kernels, as the factorization and sweep lists run, 5 the same on
+ * FP32 MFMA), so that its
  * operand layouts, triangular masks, row and column maps, Cin forms, edges
  * and k stages can be checked against a plain reference.
  * flags: the internal task flags of the tested set (transposed A, negation,

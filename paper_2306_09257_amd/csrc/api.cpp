@@ -3203,9 +3203,10 @@ extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int3
   const int32_t allowed = G_TRANS_A | G_NEG | G_CIN | G_B_COFF | G_CIN_COFF | G_B_EXT | G_A_TRI_L | G_A_TRI_U |
                           G_B_TRI_L | G_B_TRI_U | G_CIN_OWN | G_C_ACC | G_K_LIM | G_ACC_CHUNK | G_C_COFF |
                           G_CIN_RANGE | G_CONTRACT | G_NO_STORE;
-  if (form < 0 || form > 4) return fail(APF_EINVAL, "form must be 0 (four-product), 1 (three-product), "
-                                                    "2 (four-product on the deep-K kernel), 3 (FP32) or 4 "
-                                                    "(four-product with the thin tiles on the thin kernel)");
+  if (form < 0 || form > 5) return fail(APF_EINVAL, "form must be 0 (four-product), 1 (three-product), "
+                                                    "2 (four-product on the deep-K kernel), 3 (FP32), 4 "
+                                                    "(four-product with the thin tiles on the thin kernels) or 5 "
+                                                    "(FP32 with the thin tiles on the thin kernels)");
   if (flags & ~allowed) return fail(APF_EINVAL, "flag outside the tested set");
   if (M < 1 || N < 1 || K < 0 || !A || !B || !C || nlim < 1) return fail(APF_EINVAL, "bad shape or null operand");
   if ((flags & G_CIN) && !Cin) return fail(APF_EINVAL, "G_CIN without Cin");
@@ -3230,13 +3231,13 @@ extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int3
     if (xcd) add_tiles_xcd(v, t);
     else add_tiles(v, t);
     int ntri = 0;
-    const int nthin = form == 4 ? split_thin(v, &ntri) : 0;
+    const int nthin = (form == 4 || form == 5) ? split_thin(v, &ntri) : 0;
     GemmTask *dv = nullptr;
     HIPCHK(hipMalloc(&dv, std::max<size_t>(v.size(), 1) * sizeof(GemmTask)));
     hipError_t e = hipMemcpyAsync(dv, v.data(), v.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = launch_gemm(dv, (int)v.size(), coff, nlim, (flags & G_B_EXT) ? reinterpret_cast<const cplx *>(B) : nullptr,
-                      s, form == 3, (flags & G_CONTRACT) ? part : nullptr, (flags & G_CONTRACT) ? pstride : 0,
+                      s, form == 3 || form == 5, (flags & G_CONTRACT) ? part : nullptr, (flags & G_CONTRACT) ? pstride : 0,
                       form == 1 || form == 2, nthin, ntri);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dv);

@@ -23,8 +23,8 @@ hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, i
 // slot g and 32-column block b at part[b * pstride + g] (unused otherwise);
 // deep: MFMA-bound deep-K task list (three-product complex form on FP64);
 // nthin: the last nthin tasks are thin tiles (thin_tile_task), run by the
-// thin kernels on the FP64 path (by the FP32 kernel with the rest
-// otherwise); the last nthin_tri of them have a triangular operand
+// thin kernels (FP64 or FP32 like the rest); the last nthin_tri of them have
+// a triangular operand
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s,
                        bool f32 = false, double *part = nullptr, int pstride = 0, bool deep = false,
                        int nthin = 0, int nthin_tri = 0);

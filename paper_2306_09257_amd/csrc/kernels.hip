@@ -910,10 +910,11 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &T, int coff, int N, in
 // is read by every wave, from cache).  Same task semantics and epilogue as
 // gemm_tile; the contraction's 32-column partials combine the row sums of
 // waves 2g and 2g + 1 through LDS (red: 4 x 16 RB doubles).
-template <int RB, int KS, bool TRI>
+template <int RB, int KS, bool TRI, bool F32>
 __device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, int nlimk, const cplx *ext,
                                           double *part, int pstride, double *red) {
-  typedef GemmPrec<false> GP;
+  typedef GemmPrec<F32> GP;
+  typedef typename GP::acc_t acc_t;
   const int M = T.M, K = ((T.flags & G_K_LIM) && nlimk < T.K) ? nlimk : T.K;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -934,11 +935,11 @@ __device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, in
     ai[r] = T.tm + 16 * r + li;
     aiok[r] = ai[r] < M;
   }
-  d4 cre[RB], cim[RB];
+  acc_t cre[RB], cim[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    cre[r] = d4{0, 0, 0, 0};
-    cim[r] = d4{0, 0, 0, 0};
+    cre[r] = acc_t{0, 0, 0, 0};
+    cim[r] = acc_t{0, 0, 0, 0};
   }
   // a triangular operand: masked loads (the stored-triangle rules of
   // tri_mask) and the k range that can hold nonzeros for this tile's rows and
@@ -979,10 +980,12 @@ __device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, in
         if (k0 + 4 * s >= kend) break;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          cre[r] = GP::mfma(a[s][r].x, b[s].x, cre[r]);
-          cre[r] = GP::mfma(-a[s][r].y, b[s].y, cre[r]);
-          cim[r] = GP::mfma(a[s][r].x, b[s].y, cim[r]);
-          cim[r] = GP::mfma(a[s][r].y, b[s].x, cim[r]);
+          // (FP32: operands rounded as the LDS stages of gemm_tile round them)
+          const auto av = GP::cvt(a[s][r]), bv = GP::cvt(b[s]);
+          cre[r] = GP::mfma(av.x, bv.x, cre[r]);
+          cre[r] = GP::mfma(-av.y, bv.y, cre[r]);
+          cim[r] = GP::mfma(av.x, bv.y, cim[r]);
+          cim[r] = GP::mfma(av.y, bv.x, cim[r]);
         }
       }
     }
@@ -1013,7 +1016,7 @@ __device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, in
       oi[r][q] = rowok[r][q] ? (m & EXT_ROW_MASK) : 0;
       const bool addold = (m & EXT_ADD) != 0;
       const int64_t ci = own ? gi : oi[r][q];
-      double2 x = make_double2(cre[r][q], cim[r][q]);
+      double2 x = make_double2((double)cre[r][q], (double)cim[r][q]);
       if (neg) x = make_double2(-x.x, -x.y);
       if (crange) {
         const int cj = gj + cshift;
@@ -1075,6 +1078,7 @@ __device__ __forceinline__ void thin_tile(const GemmTask &T, int coff, int N, in
 // accumulators this kernel holds twice the workgroups per CU of k_gemm.  A
 // thin tile is a short chain of dependent loads (task, row map, operands,
 // epilogue), so the number of tiles in flight sets its throughput.
+template <bool F32>
 __global__ __launch_bounds__(256, 8) void k_gemm_thin(const GemmTask *tasks, int coff, int nlim, const cplx *ext,
                                                       double *part, int pstride) {
   __shared__ double red[2 * 16 * 2];
@@ -1082,14 +1086,15 @@ __global__ __launch_bounds__(256, 8) void k_gemm_thin(const GemmTask *tasks, int
   const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
   if (T.tn >= N) return;
   if (T.M - T.tm <= 16)
-    thin_tile<1, 2, false>(T, coff, N, nlim, ext, part, pstride, red);
+    thin_tile<1, 2, false, F32>(T, coff, N, nlim, ext, part, pstride, red);
   else
-    thin_tile<2, 1, false>(T, coff, N, nlim, ext, part, pstride, red);
+    thin_tile<2, 1, false, F32>(T, coff, N, nlim, ext, part, pstride, red);
 }
 
 // The thin tiles with a triangular operand (after the others in a list), in
 // a kernel of their own so that their masks and k ranges do not cost the
 // plain thin tiles registers.
+template <bool F32>
 __global__ __launch_bounds__(256, 8) void k_gemm_thin_tri(const GemmTask *tasks, int coff, int nlim,
                                                           const cplx *ext, double *part, int pstride) {
   __shared__ double red[2 * 16 * 2];
@@ -1097,9 +1102,9 @@ __global__ __launch_bounds__(256, 8) void k_gemm_thin_tri(const GemmTask *tasks,
   const int N = ((T.flags & G_K_LIM) || T.N < nlim) ? T.N : nlim;
   if (T.tn >= N) return;
   if (T.M - T.tm <= 16)
-    thin_tile<1, 2, true>(T, coff, N, nlim, ext, part, pstride, red);
+    thin_tile<1, 2, true, F32>(T, coff, N, nlim, ext, part, pstride, red);
   else
-    thin_tile<2, 1, true>(T, coff, N, nlim, ext, part, pstride, red);
+    thin_tile<2, 1, true, F32>(T, coff, N, nlim, ext, part, pstride, red);
 }
 
 template <bool F32>
@@ -1777,8 +1782,7 @@ hipError_t launch_wprop(const WFront *f, int n, double scale, double *grad, hipS
 hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx *ext, hipStream_t s, bool f32,
                        double *part, int pstride, bool deep, int nthin, int nthin_tri) {
   if (n == 0) return hipSuccess;
-  // the FP32 kernel takes the thin tiles too (the thin kernel is FP64)
-  const int nreg = f32 ? n : n - nthin;
+  const int nreg = n - nthin;
   if (nreg > 0) {
     if (deep && !f32)
       hipLaunchKernelGGL(k_gemm_k3, dim3(nreg), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
@@ -1787,24 +1791,30 @@ hipError_t launch_gemm(const GemmTask *t, int n, int coff, int nlim, const cplx 
     else
       hipLaunchKernelGGL(k_gemm<false>, dim3(nreg), dim3(256), 0, s, t, coff, nlim, ext, part, pstride);
   }
-  const int nplain = nreg < n ? nthin - nthin_tri : 0, ntri = nreg < n ? nthin_tri : 0;
+  const int nplain = nthin - nthin_tri, ntri = nthin_tri;
   if (nplain > 0) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gemm_thin, dim3(nplain), dim3(256), 0, s, t + nreg, coff, nlim, ext, part, pstride);
+    if (f32)
+      hipLaunchKernelGGL(k_gemm_thin<true>, dim3(nplain), dim3(256), 0, s, t + nreg, coff, nlim, ext, part, pstride);
+    else
+      hipLaunchKernelGGL(k_gemm_thin<false>, dim3(nplain), dim3(256), 0, s, t + nreg, coff, nlim, ext, part, pstride);
   }
   if (ntri > 0) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gemm_thin_tri, dim3(ntri), dim3(256), 0, s, t + nreg + nplain, coff, nlim, ext, part,
-                       pstride);
+    if (f32)
+      hipLaunchKernelGGL(k_gemm_thin_tri<true>, dim3(ntri), dim3(256), 0, s, t + nreg + nplain, coff, nlim, ext,
+                         part, pstride);
+    else
+      hipLaunchKernelGGL(k_gemm_thin_tri<false>, dim3(ntri), dim3(256), 0, s, t + nreg + nplain, coff, nlim, ext,
+                         part, pstride);
   }
   return hipGetLastError();
 }
 
-int gemm_kernel_launches(int n, int nthin, int nthin_tri, bool f32) {
+int gemm_kernel_launches(int n, int nthin, int nthin_tri, bool) {
   if (n == 0) return 0;
-  if (f32) return 1;
   return (n - nthin > 0) + (nthin - nthin_tri > 0) + (nthin_tri > 0);
 }
 
