@@ -20,12 +20,16 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cinv(double2 a) {
-  // 1/a with scaling against overflow of |a|^2
-  double s = fmax(fabs(a.x), fabs(a.y));
+  // 1/a = conj(a) / |a|^2, with a scaled by the power of two 2^-e of its
+  // larger part (exact, and |a|^2 then neither overflows nor underflows):
+  // one division instead of one per part and scale
+  const double s = fmax(fabs(a.x), fabs(a.y));
   if (s == 0.0) return make_double2(0.0, 0.0);
-  double ar = a.x / s, ai = a.y / s;
-  double d = ar * ar + ai * ai;
-  return make_double2(ar / (d * s), -ai / (d * s));
+  int e;
+  (void)frexp(s, &e);
+  const double ar = ldexp(a.x, -e), ai = ldexp(a.y, -e);
+  const double t = 1.0 / (ar * ar + ai * ai);
+  return make_double2(ldexp(ar * t, -e), ldexp(-ai * t, -e));
 }
 // by-value select: a conditional over lvalues would take the operands'
 // addresses and push register arrays into scratch
