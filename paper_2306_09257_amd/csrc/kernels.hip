@@ -60,7 +60,7 @@ __device__ __forceinline__ void ld_lds16(const cplx *src, double2 *dst) {
 // ---------------------------------------------------------------------------
 // One block per range; the host splits ranges into chunks of at most
 // ZERO_CHUNK elements so that blocks are evenly loaded.
-__global__ void k_zero(const ZeroRange *r, int n) {
+__global__ void k_zero(const ZeroRange *r) {
   const ZeroRange z = r[blockIdx.x];
   double2 *p = reinterpret_cast<double2 *>(z.ptr);
   for (int64_t i = threadIdx.x; i < z.n; i += blockDim.x) p[i] = make_double2(0.0, 0.0);
@@ -133,7 +133,7 @@ __device__ double2 channel_value(const Phys &P, int a, int i, double eps_medium,
 
 // B rows: -2i sqrt(sin q_a) phi_a(i); C^T rows: sqrt(sin q_b) conj(phi_b(i)).
 // Each row is stored whole: the assembly is the first writer of its rows.
-__global__ void k_assemble_panel(const PanelEntry *e, int n) {
+__global__ void k_assemble_panel(const PanelEntry *e) {
   const PanelEntry E = e[blockIdx.x];
   const ChanParams &cp = *E.cp;
   const Phys &P = cp.P;
@@ -1310,7 +1310,7 @@ __global__ void k_wpow_partial(const double2 *S, const double *w, double2 *G, in
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -1323,7 +1323,7 @@ __global__ void k_wpow_final(const double *part, int n, double *f) {
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) *f = red[0];
@@ -1350,7 +1350,7 @@ __global__ void k_splitter_partial(const double2 *S, const int32_t *in_ord, cons
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -1363,20 +1363,22 @@ __global__ void k_splitter_partial(const double2 *S, const int32_t *in_ord, cons
 //   f = sum_a sum_t [ -p_ta + (p_ta - mu_a)^2 ],
 //   dF/dS_ta = (-1 + 2 (p_ta - mu_a)) conj(S_ta) on the targets, 0 elsewhere.
 // k_group_zero clears dF/dS; k_group_partial takes one input column per
-// thread (two passes over the outputs: the mean, then f and dF/dS) and sums
-// its block's f into part[]; k_wpow_final adds the parts.
+// wave at a time, its lanes striding over the outputs (two passes: the mean,
+// then f and dF/dS), and sums its block's f into part[]; k_wpow_final adds
+// the parts.
 // ---------------------------------------------------------------------------
 __global__ void k_group_zero(double2 *G, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     G[e] = make_double2(0.0, 0.0);
 }
 
-__global__ void k_group_partial(const double2 *S, const int32_t *in_ord, const int32_t *out_ord, int n_in,
-                                int n_out, int delta, int gmax, double2 *G, double *part) {
-  __shared__ double red[256];
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
-  if (a < n_in) {
+__global__ __launch_bounds__(256) void k_group_partial(const double2 *S, const int32_t *in_ord,
+                                                      const int32_t *out_ord, int n_in, int n_out, int delta,
+                                                      int gmax, double2 *G, double *part) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc = 0.0;   // f over this wave's input columns
+  for (int a = blockIdx.x * 4 + wv; a < n_in; a += gridDim.x * 4) {
     const int oa = in_ord[a];
     auto is_target = [&](int t) {
       const int d = out_ord[t] - oa;
@@ -1384,31 +1386,34 @@ __global__ void k_group_partial(const double2 *S, const int32_t *in_ord, const i
     };
     double sum = 0.0;
     int cnt = 0;
-    for (int t = 0; t < n_out; ++t)
+    for (int t = lane; t < n_out; t += 64)
       if (is_target(t)) {
         const double2 v = S[(int64_t)t * n_in + a];
         sum += v.x * v.x + v.y * v.y;
         ++cnt;
       }
+    for (int off = 32; off > 0; off >>= 1) {
+      sum += __shfl_xor(sum, off, 64);
+      cnt += __shfl_xor(cnt, off, 64);
+    }
     if (cnt > 0) {
       const double mu = sum / cnt;
-      for (int t = 0; t < n_out; ++t)
+      double fa = 0.0;
+      for (int t = lane; t < n_out; t += 64)
         if (is_target(t)) {
           const double2 v = S[(int64_t)t * n_in + a];
           const double p = v.x * v.x + v.y * v.y, dev = p - mu;
-          acc += -p + dev * dev;
+          fa += -p + dev * dev;
           const double df = -1.0 + 2.0 * dev;
           G[(int64_t)t * n_in + a] = make_double2(df * v.x, -df * v.y);
         }
+      for (int off = 32; off > 0; off >>= 1) fa += __shfl_xor(fa, off, 64);
+      acc += fa;
     }
   }
-  red[threadIdx.x] = acc;
+  if (lane == 0) red[wv] = acc;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1451,7 +1456,7 @@ __device__ double column_sum(const double *g, int nx, int nrows, int j, double *
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   const double v = red[0];
@@ -1583,7 +1588,7 @@ __global__ __launch_bounds__(256) void k_contract_rows(const int32_t *erow, int6
 }
 
 // Contiguous copies (one block per range).
-__global__ void k_copy(const CopyRange *r, int n) {
+__global__ void k_copy(const CopyRange *r) {
   const CopyRange c = r[blockIdx.x];
   const double2 *s = reinterpret_cast<const double2 *>(c.src);
   double2 *d = reinterpret_cast<double2 *>(c.dst);
@@ -1632,35 +1637,49 @@ __global__ void k_set_k3(GemmTask *t, int n, int on) {
 
 // Nonzero count of every column of G (n_out x n_in, row-major); the largest
 // goes to *maxnnz.
-__global__ void k_col_nnz(const double2 *G, int n_out, int n_in, int *nnz, int *maxnnz) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_in) return;
-  int c = 0;
-  for (int b = 0; b < n_out; ++b) {
-    const double2 v = G[(int64_t)b * n_in + m];
-    c += (v.x != 0.0 || v.y != 0.0);
+__global__ __launch_bounds__(256) void k_col_nnz(const double2 *G, int n_out, int n_in, int *nnz, int *maxnnz) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int m = blockIdx.x * 4 + wv; m < n_in; m += gridDim.x * 4) {
+    int c = 0;
+    for (int b = lane; b < n_out; b += 64) {
+      const double2 v = G[(int64_t)b * n_in + m];
+      c += (v.x != 0.0 || v.y != 0.0);
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) {
+      nnz[m] = c;
+      atomicMax(maxnnz, c);
+    }
   }
-  nnz[m] = c;
-  atomicMax(maxnnz, c);
 }
 
 // The first K nonzeros of every column as (row, value), in row order; unused
-// slots hold row 0 and value 0.
-__global__ void k_col_compact(const double2 *G, int n_out, int n_in, int K, int32_t *idx, double2 *val) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_in) return;
-  int c = 0;
-  for (int b = 0; b < n_out && c < K; ++b) {
-    const double2 v = G[(int64_t)b * n_in + m];
-    if (v.x != 0.0 || v.y != 0.0) {
-      idx[(int64_t)m * K + c] = b;
-      val[(int64_t)m * K + c] = v;
-      ++c;
+// slots hold row 0 and value 0.  One column per wave at a time: each step
+// takes 64 consecutive rows, and a lane's slot is the nonzeros before it
+// (ballot) after those of the earlier steps.
+__global__ __launch_bounds__(256) void k_col_compact(const double2 *G, int n_out, int n_in, int K, int32_t *idx,
+                                                    double2 *val) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1;
+  for (int m = blockIdx.x * 4 + wv; m < n_in; m += gridDim.x * 4) {
+    int c = 0;
+    for (int b0 = 0; b0 < n_out && c < K; b0 += 64) {
+      const int b = b0 + lane;
+      double2 v = make_double2(0.0, 0.0);
+      if (b < n_out) v = G[(int64_t)b * n_in + m];
+      const bool nz = v.x != 0.0 || v.y != 0.0;
+      const unsigned long long mask = __ballot(nz);
+      const int slot = c + __popcll(mask & below);
+      if (nz && slot < K) {
+        idx[(int64_t)m * K + slot] = b;
+        val[(int64_t)m * K + slot] = v;
+      }
+      c += __popcll(mask);
     }
-  }
-  for (; c < K; ++c) {
-    idx[(int64_t)m * K + c] = 0;
-    val[(int64_t)m * K + c] = make_double2(0.0, 0.0);
+    for (int q = min(c, K) + lane; q < K; q += 64) {
+      idx[(int64_t)m * K + q] = 0;
+      val[(int64_t)m * K + q] = make_double2(0.0, 0.0);
+    }
   }
 }
 
@@ -1725,7 +1744,7 @@ __global__ void k_compress_basis(int nx, int Mx, int a0, double half_px, int lo,
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroRange *r, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero, dim3(n), dim3(256), 0, s, r, n);
+  hipLaunchKernelGGL(k_zero, dim3(n), dim3(256), 0, s, r);
   return hipGetLastError();
 }
 hipError_t launch_stencil(const Phys &P, const double *eps, cplx *Aval, int *status, hipStream_t s) {
@@ -1744,7 +1763,7 @@ hipError_t launch_fill_int(int *p, int v, hipStream_t s) {
 }
 hipError_t launch_assemble_panel(const PanelEntry *e, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e, n);
+  hipLaunchKernelGGL(k_assemble_panel, dim3(n), dim3(256), 0, s, e);
   return hipGetLastError();
 }
 // Largest pivot block of each variant of launch_inverse.
@@ -1885,7 +1904,7 @@ hipError_t launch_group_fom(const cplx *S, const int32_t *in_ord, const int32_t 
                      reinterpret_cast<double2 *>(G), n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nb = (n_in + 255) / 256;
+  const int nb = std::min(1024, (n_in + 3) / 4);   // (part holds 1024 blocks' sums)
   hipLaunchKernelGGL(k_group_partial, dim3(nb), dim3(256), 0, s, reinterpret_cast<const double2 *>(S), in_ord,
                      out_ord, n_in, n_out, delta, gmax, reinterpret_cast<double2 *>(G), part);
   e = hipGetLastError();
@@ -1942,7 +1961,7 @@ hipError_t launch_contract_rows(const int32_t *erow, int64_t n, const cplx *Lam,
 }
 hipError_t launch_copy(const CopyRange *r, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy, dim3(n), dim3(256), 0, s, r, n);
+  hipLaunchKernelGGL(k_copy, dim3(n), dim3(256), 0, s, r);
   return hipGetLastError();
 }
 hipError_t launch_fill_double(double *p, int n, double v, hipStream_t s) {
@@ -1977,12 +1996,13 @@ hipError_t launch_set_k3(GemmTask *t, int n, bool on, hipStream_t s) {
 }
 
 hipError_t launch_col_nnz(const cplx *G, int n_out, int n_in, int *nnz, int *maxnnz, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_nnz, dim3((n_in + 255) / 256), dim3(256), 0, s, reinterpret_cast<const double2 *>(G),
-                     n_out, n_in, nnz, maxnnz);
+  // one column per wave (4 per workgroup), grid-strided
+  hipLaunchKernelGGL(k_col_nnz, dim3(std::min(65535, (n_in + 3) / 4)), dim3(256), 0, s,
+                     reinterpret_cast<const double2 *>(G), n_out, n_in, nnz, maxnnz);
   return hipGetLastError();
 }
 hipError_t launch_col_compact(const cplx *G, int n_out, int n_in, int K, int32_t *idx, cplx *val, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_compact, dim3((n_in + 255) / 256), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_col_compact, dim3(std::min(65535, (n_in + 3) / 4)), dim3(256), 0, s,
                      reinterpret_cast<const double2 *>(G), n_out, n_in, K, idx, reinterpret_cast<double2 *>(val));
   return hipGetLastError();
 }
