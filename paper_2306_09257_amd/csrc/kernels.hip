@@ -1684,23 +1684,43 @@ __global__ __launch_bounds__(256) void k_col_compact(const double2 *G, int n_out
 }
 
 // V[vmap[r]][j] = sum_k XC[r][idx[m][k]] val[m][k], m = coff + j, for the
-// chunk's w columns; one thread per (row, column), columns fastest so that a
-// wave reads consecutive entries of an XC row.
-__global__ void k_sparse_vinit(const double2 *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
-                               const double2 *val, int K, int coff, int w, double2 *V, int ldv) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t r = t / w;
-  if (r >= rows) return;
-  const int j = (int)(t - r * w), m = coff + j;
-  const double2 *x = XC + r * n_out;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int k = 0; k < K; ++k) {
-    const double2 g = val[(int64_t)m * K + k];
-    const double2 a = x[idx[(int64_t)m * K + k]];
-    acc.x = fma(a.x, g.x, fma(-a.y, g.y, acc.x));
-    acc.y = fma(a.x, g.y, fma(a.y, g.x, acc.y));
+// chunk's w columns.  A workgroup takes SV_ROWS consecutive rows and 256
+// consecutive columns: a thread loads its column's K (row, value) pairs once
+// and serves the rows with them; a wave reads consecutive entries of an XC
+// row (the target orders of consecutive inputs are consecutive) and writes
+// consecutive entries of a V row.
+constexpr int SV_ROWS = 8;
+template <int SV_KMAX>
+__global__ __launch_bounds__(256) void k_sparse_vinit(const double2 *XC, int n_out, int64_t rows,
+                                                      const int32_t *vmap, const int32_t *idx, const double2 *val,
+                                                      int K, int coff, int w, double2 *V, int ldv) {
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= w) return;
+  const int m = coff + j;
+  int ik[SV_KMAX];
+  double2 gk[SV_KMAX];
+#pragma unroll
+  for (int k = 0; k < SV_KMAX; ++k)
+    if (k < K) {
+      ik[k] = idx[(int64_t)m * K + k];
+      gk[k] = val[(int64_t)m * K + k];
+    }
+  const int64_t r0 = (int64_t)blockIdx.x * SV_ROWS;
+#pragma unroll
+  for (int q = 0; q < SV_ROWS; ++q) {
+    const int64_t r = r0 + q;
+    if (r >= rows) break;
+    const double2 *x = XC + r * n_out;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < SV_KMAX; ++k)
+      if (k < K) {
+        const double2 a = x[ik[k]];
+        acc.x = fma(a.x, gk[k].x, fma(-a.y, gk[k].y, acc.x));
+        acc.y = fma(a.x, gk[k].y, fma(a.y, gk[k].x, acc.y));
+      }
+    V[(int64_t)vmap[r] * ldv + j] = acc;
   }
-  V[(int64_t)vmap[r] * ldv + j] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -2008,11 +2028,17 @@ hipError_t launch_col_compact(const cplx *G, int n_out, int n_in, int K, int32_t
 }
 hipError_t launch_sparse_vinit(const cplx *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
                                const cplx *val, int K, int coff, int w, cplx *V, int ldv, hipStream_t s) {
-  const int64_t n = rows * w;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sparse_vinit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     reinterpret_cast<const double2 *>(XC), n_out, rows, vmap, idx,
-                     reinterpret_cast<const double2 *>(val), K, coff, w, reinterpret_cast<double2 *>(V), ldv);
+  if (rows == 0 || w == 0) return hipSuccess;
+  if (K < 1 || K > 32) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((rows + SV_ROWS - 1) / SV_ROWS), (unsigned)((w + 255) / 256));
+  // (the column's list lives in registers: size the kernel to K)
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, reinterpret_cast<const double2 *>(XC), n_out, rows, vmap, idx,
+                       reinterpret_cast<const double2 *>(val), K, coff, w, reinterpret_cast<double2 *>(V), ldv);
+  };
+  if (K <= 8) go(k_sparse_vinit<8>);
+  else if (K <= 16) go(k_sparse_vinit<16>);
+  else go(k_sparse_vinit<32>);
   return hipGetLastError();
 }
 

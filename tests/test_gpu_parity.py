@@ -317,6 +317,34 @@ def test_sparse_adjoint_source_matches_the_dense_product_and_the_oracle():
     assert _rel(g_sparse, g_dense) < 1e-12
 
 
+@pytest.mark.parametrize("nx,width", [(1200, 12), (2400, 25)])
+def test_sparse_adjoint_source_wider_lists_match_the_dense_product(nx, width):
+    """Random dF/dS with `width` nonzeros in every input column (the sparse
+    kernel's 16- and 32-entry variants): the gradient equals the dense
+    product's to rounding."""
+    from paper_2306_09257_amd import binding
+    prob = inputs.make_problem(nx, 92)
+    rng = np.random.default_rng(nx + width)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    apf = binding.APF(prob).analyze()
+    apf.assemble(_dev(eps, torch.float64))
+    apf.factor_schur()
+    assert 8 * width <= prob.n_out
+    G = np.zeros((prob.n_out, prob.n_in), complex)
+    for m in range(prob.n_in):
+        rows = rng.choice(prob.n_out, width, replace=False)
+        G[rows, m] = rng.standard_normal(width) + 1j * rng.standard_normal(width)
+    g_sparse = apf.grad(_dev(G, torch.complex128)).cpu().numpy()
+    k = apf.query("adjoint_source_sparse_k")
+    Gd = G.copy()
+    Gd[Gd == 0] = 1e-300
+    g_dense = apf.grad(_dev(Gd, torch.complex128)).cpu().numpy()
+    assert apf.query("adjoint_source_sparse_k") == 0
+    print(f"[gpu] sparse adjoint source {nx}x92 width {k:.0f}: vs dense {_rel(g_sparse, g_dense):.2e}", flush=True)
+    assert k == width
+    assert _rel(g_sparse, g_dense) < 1e-12
+
+
 def _pivot_spreads_by_elimination(apf, prob, eps):
     """Per front, min |u_kk| / max |u_kk| of LU with partial pivoting (largest
     modulus, ties to the lowest row) of the front's pivot block, the Schur
