@@ -95,6 +95,7 @@ struct Phys {
 struct ChanParams {
   Phys P;
   const int32_t *orders;
+  double *amp;             // per order: sqrt(sin q / nx) in the panel's medium (filled on the device)
   int32_t m, is_source;
 };
 

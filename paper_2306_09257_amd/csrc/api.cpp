@@ -1124,20 +1124,27 @@ static void build_plan(apf_handle *H) {
   // channel parameters of the two panels, in a small buffer of their own
   const ChanParams *cp_src, *cp_prj;
   {
-    std::vector<char> hb(2 * sizeof(ChanParams) + (d.n_in + d.n_out) * sizeof(int32_t));
+    // [2 ChanParams][orders: n_in + n_out int32][amplitudes: n_in + n_out doubles]
+    const size_t ord_off = 2 * sizeof(ChanParams);
+    const size_t amp_off = (ord_off + (d.n_in + d.n_out) * sizeof(int32_t) + 15) / 16 * 16;
+    std::vector<char> hb(amp_off + (d.n_in + d.n_out) * sizeof(double));
     HIPCHK(hipMalloc(&P.chan, hb.size()));
     ChanParams c[2];
     c[0].P = H->phys; c[0].m = d.n_in; c[0].is_source = 1;
-    c[0].orders = reinterpret_cast<const int32_t *>(P.chan + 2 * sizeof(ChanParams));
+    c[0].orders = reinterpret_cast<const int32_t *>(P.chan + ord_off);
+    c[0].amp = reinterpret_cast<double *>(P.chan + amp_off);
     c[1].P = H->phys; c[1].m = d.n_out; c[1].is_source = 0;
     c[1].orders = c[0].orders + d.n_in;
+    c[1].amp = c[0].amp + d.n_in;
     std::memcpy(hb.data(), c, sizeof c);
-    std::memcpy(hb.data() + 2 * sizeof(ChanParams), d.in_orders.data(), d.n_in * sizeof(int32_t));
-    std::memcpy(hb.data() + 2 * sizeof(ChanParams) + d.n_in * sizeof(int32_t), d.out_orders.data(),
-                d.n_out * sizeof(int32_t));
+    std::memcpy(hb.data() + ord_off, d.in_orders.data(), d.n_in * sizeof(int32_t));
+    std::memcpy(hb.data() + ord_off + d.n_in * sizeof(int32_t), d.out_orders.data(), d.n_out * sizeof(int32_t));
     HIPCHK(hipMemcpy(P.chan, hb.data(), hb.size(), hipMemcpyHostToDevice));
     cp_src = reinterpret_cast<const ChanParams *>(P.chan);
     cp_prj = cp_src + 1;
+    // the orders' amplitude factors, once per plan (the panel assembly reads them)
+    HIPCHK(launch_channel_amp(cp_src, d.n_in + d.n_out, nullptr));
+    HIPCHK(hipDeviceSynchronize());
   }
   // Channel panel rows: the first writer of a row stores, later writers add.
   // The writers of a front's panel rows, in launch order: the channel

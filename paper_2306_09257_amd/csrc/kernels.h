@@ -66,6 +66,8 @@ hipError_t launch_zero_flat(cplx *p, int64_t n, hipStream_t s);   // n contiguou
 // weighted adjoint source from a column-sparse dF/dS
 hipError_t launch_col_nnz(const cplx *G, int n_out, int n_in, int *nnz, int *maxnnz, hipStream_t s);
 hipError_t launch_col_compact(const cplx *G, int n_out, int n_in, int K, int32_t *idx, cplx *val, hipStream_t s);
+// amp[] of both panels' channel parameters (cp[0], cp[1]: n = m0 + m1 orders)
+hipError_t launch_channel_amp(const ChanParams *cp, int n, hipStream_t s);
 hipError_t launch_sparse_vinit(const cplx *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
                                const cplx *val, int K, int coff, int w, cplx *V, int ldv, hipStream_t s);
 // compressed channel basis on one channel row (nx x Mx, zeroed beforehand)

@@ -118,17 +118,39 @@ __global__ void k_fill_int(int *p, int v) { *p = v; }
 
 // Channel value at column i of order a in a medium: sqrt(sin q) phi_a(i), with
 // q from sin^2(q/2) = h^2 eps/4 - sin^2(pi a/nx) and phi_a(i) = e^{2 pi i a i/nx}/sqrt(nx).
-__device__ double2 channel_value(const Phys &P, int a, int i, double eps_medium, bool conj_phase) {
+// channel_amp is the order's factor sqrt(sin q / nx), channel_phase the
+// node's e^{+-2 pi i a i/nx}, with a i reduced mod nx exactly in FP64 (an
+// integer below 2^53: the quotient's floor is off by at most one, and the
+// products and differences are exact).
+__device__ double channel_amp(const Phys &P, int a, double eps_medium) {
   double sa = sin(M_PI * (double)a / P.nx);
   double rhs = P.h2 * eps_medium * 0.25 - sa * sa;
   double q = 2.0 * asin(sqrt(rhs));
-  double amp = sqrt(sin(q) / P.nx);
-  int64_t ph = ((int64_t)a * i) % P.nx;
-  if (ph < 0) ph += P.nx;
-  double ang = 2.0 * M_PI * (double)ph / P.nx;
+  return sqrt(sin(q) / P.nx);
+}
+__device__ double2 channel_phase(const Phys &P, int a, int i, bool conj_phase) {
+  const double nx = (double)P.nx, x = (double)a * (double)i;
+  double ph = x - floor(x / nx) * nx;
+  if (ph < 0.0) ph += nx;
+  else if (ph >= nx) ph -= nx;
+  double ang = 2.0 * M_PI * ph / P.nx;
   double s, c;
   sincos(ang, &s, &c);
-  return make_double2(amp * c, conj_phase ? -amp * s : amp * s);
+  return make_double2(c, conj_phase ? -s : s);
+}
+__device__ double2 channel_value(const Phys &P, int a, int i, double eps_medium, bool conj_phase) {
+  const double amp = channel_amp(P, a, eps_medium);
+  const double2 e = channel_phase(P, a, i, conj_phase);
+  return make_double2(amp * e.x, amp * e.y);
+}
+
+// The orders' factors channel_amp of both panels (one thread per order).
+__global__ void k_channel_amp(const ChanParams *cp, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const ChanParams &C = cp[t < cp[0].m ? 0 : 1];
+  const int a = t < cp[0].m ? t : t - cp[0].m;
+  C.amp[a] = channel_amp(C.P, C.orders[a], C.is_source ? C.P.eps_src : C.P.eps_prj);
 }
 
 // B rows: -2i sqrt(sin q_a) phi_a(i); C^T rows: sqrt(sin q_b) conj(phi_b(i)).
@@ -139,9 +161,11 @@ __global__ void k_assemble_panel(const PanelEntry *e) {
   const Phys &P = cp.P;
   const int is_source = cp.is_source, m = cp.m;
   const int i = E.node % P.nx;
-  double eps_m = is_source ? P.eps_src : P.eps_prj;
   for (int a = threadIdx.x; a < m; a += blockDim.x) {
-    double2 v = channel_value(P, cp.orders[a], i, eps_m, !is_source);
+    // (the order's factor from the table channel_amp filled for the plan)
+    const double amp = cp.amp[a];
+    const double2 e = channel_phase(P, cp.orders[a], i, !is_source);
+    double2 v = make_double2(amp * e.x, amp * e.y);
     if (is_source) v = make_double2(2.0 * v.y, -2.0 * v.x);   // times -2i
     st2(E.dest + a, v);
   }
@@ -2026,6 +2050,12 @@ hipError_t launch_col_compact(const cplx *G, int n_out, int n_in, int K, int32_t
                      reinterpret_cast<const double2 *>(G), n_out, n_in, K, idx, reinterpret_cast<double2 *>(val));
   return hipGetLastError();
 }
+hipError_t launch_channel_amp(const ChanParams *cp, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_channel_amp, dim3((n + 255) / 256), dim3(256), 0, s, cp, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_sparse_vinit(const cplx *XC, int n_out, int64_t rows, const int32_t *vmap, const int32_t *idx,
                                const cplx *val, int K, int coff, int w, cplx *V, int ldv, hipStream_t s) {
   if (rows == 0 || w == 0) return hipSuccess;
