@@ -387,7 +387,12 @@ def main():
                          "after the timed steps, S, f and the gradient are compared with an uncompressed handle")
     ap.add_argument("--lowrank", type=int, default=-1,
                     help="levels of the low-rank sweep subtrees (0-2; default: the library's)")
+    ap.add_argument("--symmetric", action="store_true",
+                    help="the symmetric route: L D L^T pivot blocks and the symmetric products (FP64)")
     args = ap.parse_args()
+    if args.symmetric and (args.compress or args.precision != "fp64"):
+        print("--symmetric runs in FP64 only and does not combine with --compress", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the APF path here is a "
               f"single-GPU build", file=sys.stderr)
@@ -418,6 +423,8 @@ def main():
         apf.set_refinement(args.refine_iters, 1e-10)
     if args.lowrank >= 0:
         apf.set_lowrank(args.lowrank)
+    if args.symmetric:
+        apf.set_symmetric(True)
     if args.compress:
         pad, window = args.compress.split(",")
         apf.set_compression(int(pad), float(window))
@@ -498,7 +505,7 @@ def main():
     k3 = cm["k3"] if args.precision == "fp64" else cm["lowrank_w"]
     executed = (8.0 * (gemm_cm - k3) + 6.0 * k3) / (gemm_ms * 1e-3) / 1e12
     peak = FP64_MFMA_PEAK_TFLOPS if args.precision == "fp64" else FP32_MFMA_PEAK_TFLOPS
-    if args.compress or args.factor_only or args.lowrank >= 0 or args.leaf:
+    if args.compress or args.factor_only or args.lowrank >= 0 or args.leaf or args.symmetric:
         traffic, traffic_note = None, "the counter summaries cover the default plan options only"
     else:
         traffic, traffic_note = profiled_traffic(args.workload, args.precision)
@@ -525,7 +532,8 @@ def main():
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "unknowns": prob.nx * prob.ny,
                    "n_in": prob.n_in, "n_out": prob.n_out, "design_pixels": prob.n_design_rows * prob.nx,
                    "precision": args.precision, "leaf_size": args.leaf or 48,
-                   "compression": args.compress or None},
+                   "compression": args.compress or None,
+                   "route": "symmetric (L D L^T)" if args.symmetric else "LU"},
         "roofline": roofline,
         "phase_ms_per_step": phases,
         "analysis_s": t_an,

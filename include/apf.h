@@ -384,6 +384,27 @@ apf_status apf_set_gradient(apf_handle *h, int32_t on);
  * APF_EINVAL for max_iter outside [0, 16] or a bad tol. */
 apf_status apf_set_refinement(apf_handle *h, int32_t max_iter, double tol);
 
+/* Symmetric route (on = 1; 0, the default, is the LU route).  The operator is
+ * complex symmetric, A = A^T (Sec. 2), and the Supplement (Sec. 1) obtains
+ * S from a symmetric factorization of K; this library factors each front's
+ * pivot block as F11 = L D L^T (no row exchanges inside the block: U = D L^T,
+ * the identity permutation) and uses the symmetry in the products: U12 =
+ * L^-1 F12 = D L21^T and the sweeps' Z = L21 L^-1 = X12^T are transposes
+ * instead of products, and the contribution block F22 - L21 U12, symmetric,
+ * is formed on its lower 64 x 64 tiles only (the lower triangle of each
+ * front's core is maintained; its upper triangle is not read).  The channel
+ * panels B and C are carried apart as on the LU route, so K itself need not
+ * be symmetric (one-sided channels serve).  Without row exchanges a pivot
+ * block close to singular loses accuracy that partial pivoting would keep:
+ * check "pivot_spread_min" after a factorization.  FP64 only: apf_factor_schur
+ * returns APF_EINVAL for the other precisions (with FP32 products the
+ * unpivoted blocks amplify the rounding: S 3.8e-5 and gradient 1.5e-4 from
+ * the FP64 values at 240 x 92, against 1.2e-6 and 8.4e-6 on the LU route);
+ * APF_EINVAL with compressed channels or refinement (set either way round),
+ * and from apf_factor_schur_batched and the augmented entry points.  Call before the first apf_assemble (else APF_ESTATE);
+ * APF_EINVAL unless on is 0 or 1. */
+apf_status apf_set_symmetric(apf_handle *h, int32_t on);
+
 /* Depth of the low-rank sweep subtrees: channel-free sweep subtrees of up to
  * `levels` levels (0, 1 or 2) whose gradient comes from the b x b product
  * Wt = Y_bnd Lam_bnd^T of their root instead of the Y and Lam sweeps (the same
@@ -443,7 +464,10 @@ apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int32_t N, int3
 /* Kernel test hook (for the kernel unit tests, not for applications): the
  * pivot-block kernel on one p x p block F (device, complex128 row-major,
  * 1 <= p <= 128; read only): LU with partial pivoting inside the block
- * (largest modulus, ties to the lowest row), then the in-place inverses.
+ * (largest modulus, ties to the lowest row), then the in-place inverses;
+ * with sym = 1 the kernel's symmetric mode (apf_set_symmetric): only the
+ * lower triangle of F is read (the block taken as symmetric) and step k
+ * pivots on row k, so perm is the identity and U = D L^T.
  * tri_dev (device, complex128 p x p) receives L^-1 below the diagonal (unit
  * diagonal implied) and U^-1 on and above it, perm_dev (device, int32 p) the
  * row of F taken at each step, so that U^-1 L^-1 F[perm] = I; *spread (host,
@@ -451,7 +475,7 @@ apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int32_t N, int3
  * a pivot was zero or non-finite (the outputs are then undefined); the
  * kernel runs to its end either way.  Allocates and synchronises `stream`. */
 apf_status apf_test_pivot_block(int32_t p, const double *F_dev, double *tri_dev, int32_t *perm_dev,
-                                double *spread, void *stream);
+                                double *spread, int32_t sym, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *apf_last_error(void);

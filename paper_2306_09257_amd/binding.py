@@ -32,7 +32,8 @@ ENTRY_POINTS = ("apf_create", "apf_analyze", "apf_assemble", "apf_factor_schur",
                 "apf_grad", "apf_set_rhs_chunk", "apf_set_lowrank", "apf_set_profiling", "apf_destroy",
                 "apf_last_error", "apf_query", "apf_front", "apf_weighted_power_noalloc", "apf_set_refinement",
                 "apf_grad_augmented", "apf_ridges_grad_augmented", "apf_autotune", "apf_tuning_apply",
-                "apf_set_compression", "apf_set_gradient", "apf_test_gemm", "apf_test_pivot_block")
+                "apf_set_compression", "apf_set_gradient", "apf_set_symmetric", "apf_test_gemm",
+                "apf_test_pivot_block")
 PROFILE_CLASSES = ("stencil", "zero", "assemble", "inverse", "gemm_factor", "gemm_schur", "gemm_sweep",
                    "contract", "wpow", "refine", "adjoint_source")
 
@@ -87,7 +88,8 @@ def load_library(path: str = LIB_PATH):
     lib.apf_set_refinement.argtypes = [vp, i32, dbl]
     lib.apf_set_compression.argtypes = [vp, i32, dbl]
     lib.apf_set_gradient.argtypes = [vp, i32]
-    lib.apf_test_pivot_block.argtypes = [i32, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    lib.apf_set_symmetric.argtypes = [vp, i32]
+    lib.apf_test_pivot_block.argtypes = [i32, vp, vp, vp, ctypes.POINTER(dbl), i32, vp]
     lib.apf_test_gemm.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, ctypes.c_int64, vp, i32, vp, i32,
                                   vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, i32, vp]
     lib.apf_autotune.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.c_char_p, vp]
@@ -157,6 +159,12 @@ class APF:
     def set_rhs_chunk(self, max_chunk: int):
         """Cap the sweeps' right-hand-side chunk (before the first assemble)."""
         _check(self._lib.apf_set_rhs_chunk(self._h, int(max_chunk)))
+        return self
+
+    def set_symmetric(self, on=True):
+        """The symmetric route (L D L^T pivot blocks, the products' symmetry),
+        before the first assemble."""
+        _check(self._lib.apf_set_symmetric(self._h, 1 if on else 0))
         return self
 
     def set_lowrank(self, levels):
@@ -369,13 +377,15 @@ def gemm_hook(form, flags, M, N, K, A, lda, B, ldb, C, ldc, Cin=None, ldcin=0, b
                              p(part), int(pstride), _stream()))
 
 
-def pivot_block_hook(F, tri, perm):
+def pivot_block_hook(F, tri, perm, sym=False):
     """Kernel test hook: the pivot-block kernel on one p x p block (device
-    tensors: F, tri complex128 [p][p], perm int32 [p]); returns the pivot
+    tensors: F, tri complex128 [p][p], perm int32 [p]; sym: the symmetric
+    mode, lower triangle of F read, no row exchanges); returns the pivot
     spread (raises APFError with APF_ESINGULAR for a singular block)."""
     lib = load_library()
     q = ctypes.c_double(0.0)
-    _check(lib.apf_test_pivot_block(int(F.shape[0]), _ptr(F), _ptr(tri), _ptr(perm), ctypes.byref(q), _stream()))
+    _check(lib.apf_test_pivot_block(int(F.shape[0]), _ptr(F), _ptr(tri), _ptr(perm), ctypes.byref(q),
+                                    1 if sym else 0, _stream()))
     return q.value
 
 

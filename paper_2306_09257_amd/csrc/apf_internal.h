@@ -181,6 +181,14 @@ inline bool tri_task(const GemmTask &T) { return T.flags & (G_A_TRI_L | G_A_TRI_
 
 struct ZeroRange { cplx *ptr; int64_t n; };
 struct CopyRange { const cplx *src; cplx *dst; int64_t n; };   // n contiguous complex entries
+// dst (rows x cols) = src^T, dst row r scaled by 1 / diag[r * ldiag + r] when
+// diag is not null (the symmetric route's U12 = D L21^T and Z = X12^T)
+struct TransTask {
+  const cplx *src;
+  cplx *dst;
+  const cplx *diag;
+  int32_t lds, ldd, ldiag, rows, cols, pad;
+};
 
 // A front of a low-rank sweep subtree.  A sweep front whose subtree holds no
 // channel rows has Y_piv = -X12 Y_bnd and Lam_piv[perm[k]] = -(Z^T Lam_bnd)[k]

@@ -115,6 +115,9 @@ struct LevelTasks {
   int64_t sch[kSchurColors] = {-1, -1, -1, -1};
   int nsch[kSchurColors] = {0, 0, 0, 0};
   int id1 = -1, id2 = -1, id2b = -1;       // the lists' entries in the plan's tunable-list table
+  // symmetric route: U12 = D L21^T of the level's fronts, between phases 1 and 2
+  int64_t utr = -1;
+  int nutr = 0;
   int64_t inv[N_INV_VARIANTS];
   int ninv[N_INV_VARIANTS];
   LevelTasks() {
@@ -296,6 +299,9 @@ struct Plan {
   int rhs_chunk = 0;
   std::vector<LevelTasks> lv;
   int64_t vinit = -1, gidx = -1, fronts = -1, gSsplit = -1, vmap_base = -1, vmap_pidx = -1;
+  bool sym = false;           // symmetric route (apf_set_symmetric)
+  int64_t ztr = -1;           // symmetric route: Z = X12^T of the sweep fronts, after the factorization
+  int nztr = 0;
   int64_t xc_rows = 0;        // rows of the weighted-adjoint operand store (sweep fronts with C rows)
   int64_t xc_elems = 0;       // its size: xc_rows x n_out, or the sum of p x mC of compressed panels
   cplx *xc = nullptr;         // L^-T U^-T FC1^T of those fronts, stacked front by front (ld mC)
@@ -487,6 +493,7 @@ struct apf_handle {
   double refine_tol = 0.0;
   bool refined = false; // the factors held come from APF_MIXED_REFINED (apf_grad refines too)
   bool sweeps = true;   // the plan prepares the gradient sweeps (apf_set_gradient)
+  bool symmetric = false;  // L D L^T pivot blocks and the products' symmetry (apf_set_symmetric)
 };
 
 // The gradient sweeps' data (X12, Z, X1B, XC1 of the sweep fronts, the X/V
@@ -1260,6 +1267,10 @@ static void build_plan(apf_handle *H) {
   std::vector<std::vector<std::vector<GemmTask>>> schL(H_ + 1);   // compressed: S~ blocks, per colour
   std::vector<std::vector<std::vector<GemmTask>>> schTiles(H_ + 1, std::vector<std::vector<GemmTask>>(LevelTasks::kSchurColors));
   std::vector<std::vector<GemmTask>> g1(H_ + 1), g2(H_ + 1), g2b(H_ + 1), swY(H_ + 1), swL(H_ + 1), swW(H_ + 1);
+  const bool sym = H->symmetric;
+  P.sym = sym;
+  std::vector<std::vector<TransTask>> utrL(H_ + 1);
+  std::vector<TransTask> ztrL;
   std::vector<std::vector<GemmTask>> wuL(H_ + 1), wqL(H_ + 1);
   std::vector<std::vector<WFront>> wpL(H_ + 1);
   std::vector<GemmTask> vinit;
@@ -1353,7 +1364,14 @@ static void build_plan(apf_handle *H) {
     cplx *u1b = mB ? U1B(f) : nullptr, *lc1t = mC ? LC1T(f) : nullptr;
     const int32_t *perm = D.perm;
     g_cmacs_acc = 0;
-    if (b) add_tiles(g1[lvl], gemm(tri, p, F12, n, u12, b, p, b, p, G_A_TRI_L, nullptr, 0, perm));
+    // Symmetric route (F11 = L D L^T, perm the identity, F12 = F21^T, only
+    // the lower triangle of each core maintained): L21 = F21 U^-1 as below,
+    // and U12 = L^-1 F12 = D L21^T by a transpose instead of a product; the
+    // contribution F22 - L21 U12 is symmetric and formed on its lower tiles
+    // only (the boundary maps keep the elimination order, so it lands in the
+    // lower triangle of the parent's core).
+    if (b && !sym) add_tiles(g1[lvl], gemm(tri, p, F12, n, u12, b, p, b, p, G_A_TRI_L, nullptr, 0, perm));
+    if (b && sym) utrL[lvl].push_back(TransTask{l21, u12, tri, p, b, p, p, b, 0});
     if (mB) add_tiles(g1[lvl], gemm(tri, p, D.bp_piv, mB, u1b, mB, p, mB, p, G_A_TRI_L, nullptr, 0, perm));
     if (b) add_tiles(g1[lvl], gemm(F21, n, tri, p, l21, p, b, p, p, G_B_TRI_U));
     if (mC) add_tiles(g1[lvl], gemm(tri, p, D.cpt_piv, mC, lc1t, mC, p, mC, p, G_TRANS_A | G_A_TRI_U));
@@ -1369,7 +1387,21 @@ static void build_plan(apf_handle *H) {
         GemmTask t = gemm(l21, p, u12, b, PD.core, PD.p + PD.b, b, b, p, G_NEG | G_CIN | G_CIN_OWN | G_C_ACC, F22, n);
         t.crowmap = reinterpret_cast<const int32_t *>((intptr_t)rmap_off[f]);  // rebased below
         t.ccolmap = t.crowmap;
-        add_tiles(gp, t);
+        if (!sym) {
+          add_tiles(gp, t);
+        } else {
+          for (int k = 1; k < b; ++k)
+            if (F.rmap[k] <= F.rmap[k - 1]) throw std::runtime_error("boundary map out of elimination order");
+          std::vector<GemmTask> all;
+          const double acc0 = g_cmacs_acc;
+          add_tiles(all, t);
+          g_cmacs_acc = acc0;
+          for (const GemmTask &u : all)
+            if (u.tn <= u.tm) {
+              g_cmacs_acc += tile_cmacs(u, u.tm, u.tn);
+              gp.push_back(u);
+            }
+        }
       }
       if (mB) {
         cplx *dst = PD.bp_piv + (cz ? H->cz.cB0[f] - H->cz.cB0[F.parent] : 0);
@@ -1417,7 +1449,8 @@ static void build_plan(apf_handle *H) {
     if (F.sweep) {
       if (b) add_tiles(g2[lvl], gemm(tri, p, u12, b, FSx(q.fs_x12), b, p, b, p, G_A_TRI_U));
       if (mB) add_tiles(g2[lvl], gemm(tri, p, u1b, mB, FSx(q.fs_x1b), mB, p, mB, p, G_A_TRI_U));
-      if (b) add_tiles(g2[lvl], gemm(l21, p, tri, p, FSx(q.fs_z), p, b, p, p, G_B_TRI_L));
+      if (b && !sym) add_tiles(g2[lvl], gemm(l21, p, tri, p, FSx(q.fs_z), p, b, p, p, G_B_TRI_L));
+      if (b && sym) ztrL.push_back(TransTask{FSx(q.fs_x12), FSx(q.fs_z), nullptr, b, p, 0, b, p, 0});
       if (mC) add_tiles(g2[lvl], gemm(tri, p, lc1t, mC, P.xc + q.xoff, mC, p, mC, p, G_TRANS_A | G_A_TRI_L));
     }
     cm_factor += g_cmacs_acc;
@@ -1591,7 +1624,9 @@ static void build_plan(apf_handle *H) {
     L.g1 = bl.add(g1[lvl]); L.ng1 = (int)g1[lvl].size();
     L.g2 = bl.add(g2[lvl]); L.ng2 = (int)g2[lvl].size();
     L.g2b = bl.add(g2b[lvl]); L.ng2b = (int)g2b[lvl].size();
+    L.utr = bl.add(utrL[lvl]); L.nutr = (int)utrL[lvl].size();
   }
+  P.ztr = bl.add(ztrL); P.nztr = (int)ztrL.size();
   P.swl.assign(H_ + 2, -1);
   P.nswl.assign(H_ + 2, 0);
   P.nswl_thin.assign(H_ + 2, 0);
@@ -1770,7 +1805,7 @@ extern "C" apf_status apf_assemble(apf_handle *h, const double *eps_dev, void *s
 // indexes; `fr` the front descriptors.
 static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const FrontDev *fr, int *status,
                        Profiler &pr, hipStream_t s, bool f32, const std::vector<AugLevel> *aug = nullptr,
-                       char *ablob = nullptr, double *pivq = nullptr) {
+                       char *ablob = nullptr, double *pivq = nullptr, bool sym = false) {
   auto at = [&](int64_t off) -> char * { return off < 0 ? nullptr : blob + off; };
   auto aat = [&](int64_t off) -> char * { return off < 0 ? nullptr : ablob + off; };
   for (size_t lvl = 0; lvl < lv.size(); ++lvl) {
@@ -1793,7 +1828,7 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
     pr.run(P_INVERSE, s, [&] {
       hipError_t e = hipSuccess;
       for (int v = 0; v < N_INV_VARIANTS && e == hipSuccess; ++v)
-        e = launch_inverse(v, fr, (const int32_t *)at(L.inv[v]), L.ninv[v], status, pivq, s);
+        e = launch_inverse(v, fr, (const int32_t *)at(L.inv[v]), L.ninv[v], status, pivq, sym ? 1 : 0, s);
       return e;
     });
     // (empty task lists launch nothing and are not counted)
@@ -1810,6 +1845,8 @@ static void run_levels(const std::vector<LevelTasks> &lv, char *blob, const Fron
                              ntri);
         }, gemm_kernel_launches(n, nthin, ntri, f32));
       pr.cur_tag = -1;
+      if (g == 0 && L.nutr > 0)
+        pr.run(P_GEMM_FACTOR, s, [&] { return launch_transpose_scale((const TransTask *)at(L.utr), L.nutr, s); });
       // the augmented panels' products after the main phase 1 (their inputs)
       // and phase 2 (no dependence either way)
       if (A && g < 2) {
@@ -1916,6 +1953,7 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
   if (!h || !S_dev) return fail(APF_EINVAL, "null argument");
   if (prec != APF_FP64 && prec != APF_MIXED && prec != APF_MIXED_REFINED) return fail(APF_EINVAL, "unknown precision");
   if (h->state < 1) return fail(APF_ESTATE, "apf_assemble has not run");
+  if (h->symmetric && prec != APF_FP64) return fail(APF_EINVAL, "the symmetric route runs in FP64 only");
   const bool refine = prec == APF_MIXED_REFINED;
   if (refine && h->refine_iters <= 0)
     return fail(APF_ESTATE, "APF_MIXED_REFINED needs apf_set_refinement before the first apf_assemble");
@@ -1929,7 +1967,9 @@ extern "C" apf_status apf_factor_schur(apf_handle *h, apf_precision prec, double
     HIPCHK(launch_fill_int(P.status, 0, s));
     const bool cz = h->cz.pad >= 0;
     if (cz) HIPCHK(launch_zero_flat(P.czS, (int64_t)h->cz.MxC * h->cz.MxB, s));
-    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32, nullptr, nullptr, P.pivq);
+    run_levels(P.lv, P.blob, P.at<FrontDev>(P.fronts), P.status, pr, s, f32, nullptr, nullptr, P.pivq, P.sym);
+    if (P.nztr > 0)
+      pr.run(P_GEMM_FACTOR, s, [&] { return launch_transpose_scale(P.at<TransTask>(P.ztr), P.nztr, s); });
     if (cz) {
       // decompression: S = D_C (S~ D_B), FP64
       pr.run(P_GEMM_SCHUR, s, [&] {
@@ -2124,6 +2164,7 @@ extern "C" apf_status apf_factor_schur_batched(apf_handle *const *hs, int32_t n,
     if (!hs[i] || !S_devs[i]) return fail(APF_EINVAL, "null handle or output");
     if (hs[i]->state < 1) return fail(APF_ESTATE, "apf_assemble has not run on every handle");
     if (hs[i]->cz.pad >= 0) return fail(APF_EINVAL, "compressed channels are not batched");
+    if (hs[i]->symmetric) return fail(APF_EINVAL, "the symmetric route is not batched");
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(APF_EINVAL, "a handle appears twice in the batch");
   }
@@ -2457,6 +2498,7 @@ static apf_status augmented_grad(apf_handle *h, int32_t n_cols, const int32_t *c
                                  int32_t n_params, const int32_t *param_begin, int32_t n_sub, int32_t flags,
                                  const double *dfdS_dev, double *S_dev, double *dfdp_dev, hipStream_t s,
                                  int32_t *n_sub_used) {
+  if (h->symmetric) return fail(APF_EINVAL, "the augmented route runs on the LU route's factor lists");
   Symbolic &S = h->sym;
   const Desc &d = h->d;
   Plan &P = h->plan;
@@ -3003,6 +3045,16 @@ extern "C" apf_status apf_set_rhs_chunk(apf_handle *h, int32_t max_chunk) {
   return APF_OK;
 }
 
+extern "C" apf_status apf_set_symmetric(apf_handle *h, int32_t on) {
+  if (!h) return fail(APF_EINVAL, "null handle");
+  if (on != 0 && on != 1) return fail(APF_EINVAL, "on must be 0 or 1");
+  if (h->planned) return fail(APF_ESTATE, "the plan is already built (apf_assemble has run)");
+  if (on && h->cz.pad >= 0) return fail(APF_EINVAL, "the symmetric route does not combine with compressed channels");
+  if (on && h->refine_iters > 0) return fail(APF_EINVAL, "the symmetric route does not combine with refinement");
+  h->symmetric = on != 0;
+  return APF_OK;
+}
+
 extern "C" apf_status apf_set_lowrank(apf_handle *h, int32_t levels) {
   if (!h) return fail(APF_EINVAL, "null handle");
   if (levels < 0 || levels > kWMaxLevels) return fail(APF_EINVAL, "low-rank subtree levels must be 0, 1 or 2");
@@ -3016,6 +3068,7 @@ extern "C" apf_status apf_set_compression(apf_handle *h, int32_t pad, double win
   if (!h->analyzed) return fail(APF_ESTATE, "apf_analyze has not run");
   if (h->planned) return fail(APF_ESTATE, "the plan is already built (apf_assemble has run)");
   if (pad < -1) return fail(APF_EINVAL, "pad must be >= 0 (or -1 to switch compression off)");
+  if (pad >= 0 && h->symmetric) return fail(APF_EINVAL, "compressed channels do not combine with the symmetric route");
   const Desc &d = h->d;
   return guarded([&]() -> apf_status {
     if (pad < 0) {
@@ -3093,6 +3146,7 @@ extern "C" apf_status apf_set_refinement(apf_handle *h, int32_t max_iter, double
   if (max_iter < 0 || max_iter > 16) return fail(APF_EINVAL, "max_iter must be in [0, 16]");
   if (max_iter > 0 && !(tol > 0.0 && tol < 1.0)) return fail(APF_EINVAL, "tol must be in (0, 1)");
   if (h->planned) return fail(APF_ESTATE, "the plan is already built (apf_assemble has run)");
+  if (max_iter > 0 && h->symmetric) return fail(APF_EINVAL, "refinement does not combine with the symmetric route");
   h->refine_iters = max_iter;
   h->refine_tol = max_iter > 0 ? tol : 0.0;
   if (h->analyzed) size_plan(h);   // the retained-factor offsets depend on it
@@ -3255,8 +3309,9 @@ extern "C" apf_status apf_test_gemm(int32_t form, int32_t flags, int32_t M, int3
 
 // Kernel test hook: the pivot-block kernel on one p x p block.
 extern "C" apf_status apf_test_pivot_block(int32_t p, const double *F_dev, double *tri_dev, int32_t *perm_dev,
-                                           double *spread, void *stream) {
+                                           double *spread, int32_t sym, void *stream) {
   if (p < 1 || p > MAX_PIVOTS) return fail(APF_EINVAL, "p must be in [1, " + std::to_string(MAX_PIVOTS) + "]");
+  if (sym != 0 && sym != 1) return fail(APF_EINVAL, "sym must be 0 or 1");
   if (!F_dev || !tri_dev || !perm_dev) return fail(APF_EINVAL, "null argument");
   return guarded([&]() -> apf_status {
     hipStream_t s = (hipStream_t)stream;
@@ -3277,7 +3332,7 @@ extern "C" apf_status apf_test_pivot_block(int32_t p, const double *F_dev, doubl
     hipError_t e = hipMemcpyAsync(dfd, &fd, sizeof fd, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(did, &zero, sizeof zero, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(dst, 0, sizeof(int), s);
-    if (e == hipSuccess) e = launch_inverse(inverse_variant(p), dfd, did, 1, dst, dq, s);
+    if (e == hipSuccess) e = launch_inverse(inverse_variant(p), dfd, did, 1, dst, dq, sym ? 1 : 0, s);
     int st = 0;
     double q = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(&st, dst, sizeof st, hipMemcpyDeviceToHost, s);

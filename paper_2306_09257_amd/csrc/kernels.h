@@ -16,9 +16,12 @@ hipError_t launch_fill_int(int *p, int v, hipStream_t s);
 constexpr int N_INV_VARIANTS = 6;
 // kernel variant of a pivot block of size p (1 <= p <= MAX_PIVOTS), -1 beyond
 int inverse_variant(int p);
-// pivq (may be null): per front index, the block's pivot spread min |u_kk| / max |u_kk|
+// pivq (may be null): per front index, the block's pivot spread min |u_kk| / max |u_kk|;
+// sym != 0: symmetric blocks, lower triangle read, no row exchanges (F11 = L D L^T)
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, double *pivq,
-                          hipStream_t s);
+                          int sym, hipStream_t s);
+// dst = src^T per task, rows scaled by the inverse of diag's diagonal when given
+hipError_t launch_transpose_scale(const TransTask *t, int n, hipStream_t s);
 // part / pstride: output of the tasks flagged G_CONTRACT, partial of design
 // slot g and 32-column block b at part[b * pstride + g] (unused otherwise);
 // deep: MFMA-bound deep-K task list (three-product complex form on FP64);

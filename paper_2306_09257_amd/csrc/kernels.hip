@@ -189,6 +189,11 @@ __global__ void k_assemble_panel(const PanelEntry *e) {
 // at once; step k updates the L triangle (i > k, j < k) with column k of L
 // and row k of L, and the U triangle (i < k, j > k) with column k of U and
 // row k of U scaled by 1/u_kk; the two touch disjoint entries.
+//
+// Symmetric mode (sym != 0; A = A^T, Sec. 2, so every pivot block is complex
+// symmetric): only the lower triangle of the block is read (entry (i, j) with
+// i < j taken from (j, i)) and step k pivots on row k, so F11 = L U with
+// U = D L^T, the L D L^T factorization of the block, and perm is the identity.
 // ---------------------------------------------------------------------------
 constexpr int INV_MAXP = 1024;   // "no step" marker of a register row past p
 
@@ -199,7 +204,7 @@ constexpr int INV_MAXP = 1024;   // "no step" marker of a register row past p
 // pivot row, found at run time, needs a run-time register choice.
 template <int TR, int TC, int RR, int RC>
 __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const int32_t *ids, int *status,
-                                                       double *pivq) {
+                                                       double *pivq, int sym) {
   constexpr int MAXP = TR * RR;
   static_assert(TR * RR == TC * RC, "square coverage");
   static_assert(MAXP < INV_MAXP, "the no-step marker must exceed every step");
@@ -224,7 +229,8 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
 #pragma unroll
     for (int ca = 0; ca < RC; ++ca) {
       const int j = tj + TC * ca;
-      a[ra][ca] = (i < p && j < p) ? ld2(F.core + (int64_t)i * n + j) : make_double2(0.0, 0.0);
+      const int64_t o = (sym && j > i) ? (int64_t)j * n + i : (int64_t)i * n + j;
+      a[ra][ca] = (i < p && j < p) ? ld2(F.core + o) : make_double2(0.0, 0.0);
     }
   }
   __syncthreads();
@@ -235,17 +241,19 @@ __global__ __launch_bounds__(TR *TC) void k_lu_inv_reg(const FrontDev *fr, const
       const int k = kq * TC + kc;
       if (k >= p) break;
       if (tj == kc) {
-        // largest unused row of column k (ties: lowest row).  bi == p means
-        // "no unused row seen"; any unused row replaces it, so the search
-        // returns an unused row even when the column holds NaNs (which no
-        // comparison selects); a NaN or zero pivot is then flagged.
+        // largest unused row of column k (ties: lowest row); row k itself in
+        // symmetric mode.  bi == p means "no unused row seen"; any unused row
+        // replaces it, so the search returns an unused row even when the
+        // column holds NaNs (which no comparison selects); a NaN or zero
+        // pivot is then flagged.
         double bv = -1.0;
         int bi = p;
 #pragma unroll
         for (int ra = 0; ra < RR; ++ra) {
           const double2 v = a[ra][kq];
           const double m = v.x * v.x + v.y * v.y;
-          if (un[ra] && (bi == p || m > bv)) { bv = m; bi = ti + TR * ra; }
+          const int i = ti + TR * ra;
+          if (un[ra] && (sym ? i == k : (bi == p || m > bv))) { bv = m; bi = i; }
         }
 #pragma unroll
         for (int off = TR / 2; off > 0; off >>= 1) {
@@ -1619,6 +1627,37 @@ __global__ void k_copy(const CopyRange *r) {
   for (int64_t i = threadIdx.x; i < c.n; i += blockDim.x) d[i] = s[i];
 }
 
+// dst (rows x cols, ld ldd) = src^T (src: cols x rows, ld lds), row r of dst
+// scaled by 1 / diag[r * ldiag + r] when diag is given: with diag the
+// diagonal of U^-1 of a symmetric pivot block this forms U12 = D L21^T from
+// L21, without it Z = X12^T.  One workgroup per task, 32 x 32 tiles through
+// LDS so that both the reads of src rows and the writes of dst rows are
+// coalesced.
+__global__ __launch_bounds__(256) void k_transpose_scale(const TransTask *tasks) {
+  const TransTask T = tasks[blockIdx.x];
+  __shared__ double2 tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int r0 = 0; r0 < T.rows; r0 += 32)
+    for (int c0 = 0; c0 < T.cols; c0 += 32) {
+      __syncthreads();   // the previous tile's reads of LDS are done
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c0 + ty + 8 * q, r = r0 + tx;   // src row c, column r
+        if (c < T.cols && r < T.rows) tile[ty + 8 * q][tx] = ld2(T.src + (int64_t)c * T.lds + r);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + ty + 8 * q, c = c0 + tx;
+        if (r < T.rows && c < T.cols) {
+          double2 v = tile[tx][ty + 8 * q];
+          if (T.diag) v = cmul(v, cinv(ld2(T.diag + (int64_t)r * T.ldiag + r)));
+          st2(T.dst + (int64_t)r * T.ldd + c, v);
+        }
+      }
+    }
+}
+
 __global__ void k_fill_double(double *p, int n, double v) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = v;
@@ -1822,15 +1861,15 @@ int inverse_variant(int p) {
 // Small blocks (p <= 48, the leaves and short separators) run on one wave:
 // the per-step barriers are then free and more fronts fit on a CU.
 hipError_t launch_inverse(int variant, const FrontDev *fr, const int32_t *ids, int n, int *status, double *pivq,
-                          hipStream_t s) {
+                          int sym, hipStream_t s) {
   if (n == 0) return hipSuccess;
   switch (variant) {
-    case 0: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 2, 2>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq); break;
-    case 1: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 4, 4>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq); break;
-    case 2: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 6, 6>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq); break;
-    case 3: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status, pivq); break;
-    case 4: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status, pivq); break;
-    case 5: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status, pivq); break;
+    case 0: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 2, 2>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq, sym); break;
+    case 1: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 4, 4>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq, sym); break;
+    case 2: hipLaunchKernelGGL((k_lu_inv_reg<8, 8, 6, 6>), dim3(n), dim3(64), 0, s, fr, ids, status, pivq, sym); break;
+    case 3: hipLaunchKernelGGL((k_lu_inv_reg<16, 16, 4, 4>), dim3(n), dim3(256), 0, s, fr, ids, status, pivq, sym); break;
+    case 4: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 3, 6>), dim3(n), dim3(512), 0, s, fr, ids, status, pivq, sym); break;
+    case 5: hipLaunchKernelGGL((k_lu_inv_reg<32, 16, 4, 8>), dim3(n), dim3(512), 0, s, fr, ids, status, pivq, sym); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2001,6 +2040,11 @@ hipError_t launch_contract_rows(const int32_t *erow, int64_t n, const cplx *Lam,
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_contract_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, erow, n, Lam, ld, w, Y, ldy,
                      coff, scale, first ? 1 : 0, grad);
+  return hipGetLastError();
+}
+hipError_t launch_transpose_scale(const TransTask *t, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_scale, dim3(n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 hipError_t launch_copy(const CopyRange *r, int n, hipStream_t s) {

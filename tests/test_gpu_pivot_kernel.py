@@ -88,3 +88,58 @@ def test_singular_or_non_finite_block_reports_esingular(kind, p):
     G = rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p))
     tri, perm, q = _run(G)
     assert np.array_equal(perm, _lu_partial(G)[0])
+
+
+@pytest.mark.parametrize("p", SIZES)
+def test_symmetric_mode_reads_the_lower_triangle_and_keeps_the_order(p):
+    """Symmetric mode on a complex symmetric block whose strict upper triangle
+    holds NaNs (never read): no row exchanges (perm is the identity), the
+    inverses satisfy U^-1 L^-1 F = I, U = D L^T (the L D L^T factorization)
+    and the pivot spread is that of the unpivoted elimination."""
+    from paper_2306_09257_amd import binding
+    rng = np.random.default_rng(100 + p)
+    X = rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p))
+    F = X + X.T + 4.0 * np.sqrt(p) * np.eye(p)
+    Fin = F.copy()
+    Fin[np.triu_indices(p, 1)] = np.nan
+    Fd = torch.as_tensor(Fin, dtype=torch.complex128, device="cuda").contiguous()
+    tri = torch.zeros((p, p), dtype=torch.complex128, device="cuda")
+    perm = torch.zeros(p, dtype=torch.int32, device="cuda")
+    q = binding.pivot_block_hook(Fd, tri, perm, sym=True)
+    tri, perm = tri.cpu().numpy(), perm.cpu().numpy()
+    Linv = np.tril(tri, -1) + np.eye(p)
+    Uinv = np.triu(tri)
+    err = np.linalg.norm(Uinv @ Linv @ F - np.eye(p)) / np.sqrt(p)
+    L, U = np.linalg.inv(Linv), np.linalg.inv(Uinv)
+    esym = np.linalg.norm(U - np.diag(np.diag(U)) @ L.T) / np.linalg.norm(U)
+    # unpivoted elimination: |u_kk| in numpy
+    A = F.copy()
+    u = []
+    for k in range(p):
+        u.append(abs(A[k, k]))
+        A[k + 1:, k:] -= np.outer(A[k + 1:, k] / A[k, k], A[k, k:])
+    u = np.array(u)
+    print(f"[gpu] symmetric pivot block p={p}: |U^-1 L^-1 F - I| {err:.2e}, |U - D L^T| {esym:.2e}", flush=True)
+    assert np.array_equal(perm, np.arange(p))
+    assert np.isfinite(tri[np.tril_indices(p)]).all() and np.isfinite(Uinv).all()
+    assert err < 1e-12 and esym < 1e-12
+    assert abs(q - u.min() / u.max()) < 1e-10 * (u.min() / u.max())
+
+
+def test_symmetric_mode_reports_a_zero_leading_pivot():
+    """Without row exchanges a zero diagonal entry is a zero pivot:
+    APF_ESINGULAR (partial pivoting factors the same block)."""
+    from paper_2306_09257_amd import binding
+    p = 24
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p))
+    F = X + X.T
+    F[0, 0] = 0.0
+    Fd = torch.as_tensor(F, dtype=torch.complex128, device="cuda").contiguous()
+    tri = torch.zeros((p, p), dtype=torch.complex128, device="cuda")
+    perm = torch.zeros(p, dtype=torch.int32, device="cuda")
+    with pytest.raises(binding.APFError) as ei:
+        binding.pivot_block_hook(Fd, tri, perm, sym=True)
+    assert ei.value.status == binding.APF_ESINGULAR
+    binding.pivot_block_hook(Fd, tri, perm)
+    assert np.array_equal(perm.cpu().numpy(), _lu_partial(F)[0])

@@ -262,3 +262,49 @@ def test_refinement_switch_is_checked(lib):
     assert lib.apf_set_refinement(h, 0, 0.0) == binding.APF_OK
     assert apf.query("retained_factor_bytes") == 0
     assert apf.query("refine_chunk") == -1.0
+
+
+def test_symmetric_switch_is_checked(lib):
+    """apf_set_symmetric takes 0 or 1 before the first assembly, and refuses
+    to combine with refinement or compressed channels, set either way round."""
+    apf = binding.APF(_problem(24, 60)).analyze()
+    h = apf._h
+    E, OK = binding.APF_EINVAL, binding.APF_OK
+    for bad in (-1, 2):
+        assert lib.apf_set_symmetric(h, bad) == E
+    assert lib.apf_set_symmetric(None, 1) == E
+    assert lib.apf_set_symmetric(h, 1) == OK
+    assert lib.apf_set_refinement(h, 2, 1e-10) == E
+    assert lib.apf_set_compression(h, 8, 3.0) == E
+    assert lib.apf_set_symmetric(h, 0) == OK
+    assert lib.apf_set_refinement(h, 2, 1e-10) == OK
+    assert lib.apf_set_symmetric(h, 1) == E
+    assert lib.apf_set_refinement(h, 0, 0.0) == OK
+    assert lib.apf_set_symmetric(h, 1) == OK
+
+
+@pytest.mark.parametrize("nx,ny,leaf", [(24, 60, 0), (37, 60, 16), (48, 160, 96), (300, 92, 0)])
+def test_boundary_maps_keep_the_elimination_order(lib, nx, ny, leaf):
+    """Each front's boundary, listed in elimination order, lands in its
+    parent's local order (pivots, then boundary) at strictly increasing
+    positions: the lower triangle of a child's contribution block maps into
+    the lower triangle of the parent's core, which the symmetric route
+    relies on."""
+    apf = binding.APF(_problem(nx, ny), leaf_size=leaf).analyze()
+    nf = int(apf.query("n_fronts"))
+    fr = [apf.front(f) for f in range(nf)]
+    elim = {}
+    for info, piv, bnd in fr:
+        for k, u in enumerate(piv):
+            elim[int(u)] = info[7] + k
+    for info, piv, bnd in fr:
+        e = [elim[int(u)] for u in bnd]
+        assert e == sorted(e)
+        parent = info[0]
+        if parent < 0:
+            assert len(bnd) == 0
+            continue
+        pinfo, ppiv, pbnd = fr[parent]
+        local = {int(u): k for k, u in enumerate(list(ppiv) + list(pbnd))}
+        pos = [local[int(u)] for u in bnd]
+        assert all(b > a for a, b in zip(pos, pos[1:]))
