@@ -401,7 +401,8 @@ apf_status apf_set_refinement(apf_handle *h, int32_t max_iter, double tol);
  * unpivoted blocks amplify the rounding: S 3.8e-5 and gradient 1.5e-4 from
  * the FP64 values at 240 x 92, against 1.2e-6 and 8.4e-6 on the LU route);
  * APF_EINVAL with compressed channels or refinement (set either way round),
- * and from apf_factor_schur_batched and the augmented entry points.  Call before the first apf_assemble (else APF_ESTATE);
+ * and from apf_factor_schur_batched, apf_autotune over several handles and
+ * the augmented entry points.  Call before the first apf_assemble (else APF_ESTATE);
  * APF_EINVAL unless on is 0 or 1. */
 apf_status apf_set_symmetric(apf_handle *h, int32_t on);
 

@@ -2900,6 +2900,8 @@ static apf_status autotune_impl(apf_handle *const *hs, int32_t n, int32_t reps, 
   if (n == 1) {
     tl = &hs[0]->plan.tl;
   } else {
+    for (int i = 0; i < n; ++i)
+      if (hs[i]->symmetric) return fail(APF_EINVAL, "the symmetric route is not batched");
     std::vector<apf_handle *> v(hs, hs + n);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     for (auto &b : g_batches)

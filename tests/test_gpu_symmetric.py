@@ -84,13 +84,22 @@ def test_symmetric_route_runs_in_fp64_only():
     assert _rel(S, S_o) < TOL
 
 
-def test_symmetric_route_refuses_batches_and_the_augmented_route():
+def test_symmetric_route_refuses_batches_the_augmented_route_and_refinement():
     from paper_2306_09257_amd import binding
     prob, eps, w = inputs.tiny_problem(nx=24, ny=60, seed=0)
     apf = binding.APF(prob).analyze().set_symmetric(True)
     apf.assemble(_dev(eps, torch.float64))
     with pytest.raises(binding.APFError) as ei:
         binding.factor_schur_batched([apf])
+    assert ei.value.status == binding.APF_EINVAL
+    other = binding.APF(prob).analyze()
+    other.assemble(_dev(eps, torch.float64))
+    with pytest.raises(binding.APFError) as ei:
+        binding.autotune([apf, other], reps=1)
+    assert ei.value.status == binding.APF_EINVAL
+    dfdS = torch.zeros((prob.n_out, prob.n_in), dtype=torch.complex128, device="cuda")
+    with pytest.raises(binding.APFError) as ei:
+        apf.grad_augmented(dfdS, [0, 1], [-1.0, -1.0], [0, 2])
     assert ei.value.status == binding.APF_EINVAL
     with pytest.raises(binding.APFError) as ei:
         apf.factor_schur(precision=binding.APF_MIXED_REFINED)
