@@ -1014,12 +1014,15 @@ static void build_plan(apf_handle *H) {
   HIPCHK(hipMalloc(&P.part, 1024 * sizeof(double)));
   HIPCHK(hipMemset(P.status, 0, 2 * sizeof(int)));
 
-  // sweep arrays: pick the right-hand-side chunk from the free memory
+  // sweep arrays: pick the right-hand-side chunk from the free memory (three
+  // quarters of it: every chunk reruns the sweeps' latency-bound bottom
+  // levels, so fewer, wider chunks pay; the quarter left covers the plan's
+  // later buffers and the caller's S and dF/dS)
   {
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
     int64_t rows = std::max<int64_t>(S.n_sweep_rows, 1);
-    double budget = 0.5 * (double)fr;
+    double budget = 0.75 * (double)fr;
     int64_t chunk = (int64_t)(budget / (2.0 * rows * sizeof(cplx)));
     chunk = std::min<int64_t>(chunk, P.ncol);
     if (H->max_chunk > 0) chunk = std::min<int64_t>(chunk, H->max_chunk);

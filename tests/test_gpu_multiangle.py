@@ -9,7 +9,9 @@ Against values the CPU FP64 oracle wrote once
   (apf_group_fom) from the GPU's S, against the oracle's from the oracle's S;
 * the gradient for that derivative, at 2,000 seeded pixels and in 2-norm;
 * the objective and its derivative over all of S, GPU kernel against the
-  oracle formula applied to the same S; passivity of every column.
+  oracle formula applied to the same S; passivity of every column;
+
+on the LU route and on the symmetric route.
 """
 import os
 import time
@@ -32,12 +34,21 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def test_multiangle_48000x160_against_oracle_samples():
+@pytest.mark.parametrize("route", ["lu", "symmetric"])
+def test_multiangle_48000x160_against_oracle_samples(route):
+    """On the default LU route (the 1e-10 bar; measured S 3.0e-13, gradient
+    1.5e-12, worst blocks 9.5e-13 and 4.1e-12) and on the symmetric route
+    (L D L^T pivot blocks without row exchanges), against the same
+    oracle-written values.  The symmetric route loses about three digits on
+    this workload (measured S 1.0e-10, gradient 1.1e-10, worst blocks
+    4.0e-10 and 4.2e-10: some pivot blocks need the row exchanges it does
+    without) and is held to 1e-9 only."""
     from paper_2306_09257_amd import binding
     gold = np.load(GOLDEN, allow_pickle=False)
     prob, eps, delta = inputs.metasurface_multiangle(seed=2)
-    print(f"[gpu] multi-angle {prob.nx}x{prob.ny}, {prob.n_in} x {prob.n_out} channels, delta {delta}", flush=True)
-    apf = binding.APF(prob).analyze()
+    print(f"[gpu] multi-angle {prob.nx}x{prob.ny}, {prob.n_in} x {prob.n_out} channels, delta {delta}, "
+          f"{route} route", flush=True)
+    apf = binding.APF(prob).analyze().set_symmetric(route == "symmetric")
     dev = torch.device("cuda:0")
     apf.assemble(torch.as_tensor(eps, dtype=torch.float64, device=dev))
     S = apf.factor_schur()
@@ -62,9 +73,12 @@ def test_multiangle_48000x160_against_oracle_samples():
           f"sampled grad {eg:.2e}, grad norm {en:.2e}; objective kernel f {abs(float(f) - f_o) / abs(f_o):.2e}, "
           f"dF/dS {_rel(G_h, G_o):.2e}; worst blocks S {eS_blk:.2e}, grad {eg_blk:.2e}; gradient call "
           f"{t_grad:.2f} s", flush=True)
+    print(f"[gpu] {route} route: smallest pivot spread {apf.query('pivot_spread_min'):.3e} "
+          f"(front {apf.query('pivot_spread_front'):.0f})", flush=True)
     assert apf.query("rhs_chunk") < prob.n_in      # the chunked sweeps take part
-    assert eS < TOL and eG < TOL and eg < TOL and en < TOL
-    assert eS_blk < TOL and eg_blk < TOL
+    tol = TOL if route == "lu" else 1e-9
+    assert eS < tol and eG < tol and eg < tol and en < tol
+    assert eS_blk < tol and eg_blk < tol
     assert abs(float(f) - f_o) < 1e-12 * abs(f_o) and _rel(G_h, G_o) < 1e-12
     flux = np.sum(np.abs(S_h) ** 2, axis=0)
     assert np.all(np.isfinite(S_h)) and flux.max() <= 1.0 + 1e-9
