@@ -124,3 +124,30 @@ def test_symmetric_and_lu_routes_agree_at_full_size():
           f"(worst block {eg_blk:.2e}); factorization complex MACs {c1:.3e} vs {c0:.3e}", flush=True)
     assert eS < TOL and eS_blk < TOL and eg < TOL and eg_blk < TOL
     assert c1 < c0
+
+
+def test_symmetric_route_without_sweep_data_and_with_plain_sweeps():
+    """The symmetric route with the plan for S only (no sweep data: no X12,
+    no Z transposes) and with the low-rank subtrees forbidden (every sweep
+    front reads its Z, the transpose of X12) against the oracle at 1200 x 92."""
+    from paper_2306_09257_amd import binding
+    prob = inputs.make_problem(1200, 92)
+    rng = np.random.default_rng(11)
+    eps = inputs.eps_binary_smoothed(prob, rng)
+    w = inputs.weights_uniform(prob, rng)
+    S_o, g_o, _ = oapf.solve_S_and_grad(prob, eps, w=w)
+    a = binding.APF(prob).analyze().set_symmetric(True).set_gradient(False)
+    a.assemble(_dev(eps, torch.float64))
+    S = a.factor_schur().cpu().numpy()
+    eS = _rel(S, S_o)
+    print(f"[gpu] symmetric 1200x92, S only: S {eS:.2e}", flush=True)
+    assert eS < TOL and worst_block(S, S_o, axis=1) < TOL
+    a.close()
+    b = binding.APF(prob).analyze().set_symmetric(True).set_lowrank(0)
+    b.assemble(_dev(eps, torch.float64))
+    S = b.factor_schur()
+    f, G = b.weighted_power(S, _dev(w, torch.float64))
+    g = b.grad(G)
+    torch.cuda.synchronize()
+    assert b.query("lowrank_roots") == 0
+    _check(S.cpu().numpy(), g.cpu().numpy(), S_o, g_o, "symmetric 1200x92 plain sweeps")
